@@ -1,0 +1,103 @@
+"""Dense brute-force checker for tiny meshes -- TEST INFRASTRUCTURE ONLY.
+
+Independent numpy code (it calls nothing in the oracle library) that assembles
+the full ES-T-FEM stiffness matrix K = sum_k V_k Bt_k^T C Bt_k, where
+Bt_k = sum_{j in patch k} w_jk B_j is the smoothed strain-displacement matrix
+of edge k (Eqs. strain_discretization and CSTet_fint_discretization, with
+V_k = (1/6) sum_j V_j), and the standard FEM stiffness K_FEM = sum_j V_j B_j^T
+C B_j for comparison.  Also the consistent dense mass-free quantities the
+dynamics pins need (eigenvalues of M^-1 K).
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def lame(E, nu):
+    return E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+
+
+def cmat(E, nu):
+    lam, mu = lame(E, nu)
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[np.arange(3), np.arange(3)] += 2 * mu
+    C[3:, 3:] = np.eye(3) * mu
+    return C
+
+
+def tet_B(x):
+    """x: [4,3] node coords. Returns (B [6, 12], V) from the barycentric map."""
+    # solve for gradients of the linear shape functions: [1 x y z] a = e_l
+    A = np.hstack([np.ones((4, 1)), x])
+    coef = np.linalg.inv(A)         # columns: coefficients of N_l
+    g = coef[1:, :].T               # [4, 3] gradient of N_l
+    V = np.linalg.det(A) / 6.0
+    B = np.zeros((6, 12))
+    for l in range(4):
+        gx, gy, gz = g[l]
+        c = 3 * l
+        B[0, c] = gx
+        B[1, c + 1] = gy
+        B[2, c + 2] = gz
+        B[3, c], B[3, c + 1] = gy, gx
+        B[4, c + 1], B[4, c + 2] = gz, gy
+        B[5, c], B[5, c + 2] = gz, gx
+    return B, V
+
+
+def _edges_and_patches(elem_nodes):
+    patches = {}
+    for j, nd in enumerate(elem_nodes):
+        for a, b in itertools.combinations(range(4), 2):
+            key = tuple(sorted((int(nd[a]), int(nd[b]))))
+            patches.setdefault(key, []).append(j)
+    return patches
+
+
+def assemble(X, elem_nodes, E, nu, Veff=None, grads_from=None):
+    """Dense K_ES and K_FEM for elements with node lists `elem_nodes`.
+
+    X: [N, 3] coordinates of every node referenced.  Veff: per-element volume
+    carried (defaults to the geometric volume).  grads_from: optional [ne, 4]
+    node ids whose coordinates define each element's geometry (for split copies
+    whose extra nodes sit on top of their twins the geometry is the same).
+    """
+    X = np.asarray(X, float)
+    elem_nodes = np.asarray(elem_nodes)
+    N = len(X)
+    C = cmat(E, nu)
+    ne = len(elem_nodes)
+    Bs, Vs = [], []
+    for j in range(ne):
+        geo = elem_nodes[j] if grads_from is None else grads_from[j]
+        B, V = tet_B(X[geo])
+        Bs.append(B)
+        Vs.append(V)
+    Vs = np.array(Vs)
+    Ve = Vs if Veff is None else np.asarray(Veff, float)
+    dof = lambda nd: np.array([[3 * n, 3 * n + 1, 3 * n + 2] for n in nd]).ravel()
+    K = np.zeros((3 * N, 3 * N))
+    for key, pj in _edges_and_patches(elem_nodes).items():
+        S = sum(Ve[j] for j in pj)
+        if S == 0:
+            continue
+        Bt = np.zeros((6, 3 * N))
+        for j in pj:
+            Bt[:, dof(elem_nodes[j])] += (Ve[j] / S) * Bs[j]
+        K += (S / 6.0) * Bt.T @ C @ Bt
+    Kf = np.zeros((3 * N, 3 * N))
+    for j in range(ne):
+        d = dof(elem_nodes[j])
+        Kf[np.ix_(d, d)] += Ve[j] * Bs[j].T @ C @ Bs[j]
+    return K, Kf
+
+
+def lumped_mass(N, elem_nodes, Veff, rho):
+    m = np.zeros(N)
+    for j, nd in enumerate(elem_nodes):
+        for n in nd:
+            m[n] += rho * Veff[j] / 4.0
+    return m

@@ -1,0 +1,973 @@
+// Oracle for the 3D crack element method step -- TEST INFRASTRUCTURE ONLY.
+//
+// Plain FP64 CPU implementation, written for readability, not speed.  Only the
+// tests, the smoke check and the bench's CPU-baseline leg load it; the GPU
+// library shares no code with it.  Each function names the passage of the
+// paper it follows.  Readings of silent or garbled passages:
+//   * energy density psi = lambda/2 (tr eps)^2 + mu eps:eps  (Section 2.1; the
+//     printed density is garbled), so sigma = lambda tr(eps) I + 2 mu eps;
+//   * smoothing-domain volume of edge k is V_k = (1/6) sum of the volumes of
+//     the elements sharing the edge (expanded form of Eq. CSTet_fint);
+//   * lumped mass m_i = sum rho V_e / 4 over the elements holding node i;
+//   * face traction t on a boundary triangle of area A adds t A / 3 to each
+//     vertex (the paper writes the load with a 2D line segment);
+//   * Newmark beta = 0 with gamma = 1/2 (gamma is not printed);
+//   * stretch test: |x_j - x_i| > |X_j - X_i| evaluated as
+//     2 dX.du + |du|^2 > 0; the Heaviside step at 0 is 0;
+//   * the "maximum principal stress vector" projected on n is taken as
+//     sigma_1 |P_1 n| (P_1: projector on the eigenspace of the largest
+//     eigenvalue, ties within 1e-10 max|lambda|), or n.sigma.n (gsig = 1);
+//     projected stretches enter as |delta.n|;
+//   * crack front: a face of an intact tet shared with a split tet whose
+//     partition cuts that face; the node alone on its side is N2, the other
+//     face nodes N1 < N3 (local order), N4 the intact tet's opposite node;
+//   * Griffith test G >= Gc (Section 2.1); ties go to the lower local face,
+//     then pattern I before II; all splits of a step are decided on one state
+//     and applied together in ascending tet id; a tet splits at most once;
+//   * a split tet becomes two phantom-node copies (or is removed in erosion
+//     mode); each copy keeps the parent's gradients, volume fraction 1/2
+//     (2|2 partition) or 1/8 and 7/8 (1|3 partition, the lone side gets 1/8),
+//     its own side's real nodes and fresh extra nodes for the other side,
+//     which copy the twin's position and u, v, a; masses are rebuilt from the
+//     elements (kept fixed in erosion mode);
+//   * dissipated energy U_d = Gc * (midpoint crack area) summed over splits
+//     decided by the G test (host pre-splits excluded);
+//   * critical step dt_crit = 2 / sqrt(max_e (4/rho) lambda_max(B^T C B)).
+#include "oracle.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace {
+
+typedef std::array<double, 3> V3;
+
+V3 sub(const V3& a, const V3& b) { return {a[0] - b[0], a[1] - b[1], a[2] - b[2]}; }
+double dot(const V3& a, const V3& b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+V3 cross(const V3& a, const V3& b) {
+  return {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+}
+double norm(const V3& a) { return std::sqrt(dot(a, a)); }
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major).
+// On return w holds the eigenvalues and column i of vec the i-th eigenvector.
+void jacobi_eig(int n, std::vector<double> A, double* w, double* vec) {
+  std::vector<double> Vm(n * n, 0.0);
+  for (int i = 0; i < n; ++i) Vm[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < n; ++p) {
+      diag += A[p * n + p] * A[p * n + p];
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    }
+    if (off == 0.0 || off <= 1e-36 * diag) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- A G
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- G^T A
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // V <- V G
+          double vkp = Vm[k * n + p], vkq = Vm[k * n + q];
+          Vm[k * n + p] = c * vkp - s * vkq;
+          Vm[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
+  if (vec)
+    for (int i = 0; i < n * n; ++i) vec[i] = Vm[i];
+}
+
+struct Elem {
+  int n[4];          // node ids (real or extra)
+  double g[4][3];    // dN_l/dx, Section 2.2 (constant per tet)
+  double V;          // volume of the parent tetrahedron
+  double Veff;       // volume the element carries (V, a fraction of V, or 0)
+  int parent;        // original tet id
+};
+
+struct Event {
+  int step, tet, mask, pattern;
+  double G;
+};
+
+struct FrontRec {
+  int c, face, lone;
+  double GI, GII;
+};
+
+int popcount4(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
+
+}  // namespace
+
+struct orc_ctx {
+  int status = 0;
+  std::string err;
+  double E = 0, nu = 0, rho = 0, Gc = 0, lam = 0, mu = 0;
+  int mode = 0, gsig = 0;
+  int N0 = 0, T0 = 0;
+  std::vector<V3> X;
+  std::vector<Elem> el;
+  std::map<std::pair<int, int>, int> edge_of;
+  std::vector<std::pair<int, int>> edge_nodes;
+  std::vector<std::vector<int>> patch;
+  std::vector<std::array<int, 4>> orig;  // original (oriented) connectivity
+  std::vector<std::array<int, 4>> nbr, nbr_face;
+  std::vector<int> smask;  // per original tet: -1 intact, else side mask
+  std::vector<double> m;
+  std::vector<V3> F;
+  double ramp_t0 = 0;
+  double dt = 0;
+  long step = 0;
+  std::vector<V3> u, v, a;
+  bool need_init = true;
+  double W = 0, Ud = 0, Gmax = 0;
+  int nfront = 0, nsplit = 0;
+  std::vector<Event> events;
+  bool replay = false;
+  std::vector<Event> schedule;
+  size_t cursor = 0;
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+};
+
+namespace {
+
+// Linear elasticity, Section 2.1: Lame constants from E and nu.
+void lame(double E, double nu, double* lam, double* mu) {
+  *lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  *mu = E / (2.0 * (1.0 + nu));
+}
+
+// 6x6 elasticity matrix in the paper's Voigt order
+// (e11, e22, e33, g12, g23, g13) with engineering shear strains.
+void cmat(double lam, double mu, double C[6][6]) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) C[i][j] = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[i][j] = lam + (i == j ? 2.0 * mu : 0.0);
+  for (int i = 3; i < 6; ++i) C[i][i] = mu;
+}
+
+// Linear tetrahedron geometry (Section 2.2): with J = [X1-X0 | X2-X0 | X3-X0],
+// V = det J / 6 and dN_l/dx (l = 1..3) is row l of J^{-1}; dN_0 = -sum.
+double tet_geometry(const V3 x[4], double g[4][3]) {
+  double J[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) J[r][c] = x[c + 1][r] - x[0][r];
+  double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+               J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  double inv[3][3];
+  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  for (int l = 1; l <= 3; ++l)
+    for (int d = 0; d < 3; ++d) g[l][d] = inv[l - 1][d];
+  for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+  return det / 6.0;
+}
+
+// Strain-displacement matrix B (6 x 12) of Eq. CSTet_strain_discretization,
+// columns ordered (u_0, v_0, w_0, u_1, ...).
+void bmat(const double g[4][3], double B[6][12]) {
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 12; ++c) B[r][c] = 0.0;
+  for (int l = 0; l < 4; ++l) {
+    double gx = g[l][0], gy = g[l][1], gz = g[l][2];
+    int c = 3 * l;
+    B[0][c + 0] = gx;
+    B[1][c + 1] = gy;
+    B[2][c + 2] = gz;
+    B[3][c + 0] = gy;
+    B[3][c + 1] = gx;
+    B[4][c + 1] = gz;
+    B[4][c + 2] = gy;
+    B[5][c + 0] = gz;
+    B[5][c + 2] = gx;
+  }
+}
+
+// Voigt stress vector (s11, s22, s33, s12, s23, s13) -> symmetric 3x3 tensor.
+void voigt_to_tensor(const double* s, double T[9]) {
+  T[0] = s[0]; T[1] = s[3]; T[2] = s[5];
+  T[3] = s[3]; T[4] = s[1]; T[5] = s[4];
+  T[6] = s[5]; T[7] = s[4]; T[8] = s[2];
+}
+
+// Stress term of Eqs. G-I / G-II: the component of the maximum principal
+// stress along the crack normal n.  gsig 0: sigma_1 * |P_1 n| with P_1 the
+// projector on the eigenspace of the largest eigenvalue; gsig 1: n.sigma.n.
+double stress_term(const double* s6, const V3& n, int gsig) {
+  double T[9];
+  voigt_to_tensor(s6, T);
+  if (gsig == 1) {
+    double r = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) r += n[i] * T[3 * i + j] * n[j];
+    return r;
+  }
+  std::vector<double> A(T, T + 9);
+  double w[3], vec[9];
+  jacobi_eig(3, A, w, vec);
+  double lmax = std::max(w[0], std::max(w[1], w[2]));
+  double amax = std::max(std::fabs(w[0]), std::max(std::fabs(w[1]), std::fabs(w[2])));
+  double gap = 1e-10 * amax;
+  double p2 = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    if (w[i] >= lmax - gap) {
+      double c = vec[0 * 3 + i] * n[0] + vec[1 * 3 + i] * n[1] + vec[2 * 3 + i] * n[2];
+      p2 += c * c;
+    }
+  }
+  return lmax * std::sqrt(p2);
+}
+
+double ramp(const orc_ctx* c, double t) {
+  if (c->ramp_t0 > 0.0 && t < c->ramp_t0) return t / c->ramp_t0;
+  return 1.0;
+}
+
+int find_or_add_edge(orc_ctx* c, int a, int b) {
+  std::pair<int, int> key(std::min(a, b), std::max(a, b));
+  auto it = c->edge_of.find(key);
+  if (it != c->edge_of.end()) return it->second;
+  int id = (int)c->edge_nodes.size();
+  c->edge_of[key] = id;
+  c->edge_nodes.push_back(key);
+  c->patch.push_back({});
+  return id;
+}
+
+const int kEdgeLocal[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+void add_elem_to_edges(orc_ctx* c, int e) {
+  for (int q = 0; q < 6; ++q) {
+    int k = find_or_add_edge(c, c->el[e].n[kEdgeLocal[q][0]], c->el[e].n[kEdgeLocal[q][1]]);
+    c->patch[k].push_back(e);
+  }
+}
+
+void remove_elem_from_edges(orc_ctx* c, int e) {
+  for (int q = 0; q < 6; ++q) {
+    int a = c->el[e].n[kEdgeLocal[q][0]], b = c->el[e].n[kEdgeLocal[q][1]];
+    int k = c->edge_of.at(std::make_pair(std::min(a, b), std::max(a, b)));
+    auto& p = c->patch[k];
+    p.erase(std::find(p.begin(), p.end(), e));
+  }
+}
+
+// Lumped (row-sum) mass, Eq. mass_discretization: m_i = sum rho V_e / 4.
+void rebuild_masses(orc_ctx* c) {
+  c->m.assign(c->X.size(), 0.0);
+  for (const Elem& e : c->el)
+    for (int l = 0; l < 4; ++l) c->m[e.n[l]] += c->rho * e.Veff / 4.0;
+}
+
+// Smoothed strain and stress of every edge (Eqs. strain_discretization and
+// CSTet_strain_discretization): eps_k = sum_j w_jk B_j u_j with
+// w_jk = V_j / sum V over the elements sharing edge k; sigma_k = C eps_k.
+void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::array<double, 6>>& eps,
+                 std::vector<std::array<double, 6>>& sig, std::vector<double>& Vsum) {
+  double C[6][6];
+  cmat(c->lam, c->mu, C);
+  std::vector<std::array<double, 6>> eps_el(c->el.size());
+  for (size_t j = 0; j < c->el.size(); ++j) {
+    double B[6][12], ue[12];
+    bmat(c->el[j].g, B);
+    for (int l = 0; l < 4; ++l)
+      for (int d = 0; d < 3; ++d) ue[3 * l + d] = u[c->el[j].n[l]][d];
+    for (int r = 0; r < 6; ++r) {
+      double s = 0;
+      for (int q = 0; q < 12; ++q) s += B[r][q] * ue[q];
+      eps_el[j][r] = s;
+    }
+  }
+  size_t nE = c->edge_nodes.size();
+  eps.assign(nE, {0, 0, 0, 0, 0, 0});
+  sig.assign(nE, {0, 0, 0, 0, 0, 0});
+  Vsum.assign(nE, 0.0);
+  for (size_t k = 0; k < nE; ++k) {
+    double S = 0;
+    for (int j : c->patch[k]) S += c->el[j].Veff;
+    Vsum[k] = S;
+    if (S == 0.0) continue;  // every element on the edge removed: no stress
+    for (int j : c->patch[k]) {
+      double w = c->el[j].Veff / S;
+      for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];
+    }
+    for (int r = 0; r < 6; ++r) {
+      double s = 0;
+      for (int q = 0; q < 6; ++q) s += C[r][q] * eps[k][q];
+      sig[k][r] = s;
+    }
+  }
+}
+
+// Internal force, Eqs. fint_discretization / CSTet_fint_discretization in the
+// expanded form: f = sum_k V_k sum_{j in patch k} w_jk B_j^T sigma_k with
+// V_k = (1/6) sum_j V_j.  Written as the edge loop it states.
+void internal_force(const orc_ctx* c, const std::vector<V3>& u, std::vector<V3>& f) {
+  std::vector<std::array<double, 6>> eps, sig;
+  std::vector<double> Vsum;
+  edge_fields(c, u, eps, sig, Vsum);
+  f.assign(c->X.size(), {0, 0, 0});
+  for (size_t k = 0; k < c->edge_nodes.size(); ++k) {
+    double S = Vsum[k];
+    if (S == 0.0) continue;
+    double Vk = S / 6.0;
+    for (int j : c->patch[k]) {
+      double w = c->el[j].Veff / S;
+      double B[6][12];
+      bmat(c->el[j].g, B);
+      for (int q = 0; q < 12; ++q) {
+        double s = 0;
+        for (int r = 0; r < 6; ++r) s += B[r][q] * sig[k][r];
+        f[c->el[j].n[q / 3]][q % 3] += Vk * w * s;
+      }
+    }
+  }
+}
+
+// Fraction of the parent volume carried by the copy holding the nodes of one
+// side: midpoint cuts leave 1/8 on the side of a lone node, 7/8 on the side of
+// three nodes and 1/2 each for a 2|2 partition.
+double side_fraction(int nodes_on_side) {
+  if (nodes_on_side == 1) return 0.125;
+  if (nodes_on_side == 3) return 0.875;
+  return 0.5;
+}
+
+// Area of the midpoint crack surface of a tet cut by `mask`: the Varignon
+// parallelogram (2|2, Appendix I) or the corner triangle (1|3).
+double crack_area(const V3 x[4], int mask) {
+  int nb = popcount4(mask);
+  if (nb == 2) {
+    int A[2], Bn[2], ia = 0, ib = 0;
+    for (int l = 0; l < 4; ++l) {
+      if ((mask >> l) & 1) Bn[ib++] = l; else A[ia++] = l;
+    }
+    return 0.25 * norm(cross(sub(x[A[1]], x[A[0]]), sub(x[Bn[1]], x[Bn[0]])));
+  }
+  // the three nodes on the larger side span the face parallel to the cut
+  int big = (nb == 1) ? 0 : 1;
+  int q[3], iq = 0;
+  for (int l = 0; l < 4; ++l)
+    if ((((mask >> l) & 1) ? 1 : 0) == big) q[iq++] = l;
+  return 0.125 * norm(cross(sub(x[q[1]], x[q[0]]), sub(x[q[2]], x[q[0]])));
+}
+
+// Split (or erode) original tet t with side mask `mask` (bit l: local node l
+// on side B).  s_index is the global split counter (extra nodes N0+4s+l).
+void apply_split(orc_ctx* c, int t, int mask) {
+  c->smask[t] = mask;
+  Elem& par = c->el[t];
+  int nb = popcount4(mask);
+  if (c->mode == 1) {  // erosion: the element no longer carries volume
+    par.Veff = 0.0;
+    return;
+  }
+  remove_elem_from_edges(c, t);
+  int base = (int)c->X.size();
+  Elem copyB = par;
+  for (int l = 0; l < 4; ++l) {
+    int real = par.n[l];
+    int extra = base + l;
+    c->X.push_back(c->X[real]);
+    c->u.push_back(c->u[real]);
+    c->v.push_back(c->v[real]);
+    c->a.push_back(c->a[real]);
+    c->F.push_back({0, 0, 0});
+    bool onB = (mask >> l) & 1;
+    if (onB) {
+      c->el[t].n[l] = extra;  // copy A sees an extra node for a B-side node
+    } else {
+      copyB.n[l] = extra;     // copy B sees an extra node for an A-side node
+    }
+  }
+  c->el[t].Veff = side_fraction(4 - nb) * c->el[t].V;
+  copyB.Veff = side_fraction(nb) * copyB.V;
+  c->el.push_back(copyB);
+  add_elem_to_edges(c, t);
+  add_elem_to_edges(c, (int)c->el.size() - 1);
+}
+
+// Crack front list (Section 3): faces of intact tets shared with a split tet
+// whose partition cuts that face.  Each record names the intact tet c, its
+// local face (opposite local node `face`) and the real node of the face that
+// lies alone on its side of the cut (N2).  Sorted by (c, face).
+std::vector<FrontRec> fronts(const orc_ctx* c) {
+  std::vector<FrontRec> fr;
+  for (int s = 0; s < c->T0; ++s) {
+    int m = c->smask[s];
+    if (m < 0) continue;
+    for (int f = 0; f < 4; ++f) {
+      int nbt = c->nbr[s][f];
+      if (nbt < 0 || c->smask[nbt] >= 0) continue;
+      int fl[3], k = 0;
+      for (int l = 0; l < 4; ++l)
+        if (l != f) fl[k++] = l;
+      int b0 = (m >> fl[0]) & 1, b1 = (m >> fl[1]) & 1, b2 = (m >> fl[2]) & 1;
+      if (b0 == b1 && b1 == b2) continue;  // face not cut
+      int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];
+      FrontRec r;
+      r.c = nbt;
+      r.face = c->nbr_face[s][f];
+      r.lone = c->orig[s][lone];
+      r.GI = r.GII = 0;
+      fr.push_back(r);
+    }
+  }
+  std::sort(fr.begin(), fr.end(), [](const FrontRec& x, const FrontRec& y) {
+    return x.c != y.c ? x.c < y.c : x.face < y.face;
+  });
+  return fr;
+}
+
+// Release rates of one front (Eqs. stretch-delta, G-I, G-II).  Candidate tet
+// c, its face `face` (opposite local node `face`) lies on the crack front;
+// `lone` is the node of that face alone on its side (N2).
+void front_G(const orc_ctx* c, const std::vector<V3>& u, const std::vector<std::array<double, 6>>& sig,
+             const FrontRec& fr, double* GI, double* GII, int* maskI, int* maskII) {
+  const auto& tn = c->orig[fr.c];
+  int lN2 = -1, lN4 = fr.face, lN1 = -1, lN3 = -1;
+  for (int l = 0; l < 4; ++l) {
+    if (l == fr.face) continue;
+    if (tn[l] == fr.lone) lN2 = l;
+    else if (lN1 < 0) lN1 = l;
+    else lN3 = l;
+  }
+  int N1 = tn[lN1], N2 = tn[lN2], N3 = tn[lN3], N4 = tn[lN4];
+  const V3 &X1 = c->X[N1], &X2 = c->X[N2], &X3 = c->X[N3], &X4 = c->X[N4];
+  auto stretch = [&](int i, int j) -> V3 {
+    V3 du = sub(u[j], u[i]);
+    V3 dX = sub(c->X[j], c->X[i]);
+    double d = 2.0 * dot(dX, du) + dot(du, du);
+    if (d > 0.0) return du;
+    return {0, 0, 0};
+  };
+  V3 d1 = stretch(N1, N2), d2 = stretch(N2, N3);
+  auto unit = [](V3 x) {
+    double l = norm(x);
+    return V3{x[0] / l, x[1] / l, x[2] / l};
+  };
+  V3 nI = unit(cross(sub(X3, X1), sub(X4, X2)));
+  V3 nII = unit(cross(sub(X3, X1), sub(X4, X1)));
+  auto edge = [&](int a, int b) { return c->edge_of.at(std::make_pair(std::min(a, b), std::max(a, b))); };
+  double s3 = stress_term(sig[edge(N1, N4)].data(), nI, c->gsig);
+  double s4 = stress_term(sig[edge(N3, N4)].data(), nI, c->gsig);
+  double s6 = stress_term(sig[edge(N2, N4)].data(), nII, c->gsig);
+  *GI = 0.5 * (s3 * std::fabs(dot(d1, nI)) + s4 * std::fabs(dot(d2, nI)));
+  *GII = 0.5 * s6 * (std::fabs(dot(d1, nII)) + std::fabs(dot(d2, nII)));
+  *maskI = (1 << lN2) | (1 << lN4);
+  *maskII = (1 << lN2);
+}
+
+int initialize(orc_ctx* c) {
+  std::vector<V3> f;
+  internal_force(c, c->u, f);
+  double r = ramp(c, c->step * c->dt);
+  for (size_t i = 0; i < c->X.size(); ++i)
+    for (int d = 0; d < 3; ++d) c->a[i][d] = (r * c->F[i][d] - f[i][d]) / c->m[i];
+  c->need_init = false;
+  return 0;
+}
+
+// Decide the splits of this step on the current state (Section 3; Griffith
+// test of Section 2.1).  Returns (tet, mask, pattern, G) sorted by tet.
+std::vector<Event> decide_splits(orc_ctx* c) {
+  std::vector<Event> out;
+  std::vector<std::array<double, 6>> eps, sig;
+  std::vector<double> Vsum;
+  edge_fields(c, c->u, eps, sig, Vsum);
+  std::vector<FrontRec> fr = fronts(c);
+  c->nfront = (int)fr.size();
+  c->Gmax = 0.0;
+  bool any = false;
+  size_t i = 0;
+  while (i < fr.size()) {
+    size_t j = i;
+    double best = -INFINITY;
+    int bmask = 0, bpat = 0;
+    for (; j < fr.size() && fr[j].c == fr[i].c; ++j) {
+      double GI, GII;
+      int mI, mII;
+      front_G(c, c->u, sig, fr[j], &GI, &GII, &mI, &mII);
+      if (GI > best) { best = GI; bmask = mI; bpat = 1; }
+      if (GII > best) { best = GII; bmask = mII; bpat = 2; }
+    }
+    if (!any || best > c->Gmax) c->Gmax = best;
+    any = true;
+    if (best >= c->Gc) out.push_back({0, fr[i].c, bmask, bpat, best});
+    i = j;
+  }
+  if (!any) c->Gmax = 0.0;
+  return out;
+}
+
+void apply_events(orc_ctx* c, const std::vector<Event>& evs, bool dynamic) {
+  const auto& on = c->orig;
+  for (const Event& e : evs) {
+    if (dynamic) {
+      V3 x[4];
+      for (int l = 0; l < 4; ++l) x[l] = c->X[on[e.tet][l]];
+      c->Ud += c->Gc * crack_area(x, e.mask);
+    }
+    apply_split(c, e.tet, e.mask);
+    c->events.push_back(e);
+    c->events.back().step = (int)c->step;
+    c->nsplit++;
+  }
+  if (!evs.empty() && c->mode == 0) rebuild_masses(c);
+}
+
+// One explicit Newmark step (beta = 0, gamma = 1/2), then the crack pass.
+void one_step(orc_ctx* c) {
+  if (c->need_init) initialize(c);
+  double dt = c->dt;
+  double tn = c->step * dt, tn1 = (c->step + 1) * dt;
+  double rn = ramp(c, tn), rn1 = ramp(c, tn1);
+  size_t N = c->X.size();
+  std::vector<V3> u1(N);
+  for (size_t i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d)
+      u1[i][d] = c->u[i][d] + dt * c->v[i][d] + 0.5 * dt * dt * c->a[i][d];
+  std::vector<V3> f;
+  internal_force(c, u1, f);
+  for (size_t i = 0; i < N; ++i) {
+    for (int d = 0; d < 3; ++d) {
+      double an1 = (rn1 * c->F[i][d] - f[i][d]) / c->m[i];
+      c->W += 0.5 * (rn + rn1) * c->F[i][d] * (u1[i][d] - c->u[i][d]);
+      c->v[i][d] = c->v[i][d] + 0.5 * dt * (c->a[i][d] + an1);
+      c->a[i][d] = an1;
+      c->u[i][d] = u1[i][d];
+    }
+  }
+  c->step += 1;
+  std::vector<Event> evs;
+  if (c->replay) {
+    // forced schedule: splits listed for this step, G test not used
+    std::vector<Event> tmp = decide_splits(c);  // keeps Gmax / n_front readbacks
+    (void)tmp;
+    while (c->cursor < c->schedule.size() && c->schedule[c->cursor].step < c->step) c->cursor++;
+    while (c->cursor < c->schedule.size() && c->schedule[c->cursor].step == c->step) {
+      Event e = c->schedule[c->cursor++];
+      if (c->smask[e.tet] >= 0) continue;
+      e.pattern = popcount4(e.mask) == 2 ? 1 : 2;
+      e.G = 0.0;
+      evs.push_back(e);
+    }
+  } else if (c->Gc < INFINITY) {
+    evs = decide_splits(c);
+  } else {
+    c->nfront = (int)fronts(c).size();
+  }
+  apply_events(c, evs, true);
+}
+
+double strain_energy(const orc_ctx* c) {
+  std::vector<std::array<double, 6>> eps, sig;
+  std::vector<double> Vsum;
+  edge_fields(c, c->u, eps, sig, Vsum);
+  double se = 0;
+  for (size_t k = 0; k < eps.size(); ++k) {
+    double s = 0;
+    for (int r = 0; r < 6; ++r) s += sig[k][r] * eps[k][r];
+    se += 0.5 * (Vsum[k] / 6.0) * s;
+  }
+  return se;
+}
+
+}  // namespace
+
+extern "C" {
+
+void orc_lame(double E, double nu, double* lam, double* mu) { lame(E, nu, lam, mu); }
+
+orc_ctx* orc_create(int n_nodes, const double* X, int n_tets, const int* tets, double E, double nu,
+                    double rho, double Gc, int split_mode, int gsig) {
+  orc_ctx* c = new orc_ctx();
+  c->E = E; c->nu = nu; c->rho = rho; c->Gc = Gc;
+  c->mode = split_mode; c->gsig = gsig;
+  lame(E, nu, &c->lam, &c->mu);
+  c->N0 = n_nodes;
+  c->T0 = n_tets;
+  c->X.resize(n_nodes);
+  for (int i = 0; i < n_nodes; ++i) c->X[i] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
+  // mean edge length for the degeneracy test
+  double lsum = 0;
+  long lcnt = 0;
+  for (int t = 0; t < n_tets; ++t)
+    for (int q = 0; q < 6; ++q) {
+      int a = tets[4 * t + kEdgeLocal[q][0]], b = tets[4 * t + kEdgeLocal[q][1]];
+      if (a < 0 || a >= n_nodes || b < 0 || b >= n_nodes) {
+        c->status = -5;
+        c->err = "node id out of range";
+        return c;
+      }
+      lsum += norm(sub(c->X[a], c->X[b]));
+      lcnt++;
+    }
+  double lmean = lcnt ? lsum / lcnt : 0;
+  std::vector<std::array<int, 4>> orig(n_tets);
+  c->el.resize(n_tets);
+  for (int t = 0; t < n_tets; ++t) {
+    Elem& e = c->el[t];
+    for (int l = 0; l < 4; ++l) e.n[l] = tets[4 * t + l];
+    V3 x[4];
+    for (int l = 0; l < 4; ++l) x[l] = c->X[e.n[l]];
+    double V = tet_geometry(x, e.g);
+    if (V < 0) {  // orient: swap local nodes 2 and 3
+      std::swap(e.n[2], e.n[3]);
+      for (int l = 0; l < 4; ++l) x[l] = c->X[e.n[l]];
+      V = tet_geometry(x, e.g);
+    }
+    if (!(std::fabs(V) > 1e-12 * lmean * lmean * lmean)) {
+      c->status = -5;
+      c->err = "degenerate tetrahedron " + std::to_string(t);
+      return c;
+    }
+    e.V = V;
+    e.Veff = V;
+    e.parent = t;
+    for (int l = 0; l < 4; ++l) orig[t][l] = e.n[l];
+  }
+  c->orig = orig;
+  for (int t = 0; t < n_tets; ++t) add_elem_to_edges(c, t);
+  // face adjacency of the original mesh
+  c->nbr.assign(n_tets, {-1, -1, -1, -1});
+  c->nbr_face.assign(n_tets, {-1, -1, -1, -1});
+  std::map<std::array<int, 3>, std::vector<std::pair<int, int>>> faces;
+  for (int t = 0; t < n_tets; ++t)
+    for (int f = 0; f < 4; ++f) {
+      std::array<int, 3> k;
+      int q = 0;
+      for (int l = 0; l < 4; ++l)
+        if (l != f) k[q++] = orig[t][l];
+      std::sort(k.begin(), k.end());
+      faces[k].push_back({t, f});
+    }
+  for (auto& kv : faces) {
+    if (kv.second.size() > 2) {
+      c->status = -5;
+      c->err = "face shared by more than two tetrahedra";
+      return c;
+    }
+    if (kv.second.size() == 2) {
+      auto p = kv.second[0], q = kv.second[1];
+      c->nbr[p.first][p.second] = q.first;
+      c->nbr_face[p.first][p.second] = q.second;
+      c->nbr[q.first][q.second] = p.first;
+      c->nbr_face[q.first][q.second] = p.second;
+    }
+  }
+  c->smask.assign(n_tets, -1);
+  c->u.assign(n_nodes, {0, 0, 0});
+  c->v.assign(n_nodes, {0, 0, 0});
+  c->a.assign(n_nodes, {0, 0, 0});
+  c->F.assign(n_nodes, {0, 0, 0});
+  rebuild_masses(c);
+  return c;
+}
+
+int orc_create_status(const orc_ctx* c) { return c->status; }
+const char* orc_error(const orc_ctx* c) { return c->err.c_str(); }
+void orc_destroy(orc_ctx* c) { delete c; }
+
+// External force (Eq. for f_ext): each loaded boundary triangle adds t A / 3
+// to its three vertices.
+int orc_set_traction(orc_ctx* c, int n_faces, const int* tri, const double* t, double ramp_t0) {
+  for (auto& x : c->F) x = {0, 0, 0};
+  for (int f = 0; f < n_faces; ++f) {
+    int a = tri[3 * f], b = tri[3 * f + 1], d = tri[3 * f + 2];
+    if (a < 0 || b < 0 || d < 0 || a >= c->N0 || b >= c->N0 || d >= c->N0)
+      return c->fail(-1, "traction face node out of range");
+    double A = 0.5 * norm(cross(sub(c->X[b], c->X[a]), sub(c->X[d], c->X[a])));
+    for (int q = 0; q < 3; ++q) {
+      int n = tri[3 * f + q];
+      for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + k] * A / 3.0;
+    }
+  }
+  c->ramp_t0 = ramp_t0;
+  c->need_init = true;
+  return 0;
+}
+
+int orc_presplit(orc_ctx* c, int n, const int* tet, const unsigned char* mask) {
+  std::vector<std::pair<int, int>> lst;
+  for (int i = 0; i < n; ++i) {
+    int nb = popcount4(mask[i] & 15);
+    if (tet[i] < 0 || tet[i] >= c->T0) return c->fail(-1, "presplit tet out of range");
+    if ((mask[i] & ~15) || nb == 0 || nb == 4) return c->fail(-1, "presplit mask is not a partition");
+    lst.push_back({tet[i], mask[i]});
+  }
+  std::sort(lst.begin(), lst.end());
+  for (auto& p : lst) {
+    if (c->smask[p.first] >= 0) continue;
+    apply_split(c, p.first, p.second);
+    c->events.push_back({(int)c->step, p.first, p.second, 0, 0.0});
+    c->nsplit++;
+  }
+  if (c->mode == 0) rebuild_masses(c);
+  c->need_init = true;
+  return 0;
+}
+
+// Critical step: dt_crit = 2 / omega_hat, omega_hat^2 the largest element
+// eigenvalue of M_e^{-1} K_e with K_e = V B^T C B and M_e = rho V / 4 I.
+int orc_critical_dt(orc_ctx* c, double* dt_crit) {
+  std::vector<double> lam(c->T0);
+  orc_elem_lambda_max(c, lam.data());
+  double lmax = 0;
+  for (double l : lam) lmax = std::max(lmax, l);
+  *dt_crit = 2.0 / std::sqrt(4.0 / c->rho * lmax);
+  return 0;
+}
+
+int orc_elem_lambda_max(orc_ctx* c, double* lam) {
+  double C[6][6];
+  cmat(c->lam, c->mu, C);
+  std::map<std::array<double, 12>, double> memo;  // identical shapes repeat
+  for (int t = 0; t < c->T0; ++t) {
+    std::array<double, 12> key;
+    for (int l = 0; l < 4; ++l)
+      for (int d = 0; d < 3; ++d) key[3 * l + d] = c->el[t].g[l][d];
+    auto it = memo.find(key);
+    if (it != memo.end()) {
+      lam[t] = it->second;
+      continue;
+    }
+    double B[6][12];
+    bmat(c->el[t].g, B);
+    std::vector<double> K(144, 0.0);
+    for (int i = 0; i < 12; ++i)
+      for (int j = 0; j < 12; ++j) {
+        double s = 0;
+        for (int r = 0; r < 6; ++r)
+          for (int q = 0; q < 6; ++q) s += B[r][i] * C[r][q] * B[q][j];
+        K[12 * i + j] = s;
+      }
+    double w[12];
+    jacobi_eig(12, K, w, nullptr);
+    double lm = w[0];
+    for (int i = 1; i < 12; ++i) lm = std::max(lm, w[i]);
+    memo[key] = lm;
+    lam[t] = lm;
+  }
+  return 0;
+}
+
+int orc_set_dt(orc_ctx* c, double dt) {
+  if (!(dt > 0)) return c->fail(-1, "dt must be positive");
+  c->dt = dt;
+  return 0;
+}
+
+int orc_counts(orc_ctx* c, int* out) {
+  out[0] = (int)c->X.size();
+  out[1] = (int)c->el.size();
+  int ne = 0;
+  for (const auto& p : c->patch) ne += p.empty() ? 0 : 1;
+  out[2] = ne;
+  out[3] = c->nsplit;
+  out[4] = (int)fronts(c).size();
+  return 0;
+}
+
+int orc_set_state(orc_ctx* c, const double* u, const double* v) {
+  for (size_t i = 0; i < c->X.size(); ++i)
+    for (int d = 0; d < 3; ++d) {
+      if (u) c->u[i][d] = u[3 * i + d];
+      if (v) c->v[i][d] = v[3 * i + d];
+    }
+  c->need_init = true;
+  return 0;
+}
+
+int orc_get_state(orc_ctx* c, double* u, double* v, double* a) {
+  if (c->need_init && c->dt > 0) initialize(c);
+  for (size_t i = 0; i < c->X.size(); ++i)
+    for (int d = 0; d < 3; ++d) {
+      if (u) u[3 * i + d] = c->u[i][d];
+      if (v) v[3 * i + d] = c->v[i][d];
+      if (a) a[3 * i + d] = c->a[i][d];
+    }
+  return 0;
+}
+
+int orc_internal_force(orc_ctx* c, const double* u, double* f) {
+  std::vector<V3> uu(c->X.size());
+  for (size_t i = 0; i < uu.size(); ++i) uu[i] = {u[3 * i], u[3 * i + 1], u[3 * i + 2]};
+  std::vector<V3> ff;
+  internal_force(c, uu, ff);
+  for (size_t i = 0; i < ff.size(); ++i)
+    for (int d = 0; d < 3; ++d) f[3 * i + d] = ff[i][d];
+  return 0;
+}
+
+int orc_step(orc_ctx* c, int n_steps) {
+  if (!(c->dt > 0)) return c->fail(-7, "dt not set");
+  for (int s = 0; s < n_steps; ++s) one_step(c);
+  return 0;
+}
+
+int orc_energy(orc_ctx* c, double* out) {
+  if (c->need_init && c->dt > 0) initialize(c);
+  double ke = 0;
+  for (size_t i = 0; i < c->X.size(); ++i) ke += 0.5 * c->m[i] * dot(c->v[i], c->v[i]);
+  out[0] = (double)c->step;
+  out[1] = c->step * c->dt;
+  out[2] = ke;
+  out[3] = strain_energy(c);
+  out[4] = c->W;
+  out[5] = c->Ud;
+  out[6] = c->Gmax;
+  out[7] = c->nsplit;
+  out[8] = c->nfront;
+  out[9] = (double)c->X.size();
+  return 0;
+}
+
+int orc_splits(orc_ctx* c, int cap, int* ev4, double* G, int* n_out) {
+  int n = (int)c->events.size();
+  *n_out = n;
+  for (int i = 0; i < n && i < cap; ++i) {
+    ev4[4 * i + 0] = c->events[i].step;
+    ev4[4 * i + 1] = c->events[i].tet;
+    ev4[4 * i + 2] = c->events[i].mask;
+    ev4[4 * i + 3] = c->events[i].pattern;
+    G[i] = c->events[i].G;
+  }
+  return 0;
+}
+
+int orc_front_G(orc_ctx* c, int cap, int* tfl3, double* g2, int* n_out) {
+  std::vector<std::array<double, 6>> eps, sig;
+  std::vector<double> Vsum;
+  edge_fields(c, c->u, eps, sig, Vsum);
+  std::vector<FrontRec> fr = fronts(c);
+  *n_out = (int)fr.size();
+  for (int i = 0; i < (int)fr.size() && i < cap; ++i) {
+    double GI, GII;
+    int mI, mII;
+    front_G(c, c->u, sig, fr[i], &GI, &GII, &mI, &mII);
+    tfl3[3 * i] = fr[i].c;
+    tfl3[3 * i + 1] = fr[i].face;
+    tfl3[3 * i + 2] = fr[i].lone;
+    g2[2 * i] = GI;
+    g2[2 * i + 1] = GII;
+  }
+  return 0;
+}
+
+int orc_replay(orc_ctx* c, int n, const int* ev3) {
+  c->schedule.clear();
+  for (int i = 0; i < n; ++i) c->schedule.push_back({ev3[3 * i], ev3[3 * i + 1], ev3[3 * i + 2], 0, 0.0});
+  std::stable_sort(c->schedule.begin(), c->schedule.end(), [](const Event& x, const Event& y) {
+    return x.step != y.step ? x.step < y.step : x.tet < y.tet;
+  });
+  c->cursor = 0;
+  c->replay = true;
+  return 0;
+}
+
+int orc_masses(orc_ctx* c, double* m) {
+  for (size_t i = 0; i < c->m.size(); ++i) m[i] = c->m[i];
+  return 0;
+}
+
+int orc_loads(orc_ctx* c, double* F) {
+  for (size_t i = 0; i < c->F.size(); ++i)
+    for (int d = 0; d < 3; ++d) F[3 * i + d] = c->F[i][d];
+  return 0;
+}
+
+int orc_elements(orc_ctx* c, int* nodes4, double* Veff, double* V, int* parent) {
+  for (size_t e = 0; e < c->el.size(); ++e) {
+    for (int l = 0; l < 4; ++l)
+      if (nodes4) nodes4[4 * e + l] = c->el[e].n[l];
+    if (Veff) Veff[e] = c->el[e].Veff;
+    if (V) V[e] = c->el[e].V;
+    if (parent) parent[e] = c->el[e].parent;
+  }
+  return 0;
+}
+
+int orc_grad(orc_ctx* c, double* g12) {
+  for (size_t e = 0; e < c->el.size(); ++e)
+    for (int l = 0; l < 4; ++l)
+      for (int d = 0; d < 3; ++d) g12[12 * e + 3 * l + d] = c->el[e].g[l][d];
+  return 0;
+}
+
+// Edges of the current element set (node pairs with a non-empty patch) with
+// their smoothed strain and stress at displacement u (current state if null).
+int orc_edges(orc_ctx* c, const double* u, int* nodes2, double* eps6, double* sig6) {
+  std::vector<V3> uu = c->u;
+  if (u)
+    for (size_t i = 0; i < uu.size(); ++i) uu[i] = {u[3 * i], u[3 * i + 1], u[3 * i + 2]};
+  std::vector<std::array<double, 6>> eps, sig;
+  std::vector<double> Vsum;
+  edge_fields(c, uu, eps, sig, Vsum);
+  int q = 0;
+  for (size_t k = 0; k < eps.size(); ++k) {
+    if (c->patch[k].empty()) continue;
+    if (nodes2) {
+      nodes2[2 * q] = c->edge_nodes[k].first;
+      nodes2[2 * q + 1] = c->edge_nodes[k].second;
+    }
+    for (int r = 0; r < 6; ++r) {
+      if (eps6) eps6[6 * q + r] = eps[k][r];
+      if (sig6) sig6[6 * q + r] = sig[k][r];
+    }
+    q++;
+  }
+  return 0;
+}
+
+int orc_sym_eig3(const double* s6, double* lam3, double* vec9) {
+  double T[9];
+  voigt_to_tensor(s6, T);
+  jacobi_eig(3, std::vector<double>(T, T + 9), lam3, vec9);
+  return 0;
+}
+
+double orc_stress_term(const double* s6, const double* n, int gsig) {
+  return stress_term(s6, V3{n[0], n[1], n[2]}, gsig);
+}
+
+double orc_crack_area(const double* X4, int mask) {
+  V3 x[4];
+  for (int l = 0; l < 4; ++l) x[l] = {X4[3 * l], X4[3 * l + 1], X4[3 * l + 2]};
+  return crack_area(x, mask);
+}
+
+}  // extern "C"
