@@ -1,0 +1,202 @@
+/*
+ * cem.h -- C-ABI of the MI355X (gfx950) explicit step of the 3D crack element
+ * method: edge-based smoothed FEM on linear tetrahedra (ES-T-FEM) with split
+ * crack elements.
+ *
+ * The method follows "A GPU-Accelerated Three-Dimensional Crack Element
+ * Method for Transient Dynamic Fracture Simulation" (arXiv 2508.04076):
+ *   - smoothed strain at every edge from the tets sharing it, weighted by
+ *     volume (Section 2.2, Eqs. strain_discretization and
+ *     CSTet_strain_discretization); stress sigma = C eps for isotropic linear
+ *     elasticity (Section 2.1);
+ *   - internal force from the edge smoothing domains (Eqs.
+ *     fint_discretization and CSTet_fint_discretization, expanded form with
+ *     V_k = (1/6) sum of the volumes sharing edge k), lumped mass (Eq.
+ *     mass_discretization), face traction loads (the f_ext equation);
+ *   - explicit Newmark, beta = 0, gamma = 1/2 (end of Section 2.2);
+ *   - crack pass of Section 3: edge stretch (Eq. stretch-delta), release
+ *     rates G_I and G_II of the two tetrahedral crack patterns (Eqs. G-I and
+ *     G-II), Griffith test G >= Gc (Section 2.1) and element splitting.
+ *
+ * Conventions
+ *   - Every call returns int status: CEM_OK (0) or a negative CEM_E* code; the
+ *     message of the last failure is cem_last_error(ctx) (context-owned).
+ *   - Ids are 0-based int32.  Coordinates, displacements, velocities and
+ *     forces are row-major [n][3] float64 host arrays in SI units.
+ *   - Host pointers are borrowed for the duration of the call and copied.
+ *     Device pointers given to cem_bind_state are borrowed, must outlive the
+ *     context and are never freed by it.
+ *   - All device work is enqueued on the stream given at creation.  Calls that
+ *     return data to the host synchronize that stream.
+ *   - A context is single-threaded; separate contexts are independent.
+ *   - cem_create performs no device call.  cem_upload_mesh validates and
+ *     preprocesses on the host first, then allocates device memory.
+ */
+#ifndef CEM_H
+#define CEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CEM_OK = 0,
+  CEM_EINVAL = -1,     /* bad argument */
+  CEM_ENOMEM = -2,     /* device or host allocation failed */
+  CEM_EHIP = -3,       /* HIP runtime error (no device, launch failure) */
+  CEM_EMESH = -4,      /* invalid mesh (degenerate or duplicated tet, face shared by > 2 tets) */
+  CEM_ECAPACITY = -5,  /* split capacity exhausted; state left at the start of the failing step */
+  CEM_EUNSTABLE = -6,  /* non-finite or runaway state (time step above the stability limit) */
+  CEM_ESTATE = -7      /* call out of order (e.g. step before upload or before cem_set_dt) */
+};
+
+enum { CEM_FP64 = 0, CEM_MIXED = 1 };          /* force arithmetic precision */
+enum { CEM_PHANTOM = 0, CEM_ERODE = 1 };       /* what a split does to the tet */
+enum { CEM_GSIG_PRINCIPAL = 0, CEM_GSIG_NORMAL = 1 };
+
+typedef struct cem_ctx cem_ctx;
+
+typedef struct {
+  int32_t device;       /* HIP device ordinal */
+  void* stream;         /* hipStream_t, borrowed; NULL: the context creates and
+                           owns a non-blocking stream */
+  int32_t precision;    /* CEM_FP64: all force arithmetic in float64.
+                           CEM_MIXED: gradients, strains, stresses and nodal
+                           force terms in float32; u, v, a, time step, forces
+                           sums, energies and G in float64 */
+  int32_t split_mode;   /* CEM_PHANTOM: a split tet becomes two copies that
+                           each carry the parent's gradients, a volume
+                           fraction (1/2,1/2 for a 2|2 partition; 1/8 on the
+                           lone-node side and 7/8 on the other for 1|3) and
+                           four fresh extra nodes for the other side.
+                           CEM_ERODE: the split tet carries no volume (the
+                           "deactivated" element of Section 3) */
+  int32_t gsig;         /* stress term of Eqs. G-I/G-II: CEM_GSIG_PRINCIPAL
+                           uses sigma_1 |P_1 n| (largest principal stress,
+                           P_1 projector on its eigenspace); CEM_GSIG_NORMAL
+                           uses n.sigma.n */
+  int32_t max_splits;   /* split capacity (host pre-splits + splits in steps) */
+  int32_t graph_steps;  /* steps per captured HIP graph in cem_step; 0 = plain launches */
+} cem_options;
+
+typedef struct {
+  double E;    /* Young's modulus (Pa) */
+  double nu;   /* Poisson ratio */
+  double rho;  /* density (kg/m^3) */
+  double Gc;   /* critical energy release rate (J/m^2); +inf disables splitting */
+} cem_material;
+
+typedef struct {
+  int64_t step;     /* steps taken */
+  double t;         /* step * dt */
+  double KE;        /* 1/2 sum m |v|^2 */
+  double SE;        /* 1/2 sum_k V_k sigma_k . eps_k over edges (engineering shear) */
+  double Wext;      /* work of the external load, trapezoidal in time */
+  double Ud;        /* Gc * midpoint crack area, summed over splits decided by the G test */
+  double Gmax;      /* largest G over the candidates of the last crack pass (0 if none) */
+  int32_t n_split;  /* split tets so far (pre-splits included) */
+  int32_t n_front;  /* crack-front faces of the current topology */
+  int32_t n_nodes;  /* nodes now (original + extra) */
+  int32_t n_elems;  /* element slots in use */
+} cem_energy;
+
+typedef struct {
+  int32_t step;       /* step at whose end the split was applied (0: before stepping) */
+  int32_t tet;        /* original tet id */
+  int32_t side_mask;  /* bit l set: local node l on side B (the lone node's side) */
+  int32_t pattern;    /* 1 = pattern I (quadrilateral), 2 = pattern II (triangle), 0 = host pre-split */
+  double G;           /* release rate that triggered the split (0 for pre-splits) */
+} cem_split_event;
+
+typedef struct {
+  int32_t tet;   /* intact candidate tet */
+  int32_t face;  /* its local face on the crack front (face opposite local node `face`) */
+  int32_t lone;  /* node of that face alone on its side of the neighbour's cut (N2) */
+  int32_t pad;
+  double G_I;    /* Eq. G-I */
+  double G_II;   /* Eq. G-II */
+} cem_front_g;
+
+/* Create a context.  Validates the options only (no device call). */
+int cem_create(const cem_options* opt, cem_ctx** out);
+void cem_destroy(cem_ctx* ctx);
+const char* cem_last_error(const cem_ctx* ctx);
+
+/* Mesh upload (Section 2.2).  X: [n_nodes][3]; tets: [n_tets][4].  Each tet is
+ * reordered to positive volume by swapping its local nodes 2 and 3; a tet with
+ * |V| <= 1e-12 (mean edge length)^3, a duplicated tet or a face shared by more
+ * than two tets gives CEM_EMESH.  Builds edges, edge patches, node and face
+ * adjacency on the host, then computes volumes and lumped masses on the
+ * device.  Callable once per context. */
+int cem_upload_mesh(cem_ctx* ctx, int32_t n_nodes, const double* X, int32_t n_tets,
+                    const int32_t* tets, const cem_material* mat);
+
+/* Face tractions (the f_ext equation): boundary triangles tri [n_faces][3]
+ * with traction vectors t [n_faces][3] (Pa).  Each triangle adds t A / 3 to
+ * each vertex.  Load factor r(t) = t / ramp_t0 below ramp_t0, else 1
+ * (ramp_t0 = 0: full load from t = 0).  Replaces earlier tractions. */
+int cem_set_traction(cem_ctx* ctx, int32_t n_faces, const int32_t* tri, const double* t,
+                     double ramp_t0);
+
+/* Split tets from the host (e.g. a pre-notch): side_mask bit l puts local node
+ * l (after orientation) on side B; it must be a 1|3 or 2|2 partition.  Already
+ * split tets are ignored.  No dissipated energy is booked. */
+int cem_presplit(cem_ctx* ctx, int32_t n, const int32_t* tet, const uint8_t* side_mask);
+
+/* dt_crit = 2 / sqrt(max_e (4 / rho) lambda_max(B_e^T C B_e)): the element
+ * bound on the largest frequency of M^-1 K, valid for every split state. */
+int cem_critical_dt(cem_ctx* ctx, double* dt_crit);
+int cem_set_dt(cem_ctx* ctx, double dt);
+
+/* Use caller device buffers (each at least capacity_nodes * 4 float64,
+ * rows padded to 4) for u and v.  The current state is copied into them. */
+int cem_bind_state(cem_ctx* ctx, double* d_u, double* d_v, int64_t capacity_nodes);
+
+/* Host state in and out, [n_nodes_now][3].  Either pointer may be NULL.  After
+ * cem_set_state the next step first recomputes a = M^-1 (f_ext - f(u)). */
+int cem_set_state(cem_ctx* ctx, const double* u, const double* v);
+int cem_get_state(cem_ctx* ctx, double* u, double* v, double* a, int32_t* n_nodes_now);
+
+/* Internal force f(u) on the current topology, [n_nodes_now][3] in and out. */
+int cem_internal_force(cem_ctx* ctx, const double* u, double* f);
+
+/* n_steps explicit steps.  Each step: smoothed strain (per tet), smoothed
+ * stress (per edge), crack pass (per candidate), node force and Newmark
+ * update, topology update of the new splits. */
+int cem_step(cem_ctx* ctx, int32_t n_steps);
+
+/* Forced split schedule (step, tet, side_mask; other fields ignored), applied
+ * at the end of the listed steps instead of the G test. */
+int cem_replay_splits(cem_ctx* ctx, int32_t n, const cem_split_event* ev);
+
+int cem_read_energy(cem_ctx* ctx, cem_energy* e);
+/* Split events in order (pre-splits first); *n = total, at most cap written. */
+int cem_read_splits(cem_ctx* ctx, int32_t cap, cem_split_event* out, int32_t* n);
+/* G_I and G_II of every current crack-front face, at the current state,
+ * sorted by (tet, face); *n = total, at most cap written. */
+int cem_read_front_G(cem_ctx* ctx, int32_t cap, cem_front_g* out, int32_t* n);
+
+/* Checkpoint of the whole simulation state into a host buffer (buf may be
+ * NULL to query the size) and restore into a context created with the same
+ * options and mesh. */
+int cem_save_state(cem_ctx* ctx, void* buf, int64_t cap, int64_t* used);
+int cem_load_state(cem_ctx* ctx, const void* buf, int64_t size);
+
+/* out[0..5]: nodes now, element slots now, edges now, splits, fronts,
+ * original edge count. */
+int cem_counts(cem_ctx* ctx, int32_t* out);
+
+/* Time of the kernels of the last cem_step, in milliseconds, measured with
+ * HIP events on the context stream: out[0] whole call, out[1] strain pass,
+ * out[2] edge stress pass, out[3] crack pass, out[4] node pass, out[5]
+ * topology pass.  Per-kernel times are recorded only when profiling was
+ * enabled with cem_set_profiling(ctx, 1) (then graphs are not used). */
+int cem_set_profiling(cem_ctx* ctx, int32_t on);
+int cem_kernel_times(cem_ctx* ctx, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CEM_H */

@@ -1,0 +1,286 @@
+"""Python binding of libcem (include/cem.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels of libcem.so; this module
+only converts numpy arrays to pointers and back, and uses PyTorch for the HIP
+stream (and optionally to own the state buffers).  If the shared library is
+missing, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcem.so")
+
+CEM_OK, CEM_EINVAL, CEM_ENOMEM, CEM_EHIP, CEM_EMESH, CEM_ECAPACITY, CEM_EUNSTABLE, CEM_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+ERROR_NAMES = {-1: "CEM_EINVAL", -2: "CEM_ENOMEM", -3: "CEM_EHIP", -4: "CEM_EMESH",
+               -5: "CEM_ECAPACITY", -6: "CEM_EUNSTABLE", -7: "CEM_ESTATE"}
+PRECISION = {"fp64": 0, "mixed": 1}
+SPLIT_MODE = {"phantom": 0, "erode": 1}
+GSIG = {"principal": 0, "normal": 1}
+
+EXPORTS = [
+    "cem_create", "cem_destroy", "cem_last_error", "cem_upload_mesh", "cem_set_traction",
+    "cem_presplit", "cem_critical_dt", "cem_set_dt", "cem_bind_state", "cem_set_state",
+    "cem_get_state", "cem_internal_force", "cem_step", "cem_replay_splits", "cem_read_energy",
+    "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
+    "cem_set_profiling", "cem_kernel_times",
+]
+
+
+class cem_options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("precision", C.c_int32),
+                ("split_mode", C.c_int32), ("gsig", C.c_int32), ("max_splits", C.c_int32),
+                ("graph_steps", C.c_int32)]
+
+
+class cem_material(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double), ("Gc", C.c_double)]
+
+
+class cem_energy(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("KE", C.c_double), ("SE", C.c_double),
+                ("Wext", C.c_double), ("Ud", C.c_double), ("Gmax", C.c_double),
+                ("n_split", C.c_int32), ("n_front", C.c_int32), ("n_nodes", C.c_int32),
+                ("n_elems", C.c_int32)]
+
+
+class cem_split_event(C.Structure):
+    _fields_ = [("step", C.c_int32), ("tet", C.c_int32), ("side_mask", C.c_int32),
+                ("pattern", C.c_int32), ("G", C.c_double)]
+
+
+class cem_front_g(C.Structure):
+    _fields_ = [("tet", C.c_int32), ("face", C.c_int32), ("lone", C.c_int32), ("pad", C.c_int32),
+                ("G_I", C.c_double), ("G_II", C.c_double)]
+
+
+class CemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libcem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2508_04076_amd/build.py")
+    # PyTorch ships its own HIP runtime.  Load it first so that libcem binds to
+    # that same runtime instance: two HIP runtimes in one process cannot share
+    # the device.
+    import torch  # noqa: F401
+    L = C.CDLL(path)
+    p, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "cem_create": [C.POINTER(cem_options), C.POINTER(C.c_void_p)],
+        "cem_destroy": [p],
+        "cem_last_error": [p],
+        "cem_upload_mesh": [p, i32, p, i32, p, C.POINTER(cem_material)],
+        "cem_set_traction": [p, i32, p, p, d],
+        "cem_presplit": [p, i32, p, p],
+        "cem_critical_dt": [p, C.POINTER(C.c_double)],
+        "cem_set_dt": [p, d],
+        "cem_bind_state": [p, p, p, i64],
+        "cem_set_state": [p, p, p],
+        "cem_get_state": [p, p, p, p, C.POINTER(C.c_int32)],
+        "cem_internal_force": [p, p, p],
+        "cem_step": [p, i32],
+        "cem_replay_splits": [p, i32, p],
+        "cem_read_energy": [p, C.POINTER(cem_energy)],
+        "cem_read_splits": [p, i32, p, C.POINTER(C.c_int32)],
+        "cem_read_front_G": [p, i32, p, C.POINTER(C.c_int32)],
+        "cem_save_state": [p, p, i64, C.POINTER(C.c_int64)],
+        "cem_load_state": [p, p, i64],
+        "cem_counts": [p, p],
+        "cem_set_profiling": [p, i32],
+        "cem_kernel_times": [p, p],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.cem_destroy.restype = None
+    L.cem_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape):
+    return np.ascontiguousarray(a, dtype=np.float64).reshape(shape)
+
+
+class Simulation:
+    """One ES-T-FEM crack-element simulation on one GPU (a libcem context)."""
+
+    def __init__(self, X, tets, material, precision="fp64", split_mode="phantom",
+                 gsig="principal", max_splits=None, graph_steps=0, device=0, stream=None):
+        self.lib = load_library()
+        self.ctx = None
+        X = _f64(X, (-1, 3))
+        tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+        if max_splits is None:
+            max_splits = max(len(tets) // 8, 64)
+        self._torch_stream = None
+        if stream is None:
+            import torch
+            self._torch_stream = torch.cuda.Stream(device=device)
+            stream = self._torch_stream.cuda_stream
+        opt = cem_options(int(device), C.c_void_p(int(stream)), PRECISION[precision],
+                          SPLIT_MODE[split_mode], GSIG[gsig], int(max_splits), int(graph_steps))
+        ctx = C.c_void_p()
+        r = self.lib.cem_create(C.byref(opt), C.byref(ctx))
+        if r != 0:
+            raise CemError(r, "cem_create rejected the options")
+        self.ctx = ctx
+        mat = cem_material(float(material["E"]), float(material["nu"]), float(material["rho"]),
+                           float(material.get("Gc", np.inf)))
+        self._chk(self.lib.cem_upload_mesh(self.ctx, len(X), _p(X), len(tets), _p(tets),
+                                           C.byref(mat)))
+        self.n_tets = len(tets)
+        self.n_nodes0 = len(X)
+        self.precision = precision
+
+    @classmethod
+    def from_mesh(cls, mesh, material, presplit=True, traction=True, ramp_t0=0.0, Gc=None,
+                  **kw):
+        mat = dict(material)
+        if Gc is not None:
+            mat["Gc"] = Gc
+        sim = cls(mesh.X, mesh.tets, mat, **kw)
+        if traction and mesh.load_tris is not None:
+            sim.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
+        if presplit and mesh.presplit_tets is not None:
+            sim.presplit(mesh.presplit_tets, mesh.presplit_masks)
+        return sim
+
+    def close(self):
+        if self.ctx is not None:
+            self.lib.cem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, r):
+        if r != 0:
+            msg = self.lib.cem_last_error(self.ctx) if self.ctx is not None else b""
+            raise CemError(r, (msg or b"").decode())
+
+    def set_traction(self, tri, t, ramp_t0=0.0):
+        tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+        t = _f64(t, (-1, 3))
+        self._chk(self.lib.cem_set_traction(self.ctx, len(tri), _p(tri), _p(t), float(ramp_t0)))
+
+    def presplit(self, tets, masks):
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        masks = np.ascontiguousarray(masks, dtype=np.uint8)
+        self._chk(self.lib.cem_presplit(self.ctx, len(tets), _p(tets), _p(masks)))
+
+    def critical_dt(self):
+        d = C.c_double()
+        self._chk(self.lib.cem_critical_dt(self.ctx, C.byref(d)))
+        return d.value
+
+    def set_dt(self, dt):
+        self._chk(self.lib.cem_set_dt(self.ctx, float(dt)))
+
+    def counts(self):
+        out = np.zeros(6, dtype=np.int32)
+        self._chk(self.lib.cem_counts(self.ctx, _p(out)))
+        return dict(nodes=int(out[0]), elems=int(out[1]), edges=int(out[2]), splits=int(out[3]),
+                    fronts=int(out[4]), edges0=int(out[5]))
+
+    @property
+    def n_nodes(self):
+        return self.counts()["nodes"]
+
+    def set_state(self, u=None, v=None):
+        n = self.n_nodes
+        uu = None if u is None else _f64(u, (n, 3))
+        vv = None if v is None else _f64(v, (n, 3))
+        self._chk(self.lib.cem_set_state(self.ctx, _p(uu), _p(vv)))
+
+    def get_state(self):
+        n = self.n_nodes
+        u, v, a = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+        nn = C.c_int32()
+        self._chk(self.lib.cem_get_state(self.ctx, _p(u), _p(v), _p(a), C.byref(nn)))
+        return u, v, a
+
+    def internal_force(self, u):
+        n = self.n_nodes
+        u = _f64(u, (n, 3))
+        f = np.zeros((n, 3))
+        self._chk(self.lib.cem_internal_force(self.ctx, _p(u), _p(f)))
+        return f
+
+    def step(self, n):
+        self._chk(self.lib.cem_step(self.ctx, int(n)))
+
+    def replay_splits(self, ev):
+        ev = np.asarray(ev, dtype=np.int32).reshape(-1, 3)
+        arr = (cem_split_event * max(len(ev), 1))()
+        for i, (s, t, m) in enumerate(ev.tolist()):
+            arr[i] = cem_split_event(s, t, m, 0, 0.0)
+        self._chk(self.lib.cem_replay_splits(self.ctx, len(ev), C.cast(arr, C.c_void_p)))
+
+    def energy(self):
+        e = cem_energy()
+        self._chk(self.lib.cem_read_energy(self.ctx, C.byref(e)))
+        return {k: getattr(e, k) for k, _ in cem_energy._fields_}
+
+    def splits(self):
+        n = C.c_int32()
+        self._chk(self.lib.cem_read_splits(self.ctx, 0, None, C.byref(n)))
+        arr = (cem_split_event * max(n.value, 1))()
+        self._chk(self.lib.cem_read_splits(self.ctx, n.value, C.cast(arr, C.c_void_p), C.byref(n)))
+        ev = np.array([[a.step, a.tet, a.side_mask, a.pattern] for a in arr[: n.value]],
+                      dtype=np.int32).reshape(-1, 4)
+        G = np.array([a.G for a in arr[: n.value]], dtype=np.float64)
+        return ev, G
+
+    def front_G(self):
+        n = C.c_int32()
+        self._chk(self.lib.cem_read_front_G(self.ctx, 0, None, C.byref(n)))
+        arr = (cem_front_g * max(n.value, 1))()
+        self._chk(self.lib.cem_read_front_G(self.ctx, n.value, C.cast(arr, C.c_void_p), C.byref(n)))
+        tfl = np.array([[a.tet, a.face, a.lone] for a in arr[: n.value]], dtype=np.int32).reshape(-1, 3)
+        g = np.array([[a.G_I, a.G_II] for a in arr[: n.value]], dtype=np.float64).reshape(-1, 2)
+        return tfl, g
+
+    def save_state(self):
+        used = C.c_int64()
+        self._chk(self.lib.cem_save_state(self.ctx, None, 0, C.byref(used)))
+        buf = np.zeros(used.value, dtype=np.uint8)
+        self._chk(self.lib.cem_save_state(self.ctx, _p(buf), used.value, C.byref(used)))
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._chk(self.lib.cem_load_state(self.ctx, _p(buf), len(buf)))
+
+    def set_profiling(self, on=True):
+        self._chk(self.lib.cem_set_profiling(self.ctx, 1 if on else 0))
+
+    def kernel_times(self):
+        out = np.zeros(6)
+        self._chk(self.lib.cem_kernel_times(self.ctx, _p(out)))
+        return dict(zip(["total", "strain", "edge_stress", "front", "node", "topology"],
+                        out.tolist()))

@@ -1,0 +1,142 @@
+// Device data layout and kernel launchers of the ES-T-FEM crack-element step.
+// Internal to libcem; the public interface is include/cem.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cem {
+
+constexpr int kBlock = 256;          // 4 wave64 per workgroup
+constexpr int kTopoBlock = 1024;     // single-workgroup topology update
+constexpr int kCompactPerThread = 16;
+constexpr int kCompactTile = kBlock * kCompactPerThread;  // tets per compaction block
+constexpr int kNodeBits = 28;        // node id bits in the packed node word
+constexpr int kNodeMask = (1 << kNodeBits) - 1;
+
+// Volume fraction codes carried in bits 28..31 of an element's first node word.
+enum FracCode { FR_ZERO = 0, FR_ONE = 1, FR_HALF = 2, FR_EIGHTH = 3, FR_SEVEN8 = 4 };
+
+enum SplitMode { MODE_PHANTOM = 0, MODE_ERODE = 1 };
+enum NodeMode { NODE_FORCE = 0, NODE_INIT = 1, NODE_STEP = 2 };
+
+// Device-resident scalars of one simulation.
+struct Counters {
+  long long step;                 // steps completed
+  int n_split;                    // splits applied
+  int n_flag;                     // tets flagged in the current step
+  int n_cand;                     // length of the candidate list
+  int err;                        // 0 or a negative status raised on the device
+  unsigned long long gmax_key;    // ordered key of the running max G (this pass)
+  unsigned long long gmax_last;   // key of the last completed crack pass
+  double Ud;                      // dissipated energy
+  int replay_cursor;              // next entry of the forced schedule
+  int ticket;                     // compaction last-block ticket
+  int n_sched;                    // forced schedule length (0: G test decides)
+  int pad;
+  unsigned long long lam_key;     // ordered key of max element eigenvalue (setup)
+  double dt_crit;
+};
+
+// Six float values of a symmetric tensor in Voigt order
+// (xx, yy, zz, xy, yz, xz); strains carry engineering shear.
+template <class R> struct alignas(2 * sizeof(R)) Six { R v[6]; };
+
+// Everything a kernel needs, passed by value.
+struct Mesh {
+  int T0, N0, E0, S_cap;
+  int T_cap, N_cap, E_cap;
+  int mode;                 // SplitMode
+  int gsig;                 // 0 principal, 1 normal
+  int n_load;               // loaded nodes
+  double lam, mu, rho, Gc;
+  double ramp_t0, dt;
+  double umax;              // runaway bound on |u|
+
+  int4* enodes;             // [T_cap] node ids; .x also holds the fraction code
+  int2* et2e;               // [T_cap * 3] six edge ids (local edge order 01 02 03 12 13 23)
+  double4* X;               // [N_cap] coordinates (extra nodes copy their twin)
+  int* poff;                // [E_cap + 1] edge patch offsets
+  int* pent;                // [6 T0 + 10 S_cap] element ids, -1 = removed
+  int* noff;                // [N_cap + 1] node -> (element, local) offsets
+  int* nent;                // [4 T0 + 4 S_cap] packed element << 2 | local
+  double* invm;             // [N_cap] 1 / lumped mass (0 for a massless node)
+  int* lslot;               // [N_cap] load slot or -1
+  double4* Fload;           // [n_load] nodal load vector at full load
+  double* wacc;             // [n_load] accumulated external work per loaded node
+  int* lnode;               // [n_load] node of each load slot
+
+  int4* nbr;                // [T0] face neighbour per local face, -1 at the boundary
+  int* nbrface;             // [T0] packed 4 x 8 bits: neighbour's local face index
+  int4* nodepos;            // [T0] position of (t, l) in the node lists
+  int2* patchpos;           // [T0 * 3] position of t in the patch of its 6 edges
+  int4* front;              // [T0] lone node per local face on the crack front, -1 none
+  int* smask;               // [T0] -1 intact, else the side mask of the split
+  uint8_t* flag;            // [T0] flagged in the current step
+  uint8_t* pmask;           // [T0] pending side mask
+  uint8_t* ppat;            // [T0] pending pattern (1 = I, 2 = II)
+  double* pG;               // [T0] pending release rate
+  int* cand;                // [T0] candidate list
+  int* candf;               // [T0] on the candidate list
+  int* splitlist;           // [max(S_cap, 1)] tets to split this step (ascending)
+  int* bcount;              // compaction block counts / offsets
+  double* area;             // [S_cap] crack area of each split (scratch)
+  int* rec_step;            // [S_cap] split records
+  int* rec_tet;
+  int* rec_mask;
+  int* rec_pat;
+  double* rec_G;
+  int* sched;               // forced schedule (step, tet, mask) triples
+};
+
+// Device pointers of the precision-dependent work arrays.
+struct Work {
+  void* veps;               // [T_cap] Six<R>: effective volume x element strain
+  void* esig;               // [E_cap] Six<R>: smoothed edge stress
+  void* einvV;              // [E_cap] R: 1 / sum of effective volumes of the patch
+  double* partial;          // reduction partials
+};
+
+struct State {
+  double4* u;   // displacement at step n
+  double4* v;   // velocity at step n
+  double4* a;   // acceleration at step n
+  double4* uh;  // predictor u_n + dt v_n + dt^2/2 a_n (the u at which f is evaluated next)
+};
+
+// ---- launchers (kernels.hip) ----
+template <class R> struct Launch {
+  static hipError_t strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
+                           hipStream_t s);
+  static hipError_t edge_stress(const Mesh& m, const Work& w, Counters* c, hipStream_t s);
+  static hipError_t front(const Mesh& m, const State& st, const Work& w, Counters* c,
+                          int flagging, hipStream_t s);
+  static hipError_t node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
+                         double4* fout, hipStream_t s);
+  static hipError_t edge_volumes(const Mesh& m, const Work& w, hipStream_t s);
+  static hipError_t front_eval(const Mesh& m, const State& st, const Work& w, Counters* c,
+                               int* out_tfl, double* out_g, int* out_n, hipStream_t s);
+};
+
+template <class R>
+hipError_t launch_strain_energy(const Mesh& m, const Work& w, Counters* c, double* partial,
+                                int nparts, hipStream_t s);
+template <class R>
+hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Counters* c,
+                             int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s);
+hipError_t launch_compact(const Mesh& m, Counters* c, hipStream_t s);
+hipError_t launch_replay_select(const Mesh& m, Counters* c, hipStream_t s);
+hipError_t launch_masses(const Mesh& m, hipStream_t s);
+hipError_t launch_loads(const Mesh& m, const int4* ftri, const double4* ftrac, const int* lfoff,
+                        const int* lfent, hipStream_t s);
+hipError_t launch_dtcrit(const Mesh& m, Counters* c, hipStream_t s);
+hipError_t launch_kinetic(const Mesh& m, const State& st, Counters* c, double* partial,
+                          int nparts, hipStream_t s);
+hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s);
+hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, hipStream_t s);
+hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, const uint8_t* masks,
+                               int n, hipStream_t s);
+int grid_for(long long n);
+double key_to_double_host(unsigned long long k);
+
+}  // namespace cem

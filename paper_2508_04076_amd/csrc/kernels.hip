@@ -1,0 +1,1208 @@
+// HIP kernels (gfx950) of the ES-T-FEM crack-element step.
+//
+// One explicit step is a chain of gather passes with no floating-point
+// atomics, so results are deterministic:
+//   strain      per element slot: V_eff * eps_e = V_eff B_e u_e          (6 values)
+//   edge_stress per edge: eps_k = sum_patch(V_eff eps) / sum_patch V_eff, sigma_k = C eps_k
+//   front       per crack-front candidate: G_I, G_II, Griffith test, flag
+//   compact     flagged tets -> ascending list (two kernels, last-block scan)
+//   node        per node: f_i = sum_{(e,l) ni i} (V_eff,e / 6) B_{e,l}^T sum_{k in edges(e)} sigma_k,
+//               then the Newmark update
+//   topology    one workgroup applies the step's splits
+// The node force uses the identity
+//   sum_k V_k Bt_k^T sigma_k = sum_e (V_eff,e / 6) B_e^T sum_{k in edges(e)} sigma_k
+// (Bt_k = sum_patch w_ek B_e, V_k = (1/6) sum_patch V_eff, w_ek V_k = V_eff,e / 6),
+// which turns the edge-smoothed force of Eq. CSTet_fint_discretization into
+// a node-ordered gather.  Gradients are not stored: V grad N_l is a face
+// cross product over 6, so no element needs a determinant or a division.
+#include "cem_device.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace cem {
+
+// ---------------------------------------------------------------- helpers
+
+// Workgroups are dispatched round-robin over the eight XCDs; renumber them so
+// each XCD walks one contiguous range of the data (its own L2 keeps the
+// shared nodes and edges of neighbouring elements).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int nx = 8;
+  int x = b % nx, local = b / nx;
+  int per = nb / nx, rem = nb % nx;
+  return x * per + (x < rem ? x : rem) + local;
+}
+
+__device__ __forceinline__ double frac_of(int code) {
+  return code == FR_ONE ? 1.0 : code == FR_HALF ? 0.5 : code == FR_EIGHTH ? 0.125
+       : code == FR_SEVEN8 ? 0.875 : 0.0;
+}
+
+__device__ __forceinline__ int pack0(int node, int code) { return node | (code << kNodeBits); }
+
+__device__ __forceinline__ unsigned long long dkey(double x) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double key_to_double(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  union { unsigned long long u; double d; } x;
+  x.u = b;
+  return x.d;
+}
+
+template <class R> __device__ __forceinline__ Six<R> load6(const Six<R>* p) { return *p; }
+template <class R> __device__ __forceinline__ void store6(Six<R>* p, const R* v) {
+  Six<R> s;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s.v[i] = v[i];
+  *p = s;
+}
+
+__device__ __forceinline__ double ramp(const Mesh& m, double t) {
+  return (m.ramp_t0 > 0.0 && t < m.ramp_t0) ? t / m.ramp_t0 : 1.0;
+}
+
+__device__ __forceinline__ int n_split_now(const Counters* c) { return c->n_split; }
+__device__ __forceinline__ int elems_now(const Mesh& m, const Counters* c) {
+  return m.T0 + (m.mode == MODE_PHANTOM ? c->n_split : 0);
+}
+__device__ __forceinline__ int nodes_now(const Mesh& m, const Counters* c) {
+  return m.N0 + (m.mode == MODE_PHANTOM ? 4 * c->n_split : 0);
+}
+__device__ __forceinline__ int edges_now(const Mesh& m, const Counters* c) {
+  return m.E0 + (m.mode == MODE_PHANTOM ? 10 * c->n_split : 0);
+}
+
+// local edge q of a tet joins local nodes (kEA[q], kEB[q])
+__device__ __constant__ int kEA[6] = {0, 0, 0, 1, 1, 2};
+__device__ __constant__ int kEB[6] = {1, 2, 3, 2, 3, 3};
+__device__ __forceinline__ int local_edge(int a, int b) {
+  int lo = a < b ? a : b, hi = a < b ? b : a;
+  return lo == 0 ? hi - 1 : (lo == 1 ? hi + 1 : 5);
+}
+
+__device__ __forceinline__ double tet_volume(double4 x0, double4 x1, double4 x2, double4 x3) {
+  double ax = x1.x - x0.x, ay = x1.y - x0.y, az = x1.z - x0.z;
+  double bx = x2.x - x0.x, by = x2.y - x0.y, bz = x2.z - x0.z;
+  double cx = x3.x - x0.x, cy = x3.y - x0.y, cz = x3.z - x0.z;
+  return (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx)) / 6.0;
+}
+
+__device__ __forceinline__ double elem_volume(const Mesh& m, int4 nd) {
+  int n0 = nd.x & kNodeMask;
+  return tet_volume(m.X[n0], m.X[nd.y], m.X[nd.z], m.X[nd.w]);
+}
+
+// ---------------------------------------------------------------- strain pass
+
+// V_eff eps_e = (frac / 6) sum_{l=1..3} sym(g_l (x) (u_l - u_0)),
+// g_1 = c2 x c3, g_2 = c3 x c1, g_3 = c1 x c2, c_l = X_l - X_0 (g_l = 6 V grad N_l).
+// Differences are taken in float64 before any conversion to R.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_strain(Mesh m, const double4* __restrict__ u,
+                                                   Six<R>* __restrict__ veps,
+                                                   const Counters* __restrict__ c) {
+  if (c->err) return;
+  int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (e >= elems_now(m, c)) return;
+  int4 nd = m.enodes[e];
+  int code = (unsigned)nd.x >> kNodeBits;
+  int n0 = nd.x & kNodeMask;
+  R out[6] = {0, 0, 0, 0, 0, 0};
+  if (code != FR_ZERO) {
+    double4 x0 = m.X[n0], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
+    double4 u0 = u[n0], u1 = u[nd.y], u2 = u[nd.z], u3 = u[nd.w];
+    R c1x = (R)(x1.x - x0.x), c1y = (R)(x1.y - x0.y), c1z = (R)(x1.z - x0.z);
+    R c2x = (R)(x2.x - x0.x), c2y = (R)(x2.y - x0.y), c2z = (R)(x2.z - x0.z);
+    R c3x = (R)(x3.x - x0.x), c3y = (R)(x3.y - x0.y), c3z = (R)(x3.z - x0.z);
+    R d1x = (R)(u1.x - u0.x), d1y = (R)(u1.y - u0.y), d1z = (R)(u1.z - u0.z);
+    R d2x = (R)(u2.x - u0.x), d2y = (R)(u2.y - u0.y), d2z = (R)(u2.z - u0.z);
+    R d3x = (R)(u3.x - u0.x), d3y = (R)(u3.y - u0.y), d3z = (R)(u3.z - u0.z);
+    R g1x = c2y * c3z - c2z * c3y, g1y = c2z * c3x - c2x * c3z, g1z = c2x * c3y - c2y * c3x;
+    R g2x = c3y * c1z - c3z * c1y, g2y = c3z * c1x - c3x * c1z, g2z = c3x * c1y - c3y * c1x;
+    R g3x = c1y * c2z - c1z * c2y, g3y = c1z * c2x - c1x * c2z, g3z = c1x * c2y - c1y * c2x;
+    R f = (R)(frac_of(code) / 6.0);
+    out[0] = f * (g1x * d1x + g2x * d2x + g3x * d3x);
+    out[1] = f * (g1y * d1y + g2y * d2y + g3y * d3y);
+    out[2] = f * (g1z * d1z + g2z * d2z + g3z * d3z);
+    out[3] = f * (g1y * d1x + g1x * d1y + g2y * d2x + g2x * d2y + g3y * d3x + g3x * d3y);
+    out[4] = f * (g1z * d1y + g1y * d1z + g2z * d2y + g2y * d2z + g3z * d3y + g3y * d3z);
+    out[5] = f * (g1z * d1x + g1x * d1z + g2z * d2x + g2x * d2z + g3z * d3x + g3x * d3z);
+  }
+  store6(veps + e, out);
+}
+
+// ---------------------------------------------------------------- edge stress pass
+
+template <class R>
+__device__ __forceinline__ void edge_sum(const Mesh& m, const Six<R>* __restrict__ veps, int k,
+                                         R* acc) {
+  int p0 = m.poff[k], p1 = m.poff[k + 1];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[i] = 0;
+  for (int p = p0; p < p1; ++p) {
+    int e = m.pent[p];
+    if (e < 0) continue;
+    Six<R> s = load6(veps + e);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] += s.v[i];
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void hooke(R lam, R mu, const R* eps, R* sig) {
+  R tr = eps[0] + eps[1] + eps[2];
+  sig[0] = lam * tr + 2 * mu * eps[0];
+  sig[1] = lam * tr + 2 * mu * eps[1];
+  sig[2] = lam * tr + 2 * mu * eps[2];
+  sig[3] = mu * eps[3];
+  sig[4] = mu * eps[4];
+  sig[5] = mu * eps[5];
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_edge_stress(Mesh m, const Six<R>* __restrict__ veps,
+                                                        const R* __restrict__ einvV,
+                                                        Six<R>* __restrict__ esig,
+                                                        const Counters* __restrict__ c) {
+  if (c->err) return;
+  int k = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (k >= edges_now(m, c)) return;
+  R acc[6], eps[6], sig[6];
+  edge_sum(m, veps, k, acc);
+  R iv = einvV[k];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) eps[i] = acc[i] * iv;
+  hooke((R)m.lam, (R)m.mu, eps, sig);
+  store6(esig + k, sig);
+}
+
+// Strain energy 1/2 sum_k V_k sigma_k . eps_k; V_k eps_k = acc_k / 6.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_strain_energy(Mesh m, const Six<R>* __restrict__ veps,
+                                                          const R* __restrict__ einvV,
+                                                          double* __restrict__ partial,
+                                                          const Counters* __restrict__ c) {
+  __shared__ double red[kBlock];
+  double s = 0;
+  int En = edges_now(m, c);
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < En; k += gridDim.x * kBlock) {
+    R acc[6], eps[6], sig[6];
+    edge_sum(m, veps, k, acc);
+    R iv = einvV[k];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) eps[i] = acc[i] * iv;
+    hooke((R)m.lam, (R)m.mu, eps, sig);
+    double d = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d += (double)sig[i] * (double)acc[i];
+    s += 0.5 * d / 6.0;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------- node pass
+
+// For local node l the face opposite l is (a, b, c) with
+// 6 V grad N_l = (X_b - X_a) x (X_c - X_a).
+__device__ __forceinline__ void face_of(int l, int n0, int n1, int n2, int n3, int& a, int& b,
+                                        int& cc) {
+  a = (l == 0) ? n1 : n0;
+  b = (l == 0) ? n3 : (l == 1) ? n2 : (l == 2) ? n3 : n1;
+  cc = (l == 0) ? n2 : (l == 1) ? n3 : (l == 2) ? n1 : n2;
+}
+
+template <class R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const Six<R>* __restrict__ esig,
+                                                 double4* __restrict__ fout,
+                                                 Counters* __restrict__ c) {
+  if (c->err) return;
+  int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= nodes_now(m, c)) return;
+  double fx = 0, fy = 0, fz = 0;
+  int p0 = m.noff[i], p1 = m.noff[i + 1];
+  for (int p = p0; p < p1; ++p) {
+    int ent = m.nent[p];
+    int e = ent >> 2, l = ent & 3;
+    int4 nd = m.enodes[e];
+    int code = (unsigned)nd.x >> kNodeBits;
+    if (code == FR_ZERO) continue;
+    int n0 = nd.x & kNodeMask;
+    int a, b, cc;
+    face_of(l, n0, nd.y, nd.z, nd.w, a, b, cc);
+    double4 xa = m.X[a], xb = m.X[b], xc = m.X[cc];
+    R bx = (R)(xb.x - xa.x), by = (R)(xb.y - xa.y), bz = (R)(xb.z - xa.z);
+    R cx = (R)(xc.x - xa.x), cy = (R)(xc.y - xa.y), cz = (R)(xc.z - xa.z);
+    R gx = by * cz - bz * cy, gy = bz * cx - bx * cz, gz = bx * cy - by * cx;
+    int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
+    Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
+    Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+    R s[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) s[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
+    R w = (R)(frac_of(code) / 36.0);
+    fx += (double)(w * (gx * s[0] + gy * s[3] + gz * s[5]));
+    fy += (double)(w * (gy * s[1] + gx * s[3] + gz * s[4]));
+    fz += (double)(w * (gz * s[2] + gy * s[4] + gx * s[5]));
+  }
+  if (MODE == NODE_FORCE) {
+    fout[i] = make_double4(fx, fy, fz, 0.0);
+    return;
+  }
+  const double dt = m.dt;
+  const long long n = c->step;
+  int ls = m.lslot[i];
+  double4 F = ls >= 0 ? m.Fload[ls] : make_double4(0, 0, 0, 0);
+  double im = m.invm[i];
+  if (MODE == NODE_INIT) {
+    double r = ramp(m, (double)n * dt);
+    double4 u0 = st.u[i], v0 = st.v[i];
+    double ax = (r * F.x - fx) * im, ay = (r * F.y - fy) * im, az = (r * F.z - fz) * im;
+    st.a[i] = make_double4(ax, ay, az, 0.0);
+    double h = 0.5 * dt * dt;
+    st.uh[i] = make_double4(u0.x + dt * v0.x + h * ax, u0.y + dt * v0.y + h * ay,
+                            u0.z + dt * v0.z + h * az, 0.0);
+    return;
+  }
+  // NODE_STEP: f was evaluated at u_{n+1} = uh
+  double r0 = ramp(m, (double)n * dt), r1 = ramp(m, (double)(n + 1) * dt);
+  double4 u1 = st.uh[i], v0 = st.v[i], a0 = st.a[i];
+  double ax = (r1 * F.x - fx) * im, ay = (r1 * F.y - fy) * im, az = (r1 * F.z - fz) * im;
+  double hdt = 0.5 * dt;
+  double vx = v0.x + hdt * (a0.x + ax), vy = v0.y + hdt * (a0.y + ay), vz = v0.z + hdt * (a0.z + az);
+  if (ls >= 0) {
+    double4 u0 = st.u[i];
+    m.wacc[ls] += 0.5 * (r0 + r1) * (F.x * (u1.x - u0.x) + F.y * (u1.y - u0.y) + F.z * (u1.z - u0.z));
+  }
+  double h = 0.5 * dt * dt;
+  st.u[i] = u1;
+  st.v[i] = make_double4(vx, vy, vz, 0.0);
+  st.a[i] = make_double4(ax, ay, az, 0.0);
+  st.uh[i] = make_double4(u1.x + dt * vx + h * ax, u1.y + dt * vy + h * ay, u1.z + dt * vz + h * az,
+                          0.0);
+  bool bad = !(fabs(ax) <= DBL_MAX && fabs(ay) <= DBL_MAX && fabs(az) <= DBL_MAX) ||
+             !(fabs(u1.x) <= m.umax && fabs(u1.y) <= m.umax && fabs(u1.z) <= m.umax);
+  if (bad) atomicCAS(&c->err, 0, -6);
+}
+
+// ---------------------------------------------------------------- crack pass
+
+// Stress term of Eqs. G-I / G-II for the smoothed edge stress s (Voigt) and the
+// unit crack normal n.  gsig 0: sigma_1 |P_1 n|, P_1 the projector on the
+// eigenspace of the largest eigenvalue (eigenvalues within 1e-10 max|lambda|
+// count as equal); gsig 1: n . sigma . n.
+__device__ double stress_term(const double* s, double nx, double ny, double nz, int gsig) {
+  double a11 = s[0], a22 = s[1], a33 = s[2], a12 = s[3], a23 = s[4], a13 = s[5];
+  if (gsig == 1) {
+    return nx * (a11 * nx + a12 * ny + a13 * nz) + ny * (a12 * nx + a22 * ny + a23 * nz) +
+           nz * (a13 * nx + a23 * ny + a33 * nz);
+  }
+  double p1 = a12 * a12 + a13 * a13 + a23 * a23;
+  double l1, l2, l3;  // l1 >= l2 >= l3
+  if (p1 == 0.0) {
+    // diagonal: eigenvectors are the axes
+    double d[3] = {a11, a22, a33};
+    double lmax = fmax(a11, fmax(a22, a33));
+    double amax = fmax(fabs(a11), fmax(fabs(a22), fabs(a33)));
+    double gap = 1e-10 * amax;
+    double nn[3] = {nx, ny, nz};
+    double p2 = 0;
+    for (int i = 0; i < 3; ++i)
+      if (d[i] >= lmax - gap) p2 += nn[i] * nn[i];
+    return lmax * sqrt(p2);
+  }
+  // trigonometric solution of the characteristic cubic
+  double q = (a11 + a22 + a33) / 3.0;
+  double b11 = a11 - q, b22 = a22 - q, b33 = a33 - q;
+  double p2 = b11 * b11 + b22 * b22 + b33 * b33 + 2.0 * p1;
+  double p = sqrt(p2 / 6.0);
+  double detB = b11 * (b22 * b33 - a23 * a23) - a12 * (a12 * b33 - a23 * a13) +
+                a13 * (a12 * a23 - b22 * a13);
+  double r = detB / (2.0 * p * p * p);
+  r = fmin(1.0, fmax(-1.0, r));
+  double phi = acos(r) / 3.0;
+  l1 = q + 2.0 * p * cos(phi);
+  l3 = q + 2.0 * p * cos(phi + 2.0943951023931954923);  // + 2 pi / 3
+  l2 = 3.0 * q - l1 - l3;
+  double amax = fmax(fabs(l1), fmax(fabs(l2), fabs(l3)));
+  double gap = 1e-10 * amax;
+  int mult = 1 + (l2 >= l1 - gap) + (l3 >= l1 - gap);
+  if (mult == 3) return l1;  // |P n| = |n| = 1
+  // eigenvector of the simple eigenvalue (l1 if mult == 1, else l3) from the
+  // largest cross product of two rows of (A - lambda I)
+  double lam = (mult == 1) ? l1 : l3;
+  double r0x = a11 - lam, r0y = a12, r0z = a13;
+  double r1x = a12, r1y = a22 - lam, r1z = a23;
+  double r2x = a13, r2y = a23, r2z = a33 - lam;
+  double c01x = r0y * r1z - r0z * r1y, c01y = r0z * r1x - r0x * r1z, c01z = r0x * r1y - r0y * r1x;
+  double c02x = r0y * r2z - r0z * r2y, c02y = r0z * r2x - r0x * r2z, c02z = r0x * r2y - r0y * r2x;
+  double c12x = r1y * r2z - r1z * r2y, c12y = r1z * r2x - r1x * r2z, c12z = r1x * r2y - r1y * r2x;
+  double d01 = c01x * c01x + c01y * c01y + c01z * c01z;
+  double d02 = c02x * c02x + c02y * c02y + c02z * c02z;
+  double d12 = c12x * c12x + c12y * c12y + c12z * c12z;
+  double vx, vy, vz, dd;
+  if (d01 >= d02 && d01 >= d12) { vx = c01x; vy = c01y; vz = c01z; dd = d01; }
+  else if (d02 >= d12) { vx = c02x; vy = c02y; vz = c02z; dd = d02; }
+  else { vx = c12x; vy = c12y; vz = c12z; dd = d12; }
+  double proj = (vx * nx + vy * ny + vz * nz);
+  double c2 = dd > 0 ? proj * proj / dd : 0.0;  // (v . n)^2 for unit v
+  if (mult == 1) return l1 * sqrt(c2);
+  return l1 * sqrt(fmax(0.0, 1.0 - c2));      // eigenspace of l1 is the plane normal to v3
+}
+
+template <class R> __device__ __forceinline__ void load_sig(const Six<R>* esig, int k, double* s) {
+  Six<R> v = load6(esig + k);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s[i] = (double)v.v[i];
+}
+
+// Release rates of the front on local face `f` of intact tet c whose lone node
+// (alone on its side of the neighbour's cut) is global node `lone`:
+// N2 = lone, N4 = local node f, N1 < N3 the other face nodes (local order);
+// stretches on N1N2 and N2N3 (Eq. stretch-delta: only lengthening edges),
+// stresses at the edge points of N1N4, N3N4 (pattern I) and N2N4 (pattern II).
+template <class R>
+__device__ void front_rates(const Mesh& m, const double4* __restrict__ u,
+                            const Six<R>* __restrict__ esig, const int* nd, const int* ed,
+                            int f, int lone, double& GI, double& GII, int& maskI, int& maskII) {
+  int l2 = -1, l1 = -1, l3 = -1;
+  for (int l = 0; l < 4; ++l) {
+    if (l == f) continue;
+    if (nd[l] == lone) l2 = l;
+    else if (l1 < 0) l1 = l;
+    else l3 = l;
+  }
+  int l4 = f;
+  if (l1 < 0 || l2 < 0 || l3 < 0) {  // the lone node is not on this face: no front
+    GI = GII = -INFINITY;
+    maskI = maskII = 0;
+    return;
+  }
+  double4 X1 = m.X[nd[l1]], X2 = m.X[nd[l2]], X3 = m.X[nd[l3]], X4 = m.X[nd[l4]];
+  double4 U1 = u[nd[l1]], U2 = u[nd[l2]], U3 = u[nd[l3]];
+  // stretch of N1N2 and N2N3: 2 dX.du + |du|^2 > 0  <=>  |x_j - x_i| > |X_j - X_i|
+  double d1x = U2.x - U1.x, d1y = U2.y - U1.y, d1z = U2.z - U1.z;
+  double e1x = X2.x - X1.x, e1y = X2.y - X1.y, e1z = X2.z - X1.z;
+  double s1 = 2.0 * (e1x * d1x + e1y * d1y + e1z * d1z) + (d1x * d1x + d1y * d1y + d1z * d1z);
+  if (!(s1 > 0.0)) { d1x = 0; d1y = 0; d1z = 0; }
+  double d2x = U3.x - U2.x, d2y = U3.y - U2.y, d2z = U3.z - U2.z;
+  double e2x = X3.x - X2.x, e2y = X3.y - X2.y, e2z = X3.z - X2.z;
+  double s2 = 2.0 * (e2x * d2x + e2y * d2y + e2z * d2z) + (d2x * d2x + d2y * d2y + d2z * d2z);
+  if (!(s2 > 0.0)) { d2x = 0; d2y = 0; d2z = 0; }
+  // crack normals: pattern I plane spanned by N1N3 and N2N4, pattern II parallel to N1N3N4
+  double ax = X3.x - X1.x, ay = X3.y - X1.y, az = X3.z - X1.z;
+  double bx = X4.x - X2.x, by = X4.y - X2.y, bz = X4.z - X2.z;
+  double cx = X4.x - X1.x, cy = X4.y - X1.y, cz = X4.z - X1.z;
+  double nIx = ay * bz - az * by, nIy = az * bx - ax * bz, nIz = ax * by - ay * bx;
+  double nn = sqrt(nIx * nIx + nIy * nIy + nIz * nIz);
+  nIx /= nn; nIy /= nn; nIz /= nn;
+  double nJx = ay * cz - az * cy, nJy = az * cx - ax * cz, nJz = ax * cy - ay * cx;
+  nn = sqrt(nJx * nJx + nJy * nJy + nJz * nJz);
+  nJx /= nn; nJy /= nn; nJz /= nn;
+  double sg[6];
+  load_sig(esig, ed[local_edge(l1, l4)], sg);
+  double t3 = stress_term(sg, nIx, nIy, nIz, m.gsig);
+  load_sig(esig, ed[local_edge(l3, l4)], sg);
+  double t4 = stress_term(sg, nIx, nIy, nIz, m.gsig);
+  load_sig(esig, ed[local_edge(l2, l4)], sg);
+  double t6 = stress_term(sg, nJx, nJy, nJz, m.gsig);
+  GI = 0.5 * (t3 * fabs(d1x * nIx + d1y * nIy + d1z * nIz) +
+              t4 * fabs(d2x * nIx + d2y * nIy + d2z * nIz));
+  GII = 0.5 * t6 * (fabs(d1x * nJx + d1y * nJy + d1z * nJz) + fabs(d2x * nJx + d2y * nJy + d2z * nJz));
+  maskI = (1 << l2) | (1 << l4);
+  maskII = (1 << l2);
+}
+
+template <class R>
+__device__ __forceinline__ void load_tet(const Mesh& m, int t, int* nd, int* ed) {
+  int4 q = m.enodes[t];
+  nd[0] = q.x & kNodeMask; nd[1] = q.y; nd[2] = q.z; nd[3] = q.w;
+  int2 a = m.et2e[3 * t], b = m.et2e[3 * t + 1], cc = m.et2e[3 * t + 2];
+  ed[0] = a.x; ed[1] = a.y; ed[2] = b.x; ed[3] = b.y; ed[4] = cc.x; ed[5] = cc.y;
+}
+
+// One thread per candidate: best (G, face, pattern) with ties to the lower
+// face, then pattern I; Griffith test G >= Gc flags the tet.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_front(Mesh m, const double4* __restrict__ u,
+                                                  const Six<R>* __restrict__ esig,
+                                                  Counters* __restrict__ c, int flagging) {
+  if (c->err) return;
+  __shared__ unsigned long long red[kBlock];
+  unsigned long long kmax = 0;
+  int nc = c->n_cand;
+  for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < nc; idx += gridDim.x * kBlock) {
+    int t = m.cand[idx];
+    if (m.smask[t] >= 0) continue;
+    int4 fr = m.front[t];
+    int frs[4] = {fr.x, fr.y, fr.z, fr.w};
+    int nd[4], ed[6];
+    load_tet<R>(m, t, nd, ed);
+    double best = -INFINITY;
+    int bmask = 0, bpat = 0;
+    bool any = false;
+    for (int f = 0; f < 4; ++f) {
+      if (frs[f] < 0) continue;
+      double GI, GII;
+      int mI, mII;
+      front_rates<R>(m, u, esig, nd, ed, f, frs[f], GI, GII, mI, mII);
+      if (!any || GI > best) { best = GI; bmask = mI; bpat = 1; }
+      any = true;
+      if (GII > best) { best = GII; bmask = mII; bpat = 2; }
+    }
+    if (!any) continue;
+    unsigned long long k = dkey(best);
+    kmax = k > kmax ? k : kmax;
+    if (flagging && best >= m.Gc) {
+      m.flag[t] = 1;
+      m.pmask[t] = (uint8_t)bmask;
+      m.ppat[t] = (uint8_t)bpat;
+      m.pG[t] = best;
+      atomicAdd(&c->n_flag, 1);
+    }
+  }
+  red[threadIdx.x] = kmax;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicMax(&c->gmax_key, red[0]);
+}
+
+// Readback of every front's G_I and G_II (unordered; the host sorts).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_front_eval(Mesh m, const double4* __restrict__ u,
+                                                       const Six<R>* __restrict__ esig,
+                                                       const Counters* __restrict__ c, int* out_tfl,
+                                                       double* out_g, int* out_n) {
+  int nc = c->n_cand;
+  for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < nc; idx += gridDim.x * kBlock) {
+    int t = m.cand[idx];
+    if (m.smask[t] >= 0) continue;
+    int4 fr = m.front[t];
+    int frs[4] = {fr.x, fr.y, fr.z, fr.w};
+    int nd[4], ed[6];
+    load_tet<R>(m, t, nd, ed);
+    for (int f = 0; f < 4; ++f) {
+      if (frs[f] < 0) continue;
+      double GI, GII;
+      int mI, mII;
+      front_rates<R>(m, u, esig, nd, ed, f, frs[f], GI, GII, mI, mII);
+      int o = atomicAdd(out_n, 1);
+      out_tfl[3 * o] = t;
+      out_tfl[3 * o + 1] = f;
+      out_tfl[3 * o + 2] = frs[f];
+      out_g[2 * o] = GI;
+      out_g[2 * o + 1] = GII;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_fronts(Mesh m, const Counters* __restrict__ c,
+                                                         int* out) {
+  int nc = c->n_cand;
+  int cnt = 0;
+  for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < nc; idx += gridDim.x * kBlock) {
+    int t = m.cand[idx];
+    if (m.smask[t] >= 0) continue;
+    int4 fr = m.front[t];
+    cnt += (fr.x >= 0) + (fr.y >= 0) + (fr.z >= 0) + (fr.w >= 0);
+  }
+  if (cnt) atomicAdd(out, cnt);
+}
+
+// ---------------------------------------------------------------- compaction
+
+__device__ __forceinline__ int count_flags(uint4 w) {
+  unsigned x[4] = {w.x, w.y, w.z, w.w};
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) n += ((x[i] >> (8 * b)) & 0xff) != 0;
+  return n;
+}
+
+__device__ int block_exclusive_scan(int v, int* sh, int& total) {
+  int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int x = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  total = sh[kBlock - 1];
+  int r = sh[tid] - v;
+  __syncthreads();
+  return r;
+}
+
+// Per-block flag counts; the last block to finish turns them into offsets
+// and checks the split capacity.
+__global__ __launch_bounds__(kBlock) void k_compact_count(Mesh m, Counters* __restrict__ c) {
+  if (c->err || c->n_flag == 0) return;
+  __shared__ int sh[kBlock];
+  __shared__ int last;
+  const uint4* f4 = (const uint4*)m.flag;
+  uint4 w = f4[(size_t)blockIdx.x * kBlock + threadIdx.x];
+  int total;
+  block_exclusive_scan(count_flags(w), sh, total);
+  if (threadIdx.x == 0) {
+    m.bcount[blockIdx.x] = total;
+    __threadfence();
+    last = (atomicAdd(&c->ticket, 1) == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // exclusive scan of the block counts, in chunks of kBlock
+  int nb = gridDim.x;
+  int carry = 0;
+  for (int base = 0; base < nb; base += kBlock) {
+    int idx = base + threadIdx.x;
+    int v = idx < nb ? atomicAdd(&m.bcount[idx], 0) : 0;
+    int tot;
+    int ex = block_exclusive_scan(v, sh, tot);
+    if (idx < nb) m.bcount[idx] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    c->ticket = 0;
+    if (c->n_split + carry > m.S_cap) c->err = -5;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_write(Mesh m, Counters* __restrict__ c) {
+  if (c->n_flag == 0) return;
+  __shared__ int sh[kBlock];
+  uint4* f4 = (uint4*)m.flag;
+  size_t wi = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  uint4 w = f4[wi];
+  int total;
+  int ex = block_exclusive_scan(count_flags(w), sh, total);
+  if (total == 0) return;
+  f4[wi] = make_uint4(0, 0, 0, 0);
+  if (c->err) return;
+  int pos = m.bcount[blockIdx.x] + ex;
+  unsigned x[4] = {w.x, w.y, w.z, w.w};
+  int t0 = (int)(wi * 16);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((x[i] >> (8 * b)) & 0xff) m.splitlist[pos++] = t0 + 4 * i + b;
+}
+
+// Forced schedule: the entries of the coming step, already sorted by tet.
+__global__ void k_replay_select(Mesh m, Counters* __restrict__ c) {
+  if (threadIdx.x != 0 || c->err) return;
+  int cur = c->replay_cursor;
+  int next = (int)(c->step + 1);
+  while (cur < c->n_sched && m.sched[3 * cur] < next) cur++;
+  int n = 0, prev = -1;
+  while (cur < c->n_sched && m.sched[3 * cur] == next) {
+    int t = m.sched[3 * cur + 1];
+    int mk = m.sched[3 * cur + 2];
+    cur++;
+    if (t == prev || t < 0 || t >= m.T0 || m.smask[t] >= 0) continue;
+    prev = t;
+    if (c->n_split + n >= m.S_cap) { c->err = -5; break; }
+    m.splitlist[n++] = t;
+    m.pmask[t] = (uint8_t)mk;
+    m.ppat[t] = __popc(mk) == 2 ? 1 : 2;
+    m.pG[t] = 0.0;
+  }
+  c->replay_cursor = cur;
+  c->n_flag = n;
+}
+
+__global__ void k_set_presplit(Mesh m, Counters* __restrict__ c, const int* tets,
+                               const uint8_t* masks, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int t = tets[i];
+    m.splitlist[i] = t;
+    m.pmask[t] = masks[i];
+    m.ppat[t] = 0;
+    m.pG[t] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->n_flag = n;
+}
+
+// ---------------------------------------------------------------- topology
+
+__device__ __forceinline__ int code_for_side(int nodes_on_side) {
+  return nodes_on_side == 1 ? FR_EIGHTH : nodes_on_side == 3 ? FR_SEVEN8 : FR_HALF;
+}
+
+// Area of the midpoint crack surface of a 2|2 cut (Varignon parallelogram) or
+// a 1|3 cut (corner triangle).
+__device__ double crack_area(const Mesh& m, const int* nd, int mask) {
+  int nb = __popc(mask);
+  double4 x[4];
+  for (int l = 0; l < 4; ++l) x[l] = m.X[nd[l]];
+  double ax, ay, az, bx, by, bz;
+  double f;
+  if (nb == 2) {
+    int A[2], B[2], ia = 0, ib = 0;
+    for (int l = 0; l < 4; ++l) {
+      if ((mask >> l) & 1) B[ib++] = l; else A[ia++] = l;
+    }
+    ax = x[A[1]].x - x[A[0]].x; ay = x[A[1]].y - x[A[0]].y; az = x[A[1]].z - x[A[0]].z;
+    bx = x[B[1]].x - x[B[0]].x; by = x[B[1]].y - x[B[0]].y; bz = x[B[1]].z - x[B[0]].z;
+    f = 0.25;
+  } else {
+    int big = nb == 1 ? 0 : 1;
+    int q[3], iq = 0;
+    for (int l = 0; l < 4; ++l)
+      if ((((mask >> l) & 1) ? 1 : 0) == big) q[iq++] = l;
+    ax = x[q[1]].x - x[q[0]].x; ay = x[q[1]].y - x[q[0]].y; az = x[q[1]].z - x[q[0]].z;
+    bx = x[q[2]].x - x[q[0]].x; by = x[q[2]].y - x[q[0]].y; bz = x[q[2]].z - x[q[0]].z;
+    f = 0.125;
+  }
+  double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+  return f * sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+// All splits of one step, applied by one workgroup in phases separated by
+// barriers.  Split i of this batch gets global index s = n_split + i; its
+// copy B takes element slot T0 + s, its extra nodes N0 + 4 s + l and its new
+// edges E0 + 10 s + r.  Copy A stays in the parent's slot.
+template <class R>
+__global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work w,
+                                                         Counters* __restrict__ c, int dynamic,
+                                                         int advance, int4* __restrict__ snodes,
+                                                         int* __restrict__ sedges) {
+  __shared__ int s_n, s_base;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_n = c->err ? 0 : c->n_flag;
+    s_base = c->n_split;
+  }
+  __syncthreads();
+  const int n = s_n, base = s_base;
+  R* einvV = (R*)w.einvV;
+  if (n > 0) {
+    // phase 0: record, keep the parent's real nodes and edges, mark split
+    for (int i = tid; i < n; i += kTopoBlock) {
+      int t = m.splitlist[i];
+      int mask = m.pmask[t];
+      int nd[4], ed[6];
+      load_tet<R>(m, t, nd, ed);
+      snodes[i] = make_int4(nd[0], nd[1], nd[2], nd[3]);
+      for (int q = 0; q < 6; ++q) sedges[6 * i + q] = ed[q];
+      m.smask[t] = mask;
+      int s = base + i;
+      m.rec_step[s] = dynamic ? (int)(c->step + 1) : (int)c->step;
+      m.rec_tet[s] = t;
+      m.rec_mask[s] = mask;
+      m.rec_pat[s] = dynamic ? m.ppat[t] : 0;
+      m.rec_G[s] = dynamic ? m.pG[t] : 0.0;
+      m.area[i] = dynamic ? crack_area(m, nd, mask) : 0.0;
+    }
+    __syncthreads();
+    // phase 1: element, edge and node-list rewrites
+    for (int i = tid; i < n; i += kTopoBlock) {
+      int t = m.splitlist[i];
+      int mask = m.pmask[t];
+      int4 q4 = snodes[i];
+      int nd[4] = {q4.x, q4.y, q4.z, q4.w};
+      if (m.mode == MODE_ERODE) {
+        m.enodes[t] = make_int4(pack0(nd[0], FR_ZERO), nd[1], nd[2], nd[3]);
+        continue;
+      }
+      int s = base + i;
+      int tb = m.T0 + s;
+      int nb = __popc(mask);
+      int codeA = code_for_side(4 - nb), codeB = code_for_side(nb);
+      int na[4], nbn[4];
+      for (int l = 0; l < 4; ++l) {
+        int x = m.N0 + 4 * s + l;
+        m.X[x] = m.X[nd[l]];
+        st.u[x] = st.u[nd[l]];
+        st.v[x] = st.v[nd[l]];
+        st.a[x] = st.a[nd[l]];
+        st.uh[x] = st.uh[nd[l]];
+        m.lslot[x] = -1;
+        bool onB = (mask >> l) & 1;
+        na[l] = onB ? x : nd[l];
+        nbn[l] = onB ? nd[l] : x;
+        int owner = onB ? t : tb;  // the copy that holds the extra node
+        m.nent[4 * m.T0 + 4 * s + l] = (owner << 2) | l;
+        if (onB) {
+          const int* np = (const int*)&m.nodepos[t];
+          m.nent[np[l]] = (tb << 2) | l;
+        }
+      }
+      m.enodes[t] = make_int4(pack0(na[0], codeA), na[1], na[2], na[3]);
+      m.enodes[tb] = make_int4(pack0(nbn[0], codeB), nbn[1], nbn[2], nbn[3]);
+      double V = tet_volume(m.X[nd[0]], m.X[nd[1]], m.X[nd[2]], m.X[nd[3]]);
+      R ivA = (R)(1.0 / (frac_of(codeA) * V)), ivB = (R)(1.0 / (frac_of(codeB) * V));
+      int eA[6], eB[6];
+      int r = 0;
+      int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
+      const int* pp = (const int*)&m.patchpos[3 * t];
+      for (int q = 0; q < 6; ++q) {
+        int k = sedges[6 * i + q];
+        int ba = (mask >> kEA[q]) & 1, bb = (mask >> kEB[q]) & 1;
+        if (!ba && !bb) {          // both nodes on side A: copy A keeps edge k
+          eA[q] = k;
+          eB[q] = ebase + r; m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; r++;
+        } else if (ba && bb) {     // both on side B: copy B takes edge k
+          eB[q] = k; m.pent[pp[q]] = tb;
+          eA[q] = ebase + r; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; r++;
+        } else {                   // cut edge: each copy gets a new one
+          m.pent[pp[q]] = -1;
+          eA[q] = ebase + r; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; r++;
+          eB[q] = ebase + r; m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; r++;
+        }
+      }
+      for (; r < 10; ++r) { m.pent[pbase + r] = -1; einvV[ebase + r] = (R)0; }
+      m.et2e[3 * t] = make_int2(eA[0], eA[1]);
+      m.et2e[3 * t + 1] = make_int2(eA[2], eA[3]);
+      m.et2e[3 * t + 2] = make_int2(eA[4], eA[5]);
+      m.et2e[3 * tb] = make_int2(eB[0], eB[1]);
+      m.et2e[3 * tb + 1] = make_int2(eB[2], eB[3]);
+      m.et2e[3 * tb + 2] = make_int2(eB[4], eB[5]);
+    }
+    __threadfence_block();
+    __syncthreads();
+    // phase 2: lumped masses of touched nodes and volumes of touched edges
+    for (int i = tid; i < n; i += kTopoBlock) {
+      int4 q4 = snodes[i];
+      int nd[4] = {q4.x, q4.y, q4.z, q4.w};
+      if (m.mode == MODE_PHANTOM) {
+        int s = base + i;
+        int mask = m.pmask[m.splitlist[i]];
+        int nb = __popc(mask);
+        double V = tet_volume(m.X[nd[0]], m.X[nd[1]], m.X[nd[2]], m.X[nd[3]]);
+        for (int l = 0; l < 4; ++l) {
+          int node = nd[l];
+          double ms = 0;
+          for (int p = m.noff[node]; p < m.noff[node + 1]; ++p) {
+            int e = m.nent[p] >> 2;
+            int4 en = m.enodes[e];
+            ms += m.rho * frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en) / 4.0;
+          }
+          m.invm[node] = ms > 0 ? 1.0 / ms : 0.0;
+          bool onB = (mask >> l) & 1;
+          double fo = frac_of(code_for_side(onB ? 4 - nb : nb));  // owner copy's fraction
+          m.invm[m.N0 + 4 * s + l] = 1.0 / (m.rho * fo * V / 4.0);
+        }
+      }
+      for (int q = 0; q < 6; ++q) {
+        int k = sedges[6 * i + q];
+        double S = 0;
+        for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
+          int e = m.pent[p];
+          if (e < 0) continue;
+          int4 en = m.enodes[e];
+          S += frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en);
+        }
+        einvV[k] = S > 0 ? (R)(1.0 / S) : (R)0;
+      }
+    }
+    // phase 3: new crack fronts on intact face neighbours
+    for (int i = tid; i < n; i += kTopoBlock) {
+      int t = m.splitlist[i];
+      int mask = m.pmask[t];
+      int4 q4 = snodes[i];
+      int nd[4] = {q4.x, q4.y, q4.z, q4.w};
+      const int* nb4 = (const int*)&m.nbr[t];
+      int nf = m.nbrface[t];
+      for (int f = 0; f < 4; ++f) {
+        int fl[3], k = 0;
+        for (int l = 0; l < 4; ++l)
+          if (l != f) fl[k++] = l;
+        int b0 = (mask >> fl[0]) & 1, b1 = (mask >> fl[1]) & 1, b2 = (mask >> fl[2]) & 1;
+        if (b0 == b1 && b1 == b2) continue;
+        int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];
+        int cn = nb4[f];
+        if (cn < 0 || m.smask[cn] >= 0) continue;
+        int fc = (nf >> (8 * f)) & 0xff;
+        ((int*)m.front)[4 * cn + fc] = nd[lone];
+        if (atomicCAS(&m.candf[cn], 0, 1) == 0) m.cand[atomicAdd(&c->n_cand, 1)] = cn;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (!c->err) {
+      if (n > 0 && dynamic) {
+        double ud = c->Ud;
+        for (int i = 0; i < n; ++i) ud += m.Gc * m.area[i];
+        c->Ud = ud;
+      }
+      c->n_split = base + n;
+      if (advance) {
+        c->step += 1;
+        c->gmax_last = c->gmax_key;
+        c->gmax_key = 0;
+      }
+    }
+    c->n_flag = 0;
+  }
+}
+
+// ---------------------------------------------------------------- setup
+
+// Lumped mass m_i = sum rho V_eff / 4 over the elements holding node i.
+__global__ __launch_bounds__(kBlock) void k_masses(Mesh m) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m.N0) return;
+  double ms = 0;
+  for (int p = m.noff[i]; p < m.noff[i + 1]; ++p) {
+    int e = m.nent[p] >> 2;
+    int4 en = m.enodes[e];
+    ms += m.rho * frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en) / 4.0;
+  }
+  m.invm[i] = ms > 0 ? 1.0 / ms : 0.0;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_edge_volumes(Mesh m, R* einvV) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= m.E0) return;
+  double S = 0;
+  for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
+    int e = m.pent[p];
+    if (e < 0) continue;
+    int4 en = m.enodes[e];
+    S += frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en);
+  }
+  einvV[k] = S > 0 ? (R)(1.0 / S) : (R)0;
+}
+
+// Nodal loads: each loaded triangle adds t A / 3 to each vertex (gathered per
+// loaded node over its triangles).
+__global__ __launch_bounds__(kBlock) void k_loads(Mesh m, const int4* ftri, const double4* ftrac,
+                                                  const int* lfoff, const int* lfent) {
+  int sl = blockIdx.x * kBlock + threadIdx.x;
+  if (sl >= m.n_load) return;
+  double fx = 0, fy = 0, fz = 0;
+  for (int p = lfoff[sl]; p < lfoff[sl + 1]; ++p) {
+    int f = lfent[p];
+    int4 tr = ftri[f];
+    double4 a = m.X[tr.x], b = m.X[tr.y], cc = m.X[tr.z];
+    double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+    double vx = cc.x - a.x, vy = cc.y - a.y, vz = cc.z - a.z;
+    double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+    double A = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    double4 t = ftrac[f];
+    fx += t.x * A / 3.0;
+    fy += t.y * A / 3.0;
+    fz += t.z * A / 3.0;
+  }
+  m.Fload[sl] = make_double4(fx, fy, fz, 0.0);
+  m.wacc[sl] = 0.0;
+}
+
+// Largest eigenvalue of B^T C B per tet: the nonzero spectrum equals that of
+// the 6 x 6 matrix (L^T B)(L^T B)^T with C = L L^T (Cholesky), solved by
+// cyclic Jacobi rotations.
+__global__ __launch_bounds__(kBlock) void k_dtcrit(Mesh m, Counters* __restrict__ c) {
+  __shared__ unsigned long long red[kBlock];
+  double lmax = 0;
+  int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < m.T0) {
+    int4 nd = m.enodes[t];
+    double4 x0 = m.X[nd.x & kNodeMask], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
+    double c1[3] = {x1.x - x0.x, x1.y - x0.y, x1.z - x0.z};
+    double c2[3] = {x2.x - x0.x, x2.y - x0.y, x2.z - x0.z};
+    double c3[3] = {x3.x - x0.x, x3.y - x0.y, x3.z - x0.z};
+    double g[4][3];
+    g[1][0] = c2[1] * c3[2] - c2[2] * c3[1]; g[1][1] = c2[2] * c3[0] - c2[0] * c3[2]; g[1][2] = c2[0] * c3[1] - c2[1] * c3[0];
+    g[2][0] = c3[1] * c1[2] - c3[2] * c1[1]; g[2][1] = c3[2] * c1[0] - c3[0] * c1[2]; g[2][2] = c3[0] * c1[1] - c3[1] * c1[0];
+    g[3][0] = c1[1] * c2[2] - c1[2] * c2[1]; g[3][1] = c1[2] * c2[0] - c1[0] * c2[2]; g[3][2] = c1[0] * c2[1] - c1[1] * c2[0];
+    double det = c1[0] * g[1][0] + c1[1] * g[1][1] + c1[2] * g[1][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      g[1][d] /= det; g[2][d] /= det; g[3][d] /= det;
+      g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    }
+    // B (6 x 12)
+    double B[6][12];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = 0; q < 12; ++q) B[r][q] = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      B[0][3 * l] = g[l][0];
+      B[1][3 * l + 1] = g[l][1];
+      B[2][3 * l + 2] = g[l][2];
+      B[3][3 * l] = g[l][1]; B[3][3 * l + 1] = g[l][0];
+      B[4][3 * l + 1] = g[l][2]; B[4][3 * l + 2] = g[l][1];
+      B[5][3 * l] = g[l][2]; B[5][3 * l + 2] = g[l][0];
+    }
+    // Cholesky of the normal block [[a b b][b a b][b b a]], a = lam + 2 mu, b = lam
+    double a = m.lam + 2 * m.mu, b = m.lam;
+    double L11 = sqrt(a), L21 = b / L11, L31 = b / L11;
+    double L22 = sqrt(a - L21 * L21), L32 = (b - L31 * L21) / L22;
+    double L33 = sqrt(a - L31 * L31 - L32 * L32);
+    double sm = sqrt(m.mu);
+    double Xm[6][12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      Xm[0][q] = L11 * B[0][q] + L21 * B[1][q] + L31 * B[2][q];
+      Xm[1][q] = L22 * B[1][q] + L32 * B[2][q];
+      Xm[2][q] = L33 * B[2][q];
+      Xm[3][q] = sm * B[3][q];
+      Xm[4][q] = sm * B[4][q];
+      Xm[5][q] = sm * B[5][q];
+    }
+    double A[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double s = 0;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) s += Xm[i][q] * Xm[j][q];
+        A[i][j] = s;
+      }
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off = 0, dg = 0;
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        dg += A[p][p] * A[p][p];
+#pragma unroll
+        for (int q = p + 1; q < 6; ++q) off += A[p][q] * A[p][q];
+      }
+      if (off <= 1e-36 * dg) break;
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+#pragma unroll
+        for (int q = p + 1; q < 6; ++q) {
+          double apq = A[p][q];
+          if (apq != 0.0) {
+            double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+            double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              double akp = A[k][p], akq = A[k][q];
+              A[k][p] = cs * akp - sn * akq;
+              A[k][q] = sn * akp + cs * akq;
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              double apk = A[p][k], aqk = A[q][k];
+              A[p][k] = cs * apk - sn * aqk;
+              A[q][k] = sn * apk + cs * aqk;
+            }
+          }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) lmax = fmax(lmax, A[i][i]);
+  }
+  red[threadIdx.x] = dkey(lmax);
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(&c->lam_key, red[0]);
+}
+
+__global__ void k_dtfinish(Mesh m, Counters* c) {
+  if (threadIdx.x == 0) {
+    double lam = key_to_double(c->lam_key);
+    c->dt_crit = 2.0 / sqrt(4.0 / m.rho * lam);
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+
+__global__ __launch_bounds__(kBlock) void k_kinetic(Mesh m, State st, const Counters* __restrict__ c,
+                                                    double* partial) {
+  __shared__ double red[kBlock];
+  double s = 0;
+  int Nn = nodes_now(m, c);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < Nn; i += gridDim.x * kBlock) {
+    double im = m.invm[i];
+    if (im > 0) {
+      double4 v = st.v[i];
+      s += 0.5 * (v.x * v.x + v.y * v.y + v.z * v.z) / im;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Fixed-order sum (single workgroup).
+__global__ __launch_bounds__(kBlock) void k_sum(const double* __restrict__ x, int n, double* out) {
+  __shared__ double red[kBlock];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// ---------------------------------------------------------------- launchers
+
+int grid_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
+double key_to_double_host(unsigned long long k) { return key_to_double(k); }
+
+template <class R>
+hipError_t Launch<R>::strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
+                             hipStream_t s) {
+  int T = m.mode == MODE_PHANTOM ? m.T_cap : m.T0;
+  hipLaunchKernelGGL(k_strain<R>, dim3(grid_for(T)), dim3(kBlock), 0, s, m, u,
+                     (Six<R>*)w.veps, c);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t Launch<R>::edge_stress(const Mesh& m, const Work& w, Counters* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_edge_stress<R>, dim3(grid_for(m.E_cap)), dim3(kBlock), 0, s, m,
+                     (const Six<R>*)w.veps, (const R*)w.einvV, (Six<R>*)w.esig, c);
+  return hipGetLastError();
+}
+
+static int front_grid(const Mesh& m) {
+  int g = grid_for(m.T0);
+  return g < 1 ? 1 : (g > 512 ? 512 : g);
+}
+
+template <class R>
+hipError_t Launch<R>::front(const Mesh& m, const State& st, const Work& w, Counters* c,
+                            int flagging, hipStream_t s) {
+  hipLaunchKernelGGL(k_front<R>, dim3(front_grid(m)), dim3(kBlock), 0, s, m,
+                     (const double4*)st.uh, (const Six<R>*)w.esig, c, flagging);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, Counters* c,
+                                 int* out_tfl, double* out_g, int* out_n, hipStream_t s) {
+  hipLaunchKernelGGL(k_front_eval<R>, dim3(front_grid(m)), dim3(kBlock), 0, s, m,
+                     (const double4*)st.u, (const Six<R>*)w.esig, c, out_tfl, out_g, out_n);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
+                           double4* fout, hipStream_t s) {
+  dim3 g(grid_for(m.N_cap)), b(kBlock);
+  const Six<R>* sig = (const Six<R>*)w.esig;
+  if (mode == NODE_FORCE)
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE>), g, b, 0, s, m, st, sig, fout, c);
+  else if (mode == NODE_INIT)
+    hipLaunchKernelGGL((k_node<R, NODE_INIT>), g, b, 0, s, m, st, sig, fout, c);
+  else
+    hipLaunchKernelGGL((k_node<R, NODE_STEP>), g, b, 0, s, m, st, sig, fout, c);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t Launch<R>::edge_volumes(const Mesh& m, const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_edge_volumes<R>, dim3(grid_for(m.E0)), dim3(kBlock), 0, s, m, (R*)w.einvV);
+  return hipGetLastError();
+}
+
+template struct Launch<double>;
+template struct Launch<float>;
+
+template <class R>
+hipError_t launch_strain_energy(const Mesh& m, const Work& w, Counters* c, double* partial,
+                                int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_strain_energy<R>, dim3(nparts), dim3(kBlock), 0, s, m,
+                     (const Six<R>*)w.veps, (const R*)w.einvV, partial, c);
+  return hipGetLastError();
+}
+template hipError_t launch_strain_energy<double>(const Mesh&, const Work&, Counters*, double*, int,
+                                                 hipStream_t);
+template hipError_t launch_strain_energy<float>(const Mesh&, const Work&, Counters*, double*, int,
+                                                hipStream_t);
+
+template <class R>
+hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Counters* c,
+                             int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s) {
+  hipLaunchKernelGGL(k_topology<R>, dim3(1), dim3(kTopoBlock), 0, s, m, st, w, c, dynamic, advance,
+                     snodes, sedges);
+  return hipGetLastError();
+}
+template hipError_t launch_topology_t<double>(const Mesh&, const State&, const Work&, Counters*,
+                                              int, int, int4*, int*, hipStream_t);
+template hipError_t launch_topology_t<float>(const Mesh&, const State&, const Work&, Counters*, int,
+                                             int, int4*, int*, hipStream_t);
+
+hipError_t launch_compact(const Mesh& m, Counters* c, hipStream_t s) {
+  int nb = (m.T0 + kCompactTile - 1) / kCompactTile;
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, s, m, c);
+  hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(kBlock), 0, s, m, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_select(const Mesh& m, Counters* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_select, dim3(1), dim3(64), 0, s, m, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, const uint8_t* masks,
+                               int n, hipStream_t s) {
+  int g = grid_for(n);
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_set_presplit, dim3(g), dim3(kBlock), 0, s, m, c, tets, masks, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_masses(const Mesh& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_masses, dim3(grid_for(m.N0)), dim3(kBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_loads(const Mesh& m, const int4* ftri, const double4* ftrac, const int* lfoff,
+                        const int* lfent, hipStream_t s) {
+  if (m.n_load == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loads, dim3(grid_for(m.n_load)), dim3(kBlock), 0, s, m, ftri, ftrac, lfoff,
+                     lfent);
+  return hipGetLastError();
+}
+
+hipError_t launch_dtcrit(const Mesh& m, Counters* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_dtcrit, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m, c);
+  hipLaunchKernelGGL(k_dtfinish, dim3(1), dim3(64), 0, s, m, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_kinetic(const Mesh& m, const State& st, Counters* c, double* partial, int nparts,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_kinetic, dim3(nparts), dim3(kBlock), 0, s, m, st, c, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, s, partial, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_fronts, dim3(front_grid(m)), dim3(kBlock), 0, s, m, c, out);
+  return hipGetLastError();
+}
+
+}  // namespace cem

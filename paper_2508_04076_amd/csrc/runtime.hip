@@ -1,0 +1,1141 @@
+// Host runtime of libcem: context, mesh preprocessing, buffers, time-step
+// driver (plain launches or captured HIP graphs) and the C-ABI of cem.h.
+#include "../../include/cem.h"
+#include "cem_device.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace cem;
+
+namespace {
+
+struct Region {
+  void* ptr;
+  size_t bytes;
+};
+
+}  // namespace
+
+struct cem_ctx {
+  cem_options opt{};
+  std::string err;
+  int stage = 0;  // 0 created, 1 mesh uploaded
+  hipStream_t stream = nullptr;
+  cem_material mat{};
+  int mixed = 0;
+
+  Mesh m{};
+  Work w{};
+  State st{};
+  Counters* d_ctr = nullptr;
+  Counters* h_ctr = nullptr;  // pinned mirror
+  int4* d_snodes = nullptr;
+  int* d_sedges = nullptr;
+  double4* d_tmp = nullptr;   // internal_force input / output staging
+  double4* d_tmp2 = nullptr;
+  double* d_out = nullptr;    // scalar outputs of reductions
+  int* d_iout = nullptr;
+  int n_partial = 1024;
+  bool bound = false;
+  bool own_stream = false;
+
+  // host mirrors
+  std::vector<double> X;       // 3 N0
+  std::vector<int> tets;       // 4 T0, oriented
+  std::vector<char> split_host;
+  int n_split_host = 0;
+  long long step_host = 0;
+  bool dt_set = false;
+  bool need_init = true;
+  bool traction_set = false;
+
+  // traction staging
+  int4* d_ftri = nullptr;
+  double4* d_ftrac = nullptr;
+  int* d_lfoff = nullptr;
+  int* d_lfent = nullptr;
+  int n_faces = 0;
+
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_steps = 0;
+  int graph_replay = -1;
+
+  // profiling
+  int profiling = 0;
+  double times[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<hipEvent_t> evpool;
+
+  std::vector<void*> allocs;
+  std::vector<Region> regions;  // checkpointed device arrays
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+};
+
+namespace {
+
+#define HIPCHK(ctx, expr)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return (ctx)->fail(CEM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int dalloc(cem_ctx* c, T** p, size_t count, bool checkpoint = false) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    return c->fail(e == hipErrorOutOfMemory ? CEM_ENOMEM : CEM_EHIP,
+                   std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  c->allocs.push_back(q);
+  *p = (T*)q;
+  if (checkpoint) c->regions.push_back({q, bytes});
+  return CEM_OK;
+}
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
+void radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int bits) {
+  size_t n = key.size();
+  std::vector<uint64_t> k2(n);
+  std::vector<uint32_t> v2(n);
+  for (int shift = 0; shift < bits; shift += 16) {
+    std::vector<size_t> cnt(65537, 0);
+    for (size_t i = 0; i < n; ++i) cnt[((key[i] >> shift) & 0xffff) + 1]++;
+    for (int d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+    for (size_t i = 0; i < n; ++i) {
+      size_t pos = cnt[(key[i] >> shift) & 0xffff]++;
+      k2[pos] = key[i];
+      v2[pos] = val[i];
+    }
+    key.swap(k2);
+    val.swap(v2);
+  }
+}
+
+int bits_for(uint64_t maxv) {
+  int b = 1;
+  while (b < 64 && (maxv >> b)) ++b;
+  return b;
+}
+
+const int kLE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+int local_edge_h(int a, int b) {
+  int lo = std::min(a, b), hi = std::max(a, b);
+  for (int q = 0; q < 6; ++q)
+    if (kLE[q][0] == lo && kLE[q][1] == hi) return q;
+  return -1;
+}
+
+struct HostTopo {
+  int E0 = 0;
+  std::vector<int> et2e;      // 6 T0
+  std::vector<int> poff;      // E0 + 1
+  std::vector<int> pent;      // 6 T0
+  std::vector<int> patchpos;  // 6 T0
+  std::vector<int> noff;      // N0 + 1
+  std::vector<int> nent;      // 4 T0
+  std::vector<int> nodepos;   // 4 T0
+  std::vector<int> nbr;       // 4 T0
+  std::vector<int> nbrface;   // T0 packed
+};
+
+// Orientation fix and degeneracy test (Section 2.2 needs V_j > 0).
+int check_orient(cem_ctx* c, int N, const double* X, int T, std::vector<int>& tets) {
+  double lsum = 0;
+  for (int t = 0; t < T; ++t)
+    for (int q = 0; q < 6; ++q) {
+      const double* a = X + 3 * tets[4 * t + kLE[q][0]];
+      const double* b = X + 3 * tets[4 * t + kLE[q][1]];
+      lsum += std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
+                        (a[2] - b[2]) * (a[2] - b[2]));
+    }
+  double lm = T ? lsum / (6.0 * T) : 0;
+  double tol = 1e-12 * lm * lm * lm;
+  (void)N;
+  for (int t = 0; t < T; ++t) {
+    int* n = &tets[4 * t];
+    const double *x0 = X + 3 * n[0], *x1 = X + 3 * n[1], *x2 = X + 3 * n[2], *x3 = X + 3 * n[3];
+    double ax = x1[0] - x0[0], ay = x1[1] - x0[1], az = x1[2] - x0[2];
+    double bx = x2[0] - x0[0], by = x2[1] - x0[1], bz = x2[2] - x0[2];
+    double cx = x3[0] - x0[0], cy = x3[1] - x0[1], cz = x3[2] - x0[2];
+    double V = (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx)) / 6.0;
+    if (!(std::fabs(V) > tol))
+      return c->fail(CEM_EMESH, "degenerate tetrahedron " + std::to_string(t));
+    if (V < 0) std::swap(n[2], n[3]);
+  }
+  return CEM_OK;
+}
+
+int build_topology(cem_ctx* c, int N, int T, const std::vector<int>& tets, HostTopo& h) {
+  // edges: sort (min, max) node-pair keys of every (tet, local edge)
+  size_t M = (size_t)6 * T;
+  std::vector<uint64_t> key(M);
+  std::vector<uint32_t> val(M);
+  for (int t = 0; t < T; ++t)
+    for (int q = 0; q < 6; ++q) {
+      uint64_t a = (uint32_t)tets[4 * t + kLE[q][0]], b = (uint32_t)tets[4 * t + kLE[q][1]];
+      if (a > b) std::swap(a, b);
+      key[(size_t)6 * t + q] = (a << 32) | b;
+      val[(size_t)6 * t + q] = (uint32_t)(6 * t + q);
+    }
+  int nb = bits_for((uint64_t)std::max(N - 1, 1));
+  // sort on b (low word) then a (high word)
+  {
+    std::vector<uint64_t> k2(M);
+    for (size_t i = 0; i < M; ++i) k2[i] = (key[i] >> 32 << nb) | (key[i] & 0xffffffffull);
+    radix_sort(k2, val, 2 * nb);
+    for (size_t i = 0; i < M; ++i) key[i] = k2[i];
+  }
+  h.et2e.assign(M, -1);
+  h.patchpos.assign(M, -1);
+  h.pent.assign(M, -1);
+  h.poff.clear();
+  int E = 0;
+  for (size_t i = 0; i < M; ++i) {
+    if (i == 0 || key[i] != key[i - 1]) {
+      h.poff.push_back((int)i);
+      E++;
+    }
+    uint32_t tq = val[i];
+    h.et2e[tq] = E - 1;
+    h.patchpos[tq] = (int)i;
+    h.pent[i] = (int)(tq / 6);
+  }
+  h.poff.push_back((int)M);
+  h.E0 = E;
+  // node lists: counting sort of (node, tet, local) in tet order
+  h.noff.assign(N + 1, 0);
+  for (int t = 0; t < T; ++t)
+    for (int l = 0; l < 4; ++l) h.noff[tets[4 * t + l] + 1]++;
+  for (int i = 0; i < N; ++i) h.noff[i + 1] += h.noff[i];
+  std::vector<int> fill(h.noff.begin(), h.noff.end() - 1);
+  h.nent.assign((size_t)4 * T, 0);
+  h.nodepos.assign((size_t)4 * T, 0);
+  for (int t = 0; t < T; ++t)
+    for (int l = 0; l < 4; ++l) {
+      int p = fill[tets[4 * t + l]]++;
+      h.nent[p] = (t << 2) | l;
+      h.nodepos[(size_t)4 * t + l] = p;
+    }
+  // faces: key (edge id of the two smallest nodes, largest node)
+  size_t F = (size_t)4 * T;
+  std::vector<uint64_t> fk(F);
+  std::vector<uint32_t> fv(F);
+  for (int t = 0; t < T; ++t)
+    for (int f = 0; f < 4; ++f) {
+      int ln[3], k = 0;
+      for (int l = 0; l < 4; ++l)
+        if (l != f) ln[k++] = l;
+      std::sort(ln, ln + 3, [&](int x, int y) { return tets[4 * t + x] < tets[4 * t + y]; });
+      int eid = h.et2e[(size_t)6 * t + local_edge_h(ln[0], ln[1])];
+      fk[(size_t)4 * t + f] = ((uint64_t)eid << nb) | (uint32_t)tets[4 * t + ln[2]];
+      fv[(size_t)4 * t + f] = (uint32_t)(4 * t + f);
+    }
+  radix_sort(fk, fv, nb + bits_for((uint64_t)std::max(E - 1, 1)));
+  h.nbr.assign(F, -1);
+  h.nbrface.assign(T, 0);
+  for (size_t i = 0; i < F;) {
+    size_t j = i;
+    while (j < F && fk[j] == fk[i]) ++j;
+    if (j - i > 2) return c->fail(CEM_EMESH, "face shared by more than two tetrahedra");
+    if (j - i == 2) {
+      uint32_t p = fv[i], q = fv[i + 1];
+      int tp = p / 4, fp = p % 4, tq = q / 4, fq = q % 4;
+      if (tp == tq) return c->fail(CEM_EMESH, "tetrahedron with a repeated face");
+      h.nbr[p] = tq;
+      h.nbr[q] = tp;
+      h.nbrface[tp] |= fq << (8 * fp);
+      h.nbrface[tq] |= fp << (8 * fq);
+    }
+    i = j;
+  }
+  for (int t = 0; t < T; ++t)
+    for (int f = 0; f < 4; ++f)
+      for (int g = f + 1; g < 4; ++g)
+        if (h.nbr[4 * t + f] >= 0 && h.nbr[4 * t + f] == h.nbr[4 * t + g])
+          return c->fail(CEM_EMESH, "duplicated tetrahedron " + std::to_string(t));
+  return CEM_OK;
+}
+
+template <class T>
+int upload(cem_ctx* c, T* d, const T* h, size_t n) {
+  if (n == 0) return CEM_OK;
+  HIPCHK(c, hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return CEM_OK;
+}
+
+int sync(cem_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CEM_OK;
+}
+
+int read_counters(cem_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+int check_device_error(cem_ctx* c) {
+  int r = read_counters(c);
+  if (r) return r;
+  int e = c->h_ctr->err;
+  if (e) {
+    int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->d_ctr->err, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    int r2 = sync(c);
+    if (r2) return r2;
+    if (e == CEM_ECAPACITY)
+      return c->fail(e, "split capacity exhausted at step " + std::to_string(c->h_ctr->step + 1) +
+                            " (state left at the start of that step)");
+    if (e == CEM_EUNSTABLE)
+      return c->fail(e, "non-finite or runaway state near step " + std::to_string(c->h_ctr->step + 1));
+    return c->fail(e, "device error");
+  }
+  c->n_split_host = c->h_ctr->n_split;
+  c->step_host = c->h_ctr->step;
+  return CEM_OK;
+}
+
+template <class R>
+int launch_strain_stress(cem_ctx* c, const double4* u) {
+  HIPCHK(c, Launch<R>::strain(c->m, u, c->w, c->d_ctr, c->stream));
+  HIPCHK(c, Launch<R>::edge_stress(c->m, c->w, c->d_ctr, c->stream));
+  return CEM_OK;
+}
+
+int strain_stress(cem_ctx* c, const double4* u) {
+  return c->mixed ? launch_strain_stress<float>(c, u) : launch_strain_stress<double>(c, u);
+}
+
+int node_pass(cem_ctx* c, int mode, double4* fout) {
+  hipError_t e = c->mixed ? Launch<float>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream)
+                          : Launch<double>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream);
+  HIPCHK(c, e);
+  return CEM_OK;
+}
+
+int initialize(cem_ctx* c) {
+  int r = strain_stress(c, c->st.u);
+  if (r) return r;
+  r = node_pass(c, NODE_INIT, nullptr);
+  if (r) return r;
+  c->need_init = false;
+  return CEM_OK;
+}
+
+// Kernels of one step, in order; ev (if not null) brackets the passes.
+int enqueue_step(cem_ctx* c, hipEvent_t* ev) {
+  hipStream_t s = c->stream;
+  bool replay = c->h_ctr->n_sched > 0;
+  if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+  if (c->mixed) HIPCHK(c, Launch<float>::strain(c->m, c->st.uh, c->w, c->d_ctr, s));
+  else HIPCHK(c, Launch<double>::strain(c->m, c->st.uh, c->w, c->d_ctr, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+  if (c->mixed) HIPCHK(c, Launch<float>::edge_stress(c->m, c->w, c->d_ctr, s));
+  else HIPCHK(c, Launch<double>::edge_stress(c->m, c->w, c->d_ctr, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
+  bool fracture = std::isfinite(c->mat.Gc) || replay;
+  if (fracture) {
+    if (c->mixed) HIPCHK(c, Launch<float>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
+    else HIPCHK(c, Launch<double>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
+    if (replay) HIPCHK(c, launch_replay_select(c->m, c->d_ctr, s));
+    else HIPCHK(c, launch_compact(c->m, c->d_ctr, s));
+  }
+  if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
+  int r = node_pass(c, NODE_STEP, nullptr);
+  if (r) return r;
+  if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+  if (c->mixed)
+    HIPCHK(c, launch_topology_t<float>(c->m, c->st, c->w, c->d_ctr, 1, 1, c->d_snodes, c->d_sedges, s));
+  else
+    HIPCHK(c, launch_topology_t<double>(c->m, c->st, c->w, c->d_ctr, 1, 1, c->d_snodes, c->d_sedges, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
+  return CEM_OK;
+}
+
+void drop_graph(cem_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_steps = 0;
+}
+
+int build_graph(cem_ctx* c, int k) {
+  drop_graph(c);
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+  int r = CEM_OK;
+  for (int i = 0; i < k && r == CEM_OK; ++i) r = enqueue_step(c, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (r) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return c->fail(CEM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+  c->graph_steps = k;
+  c->graph_replay = c->h_ctr->n_sched > 0;
+  return CEM_OK;
+}
+
+int ensure_ready(cem_ctx* c, bool need_dt) {
+  if (c->stage < 1) return c->fail(CEM_ESTATE, "no mesh uploaded");
+  if (need_dt && !c->dt_set) return c->fail(CEM_ESTATE, "time step not set (cem_set_dt)");
+  return CEM_OK;
+}
+
+void pad3(const double* src, std::vector<double4>& dst, int n) {
+  dst.resize(n);
+  for (int i = 0; i < n; ++i) dst[i] = make_double4(src[3 * i], src[3 * i + 1], src[3 * i + 2], 0.0);
+}
+
+void unpad3(const std::vector<double4>& src, double* dst, int n) {
+  for (int i = 0; i < n; ++i) {
+    dst[3 * i] = src[i].x;
+    dst[3 * i + 1] = src[i].y;
+    dst[3 * i + 2] = src[i].z;
+  }
+}
+
+int nodes_now_host(cem_ctx* c) {
+  return c->m.N0 + (c->m.mode == MODE_PHANTOM ? 4 * c->n_split_host : 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cem_create(const cem_options* opt, cem_ctx** out) {
+  if (!opt || !out) return CEM_EINVAL;
+  *out = nullptr;
+  if (opt->precision != CEM_FP64 && opt->precision != CEM_MIXED) return CEM_EINVAL;
+  if (opt->split_mode != CEM_PHANTOM && opt->split_mode != CEM_ERODE) return CEM_EINVAL;
+  if (opt->gsig != CEM_GSIG_PRINCIPAL && opt->gsig != CEM_GSIG_NORMAL) return CEM_EINVAL;
+  if (opt->max_splits < 0 || opt->graph_steps < 0 || opt->device < 0) return CEM_EINVAL;
+  cem_ctx* c = new cem_ctx();
+  c->opt = *opt;
+  c->stream = (hipStream_t)opt->stream;
+  c->mixed = opt->precision == CEM_MIXED;
+  *out = c;
+  return CEM_OK;
+}
+
+void cem_destroy(cem_ctx* c) {
+  if (!c) return;
+  if (c->stage >= 1) {
+    (void)hipSetDevice(c->opt.device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+const char* cem_last_error(const cem_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int32_t* tets,
+                    const cem_material* mat) {
+  if (!c) return CEM_EINVAL;
+  if (c->stage != 0) return c->fail(CEM_ESTATE, "mesh already uploaded");
+  if (!X || !tets || !mat || N < 4 || T < 1) return c->fail(CEM_EINVAL, "empty mesh");
+  if (N > kNodeMask / 2 || (long long)T * 6 > (1LL << 30))
+    return c->fail(CEM_EINVAL, "mesh too large for 32-bit indexing");
+  if (!(mat->E > 0) || !(mat->rho > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0))
+    return c->fail(CEM_EINVAL, "invalid material");
+  for (long long i = 0; i < (long long)T * 4; ++i)
+    if (tets[i] < 0 || tets[i] >= N) return c->fail(CEM_EMESH, "node id out of range");
+  for (long long i = 0; i < (long long)N * 3; ++i)
+    if (!std::isfinite(X[i])) return c->fail(CEM_EINVAL, "non-finite coordinate");
+  c->tets.assign(tets, tets + (size_t)4 * T);
+  c->X.assign(X, X + (size_t)3 * N);
+  int r = check_orient(c, N, X, T, c->tets);
+  if (r) return r;
+  HostTopo h;
+  r = build_topology(c, N, T, c->tets, h);
+  if (r) return r;
+
+  // ---- device side
+  HIPCHK(c, hipSetDevice(c->opt.device));
+  if (!c->stream) {
+    // graphs cannot capture the legacy null stream: use a stream of our own
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  c->mat = *mat;
+  Mesh& m = c->m;
+  const int S = c->opt.max_splits;
+  const bool ph = c->opt.split_mode == CEM_PHANTOM;
+  m.T0 = T;
+  m.N0 = N;
+  m.E0 = h.E0;
+  m.S_cap = S;
+  m.T_cap = T + (ph ? S : 0);
+  m.N_cap = N + (ph ? 4 * S : 0);
+  m.E_cap = h.E0 + (ph ? 10 * S : 0);
+  m.mode = c->opt.split_mode;
+  m.gsig = c->opt.gsig;
+  m.lam = mat->E * mat->nu / ((1 + mat->nu) * (1 - 2 * mat->nu));
+  m.mu = mat->E / (2 * (1 + mat->nu));
+  m.rho = mat->rho;
+  m.Gc = mat->Gc;
+  m.ramp_t0 = 0;
+  m.dt = 0;
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], X[3 * i + d]);
+        hi[d] = std::max(hi[d], X[3 * i + d]);
+      }
+    double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                            (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    m.umax = diag;  // a small-strain displacement as large as the body is a blow-up
+  }
+  HIPCHK(c, hipHostMalloc((void**)&c->h_ctr, sizeof(Counters), hipHostMallocDefault));
+  std::memset(c->h_ctr, 0, sizeof(Counters));
+  c->stage = 1;  // allocations from here are released by cem_destroy
+
+  const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
+  const size_t nflag = (size_t)((T + kCompactTile - 1) / kCompactTile) * kCompactTile;
+  int nb = (T + kCompactTile - 1) / kCompactTile;
+#define ALLOC(ptr, n, ck) \
+  if ((r = dalloc(c, &(ptr), (n), (ck)))) return r
+  ALLOC(c->d_ctr, 1, true);
+  ALLOC(m.enodes, m.T_cap, true);
+  ALLOC(m.et2e, (size_t)3 * m.T_cap, true);
+  ALLOC(m.X, m.N_cap, true);
+  ALLOC(m.poff, (size_t)m.E_cap + 1, false);
+  ALLOC(m.pent, (size_t)6 * T + 10 * (ph ? S : 0), true);
+  ALLOC(m.noff, (size_t)m.N_cap + 1, false);
+  ALLOC(m.nent, (size_t)4 * T + 4 * (ph ? S : 0), true);
+  ALLOC(m.invm, m.N_cap, true);
+  ALLOC(m.lslot, m.N_cap, true);
+  ALLOC(m.nbr, T, false);
+  ALLOC(m.nbrface, T, false);
+  ALLOC(m.nodepos, T, false);
+  ALLOC(m.patchpos, (size_t)3 * T, false);
+  ALLOC(m.front, T, true);
+  ALLOC(m.smask, T, true);
+  ALLOC(m.flag, nflag, false);
+  ALLOC(m.pmask, T, true);
+  ALLOC(m.ppat, T, true);
+  ALLOC(m.pG, T, true);
+  ALLOC(m.cand, T, true);
+  ALLOC(m.candf, T, true);
+  ALLOC(m.splitlist, std::max(S, 1), false);
+  ALLOC(m.bcount, nb, false);
+  ALLOC(m.area, std::max(S, 1), false);
+  ALLOC(m.rec_step, std::max(S, 1), true);
+  ALLOC(m.rec_tet, std::max(S, 1), true);
+  ALLOC(m.rec_mask, std::max(S, 1), true);
+  ALLOC(m.rec_pat, std::max(S, 1), true);
+  ALLOC(m.rec_G, std::max(S, 1), true);
+  ALLOC(c->d_snodes, std::max(S, 1), false);
+  ALLOC(c->d_sedges, (size_t)6 * std::max(S, 1), false);
+  char* vb;
+  ALLOC(vb, RS * 6 * (size_t)m.T_cap, false);
+  c->w.veps = vb;
+  ALLOC(vb, RS * 6 * (size_t)m.E_cap, false);
+  c->w.esig = vb;
+  ALLOC(vb, RS * (size_t)m.E_cap, true);
+  c->w.einvV = vb;
+  ALLOC(c->w.partial, c->n_partial, false);
+  ALLOC(c->d_out, 8, false);
+  ALLOC(c->d_iout, 8, false);
+  ALLOC(c->st.u, m.N_cap, true);
+  ALLOC(c->st.v, m.N_cap, true);
+  ALLOC(c->st.a, m.N_cap, true);
+  ALLOC(c->st.uh, m.N_cap, true);
+  ALLOC(c->d_tmp, m.N_cap, false);
+  ALLOC(c->d_tmp2, m.N_cap, false);
+  m.sched = nullptr;
+  m.Fload = nullptr;
+  m.wacc = nullptr;
+  m.lnode = nullptr;
+  m.n_load = 0;
+
+  // host images of the initial device arrays
+  std::vector<int4> en(m.T_cap, make_int4(0, 0, 0, 0));
+  for (int t = 0; t < T; ++t)
+    en[t] = make_int4(c->tets[4 * t] | (FR_ONE << kNodeBits), c->tets[4 * t + 1], c->tets[4 * t + 2],
+                      c->tets[4 * t + 3]);
+  if ((r = upload(c, m.enodes, en.data(), en.size()))) return r;
+  std::vector<int2> t2e((size_t)3 * m.T_cap, make_int2(0, 0));
+  for (size_t i = 0; i < (size_t)3 * T; ++i) t2e[i] = make_int2(h.et2e[2 * i], h.et2e[2 * i + 1]);
+  if ((r = upload(c, m.et2e, t2e.data(), t2e.size()))) return r;
+  std::vector<double4> Xp(m.N_cap, make_double4(0, 0, 0, 0));
+  for (int i = 0; i < N; ++i) Xp[i] = make_double4(X[3 * i], X[3 * i + 1], X[3 * i + 2], 0.0);
+  if ((r = upload(c, m.X, Xp.data(), Xp.size()))) return r;
+  std::vector<int> poff(m.E_cap + 1);
+  for (int k = 0; k <= h.E0; ++k) poff[k] = h.poff[k];
+  for (int k = h.E0 + 1; k <= m.E_cap; ++k) poff[k] = 6 * T + (k - h.E0);
+  if ((r = upload(c, m.poff, poff.data(), poff.size()))) return r;
+  std::vector<int> pent((size_t)6 * T + 10 * (ph ? S : 0), -1);
+  std::copy(h.pent.begin(), h.pent.end(), pent.begin());
+  if ((r = upload(c, m.pent, pent.data(), pent.size()))) return r;
+  std::vector<int> noff(m.N_cap + 1);
+  for (int i = 0; i <= N; ++i) noff[i] = h.noff[i];
+  for (int i = N + 1; i <= m.N_cap; ++i) noff[i] = 4 * T + (i - N);
+  if ((r = upload(c, m.noff, noff.data(), noff.size()))) return r;
+  std::vector<int> nent((size_t)4 * T + 4 * (ph ? S : 0), 0);
+  std::copy(h.nent.begin(), h.nent.end(), nent.begin());
+  if ((r = upload(c, m.nent, nent.data(), nent.size()))) return r;
+  std::vector<int> lsl(m.N_cap, -1);
+  if ((r = upload(c, m.lslot, lsl.data(), lsl.size()))) return r;
+  if ((r = upload(c, (int*)m.nbr, h.nbr.data(), h.nbr.size()))) return r;
+  if ((r = upload(c, m.nbrface, h.nbrface.data(), h.nbrface.size()))) return r;
+  if ((r = upload(c, (int*)m.nodepos, h.nodepos.data(), h.nodepos.size()))) return r;
+  if ((r = upload(c, (int*)m.patchpos, h.patchpos.data(), h.patchpos.size()))) return r;
+  std::vector<int> neg((size_t)4 * T, -1);
+  if ((r = upload(c, (int*)m.front, neg.data(), (size_t)4 * T))) return r;
+  if ((r = upload(c, m.smask, neg.data(), (size_t)T))) return r;
+  HIPCHK(c, hipMemsetAsync(m.flag, 0, nflag, c->stream));
+  HIPCHK(c, hipMemsetAsync(m.candf, 0, sizeof(int) * T, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_ctr, 0, sizeof(Counters), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->st.u, 0, sizeof(double4) * m.N_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->st.v, 0, sizeof(double4) * m.N_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->st.a, 0, sizeof(double4) * m.N_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->st.uh, 0, sizeof(double4) * m.N_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.veps, 0, RS * 6 * (size_t)m.T_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.esig, 0, RS * 6 * (size_t)m.E_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.einvV, 0, RS * (size_t)m.E_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(m.invm, 0, sizeof(double) * m.N_cap, c->stream));
+  HIPCHK(c, launch_masses(m, c->stream));
+  if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, c->stream));
+  else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, c->stream));
+  if ((r = sync(c))) return r;
+  c->split_host.assign(T, 0);
+  c->need_init = true;
+  return CEM_OK;
+}
+
+int cem_set_traction(cem_ctx* c, int32_t n_faces, const int32_t* tri, const double* t,
+                     double ramp_t0) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (n_faces < 0 || (n_faces > 0 && (!tri || !t)) || !(ramp_t0 >= 0))
+    return c->fail(CEM_EINVAL, "bad traction arguments");
+  Mesh& m = c->m;
+  for (long long i = 0; i < 3LL * n_faces; ++i) {
+    if (tri[i] < 0 || tri[i] >= m.N0) return c->fail(CEM_EINVAL, "traction face node out of range");
+    if (!std::isfinite(t[i])) return c->fail(CEM_EINVAL, "non-finite traction");
+  }
+  // loaded nodes -> slots; per slot the list of its faces
+  std::vector<int> slot(m.N0, -1), lnode;
+  for (long long i = 0; i < 3LL * n_faces; ++i) slot[tri[i]] = 0;
+  for (int i = 0; i < m.N0; ++i)
+    if (slot[i] == 0) {
+      slot[i] = (int)lnode.size();
+      lnode.push_back(i);
+    }
+  int L = (int)lnode.size();
+  std::vector<int> lfoff(L + 1, 0), lfent;
+  for (long long i = 0; i < 3LL * n_faces; ++i) lfoff[slot[tri[i]] + 1]++;
+  for (int s = 0; s < L; ++s) lfoff[s + 1] += lfoff[s];
+  lfent.assign(lfoff[L], 0);
+  std::vector<int> fill(lfoff.begin(), lfoff.end() - 1);
+  for (int f = 0; f < n_faces; ++f)
+    for (int q = 0; q < 3; ++q) lfent[fill[slot[tri[3 * f + q]]]++] = f;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // (re)allocate the load arrays
+  auto release = [&](void* p) {
+    if (!p) return;
+    (void)hipFree(p);
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+    c->regions.erase(std::remove_if(c->regions.begin(), c->regions.end(),
+                                    [&](const Region& g) { return g.ptr == p; }),
+                     c->regions.end());
+  };
+  release(m.Fload); release(m.wacc); release(m.lnode);
+  release(c->d_ftri); release(c->d_ftrac); release(c->d_lfoff); release(c->d_lfent);
+  m.Fload = nullptr; m.wacc = nullptr; m.lnode = nullptr;
+  ALLOC(m.Fload, L, false);
+  ALLOC(m.wacc, L, true);
+  ALLOC(m.lnode, L, false);
+  ALLOC(c->d_ftri, n_faces, false);
+  ALLOC(c->d_ftrac, n_faces, false);
+  ALLOC(c->d_lfoff, L + 1, false);
+  ALLOC(c->d_lfent, lfent.size(), false);
+  std::vector<int4> ft(n_faces);
+  std::vector<double4> fr(n_faces);
+  for (int f = 0; f < n_faces; ++f) {
+    ft[f] = make_int4(tri[3 * f], tri[3 * f + 1], tri[3 * f + 2], 0);
+    fr[f] = make_double4(t[3 * f], t[3 * f + 1], t[3 * f + 2], 0);
+  }
+  if ((r = upload(c, c->d_ftri, ft.data(), ft.size()))) return r;
+  if ((r = upload(c, c->d_ftrac, fr.data(), fr.size()))) return r;
+  if ((r = upload(c, c->d_lfoff, lfoff.data(), lfoff.size()))) return r;
+  if ((r = upload(c, c->d_lfent, lfent.data(), lfent.size()))) return r;
+  if ((r = upload(c, m.lnode, lnode.data(), lnode.size()))) return r;
+  std::vector<int> lsl(m.N0, -1);
+  for (int s = 0; s < L; ++s) lsl[lnode[s]] = s;
+  if ((r = upload(c, m.lslot, lsl.data(), lsl.size()))) return r;
+  m.n_load = L;
+  m.ramp_t0 = ramp_t0;
+  HIPCHK(c, launch_loads(m, c->d_ftri, c->d_ftrac, c->d_lfoff, c->d_lfent, c->stream));
+  if ((r = sync(c))) return r;
+  c->traction_set = true;
+  c->need_init = true;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_mask) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->step_host != 0) return c->fail(CEM_ESTATE, "pre-splits must precede the first step");
+  if (n < 0 || (n > 0 && (!tet || !side_mask))) return c->fail(CEM_EINVAL, "bad presplit arguments");
+  std::vector<std::pair<int, int>> lst;
+  for (int i = 0; i < n; ++i) {
+    int mk = side_mask[i];
+    int nb = __builtin_popcount(mk & 15);
+    if (tet[i] < 0 || tet[i] >= c->m.T0) return c->fail(CEM_EINVAL, "presplit tet out of range");
+    if ((mk & ~15) || nb == 0 || nb == 4) return c->fail(CEM_EINVAL, "presplit mask is not a partition");
+    lst.push_back({tet[i], mk});
+  }
+  std::sort(lst.begin(), lst.end());
+  std::vector<int> tt;
+  std::vector<uint8_t> mm;
+  for (size_t i = 0; i < lst.size(); ++i) {
+    if (i > 0 && lst[i].first == lst[i - 1].first) continue;
+    if (c->split_host[lst[i].first]) continue;
+    tt.push_back(lst[i].first);
+    mm.push_back((uint8_t)lst[i].second);
+  }
+  if ((long long)c->n_split_host + (long long)tt.size() > c->m.S_cap)
+    return c->fail(CEM_ECAPACITY, "presplit exceeds the split capacity");
+  if (tt.empty()) return CEM_OK;
+  int* d_t = nullptr;
+  uint8_t* d_m = nullptr;
+  HIPCHK(c, hipMalloc(&d_t, sizeof(int) * tt.size()));
+  HIPCHK(c, hipMalloc(&d_m, mm.size()));
+  HIPCHK(c, hipMemcpyAsync(d_t, tt.data(), sizeof(int) * tt.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d_m, mm.data(), mm.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_set_presplit(c->m, c->d_ctr, d_t, d_m, (int)tt.size(), c->stream));
+  if (c->mixed)
+    HIPCHK(c, launch_topology_t<float>(c->m, c->st, c->w, c->d_ctr, 0, 0, c->d_snodes, c->d_sedges, c->stream));
+  else
+    HIPCHK(c, launch_topology_t<double>(c->m, c->st, c->w, c->d_ctr, 0, 0, c->d_snodes, c->d_sedges, c->stream));
+  r = sync(c);
+  (void)hipFree(d_t);
+  (void)hipFree(d_m);
+  if (r) return r;
+  for (int t : tt) c->split_host[t] = 1;
+  r = check_device_error(c);
+  if (r) return r;
+  c->need_init = true;
+  return CEM_OK;
+}
+
+int cem_critical_dt(cem_ctx* c, double* dt_crit) {
+  if (!c || !dt_crit) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  unsigned long long zero = 0;
+  HIPCHK(c, hipMemcpyAsync(&c->d_ctr->lam_key, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_dtcrit(c->m, c->d_ctr, c->stream));
+  if ((r = read_counters(c))) return r;
+  *dt_crit = c->h_ctr->dt_crit;
+  return CEM_OK;
+}
+
+int cem_set_dt(cem_ctx* c, double dt) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (!(dt > 0) || !std::isfinite(dt)) return c->fail(CEM_EINVAL, "dt must be positive");
+  c->m.dt = dt;
+  c->dt_set = true;
+  c->need_init = true;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_bind_state(cem_ctx* c, double* d_u, double* d_v, int64_t cap) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (!d_u || !d_v || cap < c->m.N_cap) return c->fail(CEM_EINVAL, "bound buffers too small");
+  HIPCHK(c, hipMemcpyAsync(d_u, c->st.u, sizeof(double4) * c->m.N_cap, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d_v, c->st.v, sizeof(double4) * c->m.N_cap, hipMemcpyDeviceToDevice, c->stream));
+  if ((r = sync(c))) return r;
+  for (auto& g : c->regions) {
+    if (g.ptr == c->st.u) g.ptr = d_u;
+    else if (g.ptr == c->st.v) g.ptr = d_v;
+  }
+  c->st.u = (double4*)d_u;
+  c->st.v = (double4*)d_v;
+  c->bound = true;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_set_state(cem_ctx* c, const double* u, const double* v) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  int n = nodes_now_host(c);
+  std::vector<double4> tmp;
+  if (u) {
+    pad3(u, tmp, n);
+    if ((r = upload(c, c->st.u, tmp.data(), n))) return r;
+  }
+  if (v) {
+    pad3(v, tmp, n);
+    if ((r = upload(c, c->st.v, tmp.data(), n))) return r;
+  }
+  if ((r = sync(c))) return r;
+  c->need_init = true;
+  return CEM_OK;
+}
+
+int cem_get_state(cem_ctx* c, double* u, double* v, double* a, int32_t* n_now) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->need_init && c->dt_set) {
+    if ((r = initialize(c))) return r;
+  }
+  int n = nodes_now_host(c);
+  if (n_now) *n_now = n;
+  std::vector<double4> tmp(n);
+  double4* src[3] = {c->st.u, c->st.v, c->st.a};
+  double* dst[3] = {u, v, a};
+  for (int q = 0; q < 3; ++q) {
+    if (!dst[q]) continue;
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), src[q], sizeof(double4) * n, hipMemcpyDeviceToHost, c->stream));
+    if ((r = sync(c))) return r;
+    unpad3(tmp, dst[q], n);
+  }
+  return CEM_OK;
+}
+
+int cem_internal_force(cem_ctx* c, const double* u, double* f) {
+  if (!c || !u || !f) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  int n = nodes_now_host(c);
+  std::vector<double4> tmp;
+  pad3(u, tmp, n);
+  if ((r = upload(c, c->d_tmp, tmp.data(), n))) return r;
+  if ((r = strain_stress(c, c->d_tmp))) return r;
+  if ((r = node_pass(c, NODE_FORCE, c->d_tmp2))) return r;
+  tmp.resize(n);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), c->d_tmp2, sizeof(double4) * n, hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  unpad3(tmp, f, n);
+  return CEM_OK;
+}
+
+int cem_step(cem_ctx* c, int32_t n_steps) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, true);
+  if (r) return r;
+  if (n_steps < 0) return c->fail(CEM_EINVAL, "negative step count");
+  if (n_steps == 0) return CEM_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  if (c->need_init && (r = initialize(c))) return r;
+  for (int q = 0; q < 6; ++q) c->times[q] = 0;
+  int K = c->opt.graph_steps;
+  int done = 0;
+  if (c->profiling) {
+    const int chunk = 64;
+    if ((int)c->evpool.size() < 6 * chunk) {
+      for (int i = (int)c->evpool.size(); i < 6 * chunk; ++i) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->evpool.push_back(e);
+      }
+    }
+    while (done < n_steps) {
+      int k = std::min(chunk, n_steps - done);
+      for (int i = 0; i < k; ++i)
+        if ((r = enqueue_step(c, &c->evpool[6 * i]))) return r;
+      if ((r = sync(c))) return r;
+      for (int i = 0; i < k; ++i)
+        for (int q = 1; q < 6; ++q) {
+          float ms = 0;
+          HIPCHK(c, hipEventElapsedTime(&ms, c->evpool[6 * i + q - 1], c->evpool[6 * i + q]));
+          c->times[q] += ms;
+        }
+      done += k;
+    }
+  } else if (K > 0 && n_steps >= K) {
+    int replay = c->h_ctr->n_sched > 0;
+    if (!c->gexec || c->graph_steps != K || c->graph_replay != replay) {
+      if ((r = build_graph(c, K))) return r;
+    }
+    while (n_steps - done >= K) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      done += K;
+    }
+  }
+  for (; done < n_steps; ++done)
+    if ((r = enqueue_step(c, nullptr))) return r;
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  r = check_device_error(c);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  c->times[0] = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return r;
+}
+
+int cem_replay_splits(cem_ctx* c, int32_t n, const cem_split_event* ev) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (n < 0 || (n > 0 && !ev)) return c->fail(CEM_EINVAL, "bad schedule");
+  std::vector<std::array<int, 3>> s;
+  for (int i = 0; i < n; ++i) {
+    int nb = __builtin_popcount(ev[i].side_mask & 15);
+    if (ev[i].tet < 0 || ev[i].tet >= c->m.T0 || (ev[i].side_mask & ~15) || nb == 0 || nb == 4)
+      return c->fail(CEM_EINVAL, "bad schedule entry");
+    s.push_back({ev[i].step, ev[i].tet, ev[i].side_mask});
+  }
+  std::stable_sort(s.begin(), s.end(), [](const std::array<int, 3>& x, const std::array<int, 3>& y) {
+    return x[0] != y[0] ? x[0] < y[0] : x[1] < y[1];
+  });
+  if (c->m.sched) {
+    (void)hipFree(c->m.sched);
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)c->m.sched), c->allocs.end());
+    c->m.sched = nullptr;
+  }
+  ALLOC(c->m.sched, (size_t)3 * std::max(n, 1), false);
+  if ((r = upload(c, c->m.sched, (const int*)s.data(), (size_t)3 * n))) return r;
+  if ((r = read_counters(c))) return r;
+  c->h_ctr->n_sched = n;
+  c->h_ctr->replay_cursor = 0;
+  HIPCHK(c, hipMemcpyAsync(&c->d_ctr->replay_cursor, &c->h_ctr->replay_cursor, 2 * sizeof(int) + sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+  if ((r = sync(c))) return r;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_read_energy(cem_ctx* c, cem_energy* e) {
+  if (!c || !e) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->need_init && c->dt_set && (r = initialize(c))) return r;
+  Mesh& m = c->m;
+  int np = c->n_partial;
+  HIPCHK(c, launch_kinetic(m, c->st, c->d_ctr, c->w.partial, np, c->stream));
+  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out, c->stream));
+  if (c->mixed) {
+    HIPCHK(c, Launch<float>::strain(m, c->st.u, c->w, c->d_ctr, c->stream));
+    HIPCHK(c, launch_strain_energy<float>(m, c->w, c->d_ctr, c->w.partial, np, c->stream));
+  } else {
+    HIPCHK(c, Launch<double>::strain(m, c->st.u, c->w, c->d_ctr, c->stream));
+    HIPCHK(c, launch_strain_energy<double>(m, c->w, c->d_ctr, c->w.partial, np, c->stream));
+  }
+  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out + 1, c->stream));
+  if (m.n_load > 0) HIPCHK(c, launch_sum(m.wacc, m.n_load, c->d_out + 2, c->stream));
+  else HIPCHK(c, hipMemsetAsync(c->d_out + 2, 0, sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_iout, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_count_fronts(m, c->d_ctr, c->d_iout, c->stream));
+  double out[3];
+  int nf = 0;
+  HIPCHK(c, hipMemcpyAsync(out, c->d_out, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&nf, c->d_iout, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if ((r = read_counters(c))) return r;
+  const Counters& k = *c->h_ctr;
+  e->step = k.step;
+  e->t = (double)k.step * m.dt;
+  e->KE = out[0];
+  e->SE = out[1];
+  e->Wext = out[2];
+  e->Ud = k.Ud;
+  e->Gmax = k.gmax_last ? key_to_double_host(k.gmax_last) : 0.0;
+  e->n_split = k.n_split;
+  e->n_front = nf;
+  e->n_nodes = m.N0 + (m.mode == MODE_PHANTOM ? 4 * k.n_split : 0);
+  e->n_elems = m.T0 + (m.mode == MODE_PHANTOM ? k.n_split : 0);
+  return CEM_OK;
+}
+
+int cem_read_splits(cem_ctx* c, int32_t cap, cem_split_event* out, int32_t* n) {
+  if (!c || !n) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if ((r = read_counters(c))) return r;
+  int ns = c->h_ctr->n_split;
+  *n = ns;
+  int k = std::min(ns, std::max(cap, 0));
+  if (k == 0 || !out) return CEM_OK;
+  std::vector<int> st(k), tt(k), mk(k), pt(k);
+  std::vector<double> G(k);
+  HIPCHK(c, hipMemcpyAsync(st.data(), c->m.rec_step, sizeof(int) * k, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tt.data(), c->m.rec_tet, sizeof(int) * k, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(mk.data(), c->m.rec_mask, sizeof(int) * k, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(pt.data(), c->m.rec_pat, sizeof(int) * k, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(G.data(), c->m.rec_G, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  for (int i = 0; i < k; ++i) out[i] = cem_split_event{st[i], tt[i], mk[i], pt[i], G[i]};
+  return CEM_OK;
+}
+
+int cem_read_front_G(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* n) {
+  if (!c || !n) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->need_init && c->dt_set && (r = initialize(c))) return r;
+  if ((r = read_counters(c))) return r;
+  int nc = c->h_ctr->n_cand;
+  size_t capf = (size_t)4 * std::max(nc, 1);
+  int* d_tfl = nullptr;
+  double* d_g = nullptr;
+  HIPCHK(c, hipMalloc(&d_tfl, sizeof(int) * 3 * capf));
+  HIPCHK(c, hipMalloc(&d_g, sizeof(double) * 2 * capf));
+  if ((r = strain_stress(c, c->st.u))) return r;
+  HIPCHK(c, hipMemsetAsync(c->d_iout, 0, sizeof(int), c->stream));
+  hipError_t e = c->mixed ? Launch<float>::front_eval(c->m, c->st, c->w, c->d_ctr, d_tfl, d_g, c->d_iout, c->stream)
+                          : Launch<double>::front_eval(c->m, c->st, c->w, c->d_ctr, d_tfl, d_g, c->d_iout, c->stream);
+  HIPCHK(c, e);
+  int nf = 0;
+  HIPCHK(c, hipMemcpyAsync(&nf, c->d_iout, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  std::vector<int> tfl((size_t)3 * nf);
+  std::vector<double> g((size_t)2 * nf);
+  if (nf > 0) {
+    HIPCHK(c, hipMemcpyAsync(tfl.data(), d_tfl, sizeof(int) * 3 * nf, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(g.data(), d_g, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost, c->stream));
+  }
+  r = sync(c);
+  (void)hipFree(d_tfl);
+  (void)hipFree(d_g);
+  if (r) return r;
+  std::vector<int> ord(nf);
+  for (int i = 0; i < nf; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) {
+    return tfl[3 * x] != tfl[3 * y] ? tfl[3 * x] < tfl[3 * y] : tfl[3 * x + 1] < tfl[3 * y + 1];
+  });
+  *n = nf;
+  for (int i = 0; i < nf && i < cap && out; ++i) {
+    int o = ord[i];
+    out[i] = cem_front_g{tfl[3 * o], tfl[3 * o + 1], tfl[3 * o + 2], 0, g[2 * o], g[2 * o + 1]};
+  }
+  return CEM_OK;
+}
+
+// Checkpoint layout: magic, version, T0, N0, E0, S_cap, mixed, mode,
+// need_init, step_host, then every checkpointed device region in allocation
+// order, then the split mirror.
+int cem_save_state(cem_ctx* c, void* buf, int64_t cap, int64_t* used) {
+  if (!c || !used) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  const int hdr = 16;
+  int64_t total = hdr * 8;
+  for (auto& g : c->regions) total += (int64_t)g.bytes;
+  total += c->m.T0;
+  *used = total;
+  if (!buf) return CEM_OK;
+  if (cap < total) return c->fail(CEM_EINVAL, "checkpoint buffer too small");
+  int64_t h[hdr] = {0x43454d31, 1, c->m.T0, c->m.N0, c->m.E0, c->m.S_cap, c->mixed, c->m.mode,
+                    c->need_init ? 1 : 0, c->step_host, c->n_split_host, c->dt_set ? 1 : 0, 0, 0, 0, 0};
+  double dtv = c->m.dt;
+  std::memcpy(&h[12], &dtv, 8);
+  char* p = (char*)buf;
+  std::memcpy(p, h, sizeof(h));
+  p += sizeof(h);
+  for (auto& g : c->regions) {
+    HIPCHK(c, hipMemcpyAsync(p, g.ptr, g.bytes, hipMemcpyDeviceToHost, c->stream));
+    p += g.bytes;
+  }
+  if ((r = sync(c))) return r;
+  std::memcpy(p, c->split_host.data(), c->m.T0);
+  return CEM_OK;
+}
+
+int cem_load_state(cem_ctx* c, const void* buf, int64_t size) {
+  if (!c || !buf) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  const int hdr = 16;
+  int64_t h[hdr];
+  if (size < (int64_t)sizeof(h)) return c->fail(CEM_EINVAL, "checkpoint too short");
+  std::memcpy(h, buf, sizeof(h));
+  if (h[0] != 0x43454d31 || h[1] != 1 || h[2] != c->m.T0 || h[3] != c->m.N0 || h[4] != c->m.E0 ||
+      h[5] != c->m.S_cap || h[6] != c->mixed || h[7] != c->m.mode)
+    return c->fail(CEM_EINVAL, "checkpoint does not match this context");
+  int64_t total = sizeof(h);
+  for (auto& g : c->regions) total += (int64_t)g.bytes;
+  total += c->m.T0;
+  if (size < total) return c->fail(CEM_EINVAL, "checkpoint too short");
+  const char* p = (const char*)buf + sizeof(h);
+  for (auto& g : c->regions) {
+    HIPCHK(c, hipMemcpyAsync(g.ptr, p, g.bytes, hipMemcpyHostToDevice, c->stream));
+    p += g.bytes;
+  }
+  if ((r = sync(c))) return r;
+  std::memcpy(c->split_host.data(), p, c->m.T0);
+  c->need_init = h[8] != 0;
+  c->step_host = h[9];
+  c->n_split_host = (int)h[10];
+  c->dt_set = h[11] != 0;
+  std::memcpy(&c->m.dt, &h[12], 8);
+  drop_graph(c);
+  return read_counters(c);
+}
+
+int cem_counts(cem_ctx* c, int32_t* out) {
+  if (!c || !out) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if ((r = read_counters(c))) return r;
+  const Counters& k = *c->h_ctr;
+  const Mesh& m = c->m;
+  bool ph = m.mode == MODE_PHANTOM;
+  HIPCHK(c, hipMemsetAsync(c->d_iout, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_count_fronts(m, c->d_ctr, c->d_iout, c->stream));
+  int nf = 0;
+  HIPCHK(c, hipMemcpyAsync(&nf, c->d_iout, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  out[0] = m.N0 + (ph ? 4 * k.n_split : 0);
+  out[1] = m.T0 + (ph ? k.n_split : 0);
+  out[2] = m.E0 + (ph ? 10 * k.n_split : 0);
+  out[3] = k.n_split;
+  out[4] = nf;
+  out[5] = m.E0;
+  return CEM_OK;
+}
+
+int cem_set_profiling(cem_ctx* c, int32_t on) {
+  if (!c) return CEM_EINVAL;
+  c->profiling = on ? 1 : 0;
+  return CEM_OK;
+}
+
+int cem_kernel_times(cem_ctx* c, double* out) {
+  if (!c || !out) return CEM_EINVAL;
+  for (int q = 0; q < 6; ++q) out[q] = c->times[q];
+  return CEM_OK;
+}
+
+}  // extern "C"
