@@ -1,0 +1,246 @@
+"""Throughput of the ES-T-FEM crack-element step on one MI355X.
+
+Default workload: the notched plate of the paper's crack-branching example
+(Section 4.4) on a synthetic structured mesh, 100 x 40 x 4 mm at 200 x 80 x 8
+cells x 6 tets = 768,000 tets, 1 MPa traction ramped over 1 us, splitting on.
+A step is the whole hot path: strain pass, edge stress pass, crack-front pass
+with flag compaction, node force + Newmark pass, topology update.
+
+Prints one JSON line (rank 0).  Phases:
+  1. FP64 run, plain launches with per-pass HIP events: warmup, then the timed
+     region of --steps steps (value, ms_per_step, per-pass durations);
+  2. the same region length replayed as captured HIP graphs (reported as
+     "graph");
+  3. mixed precision with the FP64 split schedule replayed: throughput and
+     relative L2 error of u against the FP64 run;
+  4. the CPU oracle on a bounded sample (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tet-steps/sec and HBM GB/s, FP32-mixed vs FP64 at stated displacement error"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per tet-step of each pass (compulsory traffic of the
+# three-pass formulation with stored gradients; FP64 / mixed).
+ALG_BYTES = {
+    "fp64": {"strain": 149.0, "edge_stress": 146.0, "node": 200.0},
+    "mixed": {"strain": 85.0, "edge_stress": 88.0, "node": 130.0},
+}
+KERNEL_NAMES = {"strain": "k_strain", "edge_stress": "k_edge_stress", "node": "k_node"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2508_04076_amd import meshgen as mg
+    if name == "plate":
+        return mg.plate_notched(), 1e-6, ("notched plate 100x40x4 mm, 200x80x8 cells x 6 tets "
+                                         "(768,000 tets), 50 mm edge notch at mid-height, "
+                                         "1 MPa traction ramped over 1 us")
+    if name == "cube":
+        return mg.cube_notched(10), 0.0, ("unit cube 10x10x10 cells x 6 tets (6,000 tets), "
+                                          "notch z=0.5 over x<0.3, 1 MPa step traction")
+    if name == "block":
+        return mg.block_notched(), 1e-6, ("notched block 400x200x100 cells x 6 tets at 0.5 mm "
+                                          "(48,000,000 tets), 2% pre-split, 1 MPa ramped")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def counters_for(kernel_src_hash):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "hbm_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    return d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="plate", choices=["plate", "cube", "block"])
+    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps for the CPU baseline (0: about 15 s of work)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes, 5 times "
+                         "(calibrates the HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n,
+                          "launches": 5}), flush=True)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2508_04076_amd import meshgen as mg
+    from paper_2508_04076_amd.cem import Simulation
+
+    mat = dict(mg.BRANCHING_MATERIAL)
+    mesh, ramp, desc = workload(args.workload)
+    T = mesh.n_tets
+    log(f"workload {args.workload}: {T} tets, {mesh.n_nodes} nodes")
+    K, W = args.steps, args.warmup
+    max_splits = max(T // 8, len(mesh.presplit_tets) + 20000)
+
+    def make(precision, graph):
+        return Simulation.from_mesh(mesh, mat, ramp_t0=ramp, precision=precision,
+                                    max_splits=max_splits, graph_steps=graph, device=0)
+
+    # ---- 1. FP64, per-pass events (the timed region)
+    sim = make("fp64", 0)
+    dt = 0.5 * sim.critical_dt()
+    sim.set_dt(dt)
+    log(f"dt = {dt:.6e} s; warmup {W} steps")
+    sim.set_profiling(True)
+    sim.step(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = sim.kernel_times()
+    u64, _, _ = sim.get_state()
+    e64 = sim.energy()
+    ev64, _ = sim.splits()
+    value = T * K / wall
+    log(f"fp64 plain+events: {wall * 1e3 / K:.4f} ms/step, {value:.4e} tet-steps/s, "
+        f"splits {e64['n_split']}")
+    per_launch = {k: kt[k] / K for k in ("strain", "edge_stress", "front", "node", "topology")}
+    sim.close()
+
+    # ---- 2. FP64 graphs, same region length
+    graph = None
+    if not args.no_graph and args.graph_steps > 0:
+        g = make("fp64", args.graph_steps)
+        g.set_dt(dt)
+        g.step(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(K)
+        torch.cuda.synchronize()
+        gw = time.perf_counter() - t0
+        ug, _, _ = g.get_state()
+        graph = {"ms_per_step": gw * 1e3 / K, "tet_steps_per_s": T * K / gw,
+                 "graph_steps": args.graph_steps,
+                 "bitwise_equal_to_plain": bool(np.array_equal(ug, u64))}
+        log(f"fp64 graphs: {gw * 1e3 / K:.4f} ms/step, {T * K / gw:.4e} tet-steps/s")
+        g.close()
+
+    # ---- 3. mixed precision, FP64 split schedule replayed
+    mixed = None
+    if not args.no_mixed:
+        mx = make("mixed", args.graph_steps if not args.no_graph else 0)
+        mx.set_dt(dt)
+        sched = ev64[ev64[:, 3] > 0][:, :3]
+        if len(sched):
+            mx.replay_splits(sched)
+        mx.step(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mx.step(K)
+        torch.cuda.synchronize()
+        mw = time.perf_counter() - t0
+        um, _, _ = mx.get_state()
+        err = float(np.linalg.norm(um - u64) / np.linalg.norm(u64))
+        mixed = {"tet_steps_per_s": T * K / mw, "ms_per_step": mw * 1e3 / K,
+                 "rel_l2_u_vs_fp64": err, "steps_compared": W + K,
+                 "split_schedule": "fp64 run replayed", "dtype": "f32 force / f64 state"}
+        log(f"mixed: {mw * 1e3 / K:.4f} ms/step, {T * K / mw:.4e} tet-steps/s, "
+            f"rel L2 u err {err:.3e}")
+        mx.close()
+
+    # ---- roofline of the dominant pass (largest average launch time)
+    dom = max(("strain", "edge_stress", "node"), key=lambda k: per_launch[k])
+    dur_s = per_launch[dom] * 1e-3
+    alg = ALG_BYTES["fp64"][dom] * T
+    achieved = alg / dur_s / 1e9
+    src = open(os.path.join(ROOT, "paper_2508_04076_amd", "csrc", "kernels.hip"), "rb").read()
+    cnt = counters_for(hashlib.sha256(src).hexdigest())
+    traffic = None
+    if cnt and cnt.get("workload") == args.workload and KERNEL_NAMES[dom] in cnt.get("kernels", {}):
+        traffic = cnt["kernels"][KERNEL_NAMES[dom]]["hbm_bytes_per_launch"]
+    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "alg_bytes_per_tet": ALG_BYTES["fp64"][dom],
+                "avg_launch_ms": per_launch[dom]}
+
+    # ---- 4. CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        from oracle.oracle import Oracle
+        o = Oracle.from_mesh(mesh, mat, ramp_t0=ramp)
+        o.set_dt(dt)
+        n_cpu = args.cpu_steps
+        if n_cpu <= 0:
+            t0 = time.perf_counter()
+            o.step(1)
+            one = time.perf_counter() - t0
+            n_cpu = max(1, min(200, int(15.0 / max(one, 1e-6))))
+            done = 1
+        else:
+            done = 0
+        log(f"oracle: {n_cpu} steps on the host")
+        t0 = time.perf_counter()
+        o.step(n_cpu - done)
+        el = time.perf_counter() - t0
+        n_timed = n_cpu - done
+        if n_timed == 0:
+            n_timed, el = 1, one
+        cpu = {"value": T * n_timed / el, "unit": "tet-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_timed} steps of the same workload from t=0 (single-threaded FP64 "
+                         f"C++ oracle, {el:.1f} s)",
+               "host_cpus": os.cpu_count()}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "tet-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": wall * 1e3 / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "tets": T, "nodes": mesh.n_nodes,
+                   "dt_s": dt, "splits_after_run": int(e64["n_split"]),
+                   "launch": "plain launches with per-pass HIP events"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_ms_per_step": per_launch,
+        "graph": graph,
+        "mixed": mixed,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -9,8 +9,17 @@ namespace cem {
 
 constexpr int kBlock = 256;          // 4 wave64 per workgroup
 constexpr int kTopoBlock = 1024;     // single-workgroup topology update
-constexpr int kCompactPerThread = 16;
-constexpr int kCompactTile = kBlock * kCompactPerThread;  // tets per compaction block
+#ifndef CEM_NODE_LANES
+#define CEM_NODE_LANES 8
+#endif
+constexpr int kNodeLanes = CEM_NODE_LANES;  // lanes that share one node in the node pass
+#ifndef CEM_NODE_FUSED
+#define CEM_NODE_FUSED 0
+#endif
+#ifndef CEM_PERSISTENT_BLOCKS
+#define CEM_PERSISTENT_BLOCKS 2048
+#endif
+constexpr int kPersistentBlocks = CEM_PERSISTENT_BLOCKS;  // grid cap of the step passes
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
@@ -31,7 +40,7 @@ struct Counters {
   unsigned long long gmax_last;   // key of the last completed crack pass
   double Ud;                      // dissipated energy
   int replay_cursor;              // next entry of the forced schedule
-  int ticket;                     // compaction last-block ticket
+  int ticket;                     // crack pass last-block ticket
   int n_sched;                    // forced schedule length (0: G test decides)
   int pad;
   unsigned long long lam_key;     // ordered key of max element eigenvalue (setup)
@@ -68,18 +77,18 @@ struct Mesh {
 
   int4* nbr;                // [T0] face neighbour per local face, -1 at the boundary
   int* nbrface;             // [T0] packed 4 x 8 bits: neighbour's local face index
-  int4* nodepos;            // [T0] position of (t, l) in the node lists
+  int4* epos;               // [T_cap] position of each (element, local node) in the node lists
+  double* vol;              // [T_cap] volume of the parent tetrahedron
+  int* tet_ext;             // [T0] the caller's id of each tet (split order key)
   int2* patchpos;           // [T0 * 3] position of t in the patch of its 6 edges
   int4* front;              // [T0] lone node per local face on the crack front, -1 none
   int* smask;               // [T0] -1 intact, else the side mask of the split
-  uint8_t* flag;            // [T0] flagged in the current step
   uint8_t* pmask;           // [T0] pending side mask
   uint8_t* ppat;            // [T0] pending pattern (1 = I, 2 = II)
   double* pG;               // [T0] pending release rate
   int* cand;                // [T0] candidate list
   int* candf;               // [T0] on the candidate list
-  int* splitlist;           // [max(S_cap, 1)] tets to split this step (ascending)
-  int* bcount;              // compaction block counts / offsets
+  int* splitlist;           // [next pow2 of S_cap] tets to split this step
   double* area;             // [S_cap] crack area of each split (scratch)
   int* rec_step;            // [S_cap] split records
   int* rec_tet;
@@ -94,6 +103,7 @@ struct Work {
   void* veps;               // [T_cap] Six<R>: effective volume x element strain
   void* esig;               // [E_cap] Six<R>: smoothed edge stress
   void* einvV;              // [E_cap] R: 1 / sum of effective volumes of the patch
+  void* contrib;            // [T_cap][4] R4: nodal force terms, index (e << 2) | l
   double* partial;          // reduction partials
 };
 
@@ -124,7 +134,6 @@ hipError_t launch_strain_energy(const Mesh& m, const Work& w, Counters* c, doubl
 template <class R>
 hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Counters* c,
                              int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s);
-hipError_t launch_compact(const Mesh& m, Counters* c, hipStream_t s);
 hipError_t launch_replay_select(const Mesh& m, Counters* c, hipStream_t s);
 hipError_t launch_masses(const Mesh& m, hipStream_t s);
 hipError_t launch_loads(const Mesh& m, const int4* ftri, const double4* ftrac, const int* lfoff,

@@ -24,15 +24,27 @@ namespace cem {
 
 // ---------------------------------------------------------------- helpers
 
-// Workgroups are dispatched round-robin over the eight XCDs; renumber them so
-// each XCD walks one contiguous range of the data (its own L2 keeps the
-// shared nodes and edges of neighbouring elements).
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-  const int nx = 8;
-  int x = b % nx, local = b / nx;
-  int per = nb / nx, rem = nb % nx;
-  return x * per + (x < rem ? x : rem) + local;
-}
+// Persistent grid-stride launch: the grid (a multiple of 8 workgroups) is
+// sized to the chip, not to the data.  Chunks of kBlock items are split into
+// eight contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), and
+// the workgroups of an XCD stride through its range.  The item count is read
+// on the device, so a captured graph stays valid as splits add elements.
+struct Chunks {
+  int ch, hi, stride;
+  __device__ __forceinline__ Chunks(long long count) {
+    long long nch = (count + kBlock - 1) / kBlock;
+    int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    stride = gridDim.x / 8;
+    ch = (int)(nch * x / 8) + j;
+    hi = (int)(nch * (x + 1) / 8);
+  }
+  __device__ __forceinline__ bool next(int& item) {
+    if (ch >= hi) return false;
+    item = ch * kBlock + threadIdx.x;
+    ch += stride;
+    return true;
+  }
+};
 
 __device__ __forceinline__ double frac_of(int code) {
   return code == FR_ONE ? 1.0 : code == FR_HALF ? 0.5 : code == FR_EIGHTH ? 0.125
@@ -59,6 +71,20 @@ template <class R> __device__ __forceinline__ void store6(Six<R>* p, const R* v)
   for (int i = 0; i < 6; ++i) s.v[i] = v[i];
   *p = s;
 }
+
+template <class R> struct Vec4;
+template <> struct Vec4<double> {
+  typedef double4 T;
+  static __device__ __forceinline__ double4 make(double x, double y, double z) {
+    return make_double4(x, y, z, 0.0);
+  }
+};
+template <> struct Vec4<float> {
+  typedef float4 T;
+  static __device__ __forceinline__ float4 make(float x, float y, float z) {
+    return make_float4(x, y, z, 0.0f);
+  }
+};
 
 __device__ __forceinline__ double ramp(const Mesh& m, double t) {
   return (m.ramp_t0 > 0.0 && t < m.ramp_t0) ? t / m.ramp_t0 : 1.0;
@@ -105,8 +131,10 @@ __global__ __launch_bounds__(kBlock) void k_strain(Mesh m, const double4* __rest
                                                    Six<R>* __restrict__ veps,
                                                    const Counters* __restrict__ c) {
   if (c->err) return;
-  int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (e >= elems_now(m, c)) return;
+  const int Tn = elems_now(m, c);
+  Chunks it(Tn);
+  for (int e; it.next(e);) {
+  if (e >= Tn) continue;
   int4 nd = m.enodes[e];
   int code = (unsigned)nd.x >> kNodeBits;
   int n0 = nd.x & kNodeMask;
@@ -132,22 +160,37 @@ __global__ __launch_bounds__(kBlock) void k_strain(Mesh m, const double4* __rest
     out[5] = f * (g1z * d1x + g1x * d1z + g2z * d2x + g2x * d2z + g3z * d3x + g3x * d3z);
   }
   store6(veps + e, out);
+  }
 }
 
 // ---------------------------------------------------------------- edge stress pass
 
+// Sum of V_eff eps over the patch of edge k, in patch order.  Entry ids are
+// fetched in batches so that the element gathers of a batch are in flight
+// together.
 template <class R>
 __device__ __forceinline__ void edge_sum(const Mesh& m, const Six<R>* __restrict__ veps, int k,
                                          R* acc) {
+  constexpr int B = 6;
   int p0 = m.poff[k], p1 = m.poff[k + 1];
 #pragma unroll
   for (int i = 0; i < 6; ++i) acc[i] = 0;
-  for (int p = p0; p < p1; ++p) {
-    int e = m.pent[p];
-    if (e < 0) continue;
-    Six<R> s = load6(veps + e);
+  for (int base = p0; base < p1; base += B) {
+    int ids[B];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i] += s.v[i];
+    for (int j = 0; j < B; ++j) ids[j] = base + j < p1 ? m.pent[base + j] : -1;
+    Six<R> v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      if (ids[j] >= 0) v[j] = load6(veps + ids[j]);
+      else
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[j].v[i] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) acc[i] += v[j].v[i];
   }
 }
 
@@ -168,15 +211,18 @@ __global__ __launch_bounds__(kBlock) void k_edge_stress(Mesh m, const Six<R>* __
                                                         Six<R>* __restrict__ esig,
                                                         const Counters* __restrict__ c) {
   if (c->err) return;
-  int k = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (k >= edges_now(m, c)) return;
-  R acc[6], eps[6], sig[6];
-  edge_sum(m, veps, k, acc);
-  R iv = einvV[k];
+  const int En = edges_now(m, c);
+  Chunks it(En);
+  for (int k; it.next(k);) {
+    if (k >= En) continue;
+    R acc[6], eps[6], sig[6];
+    edge_sum(m, veps, k, acc);
+    R iv = einvV[k];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) eps[i] = acc[i] * iv;
-  hooke((R)m.lam, (R)m.mu, eps, sig);
-  store6(esig + k, sig);
+    for (int i = 0; i < 6; ++i) eps[i] = acc[i] * iv;
+    hooke((R)m.lam, (R)m.mu, eps, sig);
+    store6(esig + k, sig);
+  }
 }
 
 // Strain energy 1/2 sum_k V_k sigma_k . eps_k; V_k eps_k = acc_k / 6.
@@ -211,51 +257,139 @@ __global__ __launch_bounds__(kBlock) void k_strain_energy(Mesh m, const Six<R>* 
 
 // ---------------------------------------------------------------- node pass
 
-// For local node l the face opposite l is (a, b, c) with
-// 6 V grad N_l = (X_b - X_a) x (X_c - X_a).
-__device__ __forceinline__ void face_of(int l, int n0, int n1, int n2, int n3, int& a, int& b,
-                                        int& cc) {
-  a = (l == 0) ? n1 : n0;
-  b = (l == 0) ? n3 : (l == 1) ? n2 : (l == 2) ? n3 : n1;
-  cc = (l == 0) ? n2 : (l == 1) ? n3 : (l == 2) ? n1 : n2;
+// Element force pass: for element e with effective volume fraction f,
+//   c_{e,l} = (V_eff / 6) B_l^T sum_{k in edges(e)} sigma_k = (f / 36) G_l^T s,
+// G_l = 6 V grad N_l (face cross products; G_0 = -(G_1 + G_2 + G_3)).  The
+// four 3-vectors (padded to 4) are stored at the element's positions in the
+// node lists (epos), so the node pass reads each node's terms contiguously.
+// More tets flagged than split capacity left: raise the error before the
+// force passes touch the state, so it stays at the start of the step.
+__device__ __forceinline__ bool over_capacity(const Mesh& m, Counters* c) {
+  if (c->n_flag <= m.S_cap - c->n_split) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->err = -5;
+  return true;
 }
 
-template <class R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const Six<R>* __restrict__ esig,
-                                                 double4* __restrict__ fout,
-                                                 Counters* __restrict__ c) {
-  if (c->err) return;
-  int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (i >= nodes_now(m, c)) return;
-  double fx = 0, fy = 0, fz = 0;
-  int p0 = m.noff[i], p1 = m.noff[i + 1];
-  for (int p = p0; p < p1; ++p) {
-    int ent = m.nent[p];
-    int e = ent >> 2, l = ent & 3;
-    int4 nd = m.enodes[e];
-    int code = (unsigned)nd.x >> kNodeBits;
-    if (code == FR_ZERO) continue;
-    int n0 = nd.x & kNodeMask;
-    int a, b, cc;
-    face_of(l, n0, nd.y, nd.z, nd.w, a, b, cc);
-    double4 xa = m.X[a], xb = m.X[b], xc = m.X[cc];
-    R bx = (R)(xb.x - xa.x), by = (R)(xb.y - xa.y), bz = (R)(xb.z - xa.z);
-    R cx = (R)(xc.x - xa.x), cy = (R)(xc.y - xa.y), cz = (R)(xc.z - xa.z);
-    R gx = by * cz - bz * cy, gy = bz * cx - bx * cz, gz = bx * cy - by * cx;
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_elem_force(Mesh m, const Six<R>* __restrict__ esig,
+                                                       R* __restrict__ contrib,
+                                                       Counters* __restrict__ c) {
+  if (c->err || over_capacity(m, c)) return;
+  const int Tn = elems_now(m, c);
+  Chunks it(Tn);
+  for (int e; it.next(e);) {
+  if (e >= Tn) continue;
+  int4 nd = m.enodes[e];
+  int4 pos = m.epos[e];
+  int code = (unsigned)nd.x >> kNodeBits;
+  R out[4][3];
+  if (code == FR_ZERO) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) out[l][0] = out[l][1] = out[l][2] = 0;
+  } else {
     int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
+    double4 x0 = m.X[nd.x & kNodeMask], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
     Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
     Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
-    R s[6];
+    R c1x = (R)(x1.x - x0.x), c1y = (R)(x1.y - x0.y), c1z = (R)(x1.z - x0.z);
+    R c2x = (R)(x2.x - x0.x), c2y = (R)(x2.y - x0.y), c2z = (R)(x2.z - x0.z);
+    R c3x = (R)(x3.x - x0.x), c3y = (R)(x3.y - x0.y), c3z = (R)(x3.z - x0.z);
+    R g[4][3];
+    g[1][0] = c2y * c3z - c2z * c3y; g[1][1] = c2z * c3x - c2x * c3z; g[1][2] = c2x * c3y - c2y * c3x;
+    g[2][0] = c3y * c1z - c3z * c1y; g[2][1] = c3z * c1x - c3x * c1z; g[2][2] = c3x * c1y - c3y * c1x;
+    g[3][0] = c1y * c2z - c1z * c2y; g[3][1] = c1z * c2x - c1x * c2z; g[3][2] = c1x * c2y - c1y * c2x;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) s[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    R sg[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
     R w = (R)(frac_of(code) / 36.0);
-    fx += (double)(w * (gx * s[0] + gy * s[3] + gz * s[5]));
-    fy += (double)(w * (gy * s[1] + gx * s[3] + gz * s[4]));
-    fz += (double)(w * (gz * s[2] + gy * s[4] + gx * s[5]));
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      R gx = g[l][0], gy = g[l][1], gz = g[l][2];
+      out[l][0] = w * (gx * sg[0] + gy * sg[3] + gz * sg[5]);
+      out[l][1] = w * (gy * sg[1] + gx * sg[3] + gz * sg[4]);
+      out[l][2] = w * (gz * sg[2] + gy * sg[4] + gx * sg[5]);
+    }
   }
+  typedef typename Vec4<R>::T R4;
+  R4* o = (R4*)contrib;
+  o[pos.x] = Vec4<R>::make(out[0][0], out[0][1], out[0][2]);
+  o[pos.y] = Vec4<R>::make(out[1][0], out[1][1], out[1][2]);
+  o[pos.z] = Vec4<R>::make(out[2][0], out[2][1], out[2][2]);
+  o[pos.w] = Vec4<R>::make(out[3][0], out[3][1], out[3][2]);
+  }
+}
+
+// Fused node pass (one kernel): G lanes per node; for each (element, local)
+// entry of the node the lane recomputes that element's term
+// (f / 36) G_l^T sum_{k in edges(e)} sigma_k from the face opposite l.
+template <class R>
+__device__ __forceinline__ void entry_force(const Mesh& m, const Six<R>* __restrict__ esig, int ent,
+                                            double& fx, double& fy, double& fz) {
+  int e = ent >> 2, l = ent & 3;
+  int4 nd = m.enodes[e];
+  int code = (unsigned)nd.x >> kNodeBits;
+  if (code == FR_ZERO) return;
+  int n0 = nd.x & kNodeMask;
+  // face opposite l as (a, b, c) with G_l = (X_b - X_a) x (X_c - X_a)
+  int a = (l == 0) ? nd.y : n0;
+  int b = (l == 0) ? nd.w : (l == 1) ? nd.z : (l == 2) ? nd.w : nd.y;
+  int cc = (l == 0) ? nd.z : (l == 1) ? nd.w : (l == 2) ? nd.y : nd.z;
+  int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
+  double4 xa = m.X[a], xb = m.X[b], xc = m.X[cc];
+  Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
+  Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+  R bx = (R)(xb.x - xa.x), by = (R)(xb.y - xa.y), bz = (R)(xb.z - xa.z);
+  R cx = (R)(xc.x - xa.x), cy = (R)(xc.y - xa.y), cz = (R)(xc.z - xa.z);
+  R gx = by * cz - bz * cy, gy = bz * cx - bx * cz, gz = bx * cy - by * cx;
+  R sg[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
+  R w = (R)(frac_of(code) / 36.0);
+  fx += (double)(w * (gx * sg[0] + gy * sg[3] + gz * sg[5]));
+  fy += (double)(w * (gy * sg[1] + gx * sg[3] + gz * sg[4]));
+  fz += (double)(w * (gz * sg[2] + gy * sg[4] + gx * sg[5]));
+}
+
+// Node pass: G lanes per node sum the node's contributions (lane g takes
+// entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
+// the sum is the same on every run), then the Newmark update.
+template <class R, int MODE, int G, int FUSED>
+__global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __restrict__ contrib,
+                                                 const Six<R>* __restrict__ esig,
+                                                 double4* __restrict__ fout,
+                                                 Counters* __restrict__ c) {
+  if (c->err || over_capacity(m, c)) return;
+  const int Nn = nodes_now(m, c);
+  Chunks it((long long)Nn * G);
+  const int g = (int)threadIdx.x % G;
+  for (int item; it.next(item);) {
+  const int i = item / G;
+  const bool active = i < Nn;
+  double fx = 0, fy = 0, fz = 0;
+  const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
+  typedef typename Vec4<R>::T R4;
+  for (int p = p0 + g; p < p1; p += G) {
+    if (FUSED) {
+      entry_force<R>(m, esig, m.nent[p], fx, fy, fz);
+    } else {
+      R4 q = ((const R4*)contrib)[p];
+      fx += (double)q.x;
+      fy += (double)q.y;
+      fz += (double)q.z;
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    fx += __shfl_xor(fx, off, G);
+    fy += __shfl_xor(fy, off, G);
+    fz += __shfl_xor(fz, off, G);
+  }
+  if (!active || g != 0) continue;
   if (MODE == NODE_FORCE) {
     fout[i] = make_double4(fx, fy, fz, 0.0);
-    return;
+    continue;
   }
   const double dt = m.dt;
   const long long n = c->step;
@@ -270,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const Six<R>*
     double h = 0.5 * dt * dt;
     st.uh[i] = make_double4(u0.x + dt * v0.x + h * ax, u0.y + dt * v0.y + h * ay,
                             u0.z + dt * v0.z + h * az, 0.0);
-    return;
+    continue;
   }
   // NODE_STEP: f was evaluated at u_{n+1} = uh
   double r0 = ramp(m, (double)n * dt), r1 = ramp(m, (double)(n + 1) * dt);
@@ -291,6 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const Six<R>*
   bool bad = !(fabs(ax) <= DBL_MAX && fabs(ay) <= DBL_MAX && fabs(az) <= DBL_MAX) ||
              !(fabs(u1.x) <= m.umax && fabs(u1.y) <= m.umax && fabs(u1.z) <= m.umax);
   if (bad) atomicCAS(&c->err, 0, -6);
+  }
 }
 
 // ---------------------------------------------------------------- crack pass
@@ -397,6 +532,12 @@ __device__ void front_rates(const Mesh& m, const double4* __restrict__ u,
   double e2x = X3.x - X2.x, e2y = X3.y - X2.y, e2z = X3.z - X2.z;
   double s2 = 2.0 * (e2x * d2x + e2y * d2y + e2z * d2z) + (d2x * d2x + d2y * d2y + d2z * d2z);
   if (!(s2 > 0.0)) { d2x = 0; d2y = 0; d2z = 0; }
+  if (d1x == 0 && d1y == 0 && d1z == 0 && d2x == 0 && d2y == 0 && d2z == 0) {
+    GI = GII = 0.0;  // neither front edge lengthens
+    maskI = (1 << l2) | (1 << l4);
+    maskII = (1 << l2);
+    return;
+  }
   // crack normals: pattern I plane spanned by N1N3 and N2N4, pattern II parallel to N1N3N4
   double ax = X3.x - X1.x, ay = X3.y - X1.y, az = X3.z - X1.z;
   double bx = X4.x - X2.x, by = X4.y - X2.y, bz = X4.z - X2.z;
@@ -429,8 +570,10 @@ __device__ __forceinline__ void load_tet(const Mesh& m, int t, int* nd, int* ed)
   ed[0] = a.x; ed[1] = a.y; ed[2] = b.x; ed[3] = b.y; ed[4] = cc.x; ed[5] = cc.y;
 }
 
-// One thread per candidate: best (G, face, pattern) with ties to the lower
-// face, then pattern I; Griffith test G >= Gc flags the tet.
+// Four lanes per candidate, one per local face: each evaluates its front (if
+// any); lane 0 of the group then takes the best (G, face, pattern) in face
+// order, ties to the lower face and to pattern I.  The Griffith test
+// G >= Gc flags the tet: it is appended to the (unordered) split list.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_front(Mesh m, const double4* __restrict__ u,
                                                   const Six<R>* __restrict__ esig,
@@ -438,35 +581,52 @@ __global__ __launch_bounds__(kBlock) void k_front(Mesh m, const double4* __restr
   if (c->err) return;
   __shared__ unsigned long long red[kBlock];
   unsigned long long kmax = 0;
-  int nc = c->n_cand;
-  for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < nc; idx += gridDim.x * kBlock) {
-    int t = m.cand[idx];
-    if (m.smask[t] >= 0) continue;
-    int4 fr = m.front[t];
-    int frs[4] = {fr.x, fr.y, fr.z, fr.w};
-    int nd[4], ed[6];
-    load_tet<R>(m, t, nd, ed);
+  const int nc = c->n_cand;
+  const int room = m.S_cap - c->n_split;
+  const int f = threadIdx.x & 3;
+  constexpr int cpb = kBlock / 4;
+  for (int base = blockIdx.x * cpb; base < nc; base += gridDim.x * cpb) {
+    int idx = base + (int)threadIdx.x / 4;
+    int t = idx < nc ? m.cand[idx] : -1;
+    bool act = t >= 0 && m.smask[t] < 0;
+    int lone = act ? ((const int*)m.front)[4 * t + f] : -1;
+    double GI = -INFINITY, GII = -INFINITY;
+    int mI = 0, mII = 0;
+    if (lone >= 0) {
+      int nd[4], ed[6];
+      load_tet<R>(m, t, nd, ed);
+      front_rates<R>(m, u, esig, nd, ed, f, lone, GI, GII, mI, mII);
+    }
+    double gI[4], gII[4];
+    int mi[4], mii[4], has[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      gI[q] = __shfl(GI, q, 4);
+      gII[q] = __shfl(GII, q, 4);
+      mi[q] = __shfl(mI, q, 4);
+      mii[q] = __shfl(mII, q, 4);
+      has[q] = __shfl(lone, q, 4) >= 0;
+    }
+    if (f != 0 || !act) continue;
     double best = -INFINITY;
     int bmask = 0, bpat = 0;
     bool any = false;
-    for (int f = 0; f < 4; ++f) {
-      if (frs[f] < 0) continue;
-      double GI, GII;
-      int mI, mII;
-      front_rates<R>(m, u, esig, nd, ed, f, frs[f], GI, GII, mI, mII);
-      if (!any || GI > best) { best = GI; bmask = mI; bpat = 1; }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!has[q]) continue;
+      if (!any || gI[q] > best) { best = gI[q]; bmask = mi[q]; bpat = 1; }
       any = true;
-      if (GII > best) { best = GII; bmask = mII; bpat = 2; }
+      if (gII[q] > best) { best = gII[q]; bmask = mii[q]; bpat = 2; }
     }
     if (!any) continue;
     unsigned long long k = dkey(best);
     kmax = k > kmax ? k : kmax;
     if (flagging && best >= m.Gc) {
-      m.flag[t] = 1;
       m.pmask[t] = (uint8_t)bmask;
       m.ppat[t] = (uint8_t)bpat;
       m.pG[t] = best;
-      atomicAdd(&c->n_flag, 1);
+      int slot = atomicAdd(&c->n_flag, 1);
+      if (slot < room) m.splitlist[slot] = t;  // unordered; the topology pass sorts
     }
   }
   red[threadIdx.x] = kmax;
@@ -520,89 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_count_fronts(Mesh m, const Counters*
   if (cnt) atomicAdd(out, cnt);
 }
 
-// ---------------------------------------------------------------- compaction
-
-__device__ __forceinline__ int count_flags(uint4 w) {
-  unsigned x[4] = {w.x, w.y, w.z, w.w};
-  int n = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) n += ((x[i] >> (8 * b)) & 0xff) != 0;
-  return n;
-}
-
-__device__ int block_exclusive_scan(int v, int* sh, int& total) {
-  int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    int x = tid >= off ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += x;
-    __syncthreads();
-  }
-  total = sh[kBlock - 1];
-  int r = sh[tid] - v;
-  __syncthreads();
-  return r;
-}
-
-// Per-block flag counts; the last block to finish turns them into offsets
-// and checks the split capacity.
-__global__ __launch_bounds__(kBlock) void k_compact_count(Mesh m, Counters* __restrict__ c) {
-  if (c->err || c->n_flag == 0) return;
-  __shared__ int sh[kBlock];
-  __shared__ int last;
-  const uint4* f4 = (const uint4*)m.flag;
-  uint4 w = f4[(size_t)blockIdx.x * kBlock + threadIdx.x];
-  int total;
-  block_exclusive_scan(count_flags(w), sh, total);
-  if (threadIdx.x == 0) {
-    m.bcount[blockIdx.x] = total;
-    __threadfence();
-    last = (atomicAdd(&c->ticket, 1) == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // exclusive scan of the block counts, in chunks of kBlock
-  int nb = gridDim.x;
-  int carry = 0;
-  for (int base = 0; base < nb; base += kBlock) {
-    int idx = base + threadIdx.x;
-    int v = idx < nb ? atomicAdd(&m.bcount[idx], 0) : 0;
-    int tot;
-    int ex = block_exclusive_scan(v, sh, tot);
-    if (idx < nb) m.bcount[idx] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    c->ticket = 0;
-    if (c->n_split + carry > m.S_cap) c->err = -5;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_compact_write(Mesh m, Counters* __restrict__ c) {
-  if (c->n_flag == 0) return;
-  __shared__ int sh[kBlock];
-  uint4* f4 = (uint4*)m.flag;
-  size_t wi = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  uint4 w = f4[wi];
-  int total;
-  int ex = block_exclusive_scan(count_flags(w), sh, total);
-  if (total == 0) return;
-  f4[wi] = make_uint4(0, 0, 0, 0);
-  if (c->err) return;
-  int pos = m.bcount[blockIdx.x] + ex;
-  unsigned x[4] = {w.x, w.y, w.z, w.w};
-  int t0 = (int)(wi * 16);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if ((x[i] >> (8 * b)) & 0xff) m.splitlist[pos++] = t0 + 4 * i + b;
-}
+// ---------------------------------------------------------------- forced schedule
 
 // Forced schedule: the entries of the coming step, already sorted by tet.
 __global__ void k_replay_select(Mesh m, Counters* __restrict__ c) {
@@ -674,6 +752,62 @@ __device__ double crack_area(const Mesh& m, const int* nd, int mask) {
   return f * sqrt(cx * cx + cy * cy + cz * cz);
 }
 
+// Sort of the n tets in list[0, n) by one workgroup, ascending in the
+// caller's tet id key[t] (unique): rank sort in LDS up to kSortLds tets, else a
+// bitonic sort in global memory over list[0, P) (P = next power of two, padded
+// with -1 entries that sort last; the list has room).
+constexpr int kSortLds = 2048;
+
+__device__ __forceinline__ int sort_key(const int* key, int t) { return t < 0 ? 0x7fffffff : key[t]; }
+
+__device__ void block_sort(int* list, int n, const int* key, int* shk, int* shv) {
+  const int tid = threadIdx.x;
+  if (n <= 1) return;
+  if (n <= kSortLds) {
+    for (int i = tid; i < n; i += kTopoBlock) {
+      int t = list[i];
+      shv[i] = t;
+      shk[i] = key[t];
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kTopoBlock) {
+      int v = shk[i], r = 0;
+      for (int j = 0; j < n; ++j) r += shk[j] < v;
+      list[r] = shv[i];
+    }
+    __threadfence_block();
+    __syncthreads();
+    return;
+  }
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int i = n + tid; i < P; i += kTopoBlock) list[i] = -1;
+  __threadfence_block();
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += kTopoBlock) {
+        int ixj = i ^ j;
+        if (ixj > i) {
+          int a = list[i], b = list[ixj];
+          bool up = (i & k) == 0;
+          if ((sort_key(key, a) > sort_key(key, b)) == up) {
+            list[i] = b;
+            list[ixj] = a;
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // All splits of one step, applied by one workgroup in phases separated by
 // barriers.  Split i of this batch gets global index s = n_split + i; its
 // copy B takes element slot T0 + s, its extra nodes N0 + 4 s + l and its new
@@ -684,7 +818,9 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
                                                          int advance, int4* __restrict__ snodes,
                                                          int* __restrict__ sedges) {
   __shared__ int s_n, s_base;
+  __shared__ int shk[kSortLds], shv[kSortLds];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = kTopoBlock / 64;
   if (tid == 0) {
     s_n = c->err ? 0 : c->n_flag;
     s_base = c->n_split;
@@ -693,7 +829,9 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
   const int n = s_n, base = s_base;
   R* einvV = (R*)w.einvV;
   if (n > 0) {
-    // phase 0: record, keep the parent's real nodes and edges, mark split
+    if (dynamic) block_sort(m.splitlist, n, m.tet_ext, shk, shv);
+    // phases 0 + 1, one thread per split: record the split, keep the parent's
+    // real nodes and edges, then rewrite elements, edges and node lists
     for (int i = tid; i < n; i += kTopoBlock) {
       int t = m.splitlist[i];
       int mask = m.pmask[t];
@@ -709,25 +847,19 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       m.rec_pat[s] = dynamic ? m.ppat[t] : 0;
       m.rec_G[s] = dynamic ? m.pG[t] : 0.0;
       m.area[i] = dynamic ? crack_area(m, nd, mask) : 0.0;
-    }
-    __syncthreads();
-    // phase 1: element, edge and node-list rewrites
-    for (int i = tid; i < n; i += kTopoBlock) {
-      int t = m.splitlist[i];
-      int mask = m.pmask[t];
-      int4 q4 = snodes[i];
-      int nd[4] = {q4.x, q4.y, q4.z, q4.w};
       if (m.mode == MODE_ERODE) {
         m.enodes[t] = make_int4(pack0(nd[0], FR_ZERO), nd[1], nd[2], nd[3]);
         continue;
       }
-      int s = base + i;
       int tb = m.T0 + s;
       int nb = __popc(mask);
       int codeA = code_for_side(4 - nb), codeB = code_for_side(nb);
-      int na[4], nbn[4];
+      int4 op4 = m.epos[t];
+      const int op[4] = {op4.x, op4.y, op4.z, op4.w};
+      int na[4], nbn[4], pa[4], pb[4];
       for (int l = 0; l < 4; ++l) {
         int x = m.N0 + 4 * s + l;
+        int xe = 4 * m.T0 + 4 * s + l;  // the extra node's single list entry
         m.X[x] = m.X[nd[l]];
         st.u[x] = st.u[nd[l]];
         st.v[x] = st.v[nd[l]];
@@ -737,23 +869,25 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
         bool onB = (mask >> l) & 1;
         na[l] = onB ? x : nd[l];
         nbn[l] = onB ? nd[l] : x;
+        pa[l] = onB ? xe : op[l];
+        pb[l] = onB ? op[l] : xe;
         int owner = onB ? t : tb;  // the copy that holds the extra node
-        m.nent[4 * m.T0 + 4 * s + l] = (owner << 2) | l;
-        if (onB) {
-          const int* np = (const int*)&m.nodepos[t];
-          m.nent[np[l]] = (tb << 2) | l;
-        }
+        m.nent[xe] = (owner << 2) | l;
+        if (onB) m.nent[op[l]] = (tb << 2) | l;
       }
       m.enodes[t] = make_int4(pack0(na[0], codeA), na[1], na[2], na[3]);
       m.enodes[tb] = make_int4(pack0(nbn[0], codeB), nbn[1], nbn[2], nbn[3]);
-      double V = tet_volume(m.X[nd[0]], m.X[nd[1]], m.X[nd[2]], m.X[nd[3]]);
+      m.epos[t] = make_int4(pa[0], pa[1], pa[2], pa[3]);
+      m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
+      double V = m.vol[t];
+      m.vol[tb] = V;
       R ivA = (R)(1.0 / (frac_of(codeA) * V)), ivB = (R)(1.0 / (frac_of(codeB) * V));
       int eA[6], eB[6];
       int r = 0;
       int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
       const int* pp = (const int*)&m.patchpos[3 * t];
       for (int q = 0; q < 6; ++q) {
-        int k = sedges[6 * i + q];
+        int k = ed[q];
         int ba = (mask >> kEA[q]) & 1, bb = (mask >> kEB[q]) & 1;
         if (!ba && !bb) {          // both nodes on side A: copy A keeps edge k
           eA[q] = k;
@@ -777,40 +911,40 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
     }
     __threadfence_block();
     __syncthreads();
-    // phase 2: lumped masses of touched nodes and volumes of touched edges
-    for (int i = tid; i < n; i += kTopoBlock) {
-      int4 q4 = snodes[i];
-      int nd[4] = {q4.x, q4.y, q4.z, q4.w};
-      if (m.mode == MODE_PHANTOM) {
-        int s = base + i;
-        int mask = m.pmask[m.splitlist[i]];
-        int nb = __popc(mask);
-        double V = tet_volume(m.X[nd[0]], m.X[nd[1]], m.X[nd[2]], m.X[nd[3]]);
-        for (int l = 0; l < 4; ++l) {
-          int node = nd[l];
-          double ms = 0;
-          for (int p = m.noff[node]; p < m.noff[node + 1]; ++p) {
-            int e = m.nent[p] >> 2;
-            int4 en = m.enodes[e];
-            ms += m.rho * frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en) / 4.0;
-          }
-          m.invm[node] = ms > 0 ? 1.0 / ms : 0.0;
+    // phase 2: lumped masses of touched nodes, volumes of touched edges; one
+    // wave per item, lanes over the list, fixed-order wave sum
+    if (m.mode == MODE_PHANTOM) {
+      for (int item = wave; item < 4 * n; item += nwaves) {
+        int i = item >> 2, l = item & 3;
+        int4 q4 = snodes[i];
+        int node = l == 0 ? q4.x : l == 1 ? q4.y : l == 2 ? q4.z : q4.w;
+        double part = 0;
+        for (int p = m.noff[node] + lane; p < m.noff[node + 1]; p += 64) {
+          int e = m.nent[p] >> 2;
+          part += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
+        }
+        part = wave_sum(part);
+        if (lane == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
+        if (lane == 1) {
+          int t = m.splitlist[i];
+          int mask = m.pmask[t];
+          int nbB = __popc(mask);
           bool onB = (mask >> l) & 1;
-          double fo = frac_of(code_for_side(onB ? 4 - nb : nb));  // owner copy's fraction
-          m.invm[m.N0 + 4 * s + l] = 1.0 / (m.rho * fo * V / 4.0);
+          // the extra node of l belongs to the copy of the other side
+          double fo = frac_of(code_for_side(onB ? 4 - nbB : nbB));
+          m.invm[m.N0 + 4 * (base + i) + l] = 1.0 / (m.rho * fo * m.vol[t] / 4.0);
         }
       }
-      for (int q = 0; q < 6; ++q) {
-        int k = sedges[6 * i + q];
-        double S = 0;
-        for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
-          int e = m.pent[p];
-          if (e < 0) continue;
-          int4 en = m.enodes[e];
-          S += frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en);
-        }
-        einvV[k] = S > 0 ? (R)(1.0 / S) : (R)0;
+    }
+    for (int item = wave; item < 6 * n; item += nwaves) {
+      int k = sedges[item];
+      double part = 0;
+      for (int p = m.poff[k] + lane; p < m.poff[k + 1]; p += 64) {
+        int e = m.pent[p];
+        if (e >= 0) part += frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
       }
+      part = wave_sum(part);
+      if (lane == 0) einvV[k] = part > 0 ? (R)(1.0 / part) : (R)0;
     }
     // phase 3: new crack fronts on intact face neighbours
     for (int i = tid; i < n; i += kTopoBlock) {
@@ -856,6 +990,12 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
 
 // ---------------------------------------------------------------- setup
 
+__global__ __launch_bounds__(kBlock) void k_volumes(Mesh m) {
+  int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= m.T0) return;
+  m.vol[e] = elem_volume(m, m.enodes[e]);
+}
+
 // Lumped mass m_i = sum rho V_eff / 4 over the elements holding node i.
 __global__ __launch_bounds__(kBlock) void k_masses(Mesh m) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -863,8 +1003,7 @@ __global__ __launch_bounds__(kBlock) void k_masses(Mesh m) {
   double ms = 0;
   for (int p = m.noff[i]; p < m.noff[i + 1]; ++p) {
     int e = m.nent[p] >> 2;
-    int4 en = m.enodes[e];
-    ms += m.rho * frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en) / 4.0;
+    ms += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
   }
   m.invm[i] = ms > 0 ? 1.0 / ms : 0.0;
 }
@@ -877,8 +1016,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_volumes(Mesh m, R* einvV) {
   for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
     int e = m.pent[p];
     if (e < 0) continue;
-    int4 en = m.enodes[e];
-    S += frac_of((unsigned)en.x >> kNodeBits) * elem_volume(m, en);
+    S += frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
   }
   einvV[k] = S > 0 ? (R)(1.0 / S) : (R)0;
 }
@@ -1065,25 +1203,34 @@ __global__ __launch_bounds__(kBlock) void k_sum(const double* __restrict__ x, in
 int grid_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 double key_to_double_host(unsigned long long k) { return key_to_double(k); }
 
+// Persistent grid: enough workgroups for the largest item count the launch
+// can see (capacity), capped at kPersistentBlocks; always a multiple of 8.
+static int persistent_grid(long long items) {
+  long long g = (items + kBlock - 1) / kBlock;
+  g = g < 8 ? 8 : g;
+  g = g > kPersistentBlocks ? kPersistentBlocks : g;
+  return (int)((g + 7) / 8 * 8);
+}
+
 template <class R>
 hipError_t Launch<R>::strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
                              hipStream_t s) {
-  int T = m.mode == MODE_PHANTOM ? m.T_cap : m.T0;
-  hipLaunchKernelGGL(k_strain<R>, dim3(grid_for(T)), dim3(kBlock), 0, s, m, u,
+  hipLaunchKernelGGL(k_strain<R>, dim3(persistent_grid(m.T_cap)), dim3(kBlock), 0, s, m, u,
                      (Six<R>*)w.veps, c);
   return hipGetLastError();
 }
 
 template <class R>
 hipError_t Launch<R>::edge_stress(const Mesh& m, const Work& w, Counters* c, hipStream_t s) {
-  hipLaunchKernelGGL(k_edge_stress<R>, dim3(grid_for(m.E_cap)), dim3(kBlock), 0, s, m,
+  hipLaunchKernelGGL(k_edge_stress<R>, dim3(persistent_grid(m.E_cap)), dim3(kBlock), 0, s, m,
                      (const Six<R>*)w.veps, (const R*)w.einvV, (Six<R>*)w.esig, c);
   return hipGetLastError();
 }
 
+// The candidate list is short next to the mesh: a small grid-stride grid.
 static int front_grid(const Mesh& m) {
   int g = grid_for(m.T0);
-  return g < 1 ? 1 : (g > 512 ? 512 : g);
+  return g < 1 ? 1 : (g > 64 ? 64 : g);
 }
 
 template <class R>
@@ -1105,14 +1252,20 @@ hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, 
 template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                            double4* fout, hipStream_t s) {
-  dim3 g(grid_for(m.N_cap)), b(kBlock);
-  const Six<R>* sig = (const Six<R>*)w.esig;
+  constexpr int G = kNodeLanes;
+  constexpr int FU = CEM_NODE_FUSED;
+  if (!FU)
+    hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m.T_cap)), dim3(kBlock), 0, s, m,
+                       (const Six<R>*)w.esig, (R*)w.contrib, c);
+  dim3 g(persistent_grid((long long)m.N_cap * G)), b(kBlock);
+  const R* ct = (const R*)w.contrib;
+  const Six<R>* sg = (const Six<R>*)w.esig;
   if (mode == NODE_FORCE)
-    hipLaunchKernelGGL((k_node<R, NODE_FORCE>), g, b, 0, s, m, st, sig, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, FU>), g, b, 0, s, m, st, ct, sg, fout, c);
   else if (mode == NODE_INIT)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT>), g, b, 0, s, m, st, sig, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, FU>), g, b, 0, s, m, st, ct, sg, fout, c);
   else
-    hipLaunchKernelGGL((k_node<R, NODE_STEP>), g, b, 0, s, m, st, sig, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, FU>), g, b, 0, s, m, st, ct, sg, fout, c);
   return hipGetLastError();
 }
 
@@ -1149,13 +1302,6 @@ template hipError_t launch_topology_t<double>(const Mesh&, const State&, const W
 template hipError_t launch_topology_t<float>(const Mesh&, const State&, const Work&, Counters*, int,
                                              int, int4*, int*, hipStream_t);
 
-hipError_t launch_compact(const Mesh& m, Counters* c, hipStream_t s) {
-  int nb = (m.T0 + kCompactTile - 1) / kCompactTile;
-  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, s, m, c);
-  hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(kBlock), 0, s, m, c);
-  return hipGetLastError();
-}
-
 hipError_t launch_replay_select(const Mesh& m, Counters* c, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_select, dim3(1), dim3(64), 0, s, m, c);
   return hipGetLastError();
@@ -1171,6 +1317,7 @@ hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, cons
 }
 
 hipError_t launch_masses(const Mesh& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_volumes, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m);
   hipLaunchKernelGGL(k_masses, dim3(grid_for(m.N0)), dim3(kBlock), 0, s, m);
   return hipGetLastError();
 }

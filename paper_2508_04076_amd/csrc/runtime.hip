@@ -46,9 +46,13 @@ struct cem_ctx {
   bool bound = false;
   bool own_stream = false;
 
-  // host mirrors
+  // host mirrors (internal numbering)
   std::vector<double> X;       // 3 N0
   std::vector<int> tets;       // 4 T0, oriented
+  // the library renumbers nodes and tets for locality; the API keeps the
+  // caller's numbering
+  std::vector<int> node_new, node_old;  // [N0]
+  std::vector<int> tet_new, tet_old;    // [T0]
   std::vector<char> split_host;
   int n_split_host = 0;
   long long step_host = 0;
@@ -181,6 +185,106 @@ int check_orient(cem_ctx* c, int N, const double* X, int T, std::vector<int>& te
   return CEM_OK;
 }
 
+// Reverse Cuthill-McKee order of the node graph (nodes joined by tet edges),
+// one component at a time from a pseudo-peripheral node, neighbours visited by
+// increasing degree.  Gives every tet nearby node ids, so the gathers of the
+// step kernels reuse cache lines.
+void rcm_order(int N, int T, const std::vector<int>& tets, std::vector<int>& new_of_old) {
+  size_t M = (size_t)6 * T;
+  std::vector<uint64_t> key(M);
+  std::vector<uint32_t> val(M, 0);
+  for (int t = 0; t < T; ++t)
+    for (int q = 0; q < 6; ++q) {
+      uint64_t a = (uint32_t)tets[4 * t + kLE[q][0]], b = (uint32_t)tets[4 * t + kLE[q][1]];
+      if (a > b) std::swap(a, b);
+      key[(size_t)6 * t + q] = (a << 32) | b;
+    }
+  int nb = bits_for((uint64_t)std::max(N - 1, 1));
+  for (size_t i = 0; i < M; ++i) key[i] = (key[i] >> 32 << nb) | (key[i] & 0xffffffffull);
+  radix_sort(key, val, 2 * nb);
+  std::vector<int> deg(N, 0);
+  size_t E = 0;
+  for (size_t i = 0; i < M; ++i) {
+    if (i > 0 && key[i] == key[i - 1]) continue;
+    key[E++] = key[i];
+  }
+  key.resize(E);
+  const uint64_t lo_mask = (1ull << nb) - 1;
+  for (size_t i = 0; i < E; ++i) {
+    deg[key[i] >> nb]++;
+    deg[key[i] & lo_mask]++;
+  }
+  std::vector<size_t> off(N + 1, 0);
+  for (int i = 0; i < N; ++i) off[i + 1] = off[i] + deg[i];
+  std::vector<int> adj(off[N]);
+  std::vector<size_t> fill(off.begin(), off.end() - 1);
+  for (size_t i = 0; i < E; ++i) {
+    int a = (int)(key[i] >> nb), b = (int)(key[i] & lo_mask);
+    adj[fill[a]++] = b;
+    adj[fill[b]++] = a;
+  }
+  std::vector<int> level(N, -1), order;
+  order.reserve(N);
+  std::vector<char> done(N, 0);
+  std::vector<int> queue;
+  queue.reserve(N);
+  // BFS levels from s over unvisited nodes; returns the last node of the
+  // deepest level with the smallest degree, and the depth
+  auto bfs = [&](int s0, int& depth) {
+    queue.clear();
+    queue.push_back(s0);
+    level[s0] = 0;
+    size_t h = 0;
+    while (h < queue.size()) {
+      int v = queue[h++];
+      for (size_t p = off[v]; p < off[v + 1]; ++p) {
+        int w = adj[p];
+        if (level[w] < 0 && !done[w]) {
+          level[w] = level[v] + 1;
+          queue.push_back(w);
+        }
+      }
+    }
+    depth = level[queue.back()];
+    int best = queue.back();
+    for (int v : queue)
+      if (level[v] == depth && deg[v] < deg[best]) best = v;
+    for (int v : queue) level[v] = -1;
+    return best;
+  };
+  std::vector<int> nbrs;
+  for (int s0 = 0; s0 < N; ++s0) {
+    if (done[s0]) continue;
+    int depth = 0, d2 = 0;
+    int start = bfs(s0, depth);
+    for (int it = 0; it < 4; ++it) {
+      int nxt = bfs(start, d2);
+      if (d2 <= depth) break;
+      depth = d2;
+      start = nxt;
+    }
+    // Cuthill-McKee sweep
+    size_t h = order.size();
+    order.push_back(start);
+    done[start] = 1;
+    while (h < order.size()) {
+      int v = order[h++];
+      nbrs.clear();
+      for (size_t p = off[v]; p < off[v + 1]; ++p)
+        if (!done[adj[p]]) nbrs.push_back(adj[p]);
+      std::sort(nbrs.begin(), nbrs.end(), [&](int x, int y) {
+        return deg[x] != deg[y] ? deg[x] < deg[y] : x < y;
+      });
+      for (int w : nbrs) {
+        done[w] = 1;
+        order.push_back(w);
+      }
+    }
+  }
+  new_of_old.assign(N, 0);
+  for (int k = 0; k < N; ++k) new_of_old[order[N - 1 - k]] = k;
+}
+
 int build_topology(cem_ctx* c, int N, int T, const std::vector<int>& tets, HostTopo& h) {
   // edges: sort (min, max) node-pair keys of every (tet, local edge)
   size_t M = (size_t)6 * T;
@@ -292,6 +396,8 @@ int read_counters(cem_ctx* c) {
 int check_device_error(cem_ctx* c) {
   int r = read_counters(c);
   if (r) return r;
+  c->n_split_host = c->h_ctr->n_split;
+  c->step_host = c->h_ctr->step;
   int e = c->h_ctr->err;
   if (e) {
     int zero = 0;
@@ -353,7 +459,6 @@ int enqueue_step(cem_ctx* c, hipEvent_t* ev) {
     if (c->mixed) HIPCHK(c, Launch<float>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
     else HIPCHK(c, Launch<double>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
     if (replay) HIPCHK(c, launch_replay_select(c->m, c->d_ctr, s));
-    else HIPCHK(c, launch_compact(c->m, c->d_ctr, s));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
   int r = node_pass(c, NODE_STEP, nullptr);
@@ -400,20 +505,31 @@ int ensure_ready(cem_ctx* c, bool need_dt) {
   return CEM_OK;
 }
 
-void pad3(const double* src, std::vector<double4>& dst, int n) {
+// Host [n][3] arrays in the caller's node numbering <-> padded device rows
+// in the internal numbering (extra nodes N0 + 4 s + l keep their ids).
+int node_int(const cem_ctx* c, int i) { return i < c->m.N0 ? c->node_new[i] : i; }
+
+void pad3(const cem_ctx* c, const double* src, std::vector<double4>& dst, int n) {
   dst.resize(n);
-  for (int i = 0; i < n; ++i) dst[i] = make_double4(src[3 * i], src[3 * i + 1], src[3 * i + 2], 0.0);
+  for (int i = 0; i < n; ++i)
+    dst[node_int(c, i)] = make_double4(src[3 * i], src[3 * i + 1], src[3 * i + 2], 0.0);
 }
 
-void unpad3(const std::vector<double4>& src, double* dst, int n) {
+void unpad3(const cem_ctx* c, const std::vector<double4>& src, double* dst, int n) {
   for (int i = 0; i < n; ++i) {
-    dst[3 * i] = src[i].x;
-    dst[3 * i + 1] = src[i].y;
-    dst[3 * i + 2] = src[i].z;
+    const double4& q = src[node_int(c, i)];
+    dst[3 * i] = q.x;
+    dst[3 * i + 1] = q.y;
+    dst[3 * i + 2] = q.z;
   }
 }
 
 int nodes_now_host(cem_ctx* c) {
+  // the device counters are authoritative (splits happen inside cem_step)
+  if (read_counters(c) == CEM_OK) {
+    c->n_split_host = c->h_ctr->n_split;
+    c->step_host = c->h_ctr->step;
+  }
   return c->m.N0 + (c->m.mode == MODE_PHANTOM ? 4 * c->n_split_host : 0);
 }
 
@@ -465,10 +581,38 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
     if (tets[i] < 0 || tets[i] >= N) return c->fail(CEM_EMESH, "node id out of range");
   for (long long i = 0; i < (long long)N * 3; ++i)
     if (!std::isfinite(X[i])) return c->fail(CEM_EINVAL, "non-finite coordinate");
-  c->tets.assign(tets, tets + (size_t)4 * T);
-  c->X.assign(X, X + (size_t)3 * N);
-  int r = check_orient(c, N, X, T, c->tets);
+  std::vector<int> ext(tets, tets + (size_t)4 * T);
+  int r = check_orient(c, N, X, T, ext);
   if (r) return r;
+  // internal numbering: nodes in reverse Cuthill-McKee order, tets by their
+  // smallest new node id (stable in the caller's order)
+  rcm_order(N, T, ext, c->node_new);
+  c->node_old.assign(N, 0);
+  for (int i = 0; i < N; ++i) c->node_old[c->node_new[i]] = i;
+  {
+    std::vector<int> cnt(N + 1, 0), key(T);
+    for (int t = 0; t < T; ++t) {
+      int mn = N;
+      for (int l = 0; l < 4; ++l) mn = std::min(mn, c->node_new[ext[4 * t + l]]);
+      key[t] = mn;
+      cnt[mn + 1]++;
+    }
+    for (int i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    c->tet_new.assign(T, 0);
+    c->tet_old.assign(T, 0);
+    for (int t = 0; t < T; ++t) {
+      int nt = cnt[key[t]]++;
+      c->tet_new[t] = nt;
+      c->tet_old[nt] = t;
+    }
+  }
+  c->tets.assign((size_t)4 * T, 0);
+  for (int t = 0; t < T; ++t)
+    for (int l = 0; l < 4; ++l) c->tets[4 * (size_t)c->tet_new[t] + l] = c->node_new[ext[4 * t + l]];
+  c->X.assign((size_t)3 * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d) c->X[3 * (size_t)c->node_new[i] + d] = X[3 * (size_t)i + d];
+  X = c->X.data();
   HostTopo h;
   r = build_topology(c, N, T, c->tets, h);
   if (r) return r;
@@ -515,8 +659,8 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   c->stage = 1;  // allocations from here are released by cem_destroy
 
   const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
-  const size_t nflag = (size_t)((T + kCompactTile - 1) / kCompactTile) * kCompactTile;
-  int nb = (T + kCompactTile - 1) / kCompactTile;
+  size_t nsplit_list = 1;  // a power of two >= S (room for the bitonic sort)
+  while (nsplit_list < (size_t)std::max(S, 1)) nsplit_list <<= 1;
 #define ALLOC(ptr, n, ck) \
   if ((r = dalloc(c, &(ptr), (n), (ck)))) return r
   ALLOC(c->d_ctr, 1, true);
@@ -531,18 +675,18 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   ALLOC(m.lslot, m.N_cap, true);
   ALLOC(m.nbr, T, false);
   ALLOC(m.nbrface, T, false);
-  ALLOC(m.nodepos, T, false);
+  ALLOC(m.epos, m.T_cap, true);
+  ALLOC(m.tet_ext, T, false);
+  ALLOC(m.vol, m.T_cap, true);
   ALLOC(m.patchpos, (size_t)3 * T, false);
   ALLOC(m.front, T, true);
   ALLOC(m.smask, T, true);
-  ALLOC(m.flag, nflag, false);
   ALLOC(m.pmask, T, true);
   ALLOC(m.ppat, T, true);
   ALLOC(m.pG, T, true);
   ALLOC(m.cand, T, true);
   ALLOC(m.candf, T, true);
-  ALLOC(m.splitlist, std::max(S, 1), false);
-  ALLOC(m.bcount, nb, false);
+  ALLOC(m.splitlist, nsplit_list, false);
   ALLOC(m.area, std::max(S, 1), false);
   ALLOC(m.rec_step, std::max(S, 1), true);
   ALLOC(m.rec_tet, std::max(S, 1), true);
@@ -558,6 +702,8 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   c->w.esig = vb;
   ALLOC(vb, RS * (size_t)m.E_cap, true);
   c->w.einvV = vb;
+  ALLOC(vb, RS * 4 * ((size_t)4 * m.T_cap), false);
+  c->w.contrib = vb;
   ALLOC(c->w.partial, c->n_partial, false);
   ALLOC(c->d_out, 8, false);
   ALLOC(c->d_iout, 8, false);
@@ -603,12 +749,14 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   if ((r = upload(c, m.lslot, lsl.data(), lsl.size()))) return r;
   if ((r = upload(c, (int*)m.nbr, h.nbr.data(), h.nbr.size()))) return r;
   if ((r = upload(c, m.nbrface, h.nbrface.data(), h.nbrface.size()))) return r;
-  if ((r = upload(c, (int*)m.nodepos, h.nodepos.data(), h.nodepos.size()))) return r;
+  if ((r = upload(c, m.tet_ext, c->tet_old.data(), (size_t)T))) return r;
+  std::vector<int> ep((size_t)4 * m.T_cap, 0);
+  std::copy(h.nodepos.begin(), h.nodepos.end(), ep.begin());
+  if ((r = upload(c, (int*)m.epos, ep.data(), ep.size()))) return r;
   if ((r = upload(c, (int*)m.patchpos, h.patchpos.data(), h.patchpos.size()))) return r;
   std::vector<int> neg((size_t)4 * T, -1);
   if ((r = upload(c, (int*)m.front, neg.data(), (size_t)4 * T))) return r;
   if ((r = upload(c, m.smask, neg.data(), (size_t)T))) return r;
-  HIPCHK(c, hipMemsetAsync(m.flag, 0, nflag, c->stream));
   HIPCHK(c, hipMemsetAsync(m.candf, 0, sizeof(int) * T, c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_ctr, 0, sizeof(Counters), c->stream));
   HIPCHK(c, hipMemsetAsync(c->st.u, 0, sizeof(double4) * m.N_cap, c->stream));
@@ -618,6 +766,8 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   HIPCHK(c, hipMemsetAsync(c->w.veps, 0, RS * 6 * (size_t)m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(c->w.esig, 0, RS * 6 * (size_t)m.E_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(c->w.einvV, 0, RS * (size_t)m.E_cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 4 * ((size_t)4 * m.T_cap), c->stream));
+  HIPCHK(c, hipMemsetAsync(m.vol, 0, sizeof(double) * m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(m.invm, 0, sizeof(double) * m.N_cap, c->stream));
   HIPCHK(c, launch_masses(m, c->stream));
   if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, c->stream));
@@ -641,6 +791,9 @@ int cem_set_traction(cem_ctx* c, int32_t n_faces, const int32_t* tri, const doub
     if (!std::isfinite(t[i])) return c->fail(CEM_EINVAL, "non-finite traction");
   }
   // loaded nodes -> slots; per slot the list of its faces
+  std::vector<int> tri_int((size_t)3 * n_faces);
+  for (long long i = 0; i < 3LL * n_faces; ++i) tri_int[i] = c->node_new[tri[i]];
+  tri = tri_int.data();
   std::vector<int> slot(m.N0, -1), lnode;
   for (long long i = 0; i < 3LL * n_faces; ++i) slot[tri[i]] = 0;
   for (int i = 0; i < m.N0; ++i)
@@ -715,12 +868,13 @@ int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_
     lst.push_back({tet[i], mk});
   }
   std::sort(lst.begin(), lst.end());
-  std::vector<int> tt;
+  std::vector<int> tt, text;
   std::vector<uint8_t> mm;
   for (size_t i = 0; i < lst.size(); ++i) {
     if (i > 0 && lst[i].first == lst[i - 1].first) continue;
     if (c->split_host[lst[i].first]) continue;
-    tt.push_back(lst[i].first);
+    text.push_back(lst[i].first);
+    tt.push_back(c->tet_new[lst[i].first]);  // ascending caller ids, internal slots
     mm.push_back((uint8_t)lst[i].second);
   }
   if ((long long)c->n_split_host + (long long)tt.size() > c->m.S_cap)
@@ -741,7 +895,7 @@ int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_
   (void)hipFree(d_t);
   (void)hipFree(d_m);
   if (r) return r;
-  for (int t : tt) c->split_host[t] = 1;
+  for (int t : text) c->split_host[t] = 1;
   r = check_device_error(c);
   if (r) return r;
   c->need_init = true;
@@ -798,11 +952,11 @@ int cem_set_state(cem_ctx* c, const double* u, const double* v) {
   int n = nodes_now_host(c);
   std::vector<double4> tmp;
   if (u) {
-    pad3(u, tmp, n);
+    pad3(c, u, tmp, n);
     if ((r = upload(c, c->st.u, tmp.data(), n))) return r;
   }
   if (v) {
-    pad3(v, tmp, n);
+    pad3(c, v, tmp, n);
     if ((r = upload(c, c->st.v, tmp.data(), n))) return r;
   }
   if ((r = sync(c))) return r;
@@ -826,7 +980,7 @@ int cem_get_state(cem_ctx* c, double* u, double* v, double* a, int32_t* n_now) {
     if (!dst[q]) continue;
     HIPCHK(c, hipMemcpyAsync(tmp.data(), src[q], sizeof(double4) * n, hipMemcpyDeviceToHost, c->stream));
     if ((r = sync(c))) return r;
-    unpad3(tmp, dst[q], n);
+    unpad3(c, tmp, dst[q], n);
   }
   return CEM_OK;
 }
@@ -837,14 +991,14 @@ int cem_internal_force(cem_ctx* c, const double* u, double* f) {
   if (r) return r;
   int n = nodes_now_host(c);
   std::vector<double4> tmp;
-  pad3(u, tmp, n);
+  pad3(c, u, tmp, n);
   if ((r = upload(c, c->d_tmp, tmp.data(), n))) return r;
   if ((r = strain_stress(c, c->d_tmp))) return r;
   if ((r = node_pass(c, NODE_FORCE, c->d_tmp2))) return r;
   tmp.resize(n);
   HIPCHK(c, hipMemcpyAsync(tmp.data(), c->d_tmp2, sizeof(double4) * n, hipMemcpyDeviceToHost, c->stream));
   if ((r = sync(c))) return r;
-  unpad3(tmp, f, n);
+  unpad3(c, tmp, f, n);
   return CEM_OK;
 }
 
@@ -921,6 +1075,7 @@ int cem_replay_splits(cem_ctx* c, int32_t n, const cem_split_event* ev) {
   std::stable_sort(s.begin(), s.end(), [](const std::array<int, 3>& x, const std::array<int, 3>& y) {
     return x[0] != y[0] ? x[0] < y[0] : x[1] < y[1];
   });
+  for (auto& e3 : s) e3[1] = c->tet_new[e3[1]];
   if (c->m.sched) {
     (void)hipFree(c->m.sched);
     c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)c->m.sched), c->allocs.end());
@@ -996,7 +1151,7 @@ int cem_read_splits(cem_ctx* c, int32_t cap, cem_split_event* out, int32_t* n) {
   HIPCHK(c, hipMemcpyAsync(pt.data(), c->m.rec_pat, sizeof(int) * k, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(G.data(), c->m.rec_G, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
   if ((r = sync(c))) return r;
-  for (int i = 0; i < k; ++i) out[i] = cem_split_event{st[i], tt[i], mk[i], pt[i], G[i]};
+  for (int i = 0; i < k; ++i) out[i] = cem_split_event{st[i], c->tet_old[tt[i]], mk[i], pt[i], G[i]};
   return CEM_OK;
 }
 
@@ -1030,6 +1185,10 @@ int cem_read_front_G(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* n) {
   (void)hipFree(d_tfl);
   (void)hipFree(d_g);
   if (r) return r;
+  for (int i = 0; i < nf; ++i) {
+    tfl[3 * i] = c->tet_old[tfl[3 * i]];
+    tfl[3 * i + 2] = c->node_old[tfl[3 * i + 2]];
+  }
   std::vector<int> ord(nf);
   for (int i = 0; i < nf; ++i) ord[i] = i;
   std::sort(ord.begin(), ord.end(), [&](int x, int y) {
