@@ -190,9 +190,11 @@ int cem_counts(cem_ctx* ctx, int32_t* out);
 
 /* Time of the kernels of the last cem_step, in milliseconds, measured with
  * HIP events on the context stream: out[0] whole call, out[1] strain pass,
- * out[2] edge stress pass, out[3] crack pass, out[4] node pass, out[5]
- * topology pass.  Per-kernel times are recorded only when profiling was
- * enabled with cem_set_profiling(ctx, 1) (then graphs are not used). */
+ * out[2] edge stress pass, out[3] crack pass, out[4] element force terms,
+ * out[5] node sums and update, out[6] topology pass.  Per-pass times are
+ * recorded only when profiling is on (cem_set_profiling(ctx, 1)); the steps
+ * then run as plain launches (HIP cannot time events recorded inside a
+ * graph). */
 int cem_set_profiling(cem_ctx* ctx, int32_t on);
 int cem_kernel_times(cem_ctx* ctx, double* out);
 

@@ -280,7 +280,9 @@ class Simulation:
         self._chk(self.lib.cem_set_profiling(self.ctx, 1 if on else 0))
 
     def kernel_times(self):
-        out = np.zeros(6)
+        out = np.zeros(7)
         self._chk(self.lib.cem_kernel_times(self.ctx, _p(out)))
-        return dict(zip(["total", "strain", "edge_stress", "front", "node", "topology"],
-                        out.tolist()))
+        d = dict(zip(["total", "strain", "edge_stress", "front", "elem_force", "node_sum",
+                      "topology"], out.tolist()))
+        d["node"] = d["elem_force"] + d["node_sum"]
+        return d

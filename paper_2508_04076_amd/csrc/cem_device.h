@@ -122,7 +122,7 @@ template <class R> struct Launch {
   static hipError_t front(const Mesh& m, const State& st, const Work& w, Counters* c,
                           int flagging, hipStream_t s);
   static hipError_t node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
-                         double4* fout, hipStream_t s);
+                         double4* fout, hipStream_t s, hipEvent_t mid = nullptr);
   static hipError_t edge_volumes(const Mesh& m, const Work& w, hipStream_t s);
   static hipError_t front_eval(const Mesh& m, const State& st, const Work& w, Counters* c,
                                int* out_tfl, double* out_g, int* out_n, hipStream_t s);

@@ -1251,12 +1251,16 @@ hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, 
 
 template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
-                           double4* fout, hipStream_t s) {
+                           double4* fout, hipStream_t s, hipEvent_t mid) {
   constexpr int G = kNodeLanes;
   constexpr int FU = CEM_NODE_FUSED;
   if (!FU)
     hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m.T_cap)), dim3(kBlock), 0, s, m,
                        (const Six<R>*)w.esig, (R*)w.contrib, c);
+  if (mid) {
+    hipError_t e = hipEventRecord(mid, s);
+    if (e != hipSuccess) return e;
+  }
   dim3 g(persistent_grid((long long)m.N_cap * G)), b(kBlock);
   const R* ct = (const R*)w.contrib;
   const Six<R>* sg = (const Six<R>*)w.esig;

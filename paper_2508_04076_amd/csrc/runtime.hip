@@ -14,6 +14,10 @@
 
 using namespace cem;
 
+// events per profiled step: before strain, edge, crack, element force, node
+// sum, topology, and after topology
+constexpr int kEvents = 7;
+
 namespace {
 
 struct Region {
@@ -75,7 +79,7 @@ struct cem_ctx {
 
   // profiling
   int profiling = 0;
-  double times[6] = {0, 0, 0, 0, 0, 0};
+  double times[7] = {0, 0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> evpool;
 
   std::vector<void*> allocs;
@@ -427,9 +431,9 @@ int strain_stress(cem_ctx* c, const double4* u) {
   return c->mixed ? launch_strain_stress<float>(c, u) : launch_strain_stress<double>(c, u);
 }
 
-int node_pass(cem_ctx* c, int mode, double4* fout) {
-  hipError_t e = c->mixed ? Launch<float>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream)
-                          : Launch<double>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream);
+int node_pass(cem_ctx* c, int mode, double4* fout, hipEvent_t mid = nullptr) {
+  hipError_t e = c->mixed ? Launch<float>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream, mid)
+                          : Launch<double>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream, mid);
   HIPCHK(c, e);
   return CEM_OK;
 }
@@ -461,14 +465,14 @@ int enqueue_step(cem_ctx* c, hipEvent_t* ev) {
     if (replay) HIPCHK(c, launch_replay_select(c->m, c->d_ctr, s));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
-  int r = node_pass(c, NODE_STEP, nullptr);
+  int r = node_pass(c, NODE_STEP, nullptr, ev ? ev[4] : nullptr);
   if (r) return r;
-  if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
   if (c->mixed)
     HIPCHK(c, launch_topology_t<float>(c->m, c->st, c->w, c->d_ctr, 1, 1, c->d_snodes, c->d_sedges, s));
   else
     HIPCHK(c, launch_topology_t<double>(c->m, c->st, c->w, c->d_ctr, 1, 1, c->d_snodes, c->d_sedges, s));
-  if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[6], s));
   return CEM_OK;
 }
 
@@ -480,10 +484,31 @@ void drop_graph(cem_ctx* c) {
   c->graph_steps = 0;
 }
 
+int ensure_events(cem_ctx* c, size_t n) {
+  for (size_t i = c->evpool.size(); i < n; ++i) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->evpool.push_back(e);
+  }
+  return CEM_OK;
+}
+
+// Sum the per-pass intervals of k recorded steps (kEvents events per step).
+int accumulate_times(cem_ctx* c, int k) {
+  for (int i = 0; i < k; ++i)
+    for (int q = 1; q < kEvents; ++q) {
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->evpool[kEvents * i + q - 1], c->evpool[kEvents * i + q]));
+      c->times[q] += ms;
+    }
+  return CEM_OK;
+}
+
+// Capture k steps into a graph.
 int build_graph(cem_ctx* c, int k) {
   drop_graph(c);
-  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
   int r = CEM_OK;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
   for (int i = 0; i < k && r == CEM_OK; ++i) r = enqueue_step(c, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->stream, &g);
@@ -1013,32 +1038,11 @@ int cem_step(cem_ctx* c, int32_t n_steps) {
   HIPCHK(c, hipEventCreate(&e1));
   HIPCHK(c, hipEventRecord(e0, c->stream));
   if (c->need_init && (r = initialize(c))) return r;
-  for (int q = 0; q < 6; ++q) c->times[q] = 0;
+  for (int q = 0; q < 7; ++q) c->times[q] = 0;
   int K = c->opt.graph_steps;
   int done = 0;
-  if (c->profiling) {
-    const int chunk = 64;
-    if ((int)c->evpool.size() < 6 * chunk) {
-      for (int i = (int)c->evpool.size(); i < 6 * chunk; ++i) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->evpool.push_back(e);
-      }
-    }
-    while (done < n_steps) {
-      int k = std::min(chunk, n_steps - done);
-      for (int i = 0; i < k; ++i)
-        if ((r = enqueue_step(c, &c->evpool[6 * i]))) return r;
-      if ((r = sync(c))) return r;
-      for (int i = 0; i < k; ++i)
-        for (int q = 1; q < 6; ++q) {
-          float ms = 0;
-          HIPCHK(c, hipEventElapsedTime(&ms, c->evpool[6 * i + q - 1], c->evpool[6 * i + q]));
-          c->times[q] += ms;
-        }
-      done += k;
-    }
-  } else if (K > 0 && n_steps >= K) {
+  // HIP cannot time events recorded inside a graph: profiling uses plain launches
+  if (!c->profiling && K > 0 && n_steps >= K) {
     int replay = c->h_ctr->n_sched > 0;
     if (!c->gexec || c->graph_steps != K || c->graph_replay != replay) {
       if ((r = build_graph(c, K))) return r;
@@ -1046,6 +1050,18 @@ int cem_step(cem_ctx* c, int32_t n_steps) {
     while (n_steps - done >= K) {
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
       done += K;
+    }
+  }
+  if (c->profiling) {
+    const int chunk = 64;
+    if ((r = ensure_events(c, kEvents * chunk))) return r;
+    while (done < n_steps) {
+      int k = std::min(chunk, n_steps - done);
+      for (int i = 0; i < k; ++i)
+        if ((r = enqueue_step(c, &c->evpool[kEvents * i]))) return r;
+      if ((r = sync(c))) return r;
+      if ((r = accumulate_times(c, k))) return r;
+      done += k;
     }
   }
   for (; done < n_steps; ++done)
@@ -1293,7 +1309,7 @@ int cem_set_profiling(cem_ctx* c, int32_t on) {
 
 int cem_kernel_times(cem_ctx* c, double* out) {
   if (!c || !out) return CEM_EINVAL;
-  for (int q = 0; q < 6; ++q) out[q] = c->times[q];
+  for (int q = 0; q < 7; ++q) out[q] = c->times[q];
   return CEM_OK;
 }
 
