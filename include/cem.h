@@ -188,6 +188,31 @@ int cem_load_state(cem_ctx* ctx, const void* buf, int64_t size);
  * original edge count. */
 int cem_counts(cem_ctx* ctx, int32_t* out);
 
+/* ---- Batches (ensembles of independent simulations in one launch per pass)
+ *
+ * Declare the uploaded mesh as n independent instances: instance i owns the
+ * caller's nodes [node_off[i], node_off[i+1]) and tets [tet_off[i],
+ * tet_off[i+1]); no tet may join two instances.  All instances step together
+ * in the same kernel launches, each with its own time step.  Call after
+ * cem_upload_mesh and before cem_presplit / cem_step. */
+int cem_set_instances(cem_ctx* ctx, int32_t n, const int32_t* node_off, const int32_t* tet_off);
+/* Time step of each instance, dt[n] (replaces cem_set_dt for a batch). */
+int cem_set_dt_instances(cem_ctx* ctx, const double* dt);
+/* Critical time step of each instance (same bound as cem_critical_dt). */
+int cem_critical_dt_instances(cem_ctx* ctx, double* dt_crit);
+/* Energies, Gmax and counts of each instance; n must equal the batch size. */
+int cem_read_energy_instances(cem_ctx* ctx, int32_t n, cem_energy* out);
+
+/* Launch shape of the step passes: persistent grid size (a positive multiple
+ * of 8 workgroups) and lanes per node in the node pass (4, 8 or 16).  The
+ * lane count sets the order of the node sums, hence the rounding. */
+int cem_set_launch(cem_ctx* ctx, int32_t grid_cap, int32_t lanes);
+/* Autotuner of the launch shape: times trial_steps steps of the live
+ * simulation for each candidate (grid 1024..8192 x lanes 4, 8, 16), restores
+ * the state after every trial and keeps the fastest (any output may be NULL). */
+int cem_autotune(cem_ctx* ctx, int32_t trial_steps, int32_t* best_grid, int32_t* best_lanes,
+                 double* best_ms_per_step);
+
 /* Time of the kernels of the last cem_step, in milliseconds, measured with
  * HIP events on the context stream: out[0] whole call, out[1] strain pass,
  * out[2] edge stress pass, out[3] crack pass, out[4] element force terms,

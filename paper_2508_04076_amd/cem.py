@@ -28,7 +28,8 @@ EXPORTS = [
     "cem_presplit", "cem_critical_dt", "cem_set_dt", "cem_bind_state", "cem_set_state",
     "cem_get_state", "cem_internal_force", "cem_step", "cem_replay_splits", "cem_read_energy",
     "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
-    "cem_set_profiling", "cem_kernel_times",
+    "cem_set_profiling", "cem_kernel_times", "cem_set_instances", "cem_set_dt_instances",
+    "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
 ]
 
 
@@ -104,6 +105,13 @@ def load_library(path=LIB_PATH):
         "cem_counts": [p, p],
         "cem_set_profiling": [p, i32],
         "cem_kernel_times": [p, p],
+        "cem_set_instances": [p, i32, p, p],
+        "cem_set_dt_instances": [p, p],
+        "cem_critical_dt_instances": [p, p],
+        "cem_read_energy_instances": [p, i32, p],
+        "cem_set_launch": [p, i32, i32],
+        "cem_autotune": [p, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                         C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -286,3 +294,34 @@ class Simulation:
                       "topology"], out.tolist()))
         d["node"] = d["elem_force"] + d["node_sum"]
         return d
+
+    # ---- batches
+    def set_instances(self, node_off, tet_off):
+        node_off = np.ascontiguousarray(node_off, dtype=np.int32)
+        tet_off = np.ascontiguousarray(tet_off, dtype=np.int32)
+        self.n_inst = len(node_off) - 1
+        self._chk(self.lib.cem_set_instances(self.ctx, self.n_inst, _p(node_off), _p(tet_off)))
+
+    def set_dt_instances(self, dt):
+        dt = np.ascontiguousarray(dt, dtype=np.float64)
+        self._chk(self.lib.cem_set_dt_instances(self.ctx, _p(dt)))
+
+    def critical_dt_instances(self):
+        out = np.zeros(self.n_inst)
+        self._chk(self.lib.cem_critical_dt_instances(self.ctx, _p(out)))
+        return out
+
+    def energy_instances(self):
+        arr = (cem_energy * self.n_inst)()
+        self._chk(self.lib.cem_read_energy_instances(self.ctx, self.n_inst,
+                                                     C.cast(arr, C.c_void_p)))
+        return [{k: getattr(e, k) for k, _ in cem_energy._fields_} for e in arr]
+
+    def set_launch(self, grid_cap, lanes):
+        self._chk(self.lib.cem_set_launch(self.ctx, int(grid_cap), int(lanes)))
+
+    def autotune(self, trial_steps=10):
+        g, l, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._chk(self.lib.cem_autotune(self.ctx, int(trial_steps), C.byref(g), C.byref(l),
+                                        C.byref(ms)))
+        return dict(grid_cap=g.value, lanes=l.value, ms_per_step=ms.value)

@@ -9,17 +9,8 @@ namespace cem {
 
 constexpr int kBlock = 256;          // 4 wave64 per workgroup
 constexpr int kTopoBlock = 1024;     // single-workgroup topology update
-#ifndef CEM_NODE_LANES
-#define CEM_NODE_LANES 8
-#endif
-constexpr int kNodeLanes = CEM_NODE_LANES;  // lanes that share one node in the node pass
-#ifndef CEM_NODE_FUSED
-#define CEM_NODE_FUSED 0
-#endif
-#ifndef CEM_PERSISTENT_BLOCKS
-#define CEM_PERSISTENT_BLOCKS 2048
-#endif
-constexpr int kPersistentBlocks = CEM_PERSISTENT_BLOCKS;  // grid cap of the step passes
+constexpr int kDefaultLanes = 8;         // lanes per node in the node pass
+constexpr int kDefaultGridCap = 2048;    // workgroups of the persistent step launches
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
@@ -61,6 +52,9 @@ struct Mesh {
   double lam, mu, rho, Gc;
   double ramp_t0, dt;
   double umax;              // runaway bound on |u|
+  int grid_cap;             // workgroups of the persistent step launches (multiple of 8)
+  int lanes;                // lanes per node in the node pass (4, 8 or 16)
+  int n_inst;               // independent instances of a batch (0: one simulation)
 
   int4* enodes;             // [T_cap] node ids; .x also holds the fraction code
   int2* et2e;               // [T_cap * 3] six edge ids (local edge order 01 02 03 12 13 23)
@@ -96,6 +90,16 @@ struct Mesh {
   int* rec_pat;
   double* rec_G;
   int* sched;               // forced schedule (step, tet, mask) triples
+  double* rec_area;         // [S_cap] midpoint crack area of each split
+
+  // batch of independent instances (all null when n_inst == 0)
+  int* inst;                // [N_cap] instance of each node
+  int* tinst;               // [T_cap] instance of each element slot
+  int* einst;               // [E_cap] instance of each edge
+  double* dti;              // [n_inst] time step of each instance
+  unsigned long long* gmax_inst;  // [2 n_inst] running / last max G key per instance
+  unsigned long long* lam_inst;   // [n_inst] max element eigenvalue key per instance
+  double* dtc_inst;         // [n_inst] critical time step per instance
 };
 
 // Device pointers of the precision-dependent work arrays.
@@ -130,7 +134,7 @@ template <class R> struct Launch {
 
 template <class R>
 hipError_t launch_strain_energy(const Mesh& m, const Work& w, Counters* c, double* partial,
-                                int nparts, hipStream_t s);
+                                int nparts, int inst, hipStream_t s);
 template <class R>
 hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Counters* c,
                              int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s);
@@ -139,10 +143,14 @@ hipError_t launch_masses(const Mesh& m, hipStream_t s);
 hipError_t launch_loads(const Mesh& m, const int4* ftri, const double4* ftrac, const int* lfoff,
                         const int* lfent, hipStream_t s);
 hipError_t launch_dtcrit(const Mesh& m, Counters* c, hipStream_t s);
+// readbacks: inst < 0 sums over everything, else over one instance of a batch
 hipError_t launch_kinetic(const Mesh& m, const State& st, Counters* c, double* partial,
-                          int nparts, hipStream_t s);
+                          int nparts, int inst, hipStream_t s);
 hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s);
-hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, hipStream_t s);
+hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, int inst, hipStream_t s);
+hipError_t launch_work_sum(const Mesh& m, double* out, int inst, hipStream_t s);
+hipError_t launch_dissipated(const Mesh& m, Counters* c, double* out, int inst, hipStream_t s);
+hipError_t launch_edge_instances(const Mesh& m, hipStream_t s);
 hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, const uint8_t* masks,
                                int n, hipStream_t s);
 int grid_for(long long n);

@@ -86,6 +86,11 @@ template <> struct Vec4<float> {
   }
 };
 
+// Time step of node i (one per instance in a batch).
+__device__ __forceinline__ double node_dt(const Mesh& m, int i) {
+  return m.n_inst ? m.dti[m.inst[i]] : m.dt;
+}
+
 __device__ __forceinline__ double ramp(const Mesh& m, double t) {
   return (m.ramp_t0 > 0.0 && t < m.ramp_t0) ? t / m.ramp_t0 : 1.0;
 }
@@ -230,11 +235,13 @@ template <class R>
 __global__ __launch_bounds__(kBlock) void k_strain_energy(Mesh m, const Six<R>* __restrict__ veps,
                                                           const R* __restrict__ einvV,
                                                           double* __restrict__ partial,
-                                                          const Counters* __restrict__ c) {
+                                                          const Counters* __restrict__ c,
+                                                          int want) {
   __shared__ double red[kBlock];
   double s = 0;
   int En = edges_now(m, c);
   for (int k = blockIdx.x * kBlock + threadIdx.x; k < En; k += gridDim.x * kBlock) {
+    if (want >= 0 && m.einst[k] != want) continue;
     R acc[6], eps[6], sig[6];
     edge_sum(m, veps, k, acc);
     R iv = einvV[k];
@@ -321,43 +328,11 @@ __global__ __launch_bounds__(kBlock) void k_elem_force(Mesh m, const Six<R>* __r
   }
 }
 
-// Fused node pass (one kernel): G lanes per node; for each (element, local)
-// entry of the node the lane recomputes that element's term
-// (f / 36) G_l^T sum_{k in edges(e)} sigma_k from the face opposite l.
-template <class R>
-__device__ __forceinline__ void entry_force(const Mesh& m, const Six<R>* __restrict__ esig, int ent,
-                                            double& fx, double& fy, double& fz) {
-  int e = ent >> 2, l = ent & 3;
-  int4 nd = m.enodes[e];
-  int code = (unsigned)nd.x >> kNodeBits;
-  if (code == FR_ZERO) return;
-  int n0 = nd.x & kNodeMask;
-  // face opposite l as (a, b, c) with G_l = (X_b - X_a) x (X_c - X_a)
-  int a = (l == 0) ? nd.y : n0;
-  int b = (l == 0) ? nd.w : (l == 1) ? nd.z : (l == 2) ? nd.w : nd.y;
-  int cc = (l == 0) ? nd.z : (l == 1) ? nd.w : (l == 2) ? nd.y : nd.z;
-  int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
-  double4 xa = m.X[a], xb = m.X[b], xc = m.X[cc];
-  Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
-  Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
-  R bx = (R)(xb.x - xa.x), by = (R)(xb.y - xa.y), bz = (R)(xb.z - xa.z);
-  R cx = (R)(xc.x - xa.x), cy = (R)(xc.y - xa.y), cz = (R)(xc.z - xa.z);
-  R gx = by * cz - bz * cy, gy = bz * cx - bx * cz, gz = bx * cy - by * cx;
-  R sg[6];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
-  R w = (R)(frac_of(code) / 36.0);
-  fx += (double)(w * (gx * sg[0] + gy * sg[3] + gz * sg[5]));
-  fy += (double)(w * (gy * sg[1] + gx * sg[3] + gz * sg[4]));
-  fz += (double)(w * (gz * sg[2] + gy * sg[4] + gx * sg[5]));
-}
-
 // Node pass: G lanes per node sum the node's contributions (lane g takes
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
-template <class R, int MODE, int G, int FUSED>
+template <class R, int MODE, int G>
 __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __restrict__ contrib,
-                                                 const Six<R>* __restrict__ esig,
                                                  double4* __restrict__ fout,
                                                  Counters* __restrict__ c) {
   if (c->err || over_capacity(m, c)) return;
@@ -371,14 +346,10 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __re
   const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
   typedef typename Vec4<R>::T R4;
   for (int p = p0 + g; p < p1; p += G) {
-    if (FUSED) {
-      entry_force<R>(m, esig, m.nent[p], fx, fy, fz);
-    } else {
-      R4 q = ((const R4*)contrib)[p];
-      fx += (double)q.x;
-      fy += (double)q.y;
-      fz += (double)q.z;
-    }
+    R4 q = ((const R4*)contrib)[p];
+    fx += (double)q.x;
+    fy += (double)q.y;
+    fz += (double)q.z;
   }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) {
@@ -391,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __re
     fout[i] = make_double4(fx, fy, fz, 0.0);
     continue;
   }
-  const double dt = m.dt;
+  const double dt = node_dt(m, i);
   const long long n = c->step;
   int ls = m.lslot[i];
   double4 F = ls >= 0 ? m.Fload[ls] : make_double4(0, 0, 0, 0);
@@ -621,6 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_front(Mesh m, const double4* __restr
     if (!any) continue;
     unsigned long long k = dkey(best);
     kmax = k > kmax ? k : kmax;
+    if (m.n_inst) atomicMax(&m.gmax_inst[m.tinst[t]], k);
     if (flagging && best >= m.Gc) {
       m.pmask[t] = (uint8_t)bmask;
       m.ppat[t] = (uint8_t)bpat;
@@ -668,12 +640,13 @@ __global__ __launch_bounds__(kBlock) void k_front_eval(Mesh m, const double4* __
 }
 
 __global__ __launch_bounds__(kBlock) void k_count_fronts(Mesh m, const Counters* __restrict__ c,
-                                                         int* out) {
+                                                         int* out, int want) {
   int nc = c->n_cand;
   int cnt = 0;
   for (int idx = blockIdx.x * kBlock + threadIdx.x; idx < nc; idx += gridDim.x * kBlock) {
     int t = m.cand[idx];
     if (m.smask[t] >= 0) continue;
+    if (want >= 0 && m.tinst[t] != want) continue;
     int4 fr = m.front[t];
     cnt += (fr.x >= 0) + (fr.y >= 0) + (fr.z >= 0) + (fr.w >= 0);
   }
@@ -847,6 +820,7 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       m.rec_pat[s] = dynamic ? m.ppat[t] : 0;
       m.rec_G[s] = dynamic ? m.pG[t] : 0.0;
       m.area[i] = dynamic ? crack_area(m, nd, mask) : 0.0;
+      m.rec_area[s] = m.area[i];
       if (m.mode == MODE_ERODE) {
         m.enodes[t] = make_int4(pack0(nd[0], FR_ZERO), nd[1], nd[2], nd[3]);
         continue;
@@ -866,6 +840,7 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
         st.a[x] = st.a[nd[l]];
         st.uh[x] = st.uh[nd[l]];
         m.lslot[x] = -1;
+        if (m.n_inst) m.inst[x] = m.inst[nd[l]];
         bool onB = (mask >> l) & 1;
         na[l] = onB ? x : nd[l];
         nbn[l] = onB ? nd[l] : x;
@@ -881,6 +856,11 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
       double V = m.vol[t];
       m.vol[tb] = V;
+      if (m.n_inst) {
+        int ti = m.tinst[t];
+        m.tinst[tb] = ti;
+        for (int r = 0; r < 10; ++r) m.einst[m.E0 + 10 * s + r] = ti;
+      }
       R ivA = (R)(1.0 / (frac_of(codeA) * V)), ivB = (R)(1.0 / (frac_of(codeB) * V));
       int eA[6], eB[6];
       int r = 0;
@@ -985,6 +965,12 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       }
     }
     c->n_flag = 0;
+  }
+  if (advance && m.n_inst) {
+    for (int i = tid; i < m.n_inst; i += kTopoBlock) {
+      m.gmax_inst[m.n_inst + i] = m.gmax_inst[i];
+      m.gmax_inst[i] = 0;
+    }
   }
 }
 
@@ -1144,6 +1130,7 @@ __global__ __launch_bounds__(kBlock) void k_dtcrit(Mesh m, Counters* __restrict_
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) lmax = fmax(lmax, A[i][i]);
+    if (m.n_inst) atomicMax(&m.lam_inst[m.tinst[t]], dkey(lmax));
   }
   red[threadIdx.x] = dkey(lmax);
   __syncthreads();
@@ -1159,16 +1146,25 @@ __global__ void k_dtfinish(Mesh m, Counters* c) {
     double lam = key_to_double(c->lam_key);
     c->dt_crit = 2.0 / sqrt(4.0 / m.rho * lam);
   }
+  for (int i = threadIdx.x; i < m.n_inst; i += blockDim.x)
+    m.dtc_inst[i] = 2.0 / sqrt(4.0 / m.rho * key_to_double(m.lam_inst[i]));
+}
+
+// Instance of each original edge: that of its first patch element.
+__global__ __launch_bounds__(kBlock) void k_edge_instances(Mesh m) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < m.E0) m.einst[k] = m.tinst[m.pent[m.poff[k]]];
 }
 
 // ---------------------------------------------------------------- reductions
 
 __global__ __launch_bounds__(kBlock) void k_kinetic(Mesh m, State st, const Counters* __restrict__ c,
-                                                    double* partial) {
+                                                    double* partial, int want) {
   __shared__ double red[kBlock];
   double s = 0;
   int Nn = nodes_now(m, c);
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < Nn; i += gridDim.x * kBlock) {
+    if (want >= 0 && m.inst[i] != want) continue;
     double im = m.invm[i];
     if (im > 0) {
       double4 v = st.v[i];
@@ -1182,6 +1178,50 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(Mesh m, State st, const Coun
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// External work of one instance (or all): fixed-order sum over load slots.
+__global__ __launch_bounds__(kBlock) void k_work_sum(Mesh m, double* out, int want) {
+  __shared__ double red[kBlock];
+  double s = 0;
+  for (int i = threadIdx.x; i < m.n_load; i += kBlock)
+    if (want < 0 || m.inst[m.lnode[i]] == want) s += m.wacc[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// Dissipated energy of one instance: Gc x crack area over its splits decided
+// by the G test (records with a pattern), fixed-order sum.
+__global__ __launch_bounds__(kBlock) void k_dissipated(Mesh m, const Counters* __restrict__ c,
+                                                       double* out, int want) {
+  __shared__ double red[kBlock];
+  __shared__ int cnt[kBlock];
+  double s = 0;
+  int n = 0;
+  for (int i = threadIdx.x; i < c->n_split; i += kBlock) {
+    if (want >= 0 && m.tinst[m.rec_tet[i]] != want) continue;
+    n++;
+    if (m.rec_pat[i] > 0) s += m.Gc * m.rec_area[i];
+  }
+  red[threadIdx.x] = s;
+  cnt[threadIdx.x] = n;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    out[1] = (double)cnt[0];  // splits of the instance
+  }
 }
 
 // Fixed-order sum (single workgroup).
@@ -1204,25 +1244,25 @@ int grid_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 double key_to_double_host(unsigned long long k) { return key_to_double(k); }
 
 // Persistent grid: enough workgroups for the largest item count the launch
-// can see (capacity), capped at kPersistentBlocks; always a multiple of 8.
-static int persistent_grid(long long items) {
+// can see (capacity), capped at m.grid_cap; always a multiple of 8.
+static int persistent_grid(const Mesh& m, long long items) {
   long long g = (items + kBlock - 1) / kBlock;
   g = g < 8 ? 8 : g;
-  g = g > kPersistentBlocks ? kPersistentBlocks : g;
+  g = g > m.grid_cap ? m.grid_cap : g;
   return (int)((g + 7) / 8 * 8);
 }
 
 template <class R>
 hipError_t Launch<R>::strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_strain<R>, dim3(persistent_grid(m.T_cap)), dim3(kBlock), 0, s, m, u,
+  hipLaunchKernelGGL(k_strain<R>, dim3(persistent_grid(m, m.T_cap)), dim3(kBlock), 0, s, m, u,
                      (Six<R>*)w.veps, c);
   return hipGetLastError();
 }
 
 template <class R>
 hipError_t Launch<R>::edge_stress(const Mesh& m, const Work& w, Counters* c, hipStream_t s) {
-  hipLaunchKernelGGL(k_edge_stress<R>, dim3(persistent_grid(m.E_cap)), dim3(kBlock), 0, s, m,
+  hipLaunchKernelGGL(k_edge_stress<R>, dim3(persistent_grid(m, m.E_cap)), dim3(kBlock), 0, s, m,
                      (const Six<R>*)w.veps, (const R*)w.einvV, (Six<R>*)w.esig, c);
   return hipGetLastError();
 }
@@ -1249,27 +1289,32 @@ hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, 
   return hipGetLastError();
 }
 
+template <class R, int G>
+static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
+                              Counters* c, int mode, double4* fout, hipStream_t s) {
+  dim3 g(persistent_grid(m, (long long)m.N_cap * G)), b(kBlock);
+  if (mode == NODE_FORCE)
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G>), g, b, 0, s, m, st, ct, fout, c);
+  else if (mode == NODE_INIT)
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G>), g, b, 0, s, m, st, ct, fout, c);
+  else
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G>), g, b, 0, s, m, st, ct, fout, c);
+}
+
 template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                            double4* fout, hipStream_t s, hipEvent_t mid) {
-  constexpr int G = kNodeLanes;
-  constexpr int FU = CEM_NODE_FUSED;
-  if (!FU)
-    hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m.T_cap)), dim3(kBlock), 0, s, m,
-                       (const Six<R>*)w.esig, (R*)w.contrib, c);
+  hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m, m.T_cap)), dim3(kBlock), 0, s, m,
+                     (const Six<R>*)w.esig, (R*)w.contrib, c);
   if (mid) {
     hipError_t e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
   }
-  dim3 g(persistent_grid((long long)m.N_cap * G)), b(kBlock);
   const R* ct = (const R*)w.contrib;
   const Six<R>* sg = (const Six<R>*)w.esig;
-  if (mode == NODE_FORCE)
-    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, FU>), g, b, 0, s, m, st, ct, sg, fout, c);
-  else if (mode == NODE_INIT)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, FU>), g, b, 0, s, m, st, ct, sg, fout, c);
-  else
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, FU>), g, b, 0, s, m, st, ct, sg, fout, c);
+  if (m.lanes == 4) launch_node_lanes<R, 4>(m, st, ct, sg, c, mode, fout, s);
+  else if (m.lanes == 16) launch_node_lanes<R, 16>(m, st, ct, sg, c, mode, fout, s);
+  else launch_node_lanes<R, 8>(m, st, ct, sg, c, mode, fout, s);
   return hipGetLastError();
 }
 
@@ -1284,15 +1329,15 @@ template struct Launch<float>;
 
 template <class R>
 hipError_t launch_strain_energy(const Mesh& m, const Work& w, Counters* c, double* partial,
-                                int nparts, hipStream_t s) {
+                                int nparts, int inst, hipStream_t s) {
   hipLaunchKernelGGL(k_strain_energy<R>, dim3(nparts), dim3(kBlock), 0, s, m,
-                     (const Six<R>*)w.veps, (const R*)w.einvV, partial, c);
+                     (const Six<R>*)w.veps, (const R*)w.einvV, partial, c, inst);
   return hipGetLastError();
 }
 template hipError_t launch_strain_energy<double>(const Mesh&, const Work&, Counters*, double*, int,
-                                                 hipStream_t);
+                                                 int, hipStream_t);
 template hipError_t launch_strain_energy<float>(const Mesh&, const Work&, Counters*, double*, int,
-                                                hipStream_t);
+                                                int, hipStream_t);
 
 template <class R>
 hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Counters* c,
@@ -1341,8 +1386,23 @@ hipError_t launch_dtcrit(const Mesh& m, Counters* c, hipStream_t s) {
 }
 
 hipError_t launch_kinetic(const Mesh& m, const State& st, Counters* c, double* partial, int nparts,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_kinetic, dim3(nparts), dim3(kBlock), 0, s, m, st, c, partial);
+                          int inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_kinetic, dim3(nparts), dim3(kBlock), 0, s, m, st, c, partial, inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_work_sum(const Mesh& m, double* out, int inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_work_sum, dim3(1), dim3(kBlock), 0, s, m, out, inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_instances(const Mesh& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_edge_instances, dim3(grid_for(m.E0)), dim3(kBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_dissipated(const Mesh& m, Counters* c, double* out, int inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_dissipated, dim3(1), dim3(kBlock), 0, s, m, c, out, inst);
   return hipGetLastError();
 }
 
@@ -1351,8 +1411,8 @@ hipError_t launch_sum(const double* partial, int n, double* out, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_fronts, dim3(front_grid(m)), dim3(kBlock), 0, s, m, c, out);
+hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, int inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_fronts, dim3(front_grid(m)), dim3(kBlock), 0, s, m, c, out, inst);
   return hipGetLastError();
 }
 

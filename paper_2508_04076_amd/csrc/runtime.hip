@@ -56,6 +56,7 @@ struct cem_ctx {
   // the library renumbers nodes and tets for locality; the API keeps the
   // caller's numbering
   std::vector<int> node_new, node_old;  // [N0]
+  std::vector<int> inst_nodes, inst_tets;  // original nodes / tets per instance
   std::vector<int> tet_new, tet_old;    // [T0]
   std::vector<char> split_host;
   int n_split_host = 0;
@@ -668,6 +669,12 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   m.Gc = mat->Gc;
   m.ramp_t0 = 0;
   m.dt = 0;
+  m.grid_cap = kDefaultGridCap;
+  m.lanes = kDefaultLanes;
+  m.n_inst = 0;
+  m.inst = m.tinst = m.einst = nullptr;
+  m.dti = m.dtc_inst = nullptr;
+  m.gmax_inst = m.lam_inst = nullptr;
   {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int i = 0; i < N; ++i)
@@ -718,6 +725,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   ALLOC(m.rec_mask, std::max(S, 1), true);
   ALLOC(m.rec_pat, std::max(S, 1), true);
   ALLOC(m.rec_G, std::max(S, 1), true);
+  ALLOC(m.rec_area, std::max(S, 1), true);
   ALLOC(c->d_snodes, std::max(S, 1), false);
   ALLOC(c->d_sedges, (size_t)6 * std::max(S, 1), false);
   char* vb;
@@ -1109,44 +1117,209 @@ int cem_replay_splits(cem_ctx* c, int32_t n, const cem_split_event* ev) {
   return CEM_OK;
 }
 
+// Energies of the whole run (inst < 0) or of one instance of a batch.
+int read_energy(cem_ctx* c, int inst, cem_energy* e) {
+  int r;
+  if (c->need_init && c->dt_set && (r = initialize(c))) return r;
+  Mesh& m = c->m;
+  int np = c->n_partial;
+  HIPCHK(c, launch_kinetic(m, c->st, c->d_ctr, c->w.partial, np, inst, c->stream));
+  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out, c->stream));
+  if (c->mixed) {
+    HIPCHK(c, Launch<float>::strain(m, c->st.u, c->w, c->d_ctr, c->stream));
+    HIPCHK(c, launch_strain_energy<float>(m, c->w, c->d_ctr, c->w.partial, np, inst, c->stream));
+  } else {
+    HIPCHK(c, Launch<double>::strain(m, c->st.u, c->w, c->d_ctr, c->stream));
+    HIPCHK(c, launch_strain_energy<double>(m, c->w, c->d_ctr, c->w.partial, np, inst, c->stream));
+  }
+  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out + 1, c->stream));
+  if (m.n_load > 0) HIPCHK(c, launch_work_sum(m, c->d_out + 2, inst, c->stream));
+  else HIPCHK(c, hipMemsetAsync(c->d_out + 2, 0, sizeof(double), c->stream));
+  HIPCHK(c, launch_dissipated(m, c->d_ctr, c->d_out + 3, inst, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_iout, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_count_fronts(m, c->d_ctr, c->d_iout, inst, c->stream));
+  double out[5];
+  int nf = 0;
+  HIPCHK(c, hipMemcpyAsync(out, c->d_out, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&nf, c->d_iout, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  unsigned long long gk[2] = {0, 0};
+  if (inst >= 0)
+    HIPCHK(c, hipMemcpyAsync(gk, m.gmax_inst + m.n_inst + inst, sizeof(gk[0]), hipMemcpyDeviceToHost,
+                             c->stream));
+  double dti = m.dt;
+  if (inst >= 0)
+    HIPCHK(c, hipMemcpyAsync(&dti, m.dti + inst, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if ((r = read_counters(c))) return r;
+  const Counters& k = *c->h_ctr;
+  int ns = inst >= 0 ? (int)out[4] : k.n_split;
+  int n0 = inst >= 0 ? c->inst_nodes[inst] : m.N0, t0 = inst >= 0 ? c->inst_tets[inst] : m.T0;
+  unsigned long long g = inst >= 0 ? gk[0] : k.gmax_last;
+  e->step = k.step;
+  e->t = (double)k.step * dti;
+  e->KE = out[0];
+  e->SE = out[1];
+  e->Wext = out[2];
+  e->Ud = inst >= 0 ? out[3] : k.Ud;
+  e->Gmax = g ? key_to_double_host(g) : 0.0;
+  e->n_split = ns;
+  e->n_front = nf;
+  e->n_nodes = n0 + (m.mode == MODE_PHANTOM ? 4 * ns : 0);
+  e->n_elems = t0 + (m.mode == MODE_PHANTOM ? ns : 0);
+  return CEM_OK;
+}
+
 int cem_read_energy(cem_ctx* c, cem_energy* e) {
   if (!c || !e) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
-  if (c->need_init && c->dt_set && (r = initialize(c))) return r;
+  return read_energy(c, -1, e);
+}
+
+int cem_read_energy_instances(cem_ctx* c, int32_t n, cem_energy* out) {
+  if (!c || !out) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->m.n_inst == 0 || n != c->m.n_inst) return c->fail(CEM_EINVAL, "no batch of that size");
+  for (int i = 0; i < n; ++i)
+    if ((r = read_energy(c, i, out + i))) return r;
+  return CEM_OK;
+}
+
+int cem_set_instances(cem_ctx* c, int32_t n, const int32_t* node_off, const int32_t* tet_off) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
   Mesh& m = c->m;
-  int np = c->n_partial;
-  HIPCHK(c, launch_kinetic(m, c->st, c->d_ctr, c->w.partial, np, c->stream));
-  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out, c->stream));
-  if (c->mixed) {
-    HIPCHK(c, Launch<float>::strain(m, c->st.u, c->w, c->d_ctr, c->stream));
-    HIPCHK(c, launch_strain_energy<float>(m, c->w, c->d_ctr, c->w.partial, np, c->stream));
-  } else {
-    HIPCHK(c, Launch<double>::strain(m, c->st.u, c->w, c->d_ctr, c->stream));
-    HIPCHK(c, launch_strain_energy<double>(m, c->w, c->d_ctr, c->w.partial, np, c->stream));
+  if (c->m.n_inst) return c->fail(CEM_ESTATE, "instances already declared");
+  if (c->step_host != 0 || c->n_split_host != 0)
+    return c->fail(CEM_ESTATE, "instances must be declared before pre-splits and steps");
+  if (n < 1 || !node_off || !tet_off) return c->fail(CEM_EINVAL, "bad instance arguments");
+  if (node_off[0] != 0 || tet_off[0] != 0 || node_off[n] != m.N0 || tet_off[n] != m.T0)
+    return c->fail(CEM_EINVAL, "instance ranges must cover the mesh");
+  for (int i = 0; i < n; ++i)
+    if (node_off[i + 1] <= node_off[i] || tet_off[i + 1] <= tet_off[i])
+      return c->fail(CEM_EINVAL, "empty or decreasing instance range");
+  std::vector<int> ninst(m.N0), tinst(m.T0);
+  for (int i = 0; i < n; ++i) {
+    for (int q = node_off[i]; q < node_off[i + 1]; ++q) ninst[c->node_new[q]] = i;
+    for (int t = tet_off[i]; t < tet_off[i + 1]; ++t) tinst[c->tet_new[t]] = i;
   }
-  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out + 1, c->stream));
-  if (m.n_load > 0) HIPCHK(c, launch_sum(m.wacc, m.n_load, c->d_out + 2, c->stream));
-  else HIPCHK(c, hipMemsetAsync(c->d_out + 2, 0, sizeof(double), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->d_iout, 0, sizeof(int), c->stream));
-  HIPCHK(c, launch_count_fronts(m, c->d_ctr, c->d_iout, c->stream));
-  double out[3];
-  int nf = 0;
-  HIPCHK(c, hipMemcpyAsync(out, c->d_out, sizeof(out), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(&nf, c->d_iout, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  if ((r = read_counters(c))) return r;
-  const Counters& k = *c->h_ctr;
-  e->step = k.step;
-  e->t = (double)k.step * m.dt;
-  e->KE = out[0];
-  e->SE = out[1];
-  e->Wext = out[2];
-  e->Ud = k.Ud;
-  e->Gmax = k.gmax_last ? key_to_double_host(k.gmax_last) : 0.0;
-  e->n_split = k.n_split;
-  e->n_front = nf;
-  e->n_nodes = m.N0 + (m.mode == MODE_PHANTOM ? 4 * k.n_split : 0);
-  e->n_elems = m.T0 + (m.mode == MODE_PHANTOM ? k.n_split : 0);
+  for (int t = 0; t < m.T0; ++t)
+    for (int l = 0; l < 4; ++l)
+      if (ninst[c->tets[4 * (size_t)t + l]] != tinst[t])
+        return c->fail(CEM_EINVAL, "a tet joins nodes of two instances");
+  ALLOC(m.inst, m.N_cap, true);
+  ALLOC(m.tinst, m.T_cap, true);
+  ALLOC(m.einst, m.E_cap, true);
+  ALLOC(m.dti, n, true);
+  ALLOC(m.dtc_inst, n, false);
+  ALLOC(m.gmax_inst, 2 * n, true);
+  ALLOC(m.lam_inst, n, false);
+  if ((r = upload(c, m.inst, ninst.data(), ninst.size()))) return r;
+  if ((r = upload(c, m.tinst, tinst.data(), tinst.size()))) return r;
+  std::vector<double> dts(n, m.dt);
+  if ((r = upload(c, m.dti, dts.data(), dts.size()))) return r;
+  HIPCHK(c, hipMemsetAsync(m.gmax_inst, 0, sizeof(unsigned long long) * 2 * n, c->stream));
+  m.n_inst = n;
+  HIPCHK(c, launch_edge_instances(m, c->stream));
+  if ((r = sync(c))) return r;
+  c->inst_nodes.assign(n, 0);
+  c->inst_tets.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    c->inst_nodes[i] = node_off[i + 1] - node_off[i];
+    c->inst_tets[i] = tet_off[i + 1] - tet_off[i];
+  }
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_set_dt_instances(cem_ctx* c, const double* dt) {
+  if (!c || !dt) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (!c->m.n_inst) return c->fail(CEM_ESTATE, "no instances declared");
+  for (int i = 0; i < c->m.n_inst; ++i)
+    if (!(dt[i] > 0) || !std::isfinite(dt[i])) return c->fail(CEM_EINVAL, "dt must be positive");
+  if ((r = upload(c, c->m.dti, dt, (size_t)c->m.n_inst))) return r;
+  if ((r = sync(c))) return r;
+  c->m.dt = dt[0];
+  c->dt_set = true;
+  c->need_init = true;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_critical_dt_instances(cem_ctx* c, double* out) {
+  if (!c || !out) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (!c->m.n_inst) return c->fail(CEM_ESTATE, "no instances declared");
+  HIPCHK(c, hipMemsetAsync(c->m.lam_inst, 0, sizeof(unsigned long long) * c->m.n_inst, c->stream));
+  unsigned long long zero = 0;
+  HIPCHK(c, hipMemcpyAsync(&c->d_ctr->lam_key, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_dtcrit(c->m, c->d_ctr, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->m.dtc_inst, sizeof(double) * c->m.n_inst, hipMemcpyDeviceToHost,
+                           c->stream));
+  return sync(c);
+}
+
+int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (grid_cap < 8 || grid_cap % 8 || (lanes != 4 && lanes != 8 && lanes != 16))
+    return c->fail(CEM_EINVAL, "grid_cap must be a positive multiple of 8, lanes 4, 8 or 16");
+  c->m.grid_cap = grid_cap;
+  c->m.lanes = lanes;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+// Launch-shape autotuner: times trial_steps steps of the live simulation for
+// each candidate (persistent grid size x lanes per node), restoring the state
+// after every trial, and keeps the fastest.  Lanes change the order of the
+// node sums, hence the rounding of the results.
+int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* best_lanes,
+                 double* best_ms) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, true);
+  if (r) return r;
+  if (trial_steps < 1) return c->fail(CEM_EINVAL, "trial_steps must be positive");
+  int64_t used = 0;
+  if ((r = cem_save_state(c, nullptr, 0, &used))) return r;
+  std::vector<char> buf(used);
+  if ((r = cem_save_state(c, buf.data(), used, &used))) return r;
+  const int grids[4] = {1024, 2048, 4096, 8192};
+  const int lanes[3] = {4, 8, 16};
+  int g0 = c->m.grid_cap, l0 = c->m.lanes;
+  double best = 1e300;
+  int bg = g0, bl = l0;
+  int saved_prof = c->profiling;
+  c->profiling = 0;
+  // one warm-up trial, then every candidate
+  if ((r = cem_step(c, trial_steps)) == CEM_OK) r = cem_load_state(c, buf.data(), used);
+  for (int gi = 0; gi < 4 && r == CEM_OK; ++gi)
+    for (int li = 0; li < 3 && r == CEM_OK; ++li) {
+      c->m.grid_cap = grids[gi];
+      c->m.lanes = lanes[li];
+      drop_graph(c);
+      if ((r = cem_step(c, trial_steps))) break;
+      double ms = c->times[0] / trial_steps;
+      if (ms < best) {
+        best = ms;
+        bg = grids[gi];
+        bl = lanes[li];
+      }
+      r = cem_load_state(c, buf.data(), used);
+    }
+  c->profiling = saved_prof;
+  c->m.grid_cap = r ? g0 : bg;
+  c->m.lanes = r ? l0 : bl;
+  drop_graph(c);
+  if (r) return r;
+  if (best_grid) *best_grid = bg;
+  if (best_lanes) *best_lanes = bl;
+  if (best_ms) *best_ms = best;
   return CEM_OK;
 }
 
@@ -1288,7 +1461,7 @@ int cem_counts(cem_ctx* c, int32_t* out) {
   const Mesh& m = c->m;
   bool ph = m.mode == MODE_PHANTOM;
   HIPCHK(c, hipMemsetAsync(c->d_iout, 0, sizeof(int), c->stream));
-  HIPCHK(c, launch_count_fronts(m, c->d_ctr, c->d_iout, c->stream));
+  HIPCHK(c, launch_count_fronts(m, c->d_ctr, c->d_iout, -1, c->stream));
   int nf = 0;
   HIPCHK(c, hipMemcpyAsync(&nf, c->d_iout, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   if ((r = sync(c))) return r;

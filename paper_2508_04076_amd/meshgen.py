@@ -282,3 +282,45 @@ def bar(n=100, lx=1.0, w=0.01):
 def random_displacement(n_nodes, scale=1e-6, seed=3):
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n_nodes, 3)) * scale
+
+
+def union(meshes):
+    """Disjoint union of meshes (a batch).  Returns the union mesh and the node
+    and tet offsets of each member (member i owns nodes [node_off[i],
+    node_off[i+1]) and tets [tet_off[i], tet_off[i+1]))."""
+    node_off = np.zeros(len(meshes) + 1, dtype=np.int64)
+    tet_off = np.zeros(len(meshes) + 1, dtype=np.int64)
+    for i, mm in enumerate(meshes):
+        node_off[i + 1] = node_off[i] + mm.n_nodes
+        tet_off[i + 1] = tet_off[i] + mm.n_tets
+    X = np.concatenate([mm.X for mm in meshes])
+    tets = np.concatenate([mm.tets.astype(np.int64) + node_off[i] for i, mm in enumerate(meshes)])
+    out = Mesh(X=X, tets=tets.astype(np.int32))
+    ps = [mm.presplit_tets.astype(np.int64) + tet_off[i] for i, mm in enumerate(meshes)
+          if mm.presplit_tets is not None]
+    if ps:
+        out.presplit_tets = np.concatenate(ps).astype(np.int32)
+        out.presplit_masks = np.concatenate([mm.presplit_masks for mm in meshes
+                                             if mm.presplit_tets is not None])
+    lt = [mm.load_tris.astype(np.int64) + node_off[i] for i, mm in enumerate(meshes)
+          if mm.load_tris is not None]
+    if lt:
+        out.load_tris = np.concatenate(lt).astype(np.int32)
+        out.load_trac = np.concatenate([mm.load_trac for mm in meshes if mm.load_tris is not None])
+    return out, node_off.astype(np.int32), tet_off.astype(np.int32)
+
+
+def ensemble(n=64, tmin=20000, tmax=200000, seed=2):
+    """Batch of n notched plates of the 100 x 40 x 4 mm geometry with seeded
+    sizes T_i ~ U[tmin, tmax] tets (cells round(25 s) x round(10 s) x
+    max(1, round(s)) with s = (T_i / 1500)^(1/3)) and tractions ~ U[0.5, 2] MPa."""
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(tmin, tmax, size=n)
+    trac = rng.uniform(0.5e6, 2.0e6, size=n)
+    meshes = []
+    for Ti, ti in zip(T, trac):
+        s = (Ti / 1500.0) ** (1.0 / 3.0)
+        nx, ny, nz = int(round(25 * s)), int(round(10 * s)), max(1, int(round(s)))
+        meshes.append(plate_notched(nx, ny, nz, traction=float(ti)))
+    u, no, to = union(meshes)
+    return u, no, to, meshes, trac
