@@ -57,10 +57,12 @@ def _edges_and_patches(elem_nodes):
     return patches
 
 
-def assemble(X, elem_nodes, E, nu, Veff=None, grads_from=None):
+def assemble(X, elem_nodes, E, nu, Veff=None, grads_from=None, parts=None):
     """Dense K_ES and K_FEM for elements with node lists `elem_nodes`.
 
-    X: [N, 3] coordinates of every node referenced.  Veff: per-element volume
+    X: [N, 3] coordinates of every node referenced.  E: scalar or one modulus
+    per element; the smoothing domain of an edge then has the volume-averaged
+    elasticity C_k = sum_j w_jk C(E_j).  Veff: per-element volume
     carried (defaults to the geometric volume).  grads_from: optional [ne, 4]
     node ids whose coordinates define each element's geometry (for split copies
     whose extra nodes sit on top of their twins the geometry is the same).
@@ -68,8 +70,9 @@ def assemble(X, elem_nodes, E, nu, Veff=None, grads_from=None):
     X = np.asarray(X, float)
     elem_nodes = np.asarray(elem_nodes)
     N = len(X)
-    C = cmat(E, nu)
     ne = len(elem_nodes)
+    Ej = np.broadcast_to(np.asarray(E, float), (ne,))
+    Cs = [cmat(e, nu) for e in Ej]
     Bs, Vs = [], []
     for j in range(ne):
         geo = elem_nodes[j] if grads_from is None else grads_from[j]
@@ -85,14 +88,27 @@ def assemble(X, elem_nodes, E, nu, Veff=None, grads_from=None):
         if S == 0:
             continue
         Bt = np.zeros((6, 3 * N))
+        Ck = np.zeros((6, 6))
         for j in pj:
             Bt[:, dof(elem_nodes[j])] += (Ve[j] / S) * Bs[j]
-        K += (S / 6.0) * Bt.T @ C @ Bt
+            Ck += (Ve[j] / S) * Cs[j]
+        if parts is not None:
+            for j in pj:
+                parts[j] += (Ve[j] / 6.0) * Bt.T @ cmat(1.0, nu) @ Bt
+        K += (S / 6.0) * Bt.T @ Ck @ Bt
     Kf = np.zeros((3 * N, 3 * N))
     for j in range(ne):
         d = dof(elem_nodes[j])
-        Kf[np.ix_(d, d)] += Ve[j] * Bs[j].T @ C @ Bs[j]
+        Kf[np.ix_(d, d)] += Ve[j] * Bs[j].T @ Cs[j] @ Bs[j]
     return K, Kf
+
+
+def modulus_parts(X, elem_nodes, nu, Veff=None, grads_from=None):
+    """dK_ES/dE_j for every element j (dense), so that K_ES(E) = sum_j E_j K_j."""
+    N = len(X)
+    parts = [np.zeros((3 * N, 3 * N)) for _ in range(len(elem_nodes))]
+    assemble(X, elem_nodes, 1.0, nu, Veff, grads_from, parts=parts)
+    return parts
 
 
 def lumped_mass(N, elem_nodes, Veff, rho):

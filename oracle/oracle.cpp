@@ -32,7 +32,14 @@
 //     elements (kept fixed in erosion mode);
 //   * dissipated energy U_d = Gc * (midpoint crack area) summed over splits
 //     decided by the G test (host pre-splits excluded);
-//   * critical step dt_crit = 2 / sqrt(max_e (4/rho) lambda_max(B^T C B)).
+//   * critical step dt_crit = 2 / sqrt(max_e (4/rho) lambda_max(B^T C B));
+//   * a Young's modulus per tetrahedron (split copies keep their parent's)
+//     enters the smoothing domain of edge k as C_k = sum_j w_jk C_j, the
+//     volume average of the element matrices over the domain, so that
+//     sigma_k = C_k eps_k;
+//   * the gradient of a window of fixed-topology steps is the exact reverse
+//     (discrete adjoint) of the Newmark update, with the per-tet modulus,
+//     the initial displacement and the initial velocity as the inputs.
 #include "oracle.h"
 
 #include <algorithm>
@@ -135,6 +142,9 @@ struct orc_ctx {
   std::vector<int> smask;  // per original tet: -1 intact, else side mask
   std::vector<double> m;
   std::vector<V3> F;
+  std::vector<double> Et;  // Young's modulus of each original tet
+  bool hetero = false;     // Et differs from the scalar E
+  bool frozen = false;     // topology frozen: no crack pass
   double ramp_t0 = 0;
   double dt = 0;
   long step = 0;
@@ -295,10 +305,33 @@ void rebuild_masses(orc_ctx* c) {
 // Smoothed strain and stress of every edge (Eqs. strain_discretization and
 // CSTet_strain_discretization): eps_k = sum_j w_jk B_j u_j with
 // w_jk = V_j / sum V over the elements sharing edge k; sigma_k = C eps_k.
+// Elasticity matrix of element j: that of its parent tet's modulus.
+void elem_cmat(const orc_ctx* c, int j, double C[6][6]) {
+  double lam, mu;
+  lame(c->Et[c->el[j].parent], c->nu, &lam, &mu);
+  cmat(lam, mu, C);
+}
+
+// Smoothing-domain elasticity of edge k: C_k = sum_j w_jk C_j (the volume
+// average over the domain; C_k = C for a single modulus).
+void edge_cmat(const orc_ctx* c, int k, double S, double Ck[6][6]) {
+  if (!c->hetero) {
+    cmat(c->lam, c->mu, Ck);
+    return;
+  }
+  for (int r = 0; r < 6; ++r)
+    for (int q = 0; q < 6; ++q) Ck[r][q] = 0.0;
+  for (int j : c->patch[k]) {
+    double Cj[6][6];
+    elem_cmat(c, j, Cj);
+    double w = c->el[j].Veff / S;
+    for (int r = 0; r < 6; ++r)
+      for (int q = 0; q < 6; ++q) Ck[r][q] += w * Cj[r][q];
+  }
+}
+
 void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::array<double, 6>>& eps,
                  std::vector<std::array<double, 6>>& sig, std::vector<double>& Vsum) {
-  double C[6][6];
-  cmat(c->lam, c->mu, C);
   std::vector<std::array<double, 6>> eps_el(c->el.size());
   for (size_t j = 0; j < c->el.size(); ++j) {
     double B[6][12], ue[12];
@@ -324,6 +357,8 @@ void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::ar
       double w = c->el[j].Veff / S;
       for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];
     }
+    double C[6][6];
+    edge_cmat(c, (int)k, S, C);
     for (int r = 0; r < 6; ++r) {
       double s = 0;
       for (int q = 0; q < 6; ++q) s += C[r][q] * eps[k][q];
@@ -585,6 +620,8 @@ void one_step(orc_ctx* c) {
       e.G = 0.0;
       evs.push_back(e);
     }
+  } else if (c->frozen) {
+    // fixed-topology window: no crack pass
   } else if (c->Gc < INFINITY) {
     evs = decide_splits(c);
   } else {
@@ -604,6 +641,97 @@ double strain_energy(const orc_ctx* c) {
     se += 0.5 * (Vsum[k] / 6.0) * s;
   }
   return se;
+}
+
+// lambda^T (dK/dE_j) u for every original tet j, times `scale`, added to
+// out[j].  With C_k = sum_j w_jk C_j and C_j = E_j Chat (Chat: the matrix at
+// unit modulus), dK/dE_j = sum_{k : j in patch k} V_k w_jk Bt_k^T Chat Bt_k,
+// so the term is sum_k V_k w_jk eps_k(lambda) . Chat eps_k(u) with eps_k the
+// smoothed strain of edge k.  Split copies add to their parent tet.
+void modulus_term(const orc_ctx* c, const std::vector<V3>& lam, const std::vector<V3>& u, double scale,
+                  std::vector<double>& out) {
+  std::vector<std::array<double, 6>> el, sl, eu, su;
+  std::vector<double> Vs;
+  edge_fields(c, lam, el, sl, Vs);
+  edge_fields(c, u, eu, su, Vs);
+  double lh, mh, Ch[6][6];
+  lame(1.0, c->nu, &lh, &mh);
+  cmat(lh, mh, Ch);
+  for (size_t k = 0; k < Vs.size(); ++k) {
+    double S = Vs[k];
+    if (S == 0.0) continue;
+    double q = 0;
+    for (int r = 0; r < 6; ++r)
+      for (int p = 0; p < 6; ++p) q += el[k][r] * Ch[r][p] * eu[k][p];
+    double Vk = S / 6.0;
+    for (int j : c->patch[k]) out[c->el[j].parent] += scale * Vk * (c->el[j].Veff / S) * q;
+  }
+}
+
+// Sensitivity of J = gu . u_N + gv . v_N to the modulus of every tet and to
+// the initial state, over n steps of fixed topology taken from the current
+// state.  The forward step (Newmark beta = 0, gamma = 1/2, end of
+// Section 2.2) is
+//   u_{n+1} = u_n + dt v_n + dt^2/2 a_n,
+//   a_{n+1} = M^-1 (r_{n+1} F - K u_{n+1}),
+//   v_{n+1} = v_n + dt/2 (a_n + a_{n+1}),
+// with a_0 = M^-1 (r_0 F - K u_0).  Reversing these three assignments with
+// sensitivities ub, vb, ab (K is symmetric, M diagonal) gives per step
+//   ab_{n+1} += dt/2 vb_{n+1};  lambda = M^-1 ab_{n+1};
+//   ub_{n+1} -= K lambda;  Eb_j -= lambda^T dK/dE_j u_{n+1};
+//   ub_n += ub_{n+1};  vb_n += vb_{n+1} + dt ub_{n+1};
+//   ab_n += dt/2 vb_{n+1} + dt^2/2 ub_{n+1},
+// and a_0 takes the treatment of a_{n+1} once more at the end.
+int window_gradient(orc_ctx* c, int n, const double* gu, const double* gv, double* gu0, double* gv0,
+                    double* gE) {
+  if (c->need_init) initialize(c);
+  bool was = c->frozen;
+  c->frozen = true;
+  std::vector<std::vector<V3>> us;
+  us.push_back(c->u);
+  for (int s = 0; s < n; ++s) {
+    one_step(c);
+    us.push_back(c->u);
+  }
+  c->frozen = was;
+  size_t N = c->X.size();
+  const double dt = c->dt;
+  std::vector<V3> ub(N), vb(N), ab(N, V3{0, 0, 0}), lam(N), f;
+  for (size_t i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d) {
+      ub[i][d] = gu ? gu[3 * i + d] : 0.0;
+      vb[i][d] = gv ? gv[3 * i + d] : 0.0;
+    }
+  std::vector<double> Eb(c->T0, 0.0);
+  auto invm = [&](size_t i) { return c->m[i] > 0 ? 1.0 / c->m[i] : 0.0; };
+  for (int s = n - 1; s >= -1; --s) {
+    // the acceleration of index s + 1 (s = -1: a_0 of the initial state)
+    for (size_t i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) {
+        if (s >= 0) ab[i][d] += 0.5 * dt * vb[i][d];
+        lam[i][d] = invm(i) * ab[i][d];
+      }
+    internal_force(c, lam, f);
+    for (size_t i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) ub[i][d] -= f[i][d];
+    modulus_term(c, lam, us[s + 1], -1.0, Eb);
+    if (s < 0) break;
+    for (size_t i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double u1 = ub[i][d], v1 = vb[i][d];
+        vb[i][d] = v1 + dt * u1;
+        ab[i][d] = 0.5 * dt * v1 + 0.5 * dt * dt * u1;
+        // ub_n = ub_{n+1}: unchanged
+      }
+  }
+  for (size_t i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d) {
+      if (gu0) gu0[3 * i + d] = ub[i][d];
+      if (gv0) gv0[3 * i + d] = vb[i][d];
+    }
+  if (gE)
+    for (int t = 0; t < c->T0; ++t) gE[t] = Eb[t];
+  return 0;
 }
 
 }  // namespace
@@ -690,6 +818,7 @@ orc_ctx* orc_create(int n_nodes, const double* X, int n_tets, const int* tets, d
     }
   }
   c->smask.assign(n_tets, -1);
+  c->Et.assign(n_tets, E);
   c->u.assign(n_nodes, {0, 0, 0});
   c->v.assign(n_nodes, {0, 0, 0});
   c->a.assign(n_nodes, {0, 0, 0});
@@ -782,6 +911,8 @@ int orc_elem_lambda_max(orc_ctx* c, double* lam) {
     memo[key] = lm;
     lam[t] = lm;
   }
+  // C_t = (E_t / E) C, and the eigenvalues of B^T C_t B scale with it
+  for (int t = 0; t < c->T0; ++t) lam[t] *= c->Et[t] / c->E;
   return 0;
 }
 
@@ -968,6 +1099,32 @@ double orc_crack_area(const double* X4, int mask) {
   V3 x[4];
   for (int l = 0; l < 4; ++l) x[l] = {X4[3 * l], X4[3 * l + 1], X4[3 * l + 2]};
   return crack_area(x, mask);
+}
+
+int orc_set_modulus(orc_ctx* c, const double* E_tet) {
+  for (int t = 0; t < c->T0; ++t) {
+    if (!(E_tet[t] > 0)) return c->fail(-1, "modulus must be positive");
+  }
+  bool het = false;
+  for (int t = 0; t < c->T0; ++t) {
+    c->Et[t] = E_tet[t];
+    het = het || E_tet[t] != c->E;
+  }
+  c->hetero = het;
+  c->need_init = true;
+  return 0;
+}
+
+int orc_set_frozen(orc_ctx* c, int on) {
+  c->frozen = on != 0;
+  return 0;
+}
+
+int orc_window_gradient(orc_ctx* c, int n_steps, const double* gu, const double* gv, double* gu0,
+                        double* gv0, double* gE) {
+  if (!(c->dt > 0)) return c->fail(-7, "dt not set");
+  if (n_steps < 0) return c->fail(-1, "negative step count");
+  return window_gradient(c, n_steps, gu, gv, gu0, gv0, gE);
 }
 
 }  // extern "C"

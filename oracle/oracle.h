@@ -54,6 +54,17 @@ int orc_front_G(orc_ctx* c, int cap, int* tfl3, double* g2, int* n_out);
 /* forced split schedule (step, tet, mask), sorted by step then tet */
 int orc_replay(orc_ctx* c, int n, const int* ev3);
 
+/* Young's modulus per original tet (Pa); split copies use their parent's */
+int orc_set_modulus(orc_ctx* c, const double* E_tet);
+/* 1: steps skip the crack pass (fixed topology) */
+int orc_set_frozen(orc_ctx* c, int on);
+/* Runs n fixed-topology steps from the current state and returns the
+ * sensitivities of J = gu . u_n + gv . v_n (either may be NULL = 0) to the
+ * initial u and v ([n_nodes_now][3]) and to each tet's modulus ([n_tets]).
+ * The state is left at the end of the window. */
+int orc_window_gradient(orc_ctx* c, int n_steps, const double* gu, const double* gv,
+                        double* gu0, double* gv0, double* gE);
+
 /* inspection */
 int orc_masses(orc_ctx* c, double* m);
 int orc_loads(orc_ctx* c, double* F);

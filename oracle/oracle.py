@@ -22,7 +22,9 @@ _p = C.c_void_p
 
 def build(force=False):
     """Compile the oracle with g++ (plain FP64, no fused multiply-add)."""
-    if force or not os.path.exists(LIB):
+    stale = not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+        os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "oracle.h")))
+    if force or stale:
         cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-ffp-contract=off",
                "-o", LIB + ".tmp", SRC]
         subprocess.run(cmd, check=True)
@@ -66,6 +68,9 @@ def lib():
             ("orc_edges", [_p, _p, _p, _p, _p]),
             ("orc_elem_lambda_max", [_p, _p]),
             ("orc_sym_eig3", [_p, _p, _p]),
+            ("orc_set_modulus", [_p, _p]),
+            ("orc_set_frozen", [_p, _i]),
+            ("orc_window_gradient", [_p, _i, _p, _p, _p, _p, _p]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -148,9 +153,11 @@ class Oracle:
 
     @classmethod
     def from_mesh(cls, mesh, material, split_mode="phantom", gsig="principal", presplit=True,
-                  traction=True, ramp_t0=0.0, Gc=None):
+                  traction=True, ramp_t0=0.0, Gc=None, E_tet=None):
         o = cls(mesh.X, mesh.tets, material["E"], material["nu"], material["rho"],
                 material["Gc"] if Gc is None else Gc, split_mode, gsig)
+        if E_tet is not None:
+            o.set_modulus(E_tet)
         if traction and mesh.load_tris is not None:
             o.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
         if presplit and mesh.presplit_tets is not None:
@@ -227,6 +234,28 @@ class Oracle:
         g = np.zeros((max(n.value, 1), 2))
         self._chk(lib().orc_front_G(self.c, n.value, _ptr(tfl), _ptr(g), C.byref(n)))
         return tfl[: n.value], g[: n.value]
+
+    def set_modulus(self, E_tet):
+        """Young's modulus of every original tet (split copies take their parent's)."""
+        E = _f64(E_tet)
+        if E.shape != (len(self._t),):
+            raise OracleError("one modulus per tet")
+        self._chk(lib().orc_set_modulus(self.c, _ptr(E)))
+
+    def set_frozen(self, on=True):
+        self._chk(lib().orc_set_frozen(self.c, int(bool(on))))
+
+    def window_gradient(self, n_steps, gu=None, gv=None):
+        """Run n fixed-topology steps; return (dJ/du0, dJ/dv0, dJ/dE) for
+        J = gu . u_n + gv . v_n.  The state is left at the end of the window."""
+        n = self.n_nodes
+        gu = None if gu is None else _f64(gu, (n, 3))
+        gv = None if gv is None else _f64(gv, (n, 3))
+        gu0, gv0 = np.zeros((n, 3)), np.zeros((n, 3))
+        gE = np.zeros(len(self._t))
+        self._chk(lib().orc_window_gradient(self.c, int(n_steps), _ptr(gu), _ptr(gv), _ptr(gu0),
+                                            _ptr(gv0), _ptr(gE)))
+        return gu0, gv0, gE
 
     def replay(self, ev3):
         ev3 = _i32(ev3).reshape(-1, 3)
