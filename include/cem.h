@@ -213,6 +213,50 @@ int cem_set_launch(cem_ctx* ctx, int32_t grid_cap, int32_t lanes);
 int cem_autotune(cem_ctx* ctx, int32_t trial_steps, int32_t* best_grid, int32_t* best_lanes,
                  double* best_ms_per_step);
 
+/* ---- Heterogeneous modulus and fixed-topology gradient windows
+ *
+ * Young's modulus of every tet, E[n_tets] in Pa in the caller's tet order
+ * (NULL: back to the material's scalar E).  Each split copy takes its
+ * parent's modulus.  The smoothing domain of edge k gets the volume-averaged
+ * elasticity C_k = sum_{j in patch k} w_jk C(E_j) of the expanded form of
+ * Eq. CSTet_fint_discretization, so sigma_k = C_k eps_k.  Any value that is
+ * not finite and positive is CEM_EINVAL.  Call cem_critical_dt again after a
+ * change: the bound scales with the largest modulus. */
+int cem_set_modulus(cem_ctx* ctx, int32_t n_tets, const double* E);
+
+/* Set the step counter, hence the time t = step * dt at which the load ramp
+ * is evaluated (the state and the accumulated external work are kept; the
+ * next step recomputes a from u). */
+int cem_set_step(cem_ctx* ctx, int64_t step);
+
+/* Forward half of a gradient window: n_steps steps (Newmark beta = 0,
+ * gamma = 1/2, end of Section 2.2) from the current state with the crack pass
+ * off, so the topology stays fixed.  The state (u, v, a, predictor,
+ * counters, external work) is checkpointed in device memory at the start,
+ * every `every` steps and at the end: about 128 (n_steps / every + 2) bytes
+ * per node, plus (every + 1) * 32 bytes per node of recompute tape at the
+ * backward.  The state is left at the end of the window, as cem_step leaves
+ * it.  Any call that changes the state, the mesh or the launch shape
+ * afterwards (cem_step, cem_set_state, cem_set_modulus, ...) discards the
+ * window. */
+int cem_window_forward(cem_ctx* ctx, int32_t n_steps, int32_t every);
+
+/* Reverse half: given gu = dJ/du_n and gv = dJ/dv_n at the window's end
+ * ([n_nodes_now][3] in the caller's node order, either may be NULL = 0),
+ * returns dJ/du_0 and dJ/dv_0 ([n_nodes_now][3]) and dJ/dE ([n_tets], per Pa;
+ * copies add to their parent tet); any output may be NULL.  This is the
+ * discrete adjoint of the window's update: each checkpoint segment is
+ * recomputed forward, then reversed step by step with K^T = K.  The state is
+ * restored to the window's end.  CEM_ESTATE if no window is pending. */
+int cem_window_backward(cem_ctx* ctx, const double* gu, const double* gv, double* gu0,
+                        double* gv0, double* gE);
+
+/* Time of the last cem_window_backward, in milliseconds: out[0] whole call,
+ * out[1] forward recompute of the segments, out[2] reverse strain pass,
+ * out[3] reverse edge pass, out[4] reverse element pass, out[5] reverse node
+ * pass.  out[1..5] are recorded only when profiling is on. */
+int cem_window_times(cem_ctx* ctx, double* out);
+
 /* Time of the kernels of the last cem_step, in milliseconds, measured with
  * HIP events on the context stream: out[0] whole call, out[1] strain pass,
  * out[2] edge stress pass, out[3] crack pass, out[4] element force terms,

@@ -30,6 +30,7 @@ EXPORTS = [
     "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
     "cem_set_profiling", "cem_kernel_times", "cem_set_instances", "cem_set_dt_instances",
     "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
+    "cem_set_modulus", "cem_set_step", "cem_window_forward", "cem_window_backward", "cem_window_times",
 ]
 
 
@@ -112,6 +113,11 @@ def load_library(path=LIB_PATH):
         "cem_set_launch": [p, i32, i32],
         "cem_autotune": [p, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                          C.POINTER(C.c_double)],
+        "cem_set_modulus": [p, i32, p],
+        "cem_set_step": [p, i64],
+        "cem_window_forward": [p, i32, i32],
+        "cem_window_backward": [p, p, p, p, p, p],
+        "cem_window_times": [p, p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -164,11 +170,13 @@ class Simulation:
 
     @classmethod
     def from_mesh(cls, mesh, material, presplit=True, traction=True, ramp_t0=0.0, Gc=None,
-                  **kw):
+                  E_tet=None, **kw):
         mat = dict(material)
         if Gc is not None:
             mat["Gc"] = Gc
         sim = cls(mesh.X, mesh.tets, mat, **kw)
+        if E_tet is not None:
+            sim.set_modulus(E_tet)
         if traction and mesh.load_tris is not None:
             sim.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
         if presplit and mesh.presplit_tets is not None:
@@ -325,3 +333,35 @@ class Simulation:
         self._chk(self.lib.cem_autotune(self.ctx, int(trial_steps), C.byref(g), C.byref(l),
                                         C.byref(ms)))
         return dict(grid_cap=g.value, lanes=l.value, ms_per_step=ms.value)
+
+    # ---- heterogeneous modulus and gradient windows
+    def set_modulus(self, E_tet):
+        """Young's modulus per tet (Pa, caller order); None: the scalar material E."""
+        if E_tet is None:
+            self._chk(self.lib.cem_set_modulus(self.ctx, 0, None))
+            return
+        E = np.ascontiguousarray(E_tet, dtype=np.float64).reshape(-1)
+        self._chk(self.lib.cem_set_modulus(self.ctx, len(E), _p(E)))
+
+    def set_step(self, step):
+        """Step counter (time = step * dt for the load ramp); the state is kept."""
+        self._chk(self.lib.cem_set_step(self.ctx, int(step)))
+
+    def window_forward(self, n_steps, every=50):
+        self._chk(self.lib.cem_window_forward(self.ctx, int(n_steps), int(every)))
+
+    def window_backward(self, gu=None, gv=None):
+        """(dJ/du0, dJ/dv0, dJ/dE) of J = gu . u_n + gv . v_n over the pending window."""
+        n = self.n_nodes
+        gu = None if gu is None else _f64(gu, (n, 3))
+        gv = None if gv is None else _f64(gv, (n, 3))
+        gu0, gv0, gE = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(self.n_tets)
+        self._chk(self.lib.cem_window_backward(self.ctx, _p(gu), _p(gv), _p(gu0), _p(gv0),
+                                               _p(gE)))
+        return gu0, gv0, gE
+
+    def window_times(self):
+        out = np.zeros(6)
+        self._chk(self.lib.cem_window_times(self.ctx, _p(out)))
+        return dict(zip(["total", "recompute", "strain2", "edge2", "elem_adj", "node_adj"],
+                        out.tolist()))

@@ -91,6 +91,7 @@ struct Mesh {
   double* rec_G;
   int* sched;               // forced schedule (step, tet, mask) triples
   double* rec_area;         // [S_cap] midpoint crack area of each split
+  double* kap;              // [T_cap] modulus of each element slot over E (null: uniform E)
 
   // batch of independent instances (all null when n_inst == 0)
   int* inst;                // [N_cap] instance of each node
@@ -106,7 +107,8 @@ struct Mesh {
 struct Work {
   void* veps;               // [T_cap] Six<R>: effective volume x element strain
   void* esig;               // [E_cap] Six<R>: smoothed edge stress
-  void* einvV;              // [E_cap] R: 1 / sum of effective volumes of the patch
+  void* einvV;              // [E_cap] R: kappa_k / sum of effective volumes of the patch,
+                            // kappa_k the volume-averaged relative modulus (1 if uniform)
   void* contrib;            // [T_cap][4] R4: nodal force terms, index (e << 2) | l
   double* partial;          // reduction partials
 };
@@ -127,7 +129,8 @@ template <class R> struct Launch {
                           int flagging, hipStream_t s);
   static hipError_t node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                          double4* fout, hipStream_t s, hipEvent_t mid = nullptr);
-  static hipError_t edge_volumes(const Mesh& m, const Work& w, hipStream_t s);
+  // einvV of the first `count` edges (count < 0: the original edges)
+  static hipError_t edge_volumes(const Mesh& m, const Work& w, int count, hipStream_t s);
   static hipError_t front_eval(const Mesh& m, const State& st, const Work& w, Counters* c,
                                int* out_tfl, double* out_g, int* out_n, hipStream_t s);
 };
@@ -151,8 +154,27 @@ hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, int inst, h
 hipError_t launch_work_sum(const Mesh& m, double* out, int inst, hipStream_t s);
 hipError_t launch_dissipated(const Mesh& m, Counters* c, double* out, int inst, hipStream_t s);
 hipError_t launch_edge_instances(const Mesh& m, hipStream_t s);
+// split copies take their parent's relative modulus (n_split copies)
+hipError_t launch_kap_copies(const Mesh& m, int n_split, hipStream_t s);
 hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, const uint8_t* masks,
                                int n, hipStream_t s);
+// ---- reverse sweep of a fixed-topology window (adjoint.hip) ----
+template <class R> struct Adjoint {
+  static hipError_t strain2(const Mesh& m, const double4* lam, const double4* u, void* vl,
+                            void* vu, const Counters* c, hipStream_t s);
+  // lh, mh: Lame constants at unit modulus
+  static hipError_t edge2(const Mesh& m, const void* vl, const void* vu, const void* einvV,
+                          const void* einv0, void* esig, void* z, double lh, double mh,
+                          const Counters* c, hipStream_t s);
+  static hipError_t elem(const Mesh& m, const void* esig, const void* z, void* contrib,
+                         double* gE, const Counters* c, hipStream_t s);
+  static hipError_t node(const Mesh& m, const void* contrib, double4* p, double4* q,
+                         double4* lam, int last, int half, const Counters* c, hipStream_t s);
+  static hipError_t inv_volumes(const Mesh& m, void* out, int count, hipStream_t s);
+};
+hipError_t launch_adj_init(const Mesh& m, const double4* q, double4* lam, double coef,
+                           const Counters* c, hipStream_t s);
+
 int grid_for(long long n);
 double key_to_double_host(unsigned long long k);
 

@@ -1,0 +1,244 @@
+// Device helpers shared by the kernel files of the step and of its adjoint.
+#ifndef CEM_DEVICE_UTIL_H
+#define CEM_DEVICE_UTIL_H
+
+#include "cem_device.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace cem {
+
+// ---------------------------------------------------------------- helpers
+
+// Persistent grid-stride launch: the grid (a multiple of 8 workgroups) is
+// sized to the chip, not to the data.  Chunks of kBlock items are split into
+// eight contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), and
+// the workgroups of an XCD stride through its range.  The item count is read
+// on the device, so a captured graph stays valid as splits add elements.
+struct Chunks {
+  int ch, hi, stride;
+  __device__ __forceinline__ Chunks(long long count) {
+    long long nch = (count + kBlock - 1) / kBlock;
+    int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    stride = gridDim.x / 8;
+    ch = (int)(nch * x / 8) + j;
+    hi = (int)(nch * (x + 1) / 8);
+  }
+  __device__ __forceinline__ bool next(int& item) {
+    if (ch >= hi) return false;
+    item = ch * kBlock + threadIdx.x;
+    ch += stride;
+    return true;
+  }
+};
+
+__device__ __forceinline__ double frac_of(int code) {
+  return code == FR_ONE ? 1.0 : code == FR_HALF ? 0.5 : code == FR_EIGHTH ? 0.125
+       : code == FR_SEVEN8 ? 0.875 : 0.0;
+}
+
+__device__ __forceinline__ int pack0(int node, int code) { return node | (code << kNodeBits); }
+
+__device__ __forceinline__ unsigned long long dkey(double x) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double key_to_double(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  union { unsigned long long u; double d; } x;
+  x.u = b;
+  return x.d;
+}
+
+template <class R> __device__ __forceinline__ Six<R> load6(const Six<R>* p) { return *p; }
+template <class R> __device__ __forceinline__ void store6(Six<R>* p, const R* v) {
+  Six<R> s;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s.v[i] = v[i];
+  *p = s;
+}
+
+template <class R> struct Vec4;
+template <> struct Vec4<double> {
+  typedef double4 T;
+  static __device__ __forceinline__ double4 make(double x, double y, double z) {
+    return make_double4(x, y, z, 0.0);
+  }
+};
+template <> struct Vec4<float> {
+  typedef float4 T;
+  static __device__ __forceinline__ float4 make(float x, float y, float z) {
+    return make_float4(x, y, z, 0.0f);
+  }
+};
+
+// Time step of node i (one per instance in a batch).
+__device__ __forceinline__ double node_dt(const Mesh& m, int i) {
+  return m.n_inst ? m.dti[m.inst[i]] : m.dt;
+}
+
+__device__ __forceinline__ double ramp(const Mesh& m, double t) {
+  return (m.ramp_t0 > 0.0 && t < m.ramp_t0) ? t / m.ramp_t0 : 1.0;
+}
+
+__device__ __forceinline__ int n_split_now(const Counters* c) { return c->n_split; }
+__device__ __forceinline__ int elems_now(const Mesh& m, const Counters* c) {
+  return m.T0 + (m.mode == MODE_PHANTOM ? c->n_split : 0);
+}
+__device__ __forceinline__ int nodes_now(const Mesh& m, const Counters* c) {
+  return m.N0 + (m.mode == MODE_PHANTOM ? 4 * c->n_split : 0);
+}
+__device__ __forceinline__ int edges_now(const Mesh& m, const Counters* c) {
+  return m.E0 + (m.mode == MODE_PHANTOM ? 10 * c->n_split : 0);
+}
+
+// g_l = 6 V grad N_l (l = 1..3) as face cross products of c_l = X_l - X_0:
+// g_1 = c2 x c3, g_2 = c3 x c1, g_3 = c1 x c2.  Differences in float64.
+template <class R>
+__device__ __forceinline__ void face_normals(double4 x0, double4 x1, double4 x2, double4 x3,
+                                             R g[3][3]) {
+  R c1x = (R)(x1.x - x0.x), c1y = (R)(x1.y - x0.y), c1z = (R)(x1.z - x0.z);
+  R c2x = (R)(x2.x - x0.x), c2y = (R)(x2.y - x0.y), c2z = (R)(x2.z - x0.z);
+  R c3x = (R)(x3.x - x0.x), c3y = (R)(x3.y - x0.y), c3z = (R)(x3.z - x0.z);
+  g[0][0] = c2y * c3z - c2z * c3y; g[0][1] = c2z * c3x - c2x * c3z; g[0][2] = c2x * c3y - c2y * c3x;
+  g[1][0] = c3y * c1z - c3z * c1y; g[1][1] = c3z * c1x - c3x * c1z; g[1][2] = c3x * c1y - c3y * c1x;
+  g[2][0] = c1y * c2z - c1z * c2y; g[2][1] = c1z * c2x - c1x * c2z; g[2][2] = c1x * c2y - c1y * c2x;
+}
+
+// d_l = u_l - u_0 (l = 1..3), taken in float64 before any conversion to R.
+template <class R>
+__device__ __forceinline__ void node_diffs(double4 u0, double4 u1, double4 u2, double4 u3,
+                                           R d[3][3]) {
+  d[0][0] = (R)(u1.x - u0.x); d[0][1] = (R)(u1.y - u0.y); d[0][2] = (R)(u1.z - u0.z);
+  d[1][0] = (R)(u2.x - u0.x); d[1][1] = (R)(u2.y - u0.y); d[1][2] = (R)(u2.z - u0.z);
+  d[2][0] = (R)(u3.x - u0.x); d[2][1] = (R)(u3.y - u0.y); d[2][2] = (R)(u3.z - u0.z);
+}
+
+// f sum_l sym(g_l (x) d_l) in Voigt order (xx, yy, zz, xy, yz, xz; engineering shear).
+template <class R>
+__device__ __forceinline__ void sym_grad(const R g[3][3], const R d[3][3], R f, R* out) {
+  out[0] = f * (g[0][0] * d[0][0] + g[1][0] * d[1][0] + g[2][0] * d[2][0]);
+  out[1] = f * (g[0][1] * d[0][1] + g[1][1] * d[1][1] + g[2][1] * d[2][1]);
+  out[2] = f * (g[0][2] * d[0][2] + g[1][2] * d[1][2] + g[2][2] * d[2][2]);
+  out[3] = f * (g[0][1] * d[0][0] + g[0][0] * d[0][1] + g[1][1] * d[1][0] + g[1][0] * d[1][1] +
+                g[2][1] * d[2][0] + g[2][0] * d[2][1]);
+  out[4] = f * (g[0][2] * d[0][1] + g[0][1] * d[0][2] + g[1][2] * d[1][1] + g[1][1] * d[1][2] +
+                g[2][2] * d[2][1] + g[2][1] * d[2][2]);
+  out[5] = f * (g[0][2] * d[0][0] + g[0][0] * d[0][2] + g[1][2] * d[1][0] + g[1][0] * d[1][2] +
+                g[2][2] * d[2][0] + g[2][0] * d[2][2]);
+}
+
+// Sum of V_eff eps over the patch of edge k, in patch order.  Entry ids are
+// fetched in batches so that the element gathers of a batch are in flight
+// together.
+template <class R>
+__device__ __forceinline__ void edge_sum(const Mesh& m, const Six<R>* __restrict__ veps, int k,
+                                         R* acc) {
+  constexpr int B = 6;
+  int p0 = m.poff[k], p1 = m.poff[k + 1];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[i] = 0;
+  for (int base = p0; base < p1; base += B) {
+    int ids[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) ids[j] = base + j < p1 ? m.pent[base + j] : -1;
+    Six<R> v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      if (ids[j] >= 0) v[j] = load6(veps + ids[j]);
+      else
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[j].v[i] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) acc[i] += v[j].v[i];
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void hooke(R lam, R mu, const R* eps, R* sig) {
+  R tr = eps[0] + eps[1] + eps[2];
+  sig[0] = lam * tr + 2 * mu * eps[0];
+  sig[1] = lam * tr + 2 * mu * eps[1];
+  sig[2] = lam * tr + 2 * mu * eps[2];
+  sig[3] = mu * eps[3];
+  sig[4] = mu * eps[4];
+  sig[5] = mu * eps[5];
+}
+
+// Nodal terms of element e: c_{e,l} = (V_eff / 6) B_l^T sum_{k in edges(e)} sigma_k
+// = (f / 36) G_l^T s with G_l = 6 V grad N_l (G_0 = -(G_1 + G_2 + G_3)).
+template <class R>
+__device__ __forceinline__ void elem_terms(const Mesh& m, int e, int4 nd, int code,
+                                           const Six<R>* __restrict__ esig, R out[4][3]) {
+  int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
+  double4 x0 = m.X[nd.x & kNodeMask], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
+  Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
+  Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+  R g[4][3];
+  face_normals(x0, x1, x2, x3, g + 1);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+  R sg[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
+  R w = (R)(frac_of(code) / 36.0);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    R gx = g[l][0], gy = g[l][1], gz = g[l][2];
+    out[l][0] = w * (gx * sg[0] + gy * sg[3] + gz * sg[5]);
+    out[l][1] = w * (gy * sg[1] + gx * sg[3] + gz * sg[4]);
+    out[l][2] = w * (gz * sg[2] + gy * sg[4] + gx * sg[5]);
+  }
+}
+
+// Store the four nodal terms at the element's positions in the node lists.
+template <class R>
+__device__ __forceinline__ void store_terms(R* __restrict__ contrib, int4 pos, const R out[4][3]) {
+  typedef typename Vec4<R>::T R4;
+  R4* o = (R4*)contrib;
+  o[pos.x] = Vec4<R>::make(out[0][0], out[0][1], out[0][2]);
+  o[pos.y] = Vec4<R>::make(out[1][0], out[1][1], out[1][2]);
+  o[pos.z] = Vec4<R>::make(out[2][0], out[2][1], out[2][2]);
+  o[pos.w] = Vec4<R>::make(out[3][0], out[3][1], out[3][2]);
+}
+
+// Sum of node i's contiguous terms by G lanes (lane g takes entries g, g + G,
+// ...), combined by a fixed butterfly of shuffles, so the sum is the same on
+// every run.  Every lane of the group must call it.
+template <class R, int G>
+__device__ __forceinline__ void node_gather(const Mesh& m, const R* __restrict__ contrib, int i,
+                                            bool active, int g, double& fx, double& fy,
+                                            double& fz) {
+  fx = fy = fz = 0;
+  const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
+  typedef typename Vec4<R>::T R4;
+  for (int p = p0 + g; p < p1; p += G) {
+    R4 q = ((const R4*)contrib)[p];
+    fx += (double)q.x;
+    fy += (double)q.y;
+    fz += (double)q.z;
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    fx += __shfl_xor(fx, off, G);
+    fy += __shfl_xor(fy, off, G);
+    fz += __shfl_xor(fz, off, G);
+  }
+}
+
+// Persistent grid: enough workgroups for the largest item count the launch
+// can see (capacity), capped at m.grid_cap; always a multiple of 8.
+static inline int persistent_grid(const Mesh& m, long long items) {
+  long long g = (items + kBlock - 1) / kBlock;
+  g = g < 8 ? 8 : g;
+  g = g > m.grid_cap ? m.grid_cap : g;
+  return (int)((g + 7) / 8 * 8);
+}
+
+}  // namespace cem
+
+#endif

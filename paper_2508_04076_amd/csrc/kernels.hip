@@ -15,96 +15,9 @@
 // which turns the edge-smoothed force of Eq. CSTet_fint_discretization into
 // a node-ordered gather.  Gradients are not stored: V grad N_l is a face
 // cross product over 6, so no element needs a determinant or a division.
-#include "cem_device.h"
-
-#include <float.h>
-#include <math.h>
+#include "device_util.h"
 
 namespace cem {
-
-// ---------------------------------------------------------------- helpers
-
-// Persistent grid-stride launch: the grid (a multiple of 8 workgroups) is
-// sized to the chip, not to the data.  Chunks of kBlock items are split into
-// eight contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), and
-// the workgroups of an XCD stride through its range.  The item count is read
-// on the device, so a captured graph stays valid as splits add elements.
-struct Chunks {
-  int ch, hi, stride;
-  __device__ __forceinline__ Chunks(long long count) {
-    long long nch = (count + kBlock - 1) / kBlock;
-    int x = blockIdx.x % 8, j = blockIdx.x / 8;
-    stride = gridDim.x / 8;
-    ch = (int)(nch * x / 8) + j;
-    hi = (int)(nch * (x + 1) / 8);
-  }
-  __device__ __forceinline__ bool next(int& item) {
-    if (ch >= hi) return false;
-    item = ch * kBlock + threadIdx.x;
-    ch += stride;
-    return true;
-  }
-};
-
-__device__ __forceinline__ double frac_of(int code) {
-  return code == FR_ONE ? 1.0 : code == FR_HALF ? 0.5 : code == FR_EIGHTH ? 0.125
-       : code == FR_SEVEN8 ? 0.875 : 0.0;
-}
-
-__device__ __forceinline__ int pack0(int node, int code) { return node | (code << kNodeBits); }
-
-__device__ __forceinline__ unsigned long long dkey(double x) {
-  unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__host__ __device__ inline double key_to_double(unsigned long long k) {
-  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
-  union { unsigned long long u; double d; } x;
-  x.u = b;
-  return x.d;
-}
-
-template <class R> __device__ __forceinline__ Six<R> load6(const Six<R>* p) { return *p; }
-template <class R> __device__ __forceinline__ void store6(Six<R>* p, const R* v) {
-  Six<R> s;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) s.v[i] = v[i];
-  *p = s;
-}
-
-template <class R> struct Vec4;
-template <> struct Vec4<double> {
-  typedef double4 T;
-  static __device__ __forceinline__ double4 make(double x, double y, double z) {
-    return make_double4(x, y, z, 0.0);
-  }
-};
-template <> struct Vec4<float> {
-  typedef float4 T;
-  static __device__ __forceinline__ float4 make(float x, float y, float z) {
-    return make_float4(x, y, z, 0.0f);
-  }
-};
-
-// Time step of node i (one per instance in a batch).
-__device__ __forceinline__ double node_dt(const Mesh& m, int i) {
-  return m.n_inst ? m.dti[m.inst[i]] : m.dt;
-}
-
-__device__ __forceinline__ double ramp(const Mesh& m, double t) {
-  return (m.ramp_t0 > 0.0 && t < m.ramp_t0) ? t / m.ramp_t0 : 1.0;
-}
-
-__device__ __forceinline__ int n_split_now(const Counters* c) { return c->n_split; }
-__device__ __forceinline__ int elems_now(const Mesh& m, const Counters* c) {
-  return m.T0 + (m.mode == MODE_PHANTOM ? c->n_split : 0);
-}
-__device__ __forceinline__ int nodes_now(const Mesh& m, const Counters* c) {
-  return m.N0 + (m.mode == MODE_PHANTOM ? 4 * c->n_split : 0);
-}
-__device__ __forceinline__ int edges_now(const Mesh& m, const Counters* c) {
-  return m.E0 + (m.mode == MODE_PHANTOM ? 10 * c->n_split : 0);
-}
 
 // local edge q of a tet joins local nodes (kEA[q], kEB[q])
 __device__ __constant__ int kEA[6] = {0, 0, 0, 1, 1, 2};
@@ -145,70 +58,16 @@ __global__ __launch_bounds__(kBlock) void k_strain(Mesh m, const double4* __rest
   int n0 = nd.x & kNodeMask;
   R out[6] = {0, 0, 0, 0, 0, 0};
   if (code != FR_ZERO) {
-    double4 x0 = m.X[n0], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
-    double4 u0 = u[n0], u1 = u[nd.y], u2 = u[nd.z], u3 = u[nd.w];
-    R c1x = (R)(x1.x - x0.x), c1y = (R)(x1.y - x0.y), c1z = (R)(x1.z - x0.z);
-    R c2x = (R)(x2.x - x0.x), c2y = (R)(x2.y - x0.y), c2z = (R)(x2.z - x0.z);
-    R c3x = (R)(x3.x - x0.x), c3y = (R)(x3.y - x0.y), c3z = (R)(x3.z - x0.z);
-    R d1x = (R)(u1.x - u0.x), d1y = (R)(u1.y - u0.y), d1z = (R)(u1.z - u0.z);
-    R d2x = (R)(u2.x - u0.x), d2y = (R)(u2.y - u0.y), d2z = (R)(u2.z - u0.z);
-    R d3x = (R)(u3.x - u0.x), d3y = (R)(u3.y - u0.y), d3z = (R)(u3.z - u0.z);
-    R g1x = c2y * c3z - c2z * c3y, g1y = c2z * c3x - c2x * c3z, g1z = c2x * c3y - c2y * c3x;
-    R g2x = c3y * c1z - c3z * c1y, g2y = c3z * c1x - c3x * c1z, g2z = c3x * c1y - c3y * c1x;
-    R g3x = c1y * c2z - c1z * c2y, g3y = c1z * c2x - c1x * c2z, g3z = c1x * c2y - c1y * c2x;
-    R f = (R)(frac_of(code) / 6.0);
-    out[0] = f * (g1x * d1x + g2x * d2x + g3x * d3x);
-    out[1] = f * (g1y * d1y + g2y * d2y + g3y * d3y);
-    out[2] = f * (g1z * d1z + g2z * d2z + g3z * d3z);
-    out[3] = f * (g1y * d1x + g1x * d1y + g2y * d2x + g2x * d2y + g3y * d3x + g3x * d3y);
-    out[4] = f * (g1z * d1y + g1y * d1z + g2z * d2y + g2y * d2z + g3z * d3y + g3y * d3z);
-    out[5] = f * (g1z * d1x + g1x * d1z + g2z * d2x + g2x * d2z + g3z * d3x + g3x * d3z);
+    R g[3][3], d[3][3];
+    face_normals(m.X[n0], m.X[nd.y], m.X[nd.z], m.X[nd.w], g);
+    node_diffs(u[n0], u[nd.y], u[nd.z], u[nd.w], d);
+    sym_grad(g, d, (R)(frac_of(code) / 6.0), out);
   }
   store6(veps + e, out);
   }
 }
 
 // ---------------------------------------------------------------- edge stress pass
-
-// Sum of V_eff eps over the patch of edge k, in patch order.  Entry ids are
-// fetched in batches so that the element gathers of a batch are in flight
-// together.
-template <class R>
-__device__ __forceinline__ void edge_sum(const Mesh& m, const Six<R>* __restrict__ veps, int k,
-                                         R* acc) {
-  constexpr int B = 6;
-  int p0 = m.poff[k], p1 = m.poff[k + 1];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) acc[i] = 0;
-  for (int base = p0; base < p1; base += B) {
-    int ids[B];
-#pragma unroll
-    for (int j = 0; j < B; ++j) ids[j] = base + j < p1 ? m.pent[base + j] : -1;
-    Six<R> v[B];
-#pragma unroll
-    for (int j = 0; j < B; ++j) {
-      if (ids[j] >= 0) v[j] = load6(veps + ids[j]);
-      else
-#pragma unroll
-        for (int i = 0; i < 6; ++i) v[j].v[i] = 0;
-    }
-#pragma unroll
-    for (int j = 0; j < B; ++j)
-#pragma unroll
-      for (int i = 0; i < 6; ++i) acc[i] += v[j].v[i];
-  }
-}
-
-template <class R>
-__device__ __forceinline__ void hooke(R lam, R mu, const R* eps, R* sig) {
-  R tr = eps[0] + eps[1] + eps[2];
-  sig[0] = lam * tr + 2 * mu * eps[0];
-  sig[1] = lam * tr + 2 * mu * eps[1];
-  sig[2] = lam * tr + 2 * mu * eps[2];
-  sig[3] = mu * eps[3];
-  sig[4] = mu * eps[4];
-  sig[5] = mu * eps[5];
-}
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_edge_stress(Mesh m, const Six<R>* __restrict__ veps,
@@ -294,37 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_elem_force(Mesh m, const Six<R>* __r
 #pragma unroll
     for (int l = 0; l < 4; ++l) out[l][0] = out[l][1] = out[l][2] = 0;
   } else {
-    int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
-    double4 x0 = m.X[nd.x & kNodeMask], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
-    Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
-    Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
-    R c1x = (R)(x1.x - x0.x), c1y = (R)(x1.y - x0.y), c1z = (R)(x1.z - x0.z);
-    R c2x = (R)(x2.x - x0.x), c2y = (R)(x2.y - x0.y), c2z = (R)(x2.z - x0.z);
-    R c3x = (R)(x3.x - x0.x), c3y = (R)(x3.y - x0.y), c3z = (R)(x3.z - x0.z);
-    R g[4][3];
-    g[1][0] = c2y * c3z - c2z * c3y; g[1][1] = c2z * c3x - c2x * c3z; g[1][2] = c2x * c3y - c2y * c3x;
-    g[2][0] = c3y * c1z - c3z * c1y; g[2][1] = c3z * c1x - c3x * c1z; g[2][2] = c3x * c1y - c3y * c1x;
-    g[3][0] = c1y * c2z - c1z * c2y; g[3][1] = c1z * c2x - c1x * c2z; g[3][2] = c1x * c2y - c1y * c2x;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
-    R sg[6];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
-    R w = (R)(frac_of(code) / 36.0);
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      R gx = g[l][0], gy = g[l][1], gz = g[l][2];
-      out[l][0] = w * (gx * sg[0] + gy * sg[3] + gz * sg[5]);
-      out[l][1] = w * (gy * sg[1] + gx * sg[3] + gz * sg[4]);
-      out[l][2] = w * (gz * sg[2] + gy * sg[4] + gx * sg[5]);
-    }
+    elem_terms(m, e, nd, code, esig, out);
   }
-  typedef typename Vec4<R>::T R4;
-  R4* o = (R4*)contrib;
-  o[pos.x] = Vec4<R>::make(out[0][0], out[0][1], out[0][2]);
-  o[pos.y] = Vec4<R>::make(out[1][0], out[1][1], out[1][2]);
-  o[pos.z] = Vec4<R>::make(out[2][0], out[2][1], out[2][2]);
-  o[pos.w] = Vec4<R>::make(out[3][0], out[3][1], out[3][2]);
+  store_terms(contrib, pos, out);
   }
 }
 
@@ -342,21 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __re
   for (int item; it.next(item);) {
   const int i = item / G;
   const bool active = i < Nn;
-  double fx = 0, fy = 0, fz = 0;
-  const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
-  typedef typename Vec4<R>::T R4;
-  for (int p = p0 + g; p < p1; p += G) {
-    R4 q = ((const R4*)contrib)[p];
-    fx += (double)q.x;
-    fy += (double)q.y;
-    fz += (double)q.z;
-  }
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) {
-    fx += __shfl_xor(fx, off, G);
-    fy += __shfl_xor(fy, off, G);
-    fz += __shfl_xor(fz, off, G);
-  }
+  double fx, fy, fz;
+  node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
   if (!active || g != 0) continue;
   if (MODE == NODE_FORCE) {
     fout[i] = make_double4(fx, fy, fz, 0.0);
@@ -856,12 +674,18 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
       double V = m.vol[t];
       m.vol[tb] = V;
+      double kp = 1.0;
+      if (m.kap) {
+        kp = m.kap[t];
+        m.kap[tb] = kp;
+      }
       if (m.n_inst) {
         int ti = m.tinst[t];
         m.tinst[tb] = ti;
         for (int r = 0; r < 10; ++r) m.einst[m.E0 + 10 * s + r] = ti;
       }
-      R ivA = (R)(1.0 / (frac_of(codeA) * V)), ivB = (R)(1.0 / (frac_of(codeB) * V));
+      // a new edge's patch is one copy: kappa_k is the parent's
+      R ivA = (R)(kp / (frac_of(codeA) * V)), ivB = (R)(kp / (frac_of(codeB) * V));
       int eA[6], eB[6];
       int r = 0;
       int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
@@ -918,13 +742,18 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
     }
     for (int item = wave; item < 6 * n; item += nwaves) {
       int k = sedges[item];
-      double part = 0;
+      double part = 0, partk = 0;
       for (int p = m.poff[k] + lane; p < m.poff[k + 1]; p += 64) {
         int e = m.pent[p];
-        if (e >= 0) part += frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+        if (e < 0) continue;
+        double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+        part += ve;
+        if (m.kap) partk += ve * m.kap[e];
       }
       part = wave_sum(part);
-      if (lane == 0) einvV[k] = part > 0 ? (R)(1.0 / part) : (R)0;
+      if (m.kap) partk = wave_sum(partk);
+      if (lane == 0)
+        einvV[k] = !(part > 0) ? (R)0 : m.kap ? (R)(partk / part / part) : (R)(1.0 / part);
     }
     // phase 3: new crack fronts on intact face neighbours
     for (int i = tid; i < n; i += kTopoBlock) {
@@ -994,17 +823,28 @@ __global__ __launch_bounds__(kBlock) void k_masses(Mesh m) {
   m.invm[i] = ms > 0 ? 1.0 / ms : 0.0;
 }
 
+// einvV_k = kappa_k / S_k with S_k the patch's effective volume and
+// kappa_k = sum_patch V_eff kappa_e / S_k: a per-tet modulus enters the
+// smoothing domain as the volume average of the element elasticities, and
+// folding it into this factor leaves the stress pass unchanged.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_edge_volumes(Mesh m, R* einvV) {
+__global__ __launch_bounds__(kBlock) void k_edge_volumes(Mesh m, R* einvV, int count) {
   int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= m.E0) return;
-  double S = 0;
+  if (k >= count) return;
+  double S = 0, SK = 0;
   for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
     int e = m.pent[p];
     if (e < 0) continue;
-    S += frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+    double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+    S += ve;
+    if (m.kap) SK += ve * m.kap[e];
   }
-  einvV[k] = S > 0 ? (R)(1.0 / S) : (R)0;
+  einvV[k] = !(S > 0) ? (R)0 : m.kap ? (R)(SK / S / S) : (R)(1.0 / S);
+}
+
+__global__ __launch_bounds__(kBlock) void k_kap_copies(Mesh m, int n_split) {
+  int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s < n_split && m.mode == MODE_PHANTOM) m.kap[m.T0 + s] = m.kap[m.rec_tet[s]];
 }
 
 // Nodal loads: each loaded triangle adds t A / 3 to each vertex (gathered per
@@ -1130,6 +970,7 @@ __global__ __launch_bounds__(kBlock) void k_dtcrit(Mesh m, Counters* __restrict_
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) lmax = fmax(lmax, A[i][i]);
+    if (m.kap) lmax *= m.kap[t];  // C_t = kappa_t C scales the spectrum
     if (m.n_inst) atomicMax(&m.lam_inst[m.tinst[t]], dkey(lmax));
   }
   red[threadIdx.x] = dkey(lmax);
@@ -1243,15 +1084,6 @@ __global__ __launch_bounds__(kBlock) void k_sum(const double* __restrict__ x, in
 int grid_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 double key_to_double_host(unsigned long long k) { return key_to_double(k); }
 
-// Persistent grid: enough workgroups for the largest item count the launch
-// can see (capacity), capped at m.grid_cap; always a multiple of 8.
-static int persistent_grid(const Mesh& m, long long items) {
-  long long g = (items + kBlock - 1) / kBlock;
-  g = g < 8 ? 8 : g;
-  g = g > m.grid_cap ? m.grid_cap : g;
-  return (int)((g + 7) / 8 * 8);
-}
-
 template <class R>
 hipError_t Launch<R>::strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
                              hipStream_t s) {
@@ -1319,8 +1151,17 @@ hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counte
 }
 
 template <class R>
-hipError_t Launch<R>::edge_volumes(const Mesh& m, const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_edge_volumes<R>, dim3(grid_for(m.E0)), dim3(kBlock), 0, s, m, (R*)w.einvV);
+hipError_t Launch<R>::edge_volumes(const Mesh& m, const Work& w, int count, hipStream_t s) {
+  if (count < 0) count = m.E0;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_volumes<R>, dim3(grid_for(count)), dim3(kBlock), 0, s, m, (R*)w.einvV,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_kap_copies(const Mesh& m, int n_split, hipStream_t s) {
+  if (n_split <= 0 || !m.kap) return hipSuccess;
+  hipLaunchKernelGGL(k_kap_copies, dim3(grid_for(n_split)), dim3(kBlock), 0, s, m, n_split);
   return hipGetLastError();
 }
 

@@ -86,6 +86,35 @@ struct cem_ctx {
   std::vector<void*> allocs;
   std::vector<Region> regions;  // checkpointed device arrays
 
+  // per-tet modulus (relative to mat.E); m.kap points at it while on
+  double* kap_buf = nullptr;
+  bool kap_on = false;
+
+  // any change of state, mesh or launch shape bumps gen (discards a window)
+  long long gen = 0;
+  int frozen = 0;        // steps skip the crack pass
+  int graph_frozen = -1;
+
+  // fixed-topology gradient window
+  struct Window {
+    int n = 0, every = 1, n_ck = 0, nodes = 0, n_split = 0;
+    long long gen = -1;
+    double4* ck = nullptr;    // [n_ck][4][nodes] u, v, a, predictor
+    Counters* ckc = nullptr;  // [n_ck]
+    double* ckw = nullptr;    // [n_ck][n_load] external work per loaded node
+    double4* tape = nullptr;  // [every + 1][nodes] displacement along a segment
+    double4* p = nullptr;     // [nodes] dJ/du
+    double4* q = nullptr;     // [nodes] dJ/dv
+    double4* lam = nullptr;   // [nodes] M^-1 dJ/da
+    double* gE = nullptr;     // [T_cap] dJ/dE per element slot
+    void* vu = nullptr;       // [T_cap] Six<R>: V_eff eps(u)
+    void* z = nullptr;        // [E_cap] R
+    void* einv0 = nullptr;    // [E_cap] R: 1 / patch volume
+    size_t ck_bytes = 0, tape_bytes = 0;
+    std::vector<void*> fixed;  // buffers sized by the mesh (allocated once)
+    double times[6] = {0, 0, 0, 0, 0, 0};
+  } win;
+
   int fail(int code, const std::string& msg) {
     err = msg;
     return code;
@@ -459,7 +488,7 @@ int enqueue_step(cem_ctx* c, hipEvent_t* ev) {
   if (c->mixed) HIPCHK(c, Launch<float>::edge_stress(c->m, c->w, c->d_ctr, s));
   else HIPCHK(c, Launch<double>::edge_stress(c->m, c->w, c->d_ctr, s));
   if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-  bool fracture = std::isfinite(c->mat.Gc) || replay;
+  bool fracture = (std::isfinite(c->mat.Gc) || replay) && !c->frozen;
   if (fracture) {
     if (c->mixed) HIPCHK(c, Launch<float>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
     else HIPCHK(c, Launch<double>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
@@ -522,6 +551,7 @@ int build_graph(cem_ctx* c, int k) {
   HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
   c->graph_steps = k;
   c->graph_replay = c->h_ctr->n_sched > 0;
+  c->graph_frozen = c->frozen;
   return CEM_OK;
 }
 
@@ -559,6 +589,211 @@ int nodes_now_host(cem_ctx* c) {
   return c->m.N0 + (c->m.mode == MODE_PHANTOM ? 4 * c->n_split_host : 0);
 }
 
+// n steps on the context stream (graphs of K steps where possible); checks
+// the device error word at the end.
+int run_steps(cem_ctx* c, int32_t n_steps) {
+  int r;
+  if (n_steps == 0) return CEM_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  if (c->need_init && (r = initialize(c))) return r;
+  for (int q = 0; q < 7; ++q) c->times[q] = 0;
+  int K = c->opt.graph_steps;
+  int done = 0;
+  // HIP cannot time events recorded inside a graph: profiling uses plain launches
+  if (!c->profiling && K > 0 && n_steps >= K) {
+    int replay = c->h_ctr->n_sched > 0;
+    if (!c->gexec || c->graph_steps != K || c->graph_replay != replay ||
+        c->graph_frozen != c->frozen) {
+      if ((r = build_graph(c, K))) return r;
+    }
+    while (n_steps - done >= K) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      done += K;
+    }
+  }
+  if (c->profiling) {
+    const int chunk = 64;
+    if ((r = ensure_events(c, kEvents * chunk))) return r;
+    while (done < n_steps) {
+      int k = std::min(chunk, n_steps - done);
+      for (int i = 0; i < k; ++i)
+        if ((r = enqueue_step(c, &c->evpool[kEvents * i]))) return r;
+      if ((r = sync(c))) return r;
+      if ((r = accumulate_times(c, k))) return r;
+      done += k;
+    }
+  }
+  for (; done < n_steps; ++done)
+    if ((r = enqueue_step(c, nullptr))) return r;
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  r = check_device_error(c);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  c->times[0] = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return r;
+}
+
+
+// ---- gradient windows
+
+int win_alloc(cem_ctx* c, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess)
+    return c->fail(e == hipErrorOutOfMemory ? CEM_ENOMEM : CEM_EHIP,
+                   std::string("hipMalloc: ") + hipGetErrorString(e));
+  return CEM_OK;
+}
+
+// Buffers sized by the mesh capacity, allocated on the first window.
+int win_fixed(cem_ctx* c) {
+  auto& W = c->win;
+  if (W.p) return CEM_OK;
+  const Mesh& m = c->m;
+  const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
+  void* b[7] = {};
+  size_t sz[7] = {sizeof(double4) * m.N_cap, sizeof(double4) * m.N_cap, sizeof(double4) * m.N_cap,
+                  sizeof(double) * m.T_cap, RS * 6 * (size_t)m.T_cap, RS * (size_t)m.E_cap,
+                  RS * (size_t)m.E_cap};
+  for (int i = 0; i < 7; ++i) {
+    int r = win_alloc(c, &b[i], sz[i]);
+    if (r) return r;
+    W.fixed.push_back(b[i]);
+  }
+  W.p = (double4*)b[0];
+  W.q = (double4*)b[1];
+  W.lam = (double4*)b[2];
+  W.gE = (double*)b[3];
+  W.vu = b[4];
+  W.z = b[5];
+  W.einv0 = b[6];
+  return CEM_OK;
+}
+
+int win_grow(cem_ctx* c, void** p, size_t* have, size_t bytes) {
+  if (*have >= bytes && *p) return CEM_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  int r = win_alloc(c, p, bytes);
+  if (r) return r;
+  *have = bytes;
+  return CEM_OK;
+}
+
+// Checkpoint j of the window: node state, counters and external work.
+int win_save(cem_ctx* c, int j) {
+  auto& W = c->win;
+  const size_t nb = sizeof(double4) * W.nodes;
+  double4* src[4] = {c->st.u, c->st.v, c->st.a, c->st.uh};
+  for (int q = 0; q < 4; ++q)
+    HIPCHK(c, hipMemcpyAsync(W.ck + ((size_t)4 * j + q) * W.nodes, src[q], nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(W.ckc + j, c->d_ctr, sizeof(Counters), hipMemcpyDeviceToDevice, c->stream));
+  if (c->m.n_load)
+    HIPCHK(c, hipMemcpyAsync(W.ckw + (size_t)j * c->m.n_load, c->m.wacc, sizeof(double) * c->m.n_load,
+                             hipMemcpyDeviceToDevice, c->stream));
+  return CEM_OK;
+}
+
+int win_load(cem_ctx* c, int j) {
+  auto& W = c->win;
+  const size_t nb = sizeof(double4) * W.nodes;
+  double4* dst[4] = {c->st.u, c->st.v, c->st.a, c->st.uh};
+  for (int q = 0; q < 4; ++q)
+    HIPCHK(c, hipMemcpyAsync(dst[q], W.ck + ((size_t)4 * j + q) * W.nodes, nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_ctr, W.ckc + j, sizeof(Counters), hipMemcpyDeviceToDevice, c->stream));
+  if (c->m.n_load)
+    HIPCHK(c, hipMemcpyAsync(c->m.wacc, W.ckw + (size_t)j * c->m.n_load, sizeof(double) * c->m.n_load,
+                             hipMemcpyDeviceToDevice, c->stream));
+  c->need_init = false;
+  return CEM_OK;
+}
+
+int edges_now_host(const cem_ctx* c) {
+  return c->m.E0 + (c->m.mode == MODE_PHANTOM ? 10 * c->n_split_host : 0);
+}
+
+// One reverse step: index s + 1 -> s (last: the initial acceleration's term).
+template <class R>
+int reverse_step(cem_ctx* c, const double4* u1, int last, int half, double lh, double mh,
+                 hipEvent_t* ev) {
+  auto& W = c->win;
+  hipStream_t s = c->stream;
+  if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+  HIPCHK(c, Adjoint<R>::strain2(c->m, W.lam, u1, c->w.veps, W.vu, c->d_ctr, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+  HIPCHK(c, Adjoint<R>::edge2(c->m, c->w.veps, W.vu, c->w.einvV, W.einv0, c->w.esig, W.z, lh, mh,
+                              c->d_ctr, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
+  HIPCHK(c, Adjoint<R>::elem(c->m, c->w.esig, W.z, c->w.contrib, W.gE, c->d_ctr, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
+  HIPCHK(c, Adjoint<R>::node(c->m, c->w.contrib, W.p, W.q, W.lam, last, half, c->d_ctr, s));
+  if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+  return CEM_OK;
+}
+
+// The reverse sweep proper (state and adjoint buffers set up by the caller).
+template <class R>
+int reverse_window(cem_ctx* c) {
+  auto& W = c->win;
+  double lh, mh;
+  {
+    const double nu = c->mat.nu;
+    lh = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    mh = 1.0 / (2.0 * (1.0 + nu));
+  }
+  const bool prof = c->profiling != 0;
+  int r;
+  hipEvent_t* ev = nullptr;
+  if (prof) {
+    if ((r = ensure_events(c, (size_t)5 * (W.every + 1) + 2))) return r;
+    ev = c->evpool.data();
+  }
+  const size_t nb = sizeof(double4) * W.nodes;
+  for (int j = W.n_ck - 2; j >= 0; --j) {
+    const int s0 = j * W.every;
+    const int len = std::min(W.every, W.n - s0);
+    if ((r = win_load(c, j))) return r;
+    if (prof) HIPCHK(c, hipEventRecord(ev[5 * W.every], c->stream));
+    HIPCHK(c, hipMemcpyAsync(W.tape, c->st.u, nb, hipMemcpyDeviceToDevice, c->stream));
+    for (int i = 0; i < len; ++i) {
+      if ((r = enqueue_step(c, nullptr))) return r;
+      HIPCHK(c, hipMemcpyAsync(W.tape + (size_t)(i + 1) * W.nodes, c->st.u, nb,
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (prof) HIPCHK(c, hipEventRecord(ev[5 * W.every + 1], c->stream));
+    for (int i = len - 1; i >= 0; --i) {
+      const int s = s0 + i;  // this reverse step takes index s + 1 to s
+      r = reverse_step<R>(c, W.tape + (size_t)(i + 1) * W.nodes, 0, s >= 1 ? 1 : 0, lh, mh,
+                          prof ? ev + 5 * i : nullptr);
+      if (r) return r;
+    }
+    if (prof) {
+      if ((r = sync(c))) return r;
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, ev[5 * W.every], ev[5 * W.every + 1]));
+      W.times[1] += ms;
+      for (int i = 0; i < len; ++i)
+        for (int q = 0; q < 4; ++q) {
+          HIPCHK(c, hipEventElapsedTime(&ms, ev[5 * i + q], ev[5 * i + q + 1]));
+          W.times[2 + q] += ms;
+        }
+    }
+  }
+  if (W.n == 0) {
+    if ((r = win_load(c, 0))) return r;
+    HIPCHK(c, hipMemcpyAsync(W.tape, c->st.u, nb, hipMemcpyDeviceToDevice, c->stream));
+  }
+  // a_0 = M^-1 (r_0 F - K u_0): the tape's first row holds u_0 now
+  return reverse_step<R>(c, W.tape, 1, 0, lh, mh, nullptr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -586,6 +821,9 @@ void cem_destroy(cem_ctx* c) {
     drop_graph(c);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
+    for (void* p : c->win.fixed) (void)hipFree(p);
+    (void)hipFree(c->win.ck);
+    (void)hipFree(c->win.tape);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
   }
@@ -803,8 +1041,8 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   HIPCHK(c, hipMemsetAsync(m.vol, 0, sizeof(double) * m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(m.invm, 0, sizeof(double) * m.N_cap, c->stream));
   HIPCHK(c, launch_masses(m, c->stream));
-  if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, c->stream));
-  else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, c->stream));
+  if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, -1, c->stream));
+  else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, -1, c->stream));
   if ((r = sync(c))) return r;
   c->split_host.assign(T, 0);
   c->need_init = true;
@@ -816,6 +1054,7 @@ int cem_set_traction(cem_ctx* c, int32_t n_faces, const int32_t* tri, const doub
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (n_faces < 0 || (n_faces > 0 && (!tri || !t)) || !(ramp_t0 >= 0))
     return c->fail(CEM_EINVAL, "bad traction arguments");
   Mesh& m = c->m;
@@ -890,6 +1129,7 @@ int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (c->step_host != 0) return c->fail(CEM_ESTATE, "pre-splits must precede the first step");
   if (n < 0 || (n > 0 && (!tet || !side_mask))) return c->fail(CEM_EINVAL, "bad presplit arguments");
   std::vector<std::pair<int, int>> lst;
@@ -951,6 +1191,7 @@ int cem_set_dt(cem_ctx* c, double dt) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (!(dt > 0) || !std::isfinite(dt)) return c->fail(CEM_EINVAL, "dt must be positive");
   c->m.dt = dt;
   c->dt_set = true;
@@ -963,6 +1204,7 @@ int cem_bind_state(cem_ctx* c, double* d_u, double* d_v, int64_t cap) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (!d_u || !d_v || cap < c->m.N_cap) return c->fail(CEM_EINVAL, "bound buffers too small");
   HIPCHK(c, hipMemcpyAsync(d_u, c->st.u, sizeof(double4) * c->m.N_cap, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(d_v, c->st.v, sizeof(double4) * c->m.N_cap, hipMemcpyDeviceToDevice, c->stream));
@@ -982,6 +1224,7 @@ int cem_set_state(cem_ctx* c, const double* u, const double* v) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   int n = nodes_now_host(c);
   std::vector<double4> tmp;
   if (u) {
@@ -1040,54 +1283,15 @@ int cem_step(cem_ctx* c, int32_t n_steps) {
   int r = ensure_ready(c, true);
   if (r) return r;
   if (n_steps < 0) return c->fail(CEM_EINVAL, "negative step count");
-  if (n_steps == 0) return CEM_OK;
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
-  HIPCHK(c, hipEventRecord(e0, c->stream));
-  if (c->need_init && (r = initialize(c))) return r;
-  for (int q = 0; q < 7; ++q) c->times[q] = 0;
-  int K = c->opt.graph_steps;
-  int done = 0;
-  // HIP cannot time events recorded inside a graph: profiling uses plain launches
-  if (!c->profiling && K > 0 && n_steps >= K) {
-    int replay = c->h_ctr->n_sched > 0;
-    if (!c->gexec || c->graph_steps != K || c->graph_replay != replay) {
-      if ((r = build_graph(c, K))) return r;
-    }
-    while (n_steps - done >= K) {
-      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-      done += K;
-    }
-  }
-  if (c->profiling) {
-    const int chunk = 64;
-    if ((r = ensure_events(c, kEvents * chunk))) return r;
-    while (done < n_steps) {
-      int k = std::min(chunk, n_steps - done);
-      for (int i = 0; i < k; ++i)
-        if ((r = enqueue_step(c, &c->evpool[kEvents * i]))) return r;
-      if ((r = sync(c))) return r;
-      if ((r = accumulate_times(c, k))) return r;
-      done += k;
-    }
-  }
-  for (; done < n_steps; ++done)
-    if ((r = enqueue_step(c, nullptr))) return r;
-  HIPCHK(c, hipEventRecord(e1, c->stream));
-  r = check_device_error(c);
-  float ms = 0;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  c->times[0] = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return r;
+  c->gen++;
+  return run_steps(c, n_steps);
 }
 
 int cem_replay_splits(cem_ctx* c, int32_t n, const cem_split_event* ev) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (n < 0 || (n > 0 && !ev)) return c->fail(CEM_EINVAL, "bad schedule");
   std::vector<std::array<int, 3>> s;
   for (int i = 0; i < n; ++i) {
@@ -1189,6 +1393,7 @@ int cem_set_instances(cem_ctx* c, int32_t n, const int32_t* node_off, const int3
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   Mesh& m = c->m;
   if (c->m.n_inst) return c->fail(CEM_ESTATE, "instances already declared");
   if (c->step_host != 0 || c->n_split_host != 0)
@@ -1237,6 +1442,7 @@ int cem_set_dt_instances(cem_ctx* c, const double* dt) {
   if (!c || !dt) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (!c->m.n_inst) return c->fail(CEM_ESTATE, "no instances declared");
   for (int i = 0; i < c->m.n_inst; ++i)
     if (!(dt[i] > 0) || !std::isfinite(dt[i])) return c->fail(CEM_EINVAL, "dt must be positive");
@@ -1267,6 +1473,7 @@ int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   if (grid_cap < 8 || grid_cap % 8 || (lanes != 4 && lanes != 8 && lanes != 16))
     return c->fail(CEM_EINVAL, "grid_cap must be a positive multiple of 8, lanes 4, 8 or 16");
   c->m.grid_cap = grid_cap;
@@ -1405,8 +1612,9 @@ int cem_save_state(cem_ctx* c, void* buf, int64_t cap, int64_t* used) {
   *used = total;
   if (!buf) return CEM_OK;
   if (cap < total) return c->fail(CEM_EINVAL, "checkpoint buffer too small");
-  int64_t h[hdr] = {0x43454d31, 1, c->m.T0, c->m.N0, c->m.E0, c->m.S_cap, c->mixed, c->m.mode,
-                    c->need_init ? 1 : 0, c->step_host, c->n_split_host, c->dt_set ? 1 : 0, 0, 0, 0, 0};
+  int64_t h[hdr] = {0x43454d31, 2, c->m.T0, c->m.N0, c->m.E0, c->m.S_cap, c->mixed, c->m.mode,
+                    c->need_init ? 1 : 0, c->step_host, c->n_split_host, c->dt_set ? 1 : 0, 0,
+                    c->kap_on ? 1 : 0, (int64_t)c->regions.size(), 0};
   double dtv = c->m.dt;
   std::memcpy(&h[12], &dtv, 8);
   char* p = (char*)buf;
@@ -1425,12 +1633,14 @@ int cem_load_state(cem_ctx* c, const void* buf, int64_t size) {
   if (!c || !buf) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  c->gen++;
   const int hdr = 16;
   int64_t h[hdr];
   if (size < (int64_t)sizeof(h)) return c->fail(CEM_EINVAL, "checkpoint too short");
   std::memcpy(h, buf, sizeof(h));
-  if (h[0] != 0x43454d31 || h[1] != 1 || h[2] != c->m.T0 || h[3] != c->m.N0 || h[4] != c->m.E0 ||
-      h[5] != c->m.S_cap || h[6] != c->mixed || h[7] != c->m.mode)
+  if (h[0] != 0x43454d31 || h[1] != 2 || h[2] != c->m.T0 || h[3] != c->m.N0 || h[4] != c->m.E0 ||
+      h[5] != c->m.S_cap || h[6] != c->mixed || h[7] != c->m.mode ||
+      h[14] != (int64_t)c->regions.size())
     return c->fail(CEM_EINVAL, "checkpoint does not match this context");
   int64_t total = sizeof(h);
   for (auto& g : c->regions) total += (int64_t)g.bytes;
@@ -1448,6 +1658,8 @@ int cem_load_state(cem_ctx* c, const void* buf, int64_t size) {
   c->n_split_host = (int)h[10];
   c->dt_set = h[11] != 0;
   std::memcpy(&c->m.dt, &h[12], 8);
+  c->kap_on = h[13] != 0 && c->kap_buf;
+  c->m.kap = c->kap_on ? c->kap_buf : nullptr;
   drop_graph(c);
   return read_counters(c);
 }
@@ -1471,6 +1683,158 @@ int cem_counts(cem_ctx* c, int32_t* out) {
   out[3] = k.n_split;
   out[4] = nf;
   out[5] = m.E0;
+  return CEM_OK;
+}
+
+int cem_set_modulus(cem_ctx* c, int32_t n_tets, const double* E) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  c->gen++;
+  Mesh& m = c->m;
+  if (E) {
+    if (n_tets != m.T0) return c->fail(CEM_EINVAL, "one modulus per tet");
+    std::vector<double> k(m.T0);
+    for (int t = 0; t < m.T0; ++t) {
+      if (!(E[t] > 0) || !std::isfinite(E[t])) return c->fail(CEM_EINVAL, "modulus must be finite and positive");
+      k[c->tet_new[t]] = E[t] / c->mat.E;
+    }
+    if (!c->kap_buf) ALLOC(c->kap_buf, m.T_cap, true);
+    if ((r = upload(c, c->kap_buf, k.data(), (size_t)m.T0))) return r;
+    c->kap_on = true;
+    m.kap = c->kap_buf;
+  } else {
+    c->kap_on = false;
+    m.kap = nullptr;
+  }
+  if ((r = read_counters(c))) return r;
+  c->n_split_host = c->h_ctr->n_split;
+  HIPCHK(c, launch_kap_copies(m, c->n_split_host, c->stream));
+  int En = edges_now_host(c);
+  if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, En, c->stream));
+  else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, En, c->stream));
+  if ((r = sync(c))) return r;
+  c->need_init = true;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_set_step(cem_ctx* c, int64_t step) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (step < 0) return c->fail(CEM_EINVAL, "negative step");
+  c->gen++;
+  long long s = step;
+  HIPCHK(c, hipMemcpyAsync(&c->d_ctr->step, &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
+  if ((r = sync(c))) return r;
+  c->step_host = step;
+  c->h_ctr->step = step;
+  c->need_init = true;
+  return CEM_OK;
+}
+
+int cem_window_forward(cem_ctx* c, int32_t n, int32_t every) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, true);
+  if (r) return r;
+  if (n < 0 || every < 1) return c->fail(CEM_EINVAL, "window needs n_steps >= 0 and every >= 1");
+  c->gen++;
+  auto& W = c->win;
+  W.gen = -1;
+  if ((r = win_fixed(c))) return r;
+  if (c->need_init && (r = initialize(c))) return r;
+  W.nodes = nodes_now_host(c);
+  W.n = n;
+  W.every = every;
+  W.n_ck = (n + every - 1) / every + 1;
+  const size_t nl = std::max(c->m.n_load, 1);
+  const size_t per = sizeof(double4) * 4 * W.nodes + sizeof(Counters) + sizeof(double) * nl + 256;
+  size_t bytes = per * W.n_ck;
+  if ((r = win_grow(c, (void**)&W.ck, &W.ck_bytes, bytes))) return r;
+  W.ckc = (Counters*)((char*)W.ck + sizeof(double4) * 4 * W.nodes * W.n_ck);
+  W.ckw = (double*)((char*)W.ckc + ((sizeof(Counters) * W.n_ck + 255) / 256) * 256);
+  if ((r = win_grow(c, (void**)&W.tape, &W.tape_bytes, sizeof(double4) * W.nodes * (every + 1))))
+    return r;
+  c->frozen = 1;
+  r = win_save(c, 0);
+  for (int j = 0; r == CEM_OK && j + 1 < W.n_ck; ++j) {
+    int len = std::min(every, n - j * every);
+    r = run_steps(c, len);
+    if (r == CEM_OK) r = win_save(c, j + 1);
+  }
+  c->frozen = 0;
+  if (r) return r;
+  if ((r = sync(c))) return r;
+  W.n_split = c->n_split_host;
+  W.gen = c->gen;
+  return CEM_OK;
+}
+
+int cem_window_backward(cem_ctx* c, const double* gu, const double* gv, double* gu0, double* gv0,
+                        double* gE) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, true);
+  if (r) return r;
+  auto& W = c->win;
+  if (W.gen != c->gen) return c->fail(CEM_ESTATE, "no gradient window pending (cem_window_forward)");
+  Mesh& m = c->m;
+  for (double& t : W.times) t = 0;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  // sensitivities at the window's end
+  std::vector<double4> tmp(W.nodes, make_double4(0, 0, 0, 0));
+  if (gu) pad3(c, gu, tmp, W.nodes);
+  if ((r = upload(c, W.p, tmp.data(), W.nodes))) return r;
+  tmp.assign(W.nodes, make_double4(0, 0, 0, 0));
+  if (gv) pad3(c, gv, tmp, W.nodes);
+  if ((r = upload(c, W.q, tmp.data(), W.nodes))) return r;
+  HIPCHK(c, hipMemsetAsync(W.gE, 0, sizeof(double) * m.T_cap, c->stream));
+  const int En = edges_now_host(c);
+  if (c->mixed) HIPCHK(c, Adjoint<float>::inv_volumes(m, W.einv0, En, c->stream));
+  else HIPCHK(c, Adjoint<double>::inv_volumes(m, W.einv0, En, c->stream));
+  HIPCHK(c, launch_adj_init(m, W.q, W.lam, W.n > 0 ? 0.5 : 0.0, c->d_ctr, c->stream));
+  c->frozen = 1;
+  r = c->mixed ? reverse_window<float>(c) : reverse_window<double>(c);
+  c->frozen = 0;
+  if (r) return r;
+  // back to the window's end
+  if ((r = win_load(c, W.n_ck - 1))) return r;
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  if ((r = check_device_error(c))) return r;
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  W.times[0] = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // read back in the caller's numbering
+  std::vector<double4> h(W.nodes);
+  double4* src[2] = {W.p, W.q};
+  double* dst[2] = {gu0, gv0};
+  for (int k = 0; k < 2; ++k) {
+    if (!dst[k]) continue;
+    HIPCHK(c, hipMemcpyAsync(h.data(), src[k], sizeof(double4) * W.nodes, hipMemcpyDeviceToHost, c->stream));
+    if ((r = sync(c))) return r;
+    unpad3(c, h, dst[k], W.nodes);
+  }
+  if (gE) {
+    const int ns = m.mode == MODE_PHANTOM ? c->n_split_host : 0;
+    std::vector<double> g((size_t)m.T0 + ns);
+    std::vector<int> par(std::max(ns, 1));
+    HIPCHK(c, hipMemcpyAsync(g.data(), W.gE, sizeof(double) * g.size(), hipMemcpyDeviceToHost, c->stream));
+    if (ns) HIPCHK(c, hipMemcpyAsync(par.data(), m.rec_tet, sizeof(int) * ns, hipMemcpyDeviceToHost, c->stream));
+    if ((r = sync(c))) return r;
+    for (int s = 0; s < ns; ++s) g[par[s]] += g[(size_t)m.T0 + s];  // a copy adds to its parent
+    for (int t = 0; t < m.T0; ++t) gE[t] = g[c->tet_new[t]];
+  }
+  return CEM_OK;
+}
+
+int cem_window_times(cem_ctx* c, double* out) {
+  if (!c || !out) return CEM_EINVAL;
+  for (int i = 0; i < 6; ++i) out[i] = c->win.times[i];
   return CEM_OK;
 }
 

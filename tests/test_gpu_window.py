@@ -1,0 +1,238 @@
+"""GPU per-tet modulus and gradient windows against the oracle (through the C-ABI).
+
+Tolerances: FP64 forces 1e-12 normwise relative, FP64 trajectories 1e-10 and
+FP64 window gradients 1e-9 relative L2 (rounding order differs, nothing
+else); mixed-precision gradients 1e-4; directional derivatives against
+central differences of the GPU's own forward 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2508_04076_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+MAT = dict(mg.BRANCHING_MATERIAL)
+
+
+def _sim(mesh, **kw):
+    from paper_2508_04076_amd.cem import Simulation
+    kw.setdefault("max_splits", max(mesh.n_tets // 4, 64))
+    return Simulation.from_mesh(mesh, MAT, **kw)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _setup(mesh, E, dt, ramp_t0, seed, **kw):
+    sim = _sim(mesh, ramp_t0=ramp_t0, E_tet=E, **kw)
+    orc = Oracle.from_mesh(mesh, MAT, ramp_t0=ramp_t0, E_tet=E)
+    sim.set_dt(dt)
+    orc.set_dt(dt)
+    rng = np.random.default_rng(seed)
+    n = sim.n_nodes
+    u0 = rng.standard_normal((n, 3)) * 1e-7
+    v0 = rng.standard_normal((n, 3)) * 1e-3
+    sim.set_state(u0, v0)
+    orc.set_state(u0, v0)
+    return sim, orc, u0, v0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_modulus_force_and_dt_parity(precision):
+    _case(f"per-tet modulus force parity {precision}")
+    mesh = mg.cube_notched(8)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.3, seed=5)
+    sim = _sim(mesh, precision=precision, E_tet=E)
+    orc = Oracle.from_mesh(mesh, MAT, E_tet=E)
+    u = mg.random_displacement(sim.n_nodes, 1e-6, seed=2)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert _rel(sim.internal_force(u), orc.internal_force(u)) < tol
+    assert abs(sim.critical_dt() / orc.critical_dt() - 1) < 1e-12
+    # modulus set after the pre-splits reaches the copies as well
+    sim2 = _sim(mesh, precision=precision)
+    sim2.set_modulus(E)
+    assert _rel(sim2.internal_force(u), orc.internal_force(u)) < tol
+    # back to the scalar material
+    sim2.set_modulus(None)
+    orc0 = Oracle.from_mesh(mesh, MAT)
+    assert _rel(sim2.internal_force(u), orc0.internal_force(u)) < tol
+    sim.close()
+    sim2.close()
+
+
+def test_modulus_trajectory_with_splits():
+    _case("per-tet modulus trajectory with free splitting")
+    mesh = mg.cube_notched(6)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.2, seed=6)
+    sim = _sim(mesh, E_tet=E)
+    orc = Oracle.from_mesh(mesh, MAT, E_tet=E)
+    dt = 0.5 * orc.critical_dt()
+    sim.set_dt(dt)
+    orc.set_dt(dt)
+    sim.step(300)
+    orc.step(300)
+    ev_g, ev_o = sim.splits()[0], orc.splits()[0]
+    assert len(ev_o) > len(mesh.presplit_tets), "the case must split"
+    assert (ev_g[:, :3] == ev_o[:, :3]).all()
+    assert _rel(sim.get_state()[0], orc.get_state()[0]) < 1e-10
+    # the copies made by the dynamic splits carry their parent's modulus
+    u = mg.random_displacement(sim.n_nodes, 1e-6, seed=3)
+    assert _rel(sim.internal_force(u), orc.internal_force(u)) < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("n,every", [(23, 5), (12, 50), (0, 3), (9, 1)])
+def test_window_gradient_parity(n, every):
+    _case(f"window gradient parity n={n} every={every}")
+    mesh = mg.cube_notched(6)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    dt = 6.0e-6
+    sim, orc, u0, v0 = _setup(mesh, E, dt, 5 * dt, seed=11)
+    rng = np.random.default_rng(12)
+    gu = rng.standard_normal(u0.shape)
+    gv = rng.standard_normal(u0.shape) * 1e-4
+    sim.window_forward(n, every)
+    g_sim = sim.window_backward(gu, gv)
+    g_orc = orc.window_gradient(n, gu, gv)
+    for a, b, name in zip(g_sim, g_orc, ["u0", "v0", "E"]):
+        assert _rel(a, b) < 1e-9, (name, _rel(a, b))
+    # the state is back at the window's end, equal to the oracle's
+    us, vs, _ = sim.get_state()
+    uo, vo, _ = orc.get_state()
+    if n:
+        assert _rel(us, uo) < 1e-10 and _rel(vs, vo) < 1e-10
+    assert sim.energy()["step"] == n
+    sim.close()
+
+
+def test_window_checkpoint_spacing_is_bitwise_neutral():
+    _case("window checkpoint spacing")
+    mesh = mg.cube_notched(6)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    dt = 6.0e-6
+    rng = np.random.default_rng(2)
+    out = []
+    for every in (1, 7, 40, 100):
+        sim, _, u0, v0 = _setup(mesh, E, dt, 0.0, seed=4, graph_steps=4)
+        gu = np.random.default_rng(5).standard_normal(u0.shape)
+        sim.window_forward(40, every)
+        out.append(sim.window_backward(gu, None))
+        sim.close()
+    for g in out[1:]:
+        for a, b in zip(g, out[0]):
+            assert (a == b).all()
+    del rng
+
+
+def test_window_mixed_precision():
+    _case("window gradient mixed precision")
+    mesh = mg.cube_notched(6)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    dt = 6.0e-6
+    sim, orc, u0, v0 = _setup(mesh, E, dt, 5 * dt, seed=11, precision="mixed")
+    gu = np.random.default_rng(12).standard_normal(u0.shape)
+    sim.window_forward(30, 8)
+    g_sim = sim.window_backward(gu, None)
+    g_orc = orc.window_gradient(30, gu, None)
+    for a, b in zip(g_sim, g_orc):
+        assert _rel(a, b) < 1e-4, _rel(a, b)
+    sim.close()
+
+
+def test_window_refused_after_state_change():
+    _case("window discarded by a later step")
+    from paper_2508_04076_amd.cem import CemError
+    mesh = mg.cube_notched(5)
+    sim = _sim(mesh)
+    sim.set_dt(5e-6)
+    with pytest.raises(CemError):
+        sim.window_backward(np.ones((sim.n_nodes, 3)))
+    sim.window_forward(4, 2)
+    sim.step(1)
+    with pytest.raises(CemError):
+        sim.window_backward(np.ones((sim.n_nodes, 3)))
+    sim.window_forward(4, 2)
+    sim.window_backward(np.ones((sim.n_nodes, 3)))
+    sim.close()
+
+
+def test_autograd_window_matches_finite_differences():
+    _case("autograd window vs central differences")
+    import torch
+    from paper_2508_04076_amd.window import window
+    mesh = mg.plate_notched(40, 16, 2, 0.01, 0.004, 0.0005, 0.005)
+    E0 = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    sim = _sim(mesh, ramp_t0=1e-7, graph_steps=8)
+    dt = 0.5 * sim.critical_dt()
+    sim.set_dt(dt)
+    n = sim.n_nodes
+    rng = np.random.default_rng(7)
+    dev = torch.device("cuda:0")
+    E = torch.tensor(E0, device=dev, requires_grad=True)
+    u0 = torch.tensor(rng.standard_normal((n, 3)) * 1e-8, device=dev, requires_grad=True)
+    v0 = torch.tensor(rng.standard_normal((n, 3)) * 1e-4, device=dev, requires_grad=True)
+    w = torch.tensor(rng.standard_normal((n, 3)), device=dev)
+
+    def loss(E_, u_, v_):
+        u, v = window(sim, E_, u_, v_, 120, 25)
+        return (w * u).sum() + 1e-5 * (v * v).sum()
+
+    L = loss(E, u0, v0)
+    L.backward()
+    gE, gu, gv = E.grad.clone(), u0.grad.clone(), v0.grad.clone()
+    with torch.no_grad():
+        dE = torch.tensor(rng.choice([-1.0, 1.0], mesh.n_tets), device=dev) * E
+        h = 1e-5
+        fd = (loss(E + h * dE, u0, v0) - loss(E - h * dE, u0, v0)).item() / (2 * h)
+        assert abs(fd - (gE * dE).sum().item()) < 1e-6 * abs(fd)
+        du = torch.tensor(rng.standard_normal((n, 3)), device=dev) * 1e-9
+        fd = (loss(E, u0 + du, v0) - loss(E, u0 - du, v0)).item() / 2
+        assert abs(fd - (gu * du).sum().item()) < 1e-6 * abs(fd)
+        dv = torch.tensor(rng.standard_normal((n, 3)), device=dev) * 1e-5
+        fd = (loss(E, u0, v0 + dv) - loss(E, u0, v0 - dv)).item() / 2
+        assert abs(fd - (gv * dv).sum().item()) < 1e-6 * abs(fd)
+    sim.close()
+
+
+def test_window_full_size_plate_directional_derivative():
+    # 202,800-tet plate, 500 steps with a checkpoint every 50: the gradient's
+    # directional derivative against central differences of the forward
+    _case("window 202,800-tet plate, 500 steps, every 50")
+    mesh = mg.plate_window()
+    E0 = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    sim = _sim(mesh, ramp_t0=1e-6, E_tet=E0, max_splits=4000, graph_steps=25)
+    dt = 0.5 * sim.critical_dt()
+    sim.set_dt(dt)
+    n = sim.n_nodes
+    rng = np.random.default_rng(9)
+    gu = rng.standard_normal((n, 3))
+    zero = np.zeros((n, 3))
+
+    def J(E):
+        sim.set_modulus(E)
+        sim.set_state(zero, zero)
+        sim.set_step(0)
+        sim.window_forward(500, 50)
+        return float((gu * sim.get_state()[0]).sum())
+
+    J(E0)
+    _, _, gE = sim.window_backward(gu, None)
+    dE = rng.choice([-1.0, 1.0], mesh.n_tets) * E0
+    h = 1e-5
+    fd = (J(E0 + h * dE) - J(E0 - h * dE)) / (2 * h)
+    assert abs(fd - gE @ dE) < 1e-6 * abs(fd), (fd, gE @ dE)
+    # one tet next to the notch tip
+    t = int(np.argmax(np.abs(gE)))
+    e = np.zeros(mesh.n_tets)
+    e[t] = E0[t]
+    fd = (J(E0 + h * e) - J(E0 - h * e)) / (2 * h)
+    assert abs(fd - gE[t] * E0[t]) < 1e-5 * abs(fd), (fd, gE[t] * E0[t])
+    sim.close()
