@@ -37,6 +37,12 @@
 //     enters the smoothing domain of edge k as C_k = sum_j w_jk C_j, the
 //     volume average of the element matrices over the domain, so that
 //     sigma_k = C_k eps_k;
+//   * a prescribed velocity v0 r_v(t) on listed degrees of freedom, with the
+//     ramp r_v = t / t0 up to t0 and 1 after (Section 4 examples), fixes the
+//     displacement to u_ref + v0 S(t), S the integral of r_v, the velocity to
+//     v0 r_v(t) and the acceleration to v0 dr_v/dt (1/t0 on the ramp, taken on
+//     the ramp at t = t0, else 0); the reaction is m a + f_int - f_ext on those
+//     degrees of freedom; extra nodes of split copies are not constrained;
 //   * the gradient of a window of fixed-topology steps is the exact reverse
 //     (discrete adjoint) of the Newmark update, with the per-tet modulus,
 //     the initial displacement and the initial velocity as the inputs.
@@ -145,6 +151,13 @@ struct orc_ctx {
   std::vector<double> Et;  // Young's modulus of each original tet
   bool hetero = false;     // Et differs from the scalar E
   bool frozen = false;     // topology frozen: no crack pass
+  // prescribed velocities (Dirichlet), in groups: per constrained node its
+  // group, dof mask (bit d), v0, u_ref and current reaction; per group the
+  // ramp time, the reactions' work and a history row per step
+  std::vector<int> bc_node, bc_mask, bc_group;
+  std::vector<V3> bc_v0, bc_uref, bc_R;
+  std::vector<double> grp_t0, grp_W;
+  std::vector<std::vector<std::array<double, 6>>> grp_hist;  // step, t, R_x, R_y, R_z, S(t)
   double ramp_t0 = 0;
   double dt = 0;
   long step = 0;
@@ -526,12 +539,50 @@ void front_G(const orc_ctx* c, const std::vector<V3>& u, const std::vector<std::
   *maskII = (1 << lN2);
 }
 
+// Prescribed-velocity history with ramp time t0: the velocity factor
+// r_v(t) = t / t0 up to t0, then 1 (t0 = 0: 1 from the start), its integral S
+// and its derivative.
+double bc_vel(double t0, double t) { return (t0 > 0 && t <= t0) ? t / t0 : 1.0; }
+double bc_disp(double t0, double t) {
+  if (t0 > 0 && t <= t0) return t * t / (2.0 * t0);
+  return t0 > 0 ? t - 0.5 * t0 : t;
+}
+double bc_acc(double t0, double t) { return (t0 > 0 && t <= t0) ? 1.0 / t0 : 0.0; }
+
+// Constrained components of u (if set_u), v and a at time t.
+void apply_bc(orc_ctx* c, double t, std::vector<V3>& u, bool set_u) {
+  for (size_t b = 0; b < c->bc_node.size(); ++b) {
+    int i = c->bc_node[b];
+    double t0 = c->grp_t0[c->bc_group[b]];
+    for (int d = 0; d < 3; ++d) {
+      if (!((c->bc_mask[b] >> d) & 1)) continue;
+      if (set_u) u[i][d] = c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(t0, t);
+      c->v[i][d] = c->bc_v0[b][d] * bc_vel(t0, t);
+      c->a[i][d] = c->bc_v0[b][d] * bc_acc(t0, t);
+    }
+  }
+}
+
+// Support reaction on the constrained components: m a + f_int - r F.
+void bc_reactions(orc_ctx* c, const std::vector<V3>& f, double r, std::vector<V3>& R) {
+  R.assign(c->bc_node.size(), {0, 0, 0});
+  for (size_t b = 0; b < c->bc_node.size(); ++b) {
+    int i = c->bc_node[b];
+    for (int d = 0; d < 3; ++d)
+      if ((c->bc_mask[b] >> d) & 1) R[b][d] = c->m[i] * c->a[i][d] + f[i][d] - r * c->F[i][d];
+  }
+}
+
 int initialize(orc_ctx* c) {
+  double t = c->step * c->dt;
+  apply_bc(c, t, c->u, true);
   std::vector<V3> f;
   internal_force(c, c->u, f);
-  double r = ramp(c, c->step * c->dt);
+  double r = ramp(c, t);
   for (size_t i = 0; i < c->X.size(); ++i)
     for (int d = 0; d < 3; ++d) c->a[i][d] = (r * c->F[i][d] - f[i][d]) / c->m[i];
+  apply_bc(c, t, c->u, false);
+  bc_reactions(c, f, r, c->bc_R);
   c->need_init = false;
   return 0;
 }
@@ -595,8 +646,15 @@ void one_step(orc_ctx* c) {
   for (size_t i = 0; i < N; ++i)
     for (int d = 0; d < 3; ++d)
       u1[i][d] = c->u[i][d] + dt * c->v[i][d] + 0.5 * dt * dt * c->a[i][d];
+  // prescribed components follow their history exactly
+  for (size_t b = 0; b < c->bc_node.size(); ++b)
+    for (int d = 0; d < 3; ++d)
+      if ((c->bc_mask[b] >> d) & 1)
+        u1[c->bc_node[b]][d] =
+            c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn1);
   std::vector<V3> f;
   internal_force(c, u1, f);
+  std::vector<V3> u0 = c->u;
   for (size_t i = 0; i < N; ++i) {
     for (int d = 0; d < 3; ++d) {
       double an1 = (rn1 * c->F[i][d] - f[i][d]) / c->m[i];
@@ -605,6 +663,23 @@ void one_step(orc_ctx* c) {
       c->a[i][d] = an1;
       c->u[i][d] = u1[i][d];
     }
+  }
+  if (!c->grp_t0.empty()) {
+    apply_bc(c, tn1, c->u, false);
+    std::vector<V3> R;
+    bc_reactions(c, f, rn1, R);
+    size_t G = c->grp_t0.size();
+    std::vector<std::array<double, 6>> rows(G);
+    for (size_t g = 0; g < G; ++g) rows[g] = {(double)(c->step + 1), tn1, 0, 0, 0, bc_disp(c->grp_t0[g], tn1)};
+    for (size_t b = 0; b < R.size(); ++b) {
+      int i = c->bc_node[b], g = c->bc_group[b];
+      for (int d = 0; d < 3; ++d) {
+        c->grp_W[g] += 0.5 * (c->bc_R[b][d] + R[b][d]) * (c->u[i][d] - u0[i][d]);
+        rows[g][2 + d] += R[b][d];
+      }
+    }
+    c->bc_R = R;
+    for (size_t g = 0; g < G; ++g) c->grp_hist[g].push_back(rows[g]);
   }
   c->step += 1;
   std::vector<Event> evs;
@@ -1124,7 +1199,48 @@ int orc_window_gradient(orc_ctx* c, int n_steps, const double* gu, const double*
                         double* gv0, double* gE) {
   if (!(c->dt > 0)) return c->fail(-7, "dt not set");
   if (n_steps < 0) return c->fail(-1, "negative step count");
+  if (!c->grp_t0.empty()) return c->fail(-7, "windows with prescribed velocities are not supported");
   return window_gradient(c, n_steps, gu, gv, gu0, gv0, gE);
+}
+
+int orc_add_velocity_bc(orc_ctx* c, int n, const int* node, const int* mask, const double* v0,
+                        double t0, int* group) {
+  if (c->step != 0) return c->fail(-7, "prescribed velocities must precede the first step");
+  if (!(t0 >= 0)) return c->fail(-1, "ramp time must be >= 0");
+  int g = (int)c->grp_t0.size();
+  for (int b = 0; b < n; ++b) {
+    if (node[b] < 0 || node[b] >= c->N0) return c->fail(-1, "constrained node out of range");
+    if (mask[b] < 1 || mask[b] > 7) return c->fail(-1, "dof mask must be 1..7");
+    for (int q = 0; q < b; ++q)
+      if (node[q] == node[b]) return c->fail(-1, "node listed twice");
+    if (std::find(c->bc_node.begin(), c->bc_node.end(), node[b]) != c->bc_node.end())
+      return c->fail(-1, "node already constrained");
+  }
+  for (int b = 0; b < n; ++b) {
+    c->bc_node.push_back(node[b]);
+    c->bc_mask.push_back(mask[b]);
+    c->bc_group.push_back(g);
+    c->bc_v0.push_back({v0[3 * b], v0[3 * b + 1], v0[3 * b + 2]});
+    c->bc_uref.push_back(c->u[node[b]]);
+    c->bc_R.push_back({0, 0, 0});
+  }
+  c->grp_t0.push_back(t0);
+  c->grp_W.push_back(0.0);
+  c->grp_hist.push_back({});
+  c->need_init = true;
+  if (group) *group = g;
+  return 0;
+}
+
+int orc_reactions(orc_ctx* c, int group, int cap, double* rows6, int* n_out, double* work) {
+  if (group < 0 || group >= (int)c->grp_t0.size()) return c->fail(-1, "no such group");
+  const auto& h = c->grp_hist[group];
+  int n = (int)h.size();
+  *n_out = n;
+  for (int i = 0; i < n && i < cap; ++i)
+    for (int k = 0; k < 6; ++k) rows6[6 * i + k] = h[i][k];
+  if (work) *work = c->grp_W[group];
+  return 0;
 }
 
 }  // extern "C"

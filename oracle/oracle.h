@@ -65,6 +65,15 @@ int orc_set_frozen(orc_ctx* c, int on);
 int orc_window_gradient(orc_ctx* c, int n_steps, const double* gu, const double* gv,
                         double* gu0, double* gv0, double* gE);
 
+/* Prescribed velocities, one group per call (before the first step): node[n],
+ * dof mask (bit d = component d), v0[n][3]; velocity v0 t/t0 up to t0, then
+ * v0 (t0 = 0: v0 from the start).  *group receives the group id. */
+int orc_add_velocity_bc(orc_ctx* c, int n, const int* node, const int* mask,
+                        const double* v0, double t0, int* group);
+/* one row per step of a group: step, t, summed reaction (x, y, z), S(t);
+ * work: the group's reactions' accumulated work */
+int orc_reactions(orc_ctx* c, int group, int cap, double* rows6, int* n_out, double* work);
+
 /* inspection */
 int orc_masses(orc_ctx* c, double* m);
 int orc_loads(orc_ctx* c, double* F);

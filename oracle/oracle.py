@@ -71,6 +71,8 @@ def lib():
             ("orc_set_modulus", [_p, _p]),
             ("orc_set_frozen", [_p, _i]),
             ("orc_window_gradient", [_p, _i, _p, _p, _p, _p, _p]),
+            ("orc_add_velocity_bc", [_p, _i, _p, _p, _p, _d, _p]),
+            ("orc_reactions", [_p, _i, _i, _p, _p, _p]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -256,6 +258,27 @@ class Oracle:
         self._chk(lib().orc_window_gradient(self.c, int(n_steps), _ptr(gu), _ptr(gv), _ptr(gu0),
                                             _ptr(gv0), _ptr(gE)))
         return gu0, gv0, gE
+
+    def add_velocity_bc(self, nodes, masks, v0, t0=0.0):
+        """One group of prescribed velocities v0 (t/t0 ramp, then constant) on
+        the dof bits of each node's mask; before the first step.  Returns the
+        group id."""
+        nodes, masks = _i32(nodes), _i32(masks)
+        v0 = _f64(v0, (len(nodes), 3))
+        g = C.c_int()
+        self._chk(lib().orc_add_velocity_bc(self.c, len(nodes), _ptr(nodes), _ptr(masks), _ptr(v0),
+                                            float(t0), C.byref(g)))
+        return g.value
+
+    def reactions(self, group=0):
+        """(rows [n][6]: step, t, R_x, R_y, R_z, S(t); work of the group's reactions)."""
+        n = C.c_int()
+        w = C.c_double()
+        self._chk(lib().orc_reactions(self.c, int(group), 0, None, C.byref(n), None))
+        rows = np.zeros((max(n.value, 1), 6))
+        self._chk(lib().orc_reactions(self.c, int(group), n.value, _ptr(rows), C.byref(n),
+                                      C.byref(w)))
+        return rows[: n.value], w.value
 
     def replay(self, ev3):
         ev3 = _i32(ev3).reshape(-1, 3)
