@@ -224,6 +224,29 @@ int cem_autotune(cem_ctx* ctx, int32_t trial_steps, int32_t* best_grid, int32_t*
  * change: the bound scales with the largest modulus. */
 int cem_set_modulus(cem_ctx* ctx, int32_t n_tets, const double* E);
 
+/* ---- Prescribed velocities (Dirichlet boundaries) and reactions
+ *
+ * One group per call, before the first step: the components selected by
+ * dof_mask[b] (bit d = component d, 1..7) of node[b] (caller's ids) follow
+ * the velocity v0[b][d] * V(t) with V = t / t0 up to t0, then 1 (t0 = 0: 1 from
+ * the start), the ramp of the paper's Dirichlet examples (Sections 4.1, 4.2,
+ * 4.3 and 4.5).  The displacement is u_ref + v0 S(t) (S the integral of V,
+ * u_ref the node's u when the group is added), the acceleration v0 dV/dt
+ * (1/t0 on the ramp, taken on the ramp at t = t0).  Each step records, per
+ * group, the summed reaction m a + f_int - f_ext on the constrained
+ * components (the force the support exerts on the body).  Extra nodes of
+ * split copies are free.  A node may belong to one group only; at most 64
+ * groups; not with batches or gradient windows (CEM_ESTATE).  *group gets
+ * the group id (may be NULL). */
+int cem_add_velocity_bc(cem_ctx* ctx, int32_t n, const int32_t* node, const int32_t* dof_mask,
+                        const double* v0, double t0, int32_t* group);
+/* Reaction history of a group, oldest first: rows[n][6] = step, t, R_x, R_y,
+ * R_z, S(t) (the loading points' displacement is u_ref + v0 S(t)).  The last
+ * 65,536 steps are kept; *n = rows available, at most cap written.  *work
+ * (may be NULL) = the group's reaction work, trapezoid rule per step. */
+int cem_read_reactions(cem_ctx* ctx, int32_t group, int32_t cap, double* rows, int32_t* n,
+                       double* work);
+
 /* Set the step counter, hence the time t = step * dt at which the load ramp
  * is evaluated (the state and the accumulated external work are kept; the
  * next step recomputes a from u). */

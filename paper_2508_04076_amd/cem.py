@@ -30,7 +30,7 @@ EXPORTS = [
     "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
     "cem_set_profiling", "cem_kernel_times", "cem_set_instances", "cem_set_dt_instances",
     "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
-    "cem_set_modulus", "cem_set_step", "cem_window_forward", "cem_window_backward", "cem_window_times",
+    "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step", "cem_window_forward", "cem_window_backward", "cem_window_times",
 ]
 
 
@@ -115,6 +115,8 @@ def load_library(path=LIB_PATH):
                          C.POINTER(C.c_double)],
         "cem_set_modulus": [p, i32, p],
         "cem_set_step": [p, i64],
+        "cem_add_velocity_bc": [p, i32, p, p, p, d, C.POINTER(C.c_int32)],
+        "cem_read_reactions": [p, i32, i32, p, C.POINTER(C.c_int32), C.POINTER(C.c_double)],
         "cem_window_forward": [p, i32, i32],
         "cem_window_backward": [p, p, p, p, p, p],
         "cem_window_times": [p, p],
@@ -365,3 +367,24 @@ class Simulation:
         self._chk(self.lib.cem_window_times(self.ctx, _p(out)))
         return dict(zip(["total", "recompute", "strain2", "edge2", "elem_adj", "node_adj"],
                         out.tolist()))
+
+    # ---- prescribed velocities
+    def add_velocity_bc(self, nodes, masks, v0, t0=0.0):
+        """One group of prescribed velocities (v0 t/t0 up to t0, then v0) on the
+        dof bits of each node's mask; before the first step.  Returns the group id."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32).reshape(-1)
+        masks = np.ascontiguousarray(masks, dtype=np.int32).reshape(-1)
+        v0 = _f64(v0, (len(nodes), 3))
+        g = C.c_int32()
+        self._chk(self.lib.cem_add_velocity_bc(self.ctx, len(nodes), _p(nodes), _p(masks), _p(v0),
+                                               float(t0), C.byref(g)))
+        return g.value
+
+    def reactions(self, group=0):
+        """(rows [n][6]: step, t, R_x, R_y, R_z, S(t); the group's reaction work)."""
+        n, w = C.c_int32(), C.c_double()
+        self._chk(self.lib.cem_read_reactions(self.ctx, int(group), 0, None, C.byref(n), None))
+        rows = np.zeros((max(n.value, 1), 6))
+        self._chk(self.lib.cem_read_reactions(self.ctx, int(group), n.value, _p(rows), C.byref(n),
+                                              C.byref(w)))
+        return rows[: n.value], w.value

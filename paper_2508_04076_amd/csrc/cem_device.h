@@ -93,6 +93,19 @@ struct Mesh {
   double* rec_area;         // [S_cap] midpoint crack area of each split
   double* kap;              // [T_cap] modulus of each element slot over E (null: uniform E)
 
+  // prescribed velocities in groups (all null, counts 0, when there are none)
+  int n_bc, n_grp, hist_cap;
+  int* bslot;               // [N_cap] slot of a constrained node, -1 none
+  int* bnode;               // [n_bc] node of each slot
+  int* bmask;               // [n_bc] dof mask (bit d) | group << 4
+  double4* bv0;             // [n_bc] velocity after the ramp
+  double4* bref;            // [n_bc] displacement when the group was added
+  double4* breact;          // [n_bc] current reaction m a + f_int - f_ext
+  double* bwork;            // [n_bc] accumulated work of the reaction
+  double* gt0;              // [n_grp] ramp time of each group
+  int* goff;                // [n_grp + 1] slot range of each group
+  double* ghist;            // [n_grp][hist_cap][6] step, t, R_x, R_y, R_z, S(t)
+
   // batch of independent instances (all null when n_inst == 0)
   int* inst;                // [N_cap] instance of each node
   int* tinst;               // [T_cap] instance of each element slot
@@ -154,6 +167,10 @@ hipError_t launch_count_fronts(const Mesh& m, Counters* c, int* out, int inst, h
 hipError_t launch_work_sum(const Mesh& m, double* out, int inst, hipStream_t s);
 hipError_t launch_dissipated(const Mesh& m, Counters* c, double* out, int inst, hipStream_t s);
 hipError_t launch_edge_instances(const Mesh& m, hipStream_t s);
+// prescribed displacement of the constrained components at the current time
+hipError_t launch_bc_apply(const Mesh& m, const State& st, const Counters* c, hipStream_t s);
+// per-group reaction sums of the step just taken, into the history ring
+hipError_t launch_reaction(const Mesh& m, const Counters* c, hipStream_t s);
 // split copies take their parent's relative modulus (n_split copies)
 hipError_t launch_kap_copies(const Mesh& m, int n_split, hipStream_t s);
 hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, const uint8_t* masks,

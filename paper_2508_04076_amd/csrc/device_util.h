@@ -230,6 +230,21 @@ __device__ __forceinline__ void node_gather(const Mesh& m, const R* __restrict__
   }
 }
 
+// Prescribed-velocity history with ramp time t0: the velocity factor
+// V(t) = t / t0 up to t0, then 1 (t0 = 0: 1 from the start), its integral S
+// and its derivative A (taken on the ramp at t = t0).
+__device__ __forceinline__ void bc_history(double t0, double t, double& S, double& V, double& A) {
+  if (t0 > 0 && t <= t0) {
+    S = t * t / (2.0 * t0);
+    V = t / t0;
+    A = 1.0 / t0;
+  } else {
+    S = t0 > 0 ? t - 0.5 * t0 : t;
+    V = 1.0;
+    A = 0.0;
+  }
+}
+
 // Persistent grid: enough workgroups for the largest item count the launch
 // can see (capacity), capped at m.grid_cap; always a multiple of 8.
 static inline int persistent_grid(const Mesh& m, long long items) {

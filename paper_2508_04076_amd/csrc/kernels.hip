@@ -159,6 +159,34 @@ __global__ __launch_bounds__(kBlock) void k_elem_force(Mesh m, const Six<R>* __r
   }
 }
 
+// Prescribed components of constrained slot b at time t: velocity v0 V(t),
+// acceleration v0 A(t), the predictor for t_next from the history, and the
+// reaction m a + f - r F on those components (0 on the free ones).
+__device__ __forceinline__ void bc_override(const Mesh& m, int b, double t, double t_next,
+                                            double im, double fx, double fy, double fz, double r,
+                                            double4 F, double4& v, double4& a, double4& uh,
+                                            double4& R) {
+  const int mk = m.bmask[b];
+  double S, V, A, S2, V2, A2;
+  bc_history(m.gt0[mk >> 4], t, S, V, A);
+  bc_history(m.gt0[mk >> 4], t_next, S2, V2, A2);
+  const double4 w = m.bv0[b], ref = m.bref[b];
+  const double mass = im > 0 ? 1.0 / im : 0.0;
+  R = make_double4(0, 0, 0, 0);
+  if (mk & 1) {
+    v.x = w.x * V; a.x = w.x * A; uh.x = ref.x + w.x * S2;
+    R.x = mass * a.x + fx - r * F.x;
+  }
+  if (mk & 2) {
+    v.y = w.y * V; a.y = w.y * A; uh.y = ref.y + w.y * S2;
+    R.y = mass * a.y + fy - r * F.y;
+  }
+  if (mk & 4) {
+    v.z = w.z * V; a.z = w.z * A; uh.z = ref.z + w.z * S2;
+    R.z = mass * a.z + fz - r * F.z;
+  }
+}
+
 // Node pass: G lanes per node sum the node's contributions (lane g takes
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
@@ -185,14 +213,24 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __re
   int ls = m.lslot[i];
   double4 F = ls >= 0 ? m.Fload[ls] : make_double4(0, 0, 0, 0);
   double im = m.invm[i];
+  const int bs = m.n_bc ? m.bslot[i] : -1;
   if (MODE == NODE_INIT) {
-    double r = ramp(m, (double)n * dt);
+    const double t = (double)n * dt;
+    double r = ramp(m, t);
     double4 u0 = st.u[i], v0 = st.v[i];
     double ax = (r * F.x - fx) * im, ay = (r * F.y - fy) * im, az = (r * F.z - fz) * im;
-    st.a[i] = make_double4(ax, ay, az, 0.0);
     double h = 0.5 * dt * dt;
-    st.uh[i] = make_double4(u0.x + dt * v0.x + h * ax, u0.y + dt * v0.y + h * ay,
-                            u0.z + dt * v0.z + h * az, 0.0);
+    double4 uh = make_double4(u0.x + dt * v0.x + h * ax, u0.y + dt * v0.y + h * ay,
+                              u0.z + dt * v0.z + h * az, 0.0);
+    if (bs >= 0) {
+      double4 vv = v0, aa = make_double4(ax, ay, az, 0.0), rc;
+      bc_override(m, bs, t, t + dt, im, fx, fy, fz, r, F, vv, aa, uh, rc);
+      st.v[i] = vv;
+      ax = aa.x; ay = aa.y; az = aa.z;
+      m.breact[bs] = rc;
+    }
+    st.a[i] = make_double4(ax, ay, az, 0.0);
+    st.uh[i] = uh;
     continue;
   }
   // NODE_STEP: f was evaluated at u_{n+1} = uh
@@ -206,11 +244,25 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __re
     m.wacc[ls] += 0.5 * (r0 + r1) * (F.x * (u1.x - u0.x) + F.y * (u1.y - u0.y) + F.z * (u1.z - u0.z));
   }
   double h = 0.5 * dt * dt;
+  double4 uh = make_double4(u1.x + dt * vx + h * ax, u1.y + dt * vy + h * ay, u1.z + dt * vz + h * az,
+                            0.0);
+  if (bs >= 0) {
+    // prescribed components: velocity, acceleration and the next predictor
+    // from the history; the reaction and its work (trapezoid)
+    double4 vv = make_double4(vx, vy, vz, 0.0), aa = make_double4(ax, ay, az, 0.0), rc;
+    double t1 = (double)(n + 1) * dt;
+    bc_override(m, bs, t1, t1 + dt, im, fx, fy, fz, r1, F, vv, aa, uh, rc);
+    vx = vv.x; vy = vv.y; vz = vv.z;
+    ax = aa.x; ay = aa.y; az = aa.z;
+    double4 u0 = st.u[i], r0c = m.breact[bs];
+    m.bwork[bs] += 0.5 * (r0c.x + rc.x) * (u1.x - u0.x) + 0.5 * (r0c.y + rc.y) * (u1.y - u0.y) +
+                   0.5 * (r0c.z + rc.z) * (u1.z - u0.z);
+    m.breact[bs] = rc;
+  }
   st.u[i] = u1;
   st.v[i] = make_double4(vx, vy, vz, 0.0);
   st.a[i] = make_double4(ax, ay, az, 0.0);
-  st.uh[i] = make_double4(u1.x + dt * vx + h * ax, u1.y + dt * vy + h * ay, u1.z + dt * vz + h * az,
-                          0.0);
+  st.uh[i] = uh;
   bool bad = !(fabs(ax) <= DBL_MAX && fabs(ay) <= DBL_MAX && fabs(az) <= DBL_MAX) ||
              !(fabs(u1.x) <= m.umax && fabs(u1.y) <= m.umax && fabs(u1.z) <= m.umax);
   if (bad) atomicCAS(&c->err, 0, -6);
@@ -803,6 +855,62 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
   }
 }
 
+// ---------------------------------------------------------------- prescribed velocities
+
+// Constrained components of u at the current time (before a force evaluation
+// that starts the integration).
+__global__ __launch_bounds__(kBlock) void k_bc_apply(Mesh m, State st, const Counters* c) {
+  int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= m.n_bc) return;
+  int i = m.bnode[b], mk = m.bmask[b];
+  double S, V, A;
+  bc_history(m.gt0[mk >> 4], (double)c->step * node_dt(m, i), S, V, A);
+  double4 u = st.u[i], w = m.bv0[b], ref = m.bref[b];
+  if (mk & 1) u.x = ref.x + w.x * S;
+  if (mk & 2) u.y = ref.y + w.y * S;
+  if (mk & 4) u.z = ref.z + w.z * S;
+  st.u[i] = u;
+}
+
+// Reaction of each group summed over its slots in a fixed tree order, as one
+// history row of the step just taken (the step counter advances after).
+__global__ __launch_bounds__(kBlock) void k_reaction(Mesh m, const Counters* __restrict__ c) {
+  __shared__ double red[3][kBlock];
+  if (c->err) return;
+  const long long n = c->step;
+  const double t1 = (double)(n + 1) * m.dt;
+  for (int g = 0; g < m.n_grp; ++g) {
+    double sx = 0, sy = 0, sz = 0;
+    for (int b = m.goff[g] + threadIdx.x; b < m.goff[g + 1]; b += kBlock) {
+      double4 R = m.breact[b];
+      sx += R.x;
+      sy += R.y;
+      sz += R.z;
+    }
+    red[0][threadIdx.x] = sx;
+    red[1][threadIdx.x] = sy;
+    red[2][threadIdx.x] = sz;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w)
+        for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double S, V, A;
+      bc_history(m.gt0[g], t1, S, V, A);
+      double* row = m.ghist + ((size_t)g * m.hist_cap + (size_t)(n % m.hist_cap)) * 6;
+      row[0] = (double)(n + 1);
+      row[1] = t1;
+      row[2] = red[0][0];
+      row[3] = red[1][0];
+      row[4] = red[2][0];
+      row[5] = S;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- setup
 
 __global__ __launch_bounds__(kBlock) void k_volumes(Mesh m) {
@@ -1156,6 +1264,18 @@ hipError_t Launch<R>::edge_volumes(const Mesh& m, const Work& w, int count, hipS
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_edge_volumes<R>, dim3(grid_for(count)), dim3(kBlock), 0, s, m, (R*)w.einvV,
                      count);
+  return hipGetLastError();
+}
+
+hipError_t launch_bc_apply(const Mesh& m, const State& st, const Counters* c, hipStream_t s) {
+  if (m.n_bc == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bc_apply, dim3(grid_for(m.n_bc)), dim3(kBlock), 0, s, m, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_reaction(const Mesh& m, const Counters* c, hipStream_t s) {
+  if (m.n_grp == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reaction, dim3(1), dim3(kBlock), 0, s, m, c);
   return hipGetLastError();
 }
 

@@ -86,6 +86,12 @@ struct cem_ctx {
   std::vector<void*> allocs;
   std::vector<Region> regions;  // checkpointed device arrays
 
+  // prescribed-velocity groups (host mirror, internal node ids)
+  std::vector<int> bc_node, bc_mask;      // mask | group << 4
+  std::vector<double4> bc_v0;
+  std::vector<double> bc_t0;              // per group
+  std::vector<int> bc_goff{0};            // slot range per group
+
   // per-tet modulus (relative to mat.E); m.kap points at it while on
   double* kap_buf = nullptr;
   bool kap_on = false;
@@ -469,6 +475,7 @@ int node_pass(cem_ctx* c, int mode, double4* fout, hipEvent_t mid = nullptr) {
 }
 
 int initialize(cem_ctx* c) {
+  HIPCHK(c, launch_bc_apply(c->m, c->st, c->d_ctr, c->stream));
   int r = strain_stress(c, c->st.u);
   if (r) return r;
   r = node_pass(c, NODE_INIT, nullptr);
@@ -498,6 +505,7 @@ int enqueue_step(cem_ctx* c, hipEvent_t* ev) {
   int r = node_pass(c, NODE_STEP, nullptr, ev ? ev[4] : nullptr);
   if (r) return r;
   if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
+  HIPCHK(c, launch_reaction(c->m, c->d_ctr, s));
   if (c->mixed)
     HIPCHK(c, launch_topology_t<float>(c->m, c->st, c->w, c->d_ctr, 1, 1, c->d_snodes, c->d_sedges, s));
   else
@@ -1396,6 +1404,7 @@ int cem_set_instances(cem_ctx* c, int32_t n, const int32_t* node_off, const int3
   c->gen++;
   Mesh& m = c->m;
   if (c->m.n_inst) return c->fail(CEM_ESTATE, "instances already declared");
+  if (c->m.n_grp) return c->fail(CEM_ESTATE, "prescribed velocities are not supported in batches");
   if (c->step_host != 0 || c->n_split_host != 0)
     return c->fail(CEM_ESTATE, "instances must be declared before pre-splits and steps");
   if (n < 1 || !node_off || !tet_off) return c->fail(CEM_EINVAL, "bad instance arguments");
@@ -1615,6 +1624,7 @@ int cem_save_state(cem_ctx* c, void* buf, int64_t cap, int64_t* used) {
   int64_t h[hdr] = {0x43454d31, 2, c->m.T0, c->m.N0, c->m.E0, c->m.S_cap, c->mixed, c->m.mode,
                     c->need_init ? 1 : 0, c->step_host, c->n_split_host, c->dt_set ? 1 : 0, 0,
                     c->kap_on ? 1 : 0, (int64_t)c->regions.size(), 0};
+  for (auto& g : c->regions) h[15] += (int64_t)g.bytes;
   double dtv = c->m.dt;
   std::memcpy(&h[12], &dtv, 8);
   char* p = (char*)buf;
@@ -1642,6 +1652,11 @@ int cem_load_state(cem_ctx* c, const void* buf, int64_t size) {
       h[5] != c->m.S_cap || h[6] != c->mixed || h[7] != c->m.mode ||
       h[14] != (int64_t)c->regions.size())
     return c->fail(CEM_EINVAL, "checkpoint does not match this context");
+  {
+    int64_t rb = 0;
+    for (auto& g : c->regions) rb += (int64_t)g.bytes;
+    if (rb != h[15]) return c->fail(CEM_EINVAL, "checkpoint does not match this context");
+  }
   int64_t total = sizeof(h);
   for (auto& g : c->regions) total += (int64_t)g.bytes;
   total += c->m.T0;
@@ -1719,6 +1734,132 @@ int cem_set_modulus(cem_ctx* c, int32_t n_tets, const double* E) {
   return CEM_OK;
 }
 
+int cem_add_velocity_bc(cem_ctx* c, int32_t n, const int32_t* node, const int32_t* dof_mask,
+                        const double* v0, double t0, int32_t* group) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if ((r = read_counters(c))) return r;
+  if (c->h_ctr->step != 0) return c->fail(CEM_ESTATE, "prescribed velocities must precede the first step");
+  if (c->m.n_inst) return c->fail(CEM_ESTATE, "prescribed velocities are not supported in batches");
+  if (n < 0 || (n > 0 && (!node || !dof_mask || !v0))) return c->fail(CEM_EINVAL, "bad arguments");
+  if (!(t0 >= 0) || !std::isfinite(t0)) return c->fail(CEM_EINVAL, "ramp time must be finite and >= 0");
+  if ((int)c->bc_t0.size() >= 64) return c->fail(CEM_EINVAL, "at most 64 groups");
+  Mesh& m = c->m;
+  std::vector<char> seen(m.N0, 0);
+  for (int i : c->bc_node) seen[i] = 1;
+  for (int b = 0; b < n; ++b) {
+    if (node[b] < 0 || node[b] >= m.N0) return c->fail(CEM_EINVAL, "constrained node out of range");
+    if (dof_mask[b] < 1 || dof_mask[b] > 7) return c->fail(CEM_EINVAL, "dof mask must be 1..7");
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(v0[3 * b + d])) return c->fail(CEM_EINVAL, "non-finite velocity");
+    int in = c->node_new[node[b]];
+    if (seen[in]) return c->fail(CEM_EINVAL, "node constrained twice");
+    seen[in] = 1;
+  }
+  c->gen++;
+  const int g = (int)c->bc_t0.size();
+  for (int b = 0; b < n; ++b) {
+    c->bc_node.push_back(c->node_new[node[b]]);
+    c->bc_mask.push_back(dof_mask[b] | (g << 4));
+    c->bc_v0.push_back(make_double4(v0[3 * b], v0[3 * b + 1], v0[3 * b + 2], 0.0));
+  }
+  c->bc_t0.push_back(t0);
+  c->bc_goff.push_back((int)c->bc_node.size());
+  const int nb = (int)c->bc_node.size(), ng = (int)c->bc_t0.size();
+  const int H = 65536;
+  // displacement reference: the nodes' current u
+  std::vector<double4> uall(m.N0);
+  HIPCHK(c, hipMemcpyAsync(uall.data(), c->st.u, sizeof(double4) * m.N0, hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  // previous groups keep their reference, reaction, work and history rows
+  std::vector<double4> ref(nb), react(nb, make_double4(0, 0, 0, 0));
+  std::vector<double> work(nb, 0.0), hist((size_t)ng * H * 6, 0.0);
+  const int nb_old = c->bc_goff[ng - 1];
+  if (nb_old) {
+    HIPCHK(c, hipMemcpyAsync(ref.data(), m.bref, sizeof(double4) * nb_old, hipMemcpyDeviceToHost, c->stream));
+    if ((r = sync(c))) return r;
+  }
+  for (int b = nb_old; b < nb; ++b) ref[b] = uall[c->bc_node[b]];
+  auto release = [&](void* p) {
+    if (!p) return;
+    (void)hipFree(p);
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+    c->regions.erase(std::remove_if(c->regions.begin(), c->regions.end(),
+                                    [&](const Region& q) { return q.ptr == p; }),
+                     c->regions.end());
+  };
+  release(m.bnode); release(m.bmask); release(m.bv0); release(m.bref); release(m.breact);
+  release(m.bwork); release(m.gt0); release(m.goff); release(m.ghist);
+  if (!m.bslot) ALLOC(m.bslot, m.N_cap, false);
+  ALLOC(m.bnode, nb, false);
+  ALLOC(m.bmask, nb, false);
+  ALLOC(m.bv0, nb, false);
+  ALLOC(m.bref, nb, false);
+  ALLOC(m.breact, nb, true);
+  ALLOC(m.bwork, nb, true);
+  ALLOC(m.gt0, ng, false);
+  ALLOC(m.goff, ng + 1, false);
+  ALLOC(m.ghist, (size_t)ng * H * 6, true);
+  std::vector<int> slot(m.N_cap, -1);
+  for (int b = 0; b < nb; ++b) slot[c->bc_node[b]] = b;
+  if ((r = upload(c, m.bslot, slot.data(), slot.size()))) return r;
+  if ((r = upload(c, m.bnode, c->bc_node.data(), (size_t)nb))) return r;
+  if ((r = upload(c, m.bmask, c->bc_mask.data(), (size_t)nb))) return r;
+  if ((r = upload(c, m.bv0, c->bc_v0.data(), (size_t)nb))) return r;
+  if ((r = upload(c, m.bref, ref.data(), (size_t)nb))) return r;
+  if ((r = upload(c, m.breact, react.data(), (size_t)nb))) return r;
+  if ((r = upload(c, m.bwork, work.data(), (size_t)nb))) return r;
+  if ((r = upload(c, m.gt0, c->bc_t0.data(), (size_t)ng))) return r;
+  if ((r = upload(c, m.goff, c->bc_goff.data(), (size_t)ng + 1))) return r;
+  if ((r = upload(c, m.ghist, hist.data(), hist.size()))) return r;
+  if ((r = sync(c))) return r;
+  m.n_bc = nb;
+  m.n_grp = ng;
+  m.hist_cap = H;
+  c->need_init = true;
+  drop_graph(c);
+  if (group) *group = g;
+  return CEM_OK;
+}
+
+int cem_read_reactions(cem_ctx* c, int32_t group, int32_t cap, double* rows, int32_t* n,
+                       double* work) {
+  if (!c || !n) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  Mesh& m = c->m;
+  if (group < 0 || group >= m.n_grp) return c->fail(CEM_EINVAL, "no such group");
+  if ((r = read_counters(c))) return r;
+  const long long S = c->h_ctr->step;
+  const long long cnt = std::min<long long>(S, m.hist_cap);
+  *n = (int32_t)cnt;
+  if (rows && cap > 0) {
+    std::vector<double> h((size_t)m.hist_cap * 6);
+    HIPCHK(c, hipMemcpyAsync(h.data(), m.ghist + (size_t)group * m.hist_cap * 6,
+                             sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    if ((r = sync(c))) return r;
+    long long first = S - cnt;
+    for (long long k = 0; k < cnt && k < cap; ++k) {
+      long long idx = (first + k) % m.hist_cap;
+      for (int q = 0; q < 6; ++q) rows[6 * k + q] = h[6 * idx + q];
+    }
+  }
+  if (work) {
+    const int b0 = c->bc_goff[group], b1 = c->bc_goff[group + 1];
+    std::vector<double> w(std::max(b1 - b0, 1));
+    if (b1 > b0) {
+      HIPCHK(c, hipMemcpyAsync(w.data(), m.bwork + b0, sizeof(double) * (b1 - b0),
+                               hipMemcpyDeviceToHost, c->stream));
+      if ((r = sync(c))) return r;
+    }
+    double s = 0;
+    for (int b = 0; b < b1 - b0; ++b) s += w[b];
+    *work = s;
+  }
+  return CEM_OK;
+}
+
 int cem_set_step(cem_ctx* c, int64_t step) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
@@ -1739,6 +1880,8 @@ int cem_window_forward(cem_ctx* c, int32_t n, int32_t every) {
   int r = ensure_ready(c, true);
   if (r) return r;
   if (n < 0 || every < 1) return c->fail(CEM_EINVAL, "window needs n_steps >= 0 and every >= 1");
+  if (c->m.n_bc || c->m.n_grp)
+    return c->fail(CEM_ESTATE, "gradient windows with prescribed velocities are not supported");
   c->gen++;
   auto& W = c->win;
   W.gen = -1;
