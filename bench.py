@@ -63,7 +63,26 @@ def workload(name):
     if name == "block":
         return mg.block_notched(), 1e-6, ("notched block 400x200x100 cells x 6 tets at 0.5 mm "
                                           "(48,000,000 tets), 2% pre-split, 1 MPa ramped")
+    if name == "dirichlet":
+        m = mg.plate_notched()
+        m.load_tris, m.load_trac = None, None
+        return m, 0.0, ("notched plate 100x40x4 mm, 200x80x8 cells x 6 tets (768,000 tets), "
+                        "velocity-driven: face y = 40 mm at +0.2 m/s in y ramped over 1 us, "
+                        "face y = 0 held in y")
     raise SystemExit(f"unknown workload {name}")
+
+
+def velocity_groups(name, mesh):
+    """Prescribed-velocity groups of a workload: (nodes, dof masks, v0 [n][3], t0)."""
+    if name != "dirichlet":
+        return []
+    y = mesh.X[:, 1]
+    top = np.nonzero(np.abs(y - y.max()) < 1e-12)[0]
+    bot = np.nonzero(np.abs(y - y.min()) < 1e-12)[0]
+    vt = np.zeros((len(top), 3))
+    vt[:, 1] = 0.2
+    return [(top, np.full(len(top), 2), vt, 1e-6),
+            (bot, np.full(len(bot), 2), np.zeros((len(bot), 3)), 0.0)]
 
 
 def counters_for(kernel_src_hash):
@@ -87,7 +106,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="plate",
-                    choices=["plate", "cube", "block8m", "block", "ensemble", "window"])
+                    choices=["plate", "cube", "block8m", "block", "ensemble", "window",
+                             "dirichlet"])
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps for the CPU baseline (0: about 15 s of work)")
@@ -134,9 +154,13 @@ def main():
 
     tuned = {}
 
+    groups = velocity_groups(args.workload, mesh)
+
     def make(precision, graph):
         s_ = Simulation.from_mesh(mesh, mat, ramp_t0=ramp, precision=precision,
                                   max_splits=max_splits, graph_steps=graph, device=0)
+        for g_ in groups:
+            s_.add_velocity_bc(*g_)
         if tuned:
             s_.set_launch(tuned["grid_cap"], tuned["lanes"])
         return s_
@@ -164,6 +188,11 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = sim.kernel_times()
+    reaction = None
+    if groups:
+        rows, work = sim.reactions(0)
+        reaction = {"driven_face_reaction_N_last": rows[-1, 2:5].tolist(),
+                    "driven_face_work_J": work, "rows": len(rows)}
     u64, _, _ = sim.get_state()
     e64 = sim.energy()
     ev64, _ = sim.splits()
@@ -236,6 +265,8 @@ def main():
     if not args.no_cpu:
         from oracle.oracle import Oracle
         o = Oracle.from_mesh(mesh, mat, ramp_t0=ramp)
+        for g_ in groups:
+            o.add_velocity_bc(*g_)
         o.set_dt(dt)
         n_cpu = args.cpu_steps
         if n_cpu <= 0:
@@ -272,6 +303,8 @@ def main():
         "graph_no_events": graph,
         "mixed": mixed,
     }
+    if reaction:
+        out["reactions"] = reaction
     print(json.dumps(out), flush=True)
 
 
