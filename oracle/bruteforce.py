@@ -117,3 +117,75 @@ def lumped_mass(N, elem_nodes, Veff, rho):
         for n in nd:
             m[n] += rho * Veff[j] / 4.0
     return m
+
+
+# ---------------------------------------------------------------- hexahedra
+
+_HEX_SIGN = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                      [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], float)
+# the six faces as local node quadruples, counter-clockwise seen from outside
+_HEX_FACES = [(0, 3, 2, 1), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)]
+_HEX_EDGES = [(0, 1), (1, 2), (2, 3), (3, 0), (4, 5), (5, 6), (6, 7), (7, 4),
+              (0, 4), (1, 5), (2, 6), (3, 7)]
+
+
+def hex_surface_integrals(x):
+    """x: [8, 3] hex nodes.  Returns (G [8, 3], V) with G_i = integral of grad N_i
+    over the hex and V its volume, both from surface integrals (divergence
+    theorem): G_i = sum over faces of int N_i n dS and V = (1/3) int x . n dS,
+    each face a bilinear patch integrated with 2 x 2 Gauss points (exact)."""
+    x = np.asarray(x, float)
+    G = np.zeros((8, 3))
+    V = 0.0
+    a = 1.0 / np.sqrt(3.0)
+    for f in _HEX_FACES:
+        xf = x[list(f)]
+        for s in (-a, a):
+            for t in (-a, a):
+                w = np.array([(1 - s) * (1 - t), (1 + s) * (1 - t), (1 + s) * (1 + t),
+                              (1 - s) * (1 + t)]) / 4.0
+                ds = np.array([-(1 - t), (1 - t), (1 + t), -(1 + t)]) / 4.0
+                dt = np.array([-(1 - s), -(1 + s), (1 + s), (1 - s)]) / 4.0
+                xs, xt = ds @ xf, dt @ xf
+                ndS = np.cross(xs, xt)          # outward for this node order
+                for q, i in enumerate(f):
+                    G[i] += w[q] * ndS
+                V += (w @ xf) @ ndS / 3.0
+    return G, V
+
+
+def assemble_hex(X, hexes, E, nu):
+    """Dense ES-H-FEM stiffness: each hex enters with its volume-averaged
+    gradients, edges are the 12 hex edges, V_k = (1/12) sum of the patch
+    volumes, K = sum_k V_k Bt_k^T C Bt_k."""
+    X = np.asarray(X, float)
+    hexes = np.asarray(hexes)
+    N = len(X)
+    C = cmat(E, nu)
+    Bs, Vs = [], []
+    for h in hexes:
+        G, V = hex_surface_integrals(X[h])
+        g = G / V
+        B = np.zeros((6, 24))
+        for l in range(8):
+            gx, gy, gz = g[l]
+            c = 3 * l
+            B[0, c], B[1, c + 1], B[2, c + 2] = gx, gy, gz
+            B[3, c], B[3, c + 1] = gy, gx
+            B[4, c + 1], B[4, c + 2] = gz, gy
+            B[5, c], B[5, c + 2] = gz, gx
+        Bs.append(B)
+        Vs.append(V)
+    patches = {}
+    for j, h in enumerate(hexes):
+        for a, b in _HEX_EDGES:
+            patches.setdefault(tuple(sorted((int(h[a]), int(h[b])))), []).append(j)
+    dof = lambda nd: np.array([[3 * n, 3 * n + 1, 3 * n + 2] for n in nd]).ravel()
+    K = np.zeros((3 * N, 3 * N))
+    for pj in patches.values():
+        S = sum(Vs[j] for j in pj)
+        Bt = np.zeros((6, 3 * N))
+        for j in pj:
+            Bt[:, dof(hexes[j])] += (Vs[j] / S) * Bs[j]
+        K += (S / 12.0) * Bt.T @ C @ Bt
+    return K, np.array(Vs)

@@ -37,6 +37,12 @@
 //     enters the smoothing domain of edge k as C_k = sum_j w_jk C_j, the
 //     volume average of the element matrices over the domain, so that
 //     sigma_k = C_k eps_k;
+//   * trilinear hexahedra (Eqs. hex_strain_discretization and
+//     hex_fint_discretization): each hex enters with one gradient per node,
+//     the volume average (1/V) integral of grad N_i over the element (exact with
+//     2 x 2 x 2 Gauss points); edges are the 12 hex edges and the smoothing
+//     domain of edge k has V_k = (1/12) sum of the volumes sharing it; the
+//     lumped mass is rho V / 8 per node; hexes do not split;
 //   * a prescribed velocity v0 r_v(t) on listed degrees of freedom, with the
 //     ramp r_v = t / t0 up to t0 and 1 after (Section 4 examples), fixes the
 //     displacement to u_ref + v0 S(t), S the integral of r_v, the velocity to
@@ -111,8 +117,9 @@ void jacobi_eig(int n, std::vector<double> A, double* w, double* vec) {
 }
 
 struct Elem {
-  int n[4];          // node ids (real or extra)
-  double g[4][3];    // dN_l/dx, Section 2.2 (constant per tet)
+  int nn = 4;        // nodes: 4 (tet) or 8 (hex)
+  int n[8];          // node ids (real or extra)
+  double g[8][3];    // dN_l/dx, Section 2.2 (constant per tet; volume average per hex)
   double V;          // volume of the parent tetrahedron
   double Veff;       // volume the element carries (V, a fraction of V, or 0)
   int parent;        // original tet id
@@ -138,6 +145,7 @@ struct orc_ctx {
   double E = 0, nu = 0, rho = 0, Gc = 0, lam = 0, mu = 0;
   int mode = 0, gsig = 0;
   int N0 = 0, T0 = 0;
+  double D = 6.0;  // V_k = (1/D) sum of the patch volumes: 6 (tets), 12 (hexes)
   std::vector<V3> X;
   std::vector<Elem> el;
   std::map<std::pair<int, int>, int> edge_of;
@@ -219,12 +227,13 @@ double tet_geometry(const V3 x[4], double g[4][3]) {
   return det / 6.0;
 }
 
-// Strain-displacement matrix B (6 x 12) of Eq. CSTet_strain_discretization,
-// columns ordered (u_0, v_0, w_0, u_1, ...).
-void bmat(const double g[4][3], double B[6][12]) {
+// Strain-displacement matrix B (6 x 3nn) of Eqs. CSTet_strain_discretization
+// and hex_strain_discretization, columns ordered (u_0, v_0, w_0, u_1, ...).
+void bmat(const Elem& e, double B[6][24]) {
+  const double(*g)[3] = e.g;
   for (int r = 0; r < 6; ++r)
-    for (int c = 0; c < 12; ++c) B[r][c] = 0.0;
-  for (int l = 0; l < 4; ++l) {
+    for (int c = 0; c < 24; ++c) B[r][c] = 0.0;
+  for (int l = 0; l < e.nn; ++l) {
     double gx = g[l][0], gy = g[l][1], gz = g[l][2];
     int c = 3 * l;
     B[0][c + 0] = gx;
@@ -291,10 +300,20 @@ int find_or_add_edge(orc_ctx* c, int a, int b) {
 }
 
 const int kEdgeLocal[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+// hex node order: bottom face 0-1-2-3 counter-clockwise, top face 4-7 above
+const int kHexEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
+                             {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+
+int elem_edges(const Elem& e, const int (**tab)[2]) {
+  *tab = e.nn == 8 ? kHexEdge : kEdgeLocal;
+  return e.nn == 8 ? 12 : 6;
+}
 
 void add_elem_to_edges(orc_ctx* c, int e) {
-  for (int q = 0; q < 6; ++q) {
-    int k = find_or_add_edge(c, c->el[e].n[kEdgeLocal[q][0]], c->el[e].n[kEdgeLocal[q][1]]);
+  const int(*tab)[2];
+  int ne = elem_edges(c->el[e], &tab);
+  for (int q = 0; q < ne; ++q) {
+    int k = find_or_add_edge(c, c->el[e].n[tab[q][0]], c->el[e].n[tab[q][1]]);
     c->patch[k].push_back(e);
   }
 }
@@ -312,7 +331,7 @@ void remove_elem_from_edges(orc_ctx* c, int e) {
 void rebuild_masses(orc_ctx* c) {
   c->m.assign(c->X.size(), 0.0);
   for (const Elem& e : c->el)
-    for (int l = 0; l < 4; ++l) c->m[e.n[l]] += c->rho * e.Veff / 4.0;
+    for (int l = 0; l < e.nn; ++l) c->m[e.n[l]] += c->rho * e.Veff / e.nn;
 }
 
 // Smoothed strain and stress of every edge (Eqs. strain_discretization and
@@ -347,13 +366,14 @@ void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::ar
                  std::vector<std::array<double, 6>>& sig, std::vector<double>& Vsum) {
   std::vector<std::array<double, 6>> eps_el(c->el.size());
   for (size_t j = 0; j < c->el.size(); ++j) {
-    double B[6][12], ue[12];
-    bmat(c->el[j].g, B);
-    for (int l = 0; l < 4; ++l)
+    double B[6][24], ue[24];
+    bmat(c->el[j], B);
+    const int nc = 3 * c->el[j].nn;
+    for (int l = 0; l < c->el[j].nn; ++l)
       for (int d = 0; d < 3; ++d) ue[3 * l + d] = u[c->el[j].n[l]][d];
     for (int r = 0; r < 6; ++r) {
       double s = 0;
-      for (int q = 0; q < 12; ++q) s += B[r][q] * ue[q];
+      for (int q = 0; q < nc; ++q) s += B[r][q] * ue[q];
       eps_el[j][r] = s;
     }
   }
@@ -391,12 +411,12 @@ void internal_force(const orc_ctx* c, const std::vector<V3>& u, std::vector<V3>&
   for (size_t k = 0; k < c->edge_nodes.size(); ++k) {
     double S = Vsum[k];
     if (S == 0.0) continue;
-    double Vk = S / 6.0;
+    double Vk = S / c->D;
     for (int j : c->patch[k]) {
       double w = c->el[j].Veff / S;
-      double B[6][12];
-      bmat(c->el[j].g, B);
-      for (int q = 0; q < 12; ++q) {
+      double B[6][24];
+      bmat(c->el[j], B);
+      for (int q = 0; q < 3 * c->el[j].nn; ++q) {
         double s = 0;
         for (int r = 0; r < 6; ++r) s += B[r][q] * sig[k][r];
         f[c->el[j].n[q / 3]][q % 3] += Vk * w * s;
@@ -713,7 +733,7 @@ double strain_energy(const orc_ctx* c) {
   for (size_t k = 0; k < eps.size(); ++k) {
     double s = 0;
     for (int r = 0; r < 6; ++r) s += sig[k][r] * eps[k][r];
-    se += 0.5 * (Vsum[k] / 6.0) * s;
+    se += 0.5 * (Vsum[k] / c->D) * s;
   }
   return se;
 }
@@ -738,7 +758,7 @@ void modulus_term(const orc_ctx* c, const std::vector<V3>& lam, const std::vecto
     double q = 0;
     for (int r = 0; r < 6; ++r)
       for (int p = 0; p < 6; ++p) q += el[k][r] * Ch[r][p] * eu[k][p];
-    double Vk = S / 6.0;
+    double Vk = S / c->D;
     for (int j : c->patch[k]) out[c->el[j].parent] += scale * Vk * (c->el[j].Veff / S) * q;
   }
 }
@@ -807,6 +827,61 @@ int window_gradient(orc_ctx* c, int n, const double* gu, const double* gv, doubl
   if (gE)
     for (int t = 0; t < c->T0; ++t) gE[t] = Eb[t];
   return 0;
+}
+
+// Trilinear hexahedron (Eq. hex_strain_discretization): volume and the
+// volume-averaged gradients g_i = (1/V) int grad N_i dV, with
+// N_i = (1 + xi xi_i)(1 + eta eta_i)(1 + zeta zeta_i) / 8 on [-1, 1]^3 and
+// 2 x 2 x 2 Gauss points (exact: the integrand adj(J)^T grad_xi N_i is a
+// polynomial of degree at most 3 in each reference coordinate).  Returns V;
+// *min_det receives the smallest Jacobian determinant at the Gauss points.
+double hex_geometry(const V3 x[8], double g[8][3], double* min_det) {
+  static const int sg[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                               {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+  const double a = 1.0 / std::sqrt(3.0);
+  double V = 0;
+  for (int i = 0; i < 8; ++i) g[i][0] = g[i][1] = g[i][2] = 0;
+  *min_det = INFINITY;
+  for (int p = 0; p < 8; ++p) {
+    double xi[3] = {sg[p][0] * a, sg[p][1] * a, sg[p][2] * a};
+    double dN[8][3];  // dN_i / d(xi, eta, zeta)
+    for (int i = 0; i < 8; ++i) {
+      double f[3];
+      for (int d = 0; d < 3; ++d) f[d] = 1.0 + xi[d] * sg[i][d];
+      dN[i][0] = sg[i][0] * f[1] * f[2] / 8.0;
+      dN[i][1] = f[0] * sg[i][1] * f[2] / 8.0;
+      dN[i][2] = f[0] * f[1] * sg[i][2] / 8.0;
+    }
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // J[r][c] = dx_r / dxi_c
+    for (int i = 0; i < 8; ++i)
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J[r][c] += x[i][r] * dN[i][c];
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    *min_det = std::min(*min_det, det);
+    double inv[3][3];  // J^{-1}
+    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    // grad N_i = J^{-T} grad_xi N_i, weighted by det J (Gauss weights 1)
+    for (int i = 0; i < 8; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double s = 0;
+        for (int c = 0; c < 3; ++c) s += inv[c][d] * dN[i][c];
+        g[i][d] += s * det;
+      }
+    V += det;
+  }
+  for (int i = 0; i < 8; ++i)
+    for (int d = 0; d < 3; ++d) g[i][d] /= V;
+  return V;
 }
 
 }  // namespace
@@ -902,6 +977,65 @@ orc_ctx* orc_create(int n_nodes, const double* X, int n_tets, const int* tets, d
   return c;
 }
 
+// Trilinear hexahedral mesh (node order: bottom face 0-1-2-3 counter-clockwise
+// seen from above, top face 4-7 above them).  A hex with negative Jacobian
+// determinants throughout is mirrored (local nodes 1 <-> 3, 5 <-> 7); one
+// with mixed signs is rejected.  Hexes do not split (no crack pass).
+orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex, double E, double nu,
+                        double rho) {
+  orc_ctx* c = new orc_ctx();
+  c->E = E; c->nu = nu; c->rho = rho; c->Gc = INFINITY;
+  c->D = 12.0;
+  lame(E, nu, &c->lam, &c->mu);
+  c->N0 = n_nodes;
+  c->T0 = n_hex;
+  c->X.resize(n_nodes);
+  for (int i = 0; i < n_nodes; ++i) c->X[i] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
+  c->el.resize(n_hex);
+  for (int t = 0; t < n_hex; ++t) {
+    Elem& e = c->el[t];
+    e.nn = 8;
+    for (int l = 0; l < 8; ++l) {
+      e.n[l] = hex[8 * t + l];
+      if (e.n[l] < 0 || e.n[l] >= n_nodes) {
+        c->status = -5;
+        c->err = "node id out of range";
+        return c;
+      }
+    }
+    V3 x[8];
+    for (int l = 0; l < 8; ++l) x[l] = c->X[e.n[l]];
+    double mind;
+    double V = hex_geometry(x, e.g, &mind);
+    if (V < 0) {
+      std::swap(e.n[1], e.n[3]);
+      std::swap(e.n[5], e.n[7]);
+      for (int l = 0; l < 8; ++l) x[l] = c->X[e.n[l]];
+      V = hex_geometry(x, e.g, &mind);
+    }
+    if (!(mind > 0)) {
+      c->status = -5;
+      c->err = "degenerate or inverted hexahedron " + std::to_string(t);
+      return c;
+    }
+    e.V = V;
+    e.Veff = V;
+    e.parent = t;
+  }
+  for (int t = 0; t < n_hex; ++t) add_elem_to_edges(c, t);
+  c->orig.assign(n_hex, {0, 0, 0, 0});
+  c->nbr.assign(n_hex, {-1, -1, -1, -1});
+  c->nbr_face.assign(n_hex, {-1, -1, -1, -1});
+  c->smask.assign(n_hex, -1);
+  c->Et.assign(n_hex, E);
+  c->u.assign(n_nodes, {0, 0, 0});
+  c->v.assign(n_nodes, {0, 0, 0});
+  c->a.assign(n_nodes, {0, 0, 0});
+  c->F.assign(n_nodes, {0, 0, 0});
+  rebuild_masses(c);
+  return c;
+}
+
 int orc_create_status(const orc_ctx* c) { return c->status; }
 const char* orc_error(const orc_ctx* c) { return c->err.c_str(); }
 void orc_destroy(orc_ctx* c) { delete c; }
@@ -926,6 +1060,7 @@ int orc_set_traction(orc_ctx* c, int n_faces, const int* tri, const double* t, d
 }
 
 int orc_presplit(orc_ctx* c, int n, const int* tet, const unsigned char* mask) {
+  if (c->D != 6.0) return c->fail(-7, "hexahedra do not split");
   std::vector<std::pair<int, int>> lst;
   for (int i = 0; i < n; ++i) {
     int nb = popcount4(mask[i] & 15);
@@ -952,37 +1087,39 @@ int orc_critical_dt(orc_ctx* c, double* dt_crit) {
   orc_elem_lambda_max(c, lam.data());
   double lmax = 0;
   for (double l : lam) lmax = std::max(lmax, l);
-  *dt_crit = 2.0 / std::sqrt(4.0 / c->rho * lmax);
+  // M_e = rho V / nn per node: omega^2 = (nn / rho) lambda_max(B^T C B)
+  *dt_crit = 2.0 / std::sqrt(c->el[0].nn / c->rho * lmax);
   return 0;
 }
 
 int orc_elem_lambda_max(orc_ctx* c, double* lam) {
   double C[6][6];
   cmat(c->lam, c->mu, C);
-  std::map<std::array<double, 12>, double> memo;  // identical shapes repeat
+  std::map<std::array<double, 24>, double> memo;  // identical shapes repeat
   for (int t = 0; t < c->T0; ++t) {
-    std::array<double, 12> key;
-    for (int l = 0; l < 4; ++l)
+    const int nc = 3 * c->el[t].nn;
+    std::array<double, 24> key{};
+    for (int l = 0; l < c->el[t].nn; ++l)
       for (int d = 0; d < 3; ++d) key[3 * l + d] = c->el[t].g[l][d];
     auto it = memo.find(key);
     if (it != memo.end()) {
       lam[t] = it->second;
       continue;
     }
-    double B[6][12];
-    bmat(c->el[t].g, B);
-    std::vector<double> K(144, 0.0);
-    for (int i = 0; i < 12; ++i)
-      for (int j = 0; j < 12; ++j) {
+    double B[6][24];
+    bmat(c->el[t], B);
+    std::vector<double> K(nc * nc, 0.0);
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nc; ++j) {
         double s = 0;
         for (int r = 0; r < 6; ++r)
           for (int q = 0; q < 6; ++q) s += B[r][i] * C[r][q] * B[q][j];
-        K[12 * i + j] = s;
+        K[nc * i + j] = s;
       }
-    double w[12];
-    jacobi_eig(12, K, w, nullptr);
+    double w[24];
+    jacobi_eig(nc, K, w, nullptr);
     double lm = w[0];
-    for (int i = 1; i < 12; ++i) lm = std::max(lm, w[i]);
+    for (int i = 1; i < nc; ++i) lm = std::max(lm, w[i]);
     memo[key] = lm;
     lam[t] = lm;
   }
@@ -1177,6 +1314,7 @@ double orc_crack_area(const double* X4, int mask) {
 }
 
 int orc_set_modulus(orc_ctx* c, const double* E_tet) {
+  if (c->D != 6.0) return c->fail(-7, "per-element modulus is for tetrahedra");
   for (int t = 0; t < c->T0; ++t) {
     if (!(E_tet[t] > 0)) return c->fail(-1, "modulus must be positive");
   }

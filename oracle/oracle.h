@@ -30,6 +30,10 @@ typedef struct orc_ctx orc_ctx;
 orc_ctx* orc_create(int n_nodes, const double* X, int n_tets, const int* tets,
                     double E, double nu, double rho, double Gc,
                     int split_mode, int gsig);
+/* Trilinear hexahedra, 8 nodes each (bottom face 0-1-2-3 counter-clockwise
+ * seen from above, top face 4-7 above them); no crack pass. */
+orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex,
+                        double E, double nu, double rho);
 int orc_create_status(const orc_ctx* c);
 const char* orc_error(const orc_ctx* c);
 void orc_destroy(orc_ctx* c);

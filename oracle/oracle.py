@@ -42,6 +42,8 @@ def lib():
         L = C.CDLL(LIB)
         L.orc_create.restype = _p
         L.orc_create.argtypes = [_i, _p, _i, _p, _d, _d, _d, _d, _i, _i]
+        L.orc_create_hex.restype = _p
+        L.orc_create_hex.argtypes = [_i, _p, _i, _p, _d, _d, _d]
         L.orc_error.restype = C.c_char_p
         L.orc_error.argtypes = [_p]
         L.orc_create_status.argtypes = [_p]
@@ -129,14 +131,19 @@ def crack_area(X4, mask):
 class Oracle:
     """One simulation of the oracle: mesh, material, loads, state."""
 
-    def __init__(self, X, tets, E, nu, rho, Gc=np.inf, split_mode="phantom", gsig="principal"):
+    def __init__(self, X, tets, E, nu, rho, Gc=np.inf, split_mode="phantom", gsig="principal",
+                 hexes=False):
         self._X = _f64(X)
         self._t = _i32(tets)
-        mode = {"phantom": 0, "erode": 1}[split_mode]
-        gs = {"principal": 0, "normal": 1}[gsig]
         L = lib()
-        self.c = L.orc_create(len(self._X), _ptr(self._X), len(self._t), _ptr(self._t),
-                              float(E), float(nu), float(rho), float(Gc), mode, gs)
+        if hexes:
+            self.c = L.orc_create_hex(len(self._X), _ptr(self._X), len(self._t), _ptr(self._t),
+                                      float(E), float(nu), float(rho))
+        else:
+            mode = {"phantom": 0, "erode": 1}[split_mode]
+            gs = {"principal": 0, "normal": 1}[gsig]
+            self.c = L.orc_create(len(self._X), _ptr(self._X), len(self._t), _ptr(self._t),
+                                  float(E), float(nu), float(rho), float(Gc), mode, gs)
         st = L.orc_create_status(self.c)
         if st != 0:
             msg = L.orc_error(self.c).decode()
@@ -164,6 +171,14 @@ class Oracle:
             o.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
         if presplit and mesh.presplit_tets is not None:
             o.presplit(mesh.presplit_tets, mesh.presplit_masks)
+        return o
+
+    @classmethod
+    def hex_mesh(cls, mesh, material, traction=True, ramp_t0=0.0):
+        """Oracle of a trilinear hexahedral mesh (no crack pass)."""
+        o = cls(mesh.X, mesh.hexes, material["E"], material["nu"], material["rho"], hexes=True)
+        if traction and mesh.load_tris is not None:
+            o.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
         return o
 
     def set_traction(self, tri, t, ramp_t0=0.0):

@@ -7,6 +7,15 @@
 #include <float.h>
 #include <math.h>
 
+// patch entries gathered together by the edge passes
+#ifndef CEM_EDGE_BATCH
+#define CEM_EDGE_BATCH 6
+#endif
+// edge stresses gathered together by the element force pass (6 or 3)
+#ifndef CEM_ELEM_GATHER
+#define CEM_ELEM_GATHER 6
+#endif
+
 namespace cem {
 
 // ---------------------------------------------------------------- helpers
@@ -135,7 +144,7 @@ __device__ __forceinline__ void sym_grad(const R g[3][3], const R d[3][3], R f, 
 template <class R>
 __device__ __forceinline__ void edge_sum(const Mesh& m, const Six<R>* __restrict__ veps, int k,
                                          R* acc) {
-  constexpr int B = 6;
+  constexpr int B = CEM_EDGE_BATCH;
   int p0 = m.poff[k], p1 = m.poff[k + 1];
 #pragma unroll
   for (int i = 0; i < 6; ++i) acc[i] = 0;
@@ -176,15 +185,31 @@ __device__ __forceinline__ void elem_terms(const Mesh& m, int e, int4 nd, int co
                                            const Six<R>* __restrict__ esig, R out[4][3]) {
   int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
   double4 x0 = m.X[nd.x & kNodeMask], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
-  Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
-  Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+  R sg[6];
+#if CEM_ELEM_GATHER == 3
+  {
+    Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r];
+  }
+  __asm__ volatile("" ::: "memory");  // the second three loads after the first sums
+  {
+    Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) sg[r] = sg[r] + s3.v[r] + s4.v[r] + s5.v[r];
+  }
+#else
+  {
+    Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
+    Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
+  }
+#endif
   R g[4][3];
   face_normals(x0, x1, x2, x3, g + 1);
 #pragma unroll
   for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
-  R sg[6];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
   R w = (R)(frac_of(code) / 36.0);
 #pragma unroll
   for (int l = 0; l < 4; ++l) {

@@ -17,6 +17,19 @@
 // cross product over 6, so no element needs a determinant or a division.
 #include "device_util.h"
 
+#ifndef CEM_WPE_STRAIN
+#define CEM_WPE_STRAIN 1
+#endif
+#ifndef CEM_WPE_EDGE
+#define CEM_WPE_EDGE 1
+#endif
+#ifndef CEM_WPE_ELEM
+#define CEM_WPE_ELEM 1
+#endif
+#ifndef CEM_WPE_NODE
+#define CEM_WPE_NODE 1
+#endif
+
 namespace cem {
 
 // local edge q of a tet joins local nodes (kEA[q], kEB[q])
@@ -45,7 +58,7 @@ __device__ __forceinline__ double elem_volume(const Mesh& m, int4 nd) {
 // g_1 = c2 x c3, g_2 = c3 x c1, g_3 = c1 x c2, c_l = X_l - X_0 (g_l = 6 V grad N_l).
 // Differences are taken in float64 before any conversion to R.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_strain(Mesh m, const double4* __restrict__ u,
+__global__ __launch_bounds__(kBlock, CEM_WPE_STRAIN) void k_strain(Mesh m, const double4* __restrict__ u,
                                                    Six<R>* __restrict__ veps,
                                                    const Counters* __restrict__ c) {
   if (c->err) return;
@@ -70,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_strain(Mesh m, const double4* __rest
 // ---------------------------------------------------------------- edge stress pass
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_edge_stress(Mesh m, const Six<R>* __restrict__ veps,
+__global__ __launch_bounds__(kBlock, CEM_WPE_EDGE) void k_edge_stress(Mesh m, const Six<R>* __restrict__ veps,
                                                         const R* __restrict__ einvV,
                                                         Six<R>* __restrict__ esig,
                                                         const Counters* __restrict__ c) {
@@ -137,7 +150,7 @@ __device__ __forceinline__ bool over_capacity(const Mesh& m, Counters* c) {
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_elem_force(Mesh m, const Six<R>* __restrict__ esig,
+__global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force(Mesh m, const Six<R>* __restrict__ esig,
                                                        R* __restrict__ contrib,
                                                        Counters* __restrict__ c) {
   if (c->err || over_capacity(m, c)) return;
@@ -190,8 +203,8 @@ __device__ __forceinline__ void bc_override(const Mesh& m, int b, double t, doub
 // Node pass: G lanes per node sum the node's contributions (lane g takes
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
-template <class R, int MODE, int G>
-__global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __restrict__ contrib,
+template <class R, int MODE, int G, bool BC>
+__global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st, const R* __restrict__ contrib,
                                                  double4* __restrict__ fout,
                                                  Counters* __restrict__ c) {
   if (c->err || over_capacity(m, c)) return;
@@ -213,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_node(Mesh m, State st, const R* __re
   int ls = m.lslot[i];
   double4 F = ls >= 0 ? m.Fload[ls] : make_double4(0, 0, 0, 0);
   double im = m.invm[i];
-  const int bs = m.n_bc ? m.bslot[i] : -1;
+  const int bs = BC ? m.bslot[i] : -1;
   if (MODE == NODE_INIT) {
     const double t = (double)n * dt;
     double r = ramp(m, t);
@@ -1233,12 +1246,18 @@ template <class R, int G>
 static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
                               Counters* c, int mode, double4* fout, hipStream_t s) {
   dim3 g(persistent_grid(m, (long long)m.N_cap * G)), b(kBlock);
+  // constrained nodes take their own kernel variant, so that a mesh without
+  // prescribed velocities pays nothing for them
   if (mode == NODE_FORCE)
-    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false>), g, b, 0, s, m, st, ct, fout, c);
+  else if (mode == NODE_INIT && m.n_bc)
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true>), g, b, 0, s, m, st, ct, fout, c);
   else if (mode == NODE_INIT)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false>), g, b, 0, s, m, st, ct, fout, c);
+  else if (m.n_bc)
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true>), g, b, 0, s, m, st, ct, fout, c);
   else
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false>), g, b, 0, s, m, st, ct, fout, c);
 }
 
 template <class R>

@@ -337,3 +337,42 @@ def modulus_field(n_tets, E0=32e9, sigma=0.1, seed=3):
     """Per-tet Young's modulus E_j = E0 exp(sigma z_j), z_j iid N(0, 1)."""
     rng = np.random.default_rng(seed)
     return E0 * np.exp(sigma * rng.standard_normal(n_tets))
+
+
+@dataclasses.dataclass
+class HexMesh:
+    """A trilinear hexahedral mesh plus its loads."""
+    X: np.ndarray               # [N, 3] float64 node coordinates (m)
+    hexes: np.ndarray           # [H, 8] int32 node ids, bottom face 0-1-2-3 then top 4-7
+    grid: tuple = None
+    h: tuple = None
+    load_tris: np.ndarray = None
+    load_trac: np.ndarray = None
+
+    @property
+    def n_nodes(self):
+        return int(self.X.shape[0])
+
+    @property
+    def n_hex(self):
+        return int(self.hexes.shape[0])
+
+
+def hex_box(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0):
+    """Structured grid of nx*ny*nz hexahedral cells (the node grid of
+    kuhn_box); cell order x-fastest; node order per cell (i,j,k), (i+1,j,k),
+    (i+1,j+1,k), (i,j+1,k), then the same at k+1 (positive orientation).
+    Loaded faces use face_triangles: each boundary square as two triangles."""
+    t = kuhn_box(nx, ny, nz, lx, ly, lz)
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci = ci.transpose(2, 1, 0).ravel()
+    cj = cj.transpose(2, 1, 0).ravel()
+    ck = ck.transpose(2, 1, 0).ravel()
+    off = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    hx = np.stack([node_id(ci + a, cj + b, ck + c, nx, ny) for a, b, c in off], axis=1)
+    return HexMesh(X=t.X, hexes=hx.astype(np.int32), grid=(nx, ny, nz), h=t.h)
+
+
+def hex_bar(n=100, lx=1.0, w=0.01):
+    """Slender hexahedral bar of n x 1 x 1 cells along x."""
+    return hex_box(n, 1, 1, lx, w, w)
