@@ -133,6 +133,20 @@ const char* cem_last_error(const cem_ctx* ctx);
 int cem_upload_mesh(cem_ctx* ctx, int32_t n_nodes, const double* X, int32_t n_tets,
                     const int32_t* tets, const cem_material* mat);
 
+/* Trilinear hexahedral mesh instead of tetrahedra (the paper's second element
+ * family, Eqs. hex_strain_discretization and hex_fint_discretization): hexes
+ * [H][8] with nodes 0-1-2-3 counter-clockwise on the bottom face (seen from
+ * above) and 4-7 above them; a hex inverted throughout is mirrored, one whose
+ * Jacobian changes sign inside is CEM_EMESH.  Each hex enters the edge
+ * smoothing with its volume-averaged gradients (2 x 2 x 2 Gauss points), the
+ * 12 hex edges form the smoothing domains with V_k = (1/12) sum of the patch
+ * volumes, and the lumped mass is rho V / 8 per node.  Hexes do not split:
+ * the crack pass is off (Gc is ignored) and the splitting, batch, modulus and
+ * gradient-window calls return CEM_ESTATE.  Tractions (triangles), prescribed
+ * velocities, steps, energies and checkpoints work as for tetrahedra. */
+int cem_upload_hex_mesh(cem_ctx* ctx, int32_t n_nodes, const double* X, int32_t n_hex,
+                        const int32_t* hexes, const cem_material* m);
+
 /* Face tractions (the f_ext equation): boundary triangles tri [n_faces][3]
  * with traction vectors t [n_faces][3] (Pa).  Each triangle adds t A / 3 to
  * each vertex.  Load factor r(t) = t / ramp_t0 below ramp_t0, else 1

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libcem.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "adjoint.hip", "runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "hex.hip", "adjoint.hip", "runtime.hip")]
 ARCH = os.environ.get("CEM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

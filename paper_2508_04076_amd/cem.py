@@ -24,7 +24,8 @@ SPLIT_MODE = {"phantom": 0, "erode": 1}
 GSIG = {"principal": 0, "normal": 1}
 
 EXPORTS = [
-    "cem_create", "cem_destroy", "cem_last_error", "cem_upload_mesh", "cem_set_traction",
+    "cem_create", "cem_destroy", "cem_last_error", "cem_upload_mesh", "cem_upload_hex_mesh",
+    "cem_set_traction",
     "cem_presplit", "cem_critical_dt", "cem_set_dt", "cem_bind_state", "cem_set_state",
     "cem_get_state", "cem_internal_force", "cem_step", "cem_replay_splits", "cem_read_energy",
     "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
@@ -88,6 +89,7 @@ def load_library(path=LIB_PATH):
         "cem_destroy": [p],
         "cem_last_error": [p],
         "cem_upload_mesh": [p, i32, p, i32, p, C.POINTER(cem_material)],
+        "cem_upload_hex_mesh": [p, i32, p, i32, p, C.POINTER(cem_material)],
         "cem_set_traction": [p, i32, p, p, d],
         "cem_presplit": [p, i32, p, p],
         "cem_critical_dt": [p, C.POINTER(C.c_double)],
@@ -143,13 +145,15 @@ class Simulation:
     """One ES-T-FEM crack-element simulation on one GPU (a libcem context)."""
 
     def __init__(self, X, tets, material, precision="fp64", split_mode="phantom",
-                 gsig="principal", max_splits=None, graph_steps=0, device=0, stream=None):
+                 gsig="principal", max_splits=None, graph_steps=0, device=0, stream=None,
+                 hexes=False):
+        """tets: [T, 4] tetrahedra, or [H, 8] trilinear hexahedra with hexes=True."""
         self.lib = load_library()
         self.ctx = None
         X = _f64(X, (-1, 3))
-        tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+        tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 8 if hexes else 4)
         if max_splits is None:
-            max_splits = max(len(tets) // 8, 64)
+            max_splits = 0 if hexes else max(len(tets) // 8, 64)
         self._torch_stream = None
         if stream is None:
             import torch
@@ -164,8 +168,8 @@ class Simulation:
         self.ctx = ctx
         mat = cem_material(float(material["E"]), float(material["nu"]), float(material["rho"]),
                            float(material.get("Gc", np.inf)))
-        self._chk(self.lib.cem_upload_mesh(self.ctx, len(X), _p(X), len(tets), _p(tets),
-                                           C.byref(mat)))
+        upload = self.lib.cem_upload_hex_mesh if hexes else self.lib.cem_upload_mesh
+        self._chk(upload(self.ctx, len(X), _p(X), len(tets), _p(tets), C.byref(mat)))
         self.n_tets = len(tets)
         self.n_nodes0 = len(X)
         self.precision = precision
@@ -183,6 +187,14 @@ class Simulation:
             sim.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
         if presplit and mesh.presplit_tets is not None:
             sim.presplit(mesh.presplit_tets, mesh.presplit_masks)
+        return sim
+
+    @classmethod
+    def from_hex_mesh(cls, mesh, material, traction=True, ramp_t0=0.0, **kw):
+        """Simulation of a trilinear hexahedral mesh (meshgen.HexMesh)."""
+        sim = cls(mesh.X, mesh.hexes, material, hexes=True, **kw)
+        if traction and mesh.load_tris is not None:
+            sim.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
         return sim
 
     def close(self):

@@ -55,6 +55,7 @@ struct Mesh {
   int grid_cap;             // workgroups of the persistent step launches (multiple of 8)
   int lanes;                // lanes per node in the node pass (4, 8 or 16)
   int n_inst;               // independent instances of a batch (0: one simulation)
+  int etype;                // nodes per element: 4 (tetrahedra) or 8 (hexahedra)
 
   int4* enodes;             // [T_cap] node ids; .x also holds the fraction code
   int2* et2e;               // [T_cap * 3] six edge ids (local edge order 01 02 03 12 13 23)
@@ -92,6 +93,12 @@ struct Mesh {
   int* sched;               // forced schedule (step, tet, mask) triples
   double* rec_area;         // [S_cap] midpoint crack area of each split
   double* kap;              // [T_cap] modulus of each element slot over E (null: uniform E)
+
+  // trilinear hexahedra (etype 8; no splitting, T_cap = T0)
+  int4* hnodes;             // [2 T0] node ids 0-3, 4-7
+  int2* he2e;               // [6 T0] twelve edge ids
+  int4* hpos;               // [2 T0] positions of the eight (hex, local) entries in the node lists
+  double4* hgrad;           // [6 T0] G_i = integral of grad N_i over the hex, 8 x 3 row-major
 
   // prescribed velocities in groups (all null, counts 0, when there are none)
   int n_bc, n_grp, hist_cap;
@@ -175,6 +182,15 @@ hipError_t launch_reaction(const Mesh& m, const Counters* c, hipStream_t s);
 hipError_t launch_kap_copies(const Mesh& m, int n_split, hipStream_t s);
 hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, const uint8_t* masks,
                                int n, hipStream_t s);
+// ---- trilinear hexahedra (hex.hip) ----
+hipError_t launch_hex_geometry(const Mesh& m, hipStream_t s);
+template <class R>
+hipError_t launch_strain_hex(const Mesh& m, const double4* u, void* veps, Counters* c, hipStream_t s);
+template <class R>
+hipError_t launch_elem_force_hex(const Mesh& m, const void* esig, void* contrib, Counters* c,
+                                 hipStream_t s);
+hipError_t launch_dtcrit_hex(const Mesh& m, Counters* c, hipStream_t s);
+
 // ---- reverse sweep of a fixed-topology window (adjoint.hip) ----
 template <class R> struct Adjoint {
   static hipError_t strain2(const Mesh& m, const double4* lam, const double4* u, void* vl,

@@ -270,6 +270,48 @@ __device__ __forceinline__ void bc_history(double t0, double t, double& S, doubl
   }
 }
 
+// Largest eigenvalue of a symmetric 6 x 6 matrix by cyclic Jacobi rotations
+// (A is overwritten).
+__device__ __forceinline__ double jacobi_lmax6(double A[6][6]) {
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0, dg = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      dg += A[p][p] * A[p][p];
+#pragma unroll
+      for (int q = p + 1; q < 6; ++q) off += A[p][q] * A[p][q];
+    }
+    if (off <= 1e-36 * dg) break;
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 6; ++q) {
+        double apq = A[p][q];
+        if (apq != 0.0) {
+          double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+          double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            double akp = A[k][p], akq = A[k][q];
+            A[k][p] = cs * akp - sn * akq;
+            A[k][q] = sn * akp + cs * akq;
+          }
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            double apk = A[p][k], aqk = A[q][k];
+            A[p][k] = cs * apk - sn * aqk;
+            A[q][k] = sn * apk + cs * aqk;
+          }
+        }
+      }
+  }
+  double lmax = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) lmax = fmax(lmax, A[i][i]);
+  return lmax;
+}
+
 // Persistent grid: enough workgroups for the largest item count the launch
 // can see (capacity), capped at m.grid_cap; always a multiple of 8.
 static inline int persistent_grid(const Mesh& m, long long items) {

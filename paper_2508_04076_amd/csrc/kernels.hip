@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_strain_energy(Mesh m, const Six<R>* 
     double d = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) d += (double)sig[i] * (double)acc[i];
-    s += 0.5 * d / 6.0;
+    s += 0.5 * d / (m.etype == 8 ? 12.0 : 6.0);  // V_k = S_k / 6 (tets), S_k / 12 (hexes)
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -938,6 +938,10 @@ __global__ __launch_bounds__(kBlock) void k_masses(Mesh m) {
   if (i >= m.N0) return;
   double ms = 0;
   for (int p = m.noff[i]; p < m.noff[i + 1]; ++p) {
+    if (m.etype == 8) {  // a hex gives rho V / 8 to each of its nodes
+      ms += m.rho * m.vol[m.nent[p] >> 3] / 8.0;
+      continue;
+    }
     int e = m.nent[p] >> 2;
     ms += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
   }
@@ -956,7 +960,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_volumes(Mesh m, R* einvV, int c
   for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
     int e = m.pent[p];
     if (e < 0) continue;
-    double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+    double ve = m.etype == 8 ? m.vol[e] : frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
     S += ve;
     if (m.kap) SK += ve * m.kap[e];
   }
@@ -1056,41 +1060,7 @@ __global__ __launch_bounds__(kBlock) void k_dtcrit(Mesh m, Counters* __restrict_
         for (int q = 0; q < 12; ++q) s += Xm[i][q] * Xm[j][q];
         A[i][j] = s;
       }
-    for (int sweep = 0; sweep < 30; ++sweep) {
-      double off = 0, dg = 0;
-#pragma unroll
-      for (int p = 0; p < 6; ++p) {
-        dg += A[p][p] * A[p][p];
-#pragma unroll
-        for (int q = p + 1; q < 6; ++q) off += A[p][q] * A[p][q];
-      }
-      if (off <= 1e-36 * dg) break;
-#pragma unroll
-      for (int p = 0; p < 6; ++p)
-#pragma unroll
-        for (int q = p + 1; q < 6; ++q) {
-          double apq = A[p][q];
-          if (apq != 0.0) {
-            double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
-            double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-              double akp = A[k][p], akq = A[k][q];
-              A[k][p] = cs * akp - sn * akq;
-              A[k][q] = sn * akp + cs * akq;
-            }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-              double apk = A[p][k], aqk = A[q][k];
-              A[p][k] = cs * apk - sn * aqk;
-              A[q][k] = sn * apk + cs * aqk;
-            }
-          }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) lmax = fmax(lmax, A[i][i]);
+    lmax = jacobi_lmax6(A);
     if (m.kap) lmax *= m.kap[t];  // C_t = kappa_t C scales the spectrum
     if (m.n_inst) atomicMax(&m.lam_inst[m.tinst[t]], dkey(lmax));
   }
@@ -1106,7 +1076,8 @@ __global__ __launch_bounds__(kBlock) void k_dtcrit(Mesh m, Counters* __restrict_
 __global__ void k_dtfinish(Mesh m, Counters* c) {
   if (threadIdx.x == 0) {
     double lam = key_to_double(c->lam_key);
-    c->dt_crit = 2.0 / sqrt(4.0 / m.rho * lam);
+    // lumped element mass rho V / n per node (n = 4 tets, 8 hexes)
+    c->dt_crit = 2.0 / sqrt((m.etype == 8 ? 8.0 : 4.0) / m.rho * lam);
   }
   for (int i = threadIdx.x; i < m.n_inst; i += blockDim.x)
     m.dtc_inst[i] = 2.0 / sqrt(4.0 / m.rho * key_to_double(m.lam_inst[i]));
@@ -1208,6 +1179,7 @@ double key_to_double_host(unsigned long long k) { return key_to_double(k); }
 template <class R>
 hipError_t Launch<R>::strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
                              hipStream_t s) {
+  if (m.etype == 8) return launch_strain_hex<R>(m, u, w.veps, c, s);
   hipLaunchKernelGGL(k_strain<R>, dim3(persistent_grid(m, m.T_cap)), dim3(kBlock), 0, s, m, u,
                      (Six<R>*)w.veps, c);
   return hipGetLastError();
@@ -1263,8 +1235,13 @@ static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const
 template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                            double4* fout, hipStream_t s, hipEvent_t mid) {
-  hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m, m.T_cap)), dim3(kBlock), 0, s, m,
-                     (const Six<R>*)w.esig, (R*)w.contrib, c);
+  if (m.etype == 8) {
+    hipError_t e = launch_elem_force_hex<R>(m, w.esig, w.contrib, c, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m, m.T_cap)), dim3(kBlock), 0, s, m,
+                       (const Six<R>*)w.esig, (R*)w.contrib, c);
+  }
   if (mid) {
     hipError_t e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
@@ -1346,7 +1323,12 @@ hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, cons
 }
 
 hipError_t launch_masses(const Mesh& m, hipStream_t s) {
-  hipLaunchKernelGGL(k_volumes, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m);
+  if (m.etype == 8) {
+    hipError_t e = launch_hex_geometry(m, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_volumes, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m);
+  }
   hipLaunchKernelGGL(k_masses, dim3(grid_for(m.N0)), dim3(kBlock), 0, s, m);
   return hipGetLastError();
 }
@@ -1360,7 +1342,12 @@ hipError_t launch_loads(const Mesh& m, const int4* ftri, const double4* ftrac, c
 }
 
 hipError_t launch_dtcrit(const Mesh& m, Counters* c, hipStream_t s) {
-  hipLaunchKernelGGL(k_dtcrit, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m, c);
+  if (m.etype == 8) {
+    hipError_t e = launch_dtcrit_hex(m, c, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_dtcrit, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m, c);
+  }
   hipLaunchKernelGGL(k_dtfinish, dim3(1), dim3(64), 0, s, m, c);
   return hipGetLastError();
 }

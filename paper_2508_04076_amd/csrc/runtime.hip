@@ -177,6 +177,9 @@ int bits_for(uint64_t maxv) {
 }
 
 const int kLE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+// hex edges (node order: bottom face 0-1-2-3 counter-clockwise, top face 4-7)
+const int kHexLE[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
+                           {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
 
 int local_edge_h(int a, int b) {
   int lo = std::min(a, b), hi = std::max(a, b);
@@ -229,15 +232,16 @@ int check_orient(cem_ctx* c, int N, const double* X, int T, std::vector<int>& te
 // one component at a time from a pseudo-peripheral node, neighbours visited by
 // increasing degree.  Gives every tet nearby node ids, so the gathers of the
 // step kernels reuse cache lines.
-void rcm_order(int N, int T, const std::vector<int>& tets, std::vector<int>& new_of_old) {
-  size_t M = (size_t)6 * T;
+void rcm_order(int N, int T, int K, const int (*le)[2], int nle, const std::vector<int>& elems,
+               std::vector<int>& new_of_old) {
+  size_t M = (size_t)nle * T;
   std::vector<uint64_t> key(M);
   std::vector<uint32_t> val(M, 0);
   for (int t = 0; t < T; ++t)
-    for (int q = 0; q < 6; ++q) {
-      uint64_t a = (uint32_t)tets[4 * t + kLE[q][0]], b = (uint32_t)tets[4 * t + kLE[q][1]];
+    for (int q = 0; q < nle; ++q) {
+      uint64_t a = (uint32_t)elems[(size_t)K * t + le[q][0]], b = (uint32_t)elems[(size_t)K * t + le[q][1]];
       if (a > b) std::swap(a, b);
-      key[(size_t)6 * t + q] = (a << 32) | b;
+      key[(size_t)nle * t + q] = (a << 32) | b;
     }
   int nb = bits_for((uint64_t)std::max(N - 1, 1));
   for (size_t i = 0; i < M; ++i) key[i] = (key[i] >> 32 << nb) | (key[i] & 0xffffffffull);
@@ -414,6 +418,86 @@ int build_topology(cem_ctx* c, int N, int T, const std::vector<int>& tets, HostT
         if (h.nbr[4 * t + f] >= 0 && h.nbr[4 * t + f] == h.nbr[4 * t + g])
           return c->fail(CEM_EMESH, "duplicated tetrahedron " + std::to_string(t));
   return CEM_OK;
+}
+
+// Hex mesh topology: edges (12 per hex) with their patches, node lists with
+// eight entries per hex and each (hex, local) entry's position.
+struct HexTopo {
+  int E0 = 0;
+  std::vector<int> he2e;     // 12 H
+  std::vector<int> poff;     // E0 + 1
+  std::vector<int> pent;     // 12 H
+  std::vector<int> noff;     // N + 1
+  std::vector<int> nent;     // 8 H: hex << 3 | local
+  std::vector<int> nodepos;  // 8 H
+};
+
+void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
+  size_t M = (size_t)12 * H;
+  std::vector<uint64_t> key(M);
+  std::vector<uint32_t> val(M);
+  int nb = bits_for((uint64_t)std::max(N - 1, 1));
+  for (int t = 0; t < H; ++t)
+    for (int q = 0; q < 12; ++q) {
+      uint64_t a = (uint32_t)hx[8 * (size_t)t + kHexLE[q][0]], b = (uint32_t)hx[8 * (size_t)t + kHexLE[q][1]];
+      if (a > b) std::swap(a, b);
+      key[(size_t)12 * t + q] = (a << nb) | b;
+      val[(size_t)12 * t + q] = (uint32_t)(12 * t + q);
+    }
+  radix_sort(key, val, 2 * nb);
+  h.he2e.assign(M, -1);
+  h.pent.assign(M, -1);
+  h.poff.clear();
+  int E = 0;
+  for (size_t i = 0; i < M; ++i) {
+    if (i == 0 || key[i] != key[i - 1]) {
+      h.poff.push_back((int)i);
+      E++;
+    }
+    h.he2e[val[i]] = E - 1;
+    h.pent[i] = (int)(val[i] / 12);
+  }
+  h.poff.push_back((int)M);
+  h.E0 = E;
+  h.noff.assign(N + 1, 0);
+  for (size_t i = 0; i < (size_t)8 * H; ++i) h.noff[hx[i] + 1]++;
+  for (int i = 0; i < N; ++i) h.noff[i + 1] += h.noff[i];
+  std::vector<int> fill(h.noff.begin(), h.noff.end() - 1);
+  h.nent.assign((size_t)8 * H, 0);
+  h.nodepos.assign((size_t)8 * H, 0);
+  for (int t = 0; t < H; ++t)
+    for (int l = 0; l < 8; ++l) {
+      int p = fill[hx[8 * (size_t)t + l]]++;
+      h.nent[p] = (t << 3) | l;
+      h.nodepos[8 * (size_t)t + l] = p;
+    }
+}
+
+// Jacobian determinants of a trilinear hex at its 2 x 2 x 2 Gauss points:
+// returns their minimum and maximum.
+void hex_det_range(const double* X, const int* nd, double* dmin, double* dmax) {
+  static const int sg[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                               {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+  const double a = 1.0 / std::sqrt(3.0);
+  *dmin = INFINITY;
+  *dmax = -INFINITY;
+  for (int gp = 0; gp < 8; ++gp) {
+    double J[3][3] = {};
+    for (int i = 0; i < 8; ++i) {
+      double f[3];
+      for (int d = 0; d < 3; ++d) f[d] = 1.0 + a * sg[gp][d] * sg[i][d];
+      double dN[3] = {0.125 * sg[i][0] * f[1] * f[2], 0.125 * f[0] * sg[i][1] * f[2],
+                      0.125 * f[0] * f[1] * sg[i][2]};
+      const double* x = X + 3 * (size_t)nd[i];
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) J[r][cc] += x[r] * dN[cc];
+    }
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    *dmin = std::min(*dmin, det);
+    *dmax = std::max(*dmax, det);
+  }
 }
 
 template <class T>
@@ -858,7 +942,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   if (r) return r;
   // internal numbering: nodes in reverse Cuthill-McKee order, tets by their
   // smallest new node id (stable in the caller's order)
-  rcm_order(N, T, ext, c->node_new);
+  rcm_order(N, T, 4, kLE, 6, ext, c->node_new);
   c->node_old.assign(N, 0);
   for (int i = 0; i < N; ++i) c->node_old[c->node_new[i]] = i;
   {
@@ -918,6 +1002,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
   m.n_inst = 0;
+  m.etype = 4;
   m.inst = m.tinst = m.einst = nullptr;
   m.dti = m.dtc_inst = nullptr;
   m.gmax_inst = m.lam_inst = nullptr;
@@ -1057,6 +1142,166 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   return CEM_OK;
 }
 
+int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const int32_t* hexes,
+                        const cem_material* mat) {
+  if (!c) return CEM_EINVAL;
+  if (c->stage != 0) return c->fail(CEM_ESTATE, "mesh already uploaded");
+  if (!X || !hexes || !mat || N < 8 || H < 1) return c->fail(CEM_EINVAL, "empty mesh");
+  if (N > kNodeMask / 2 || (long long)H * 12 > (1LL << 30))
+    return c->fail(CEM_EINVAL, "mesh too large for 32-bit indexing");
+  if (!(mat->E > 0) || !(mat->rho > 0) || !(mat->nu > -1.0 && mat->nu < 0.5))
+    return c->fail(CEM_EINVAL, "invalid material");
+  for (long long i = 0; i < (long long)H * 8; ++i)
+    if (hexes[i] < 0 || hexes[i] >= N) return c->fail(CEM_EMESH, "node id out of range");
+  for (long long i = 0; i < (long long)N * 3; ++i)
+    if (!std::isfinite(X[i])) return c->fail(CEM_EINVAL, "non-finite coordinate");
+  // orientation: mirror a hex that is inverted throughout (1 <-> 3, 5 <-> 7)
+  std::vector<int> ext(hexes, hexes + (size_t)8 * H);
+  for (int t = 0; t < H; ++t) {
+    int* nd = &ext[8 * (size_t)t];
+    double lo, hi;
+    hex_det_range(X, nd, &lo, &hi);
+    if (hi < 0) {
+      std::swap(nd[1], nd[3]);
+      std::swap(nd[5], nd[7]);
+      hex_det_range(X, nd, &lo, &hi);
+    }
+    if (!(lo > 0)) return c->fail(CEM_EMESH, "degenerate or inverted hexahedron " + std::to_string(t));
+  }
+  rcm_order(N, H, 8, kHexLE, 12, ext, c->node_new);
+  c->node_old.assign(N, 0);
+  for (int i = 0; i < N; ++i) c->node_old[c->node_new[i]] = i;
+  {
+    std::vector<int> cnt(N + 1, 0), key(H);
+    for (int t = 0; t < H; ++t) {
+      int mn = N;
+      for (int l = 0; l < 8; ++l) mn = std::min(mn, c->node_new[ext[8 * (size_t)t + l]]);
+      key[t] = mn;
+      cnt[mn + 1]++;
+    }
+    for (int i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    c->tet_new.assign(H, 0);
+    c->tet_old.assign(H, 0);
+    for (int t = 0; t < H; ++t) {
+      int nt = cnt[key[t]]++;
+      c->tet_new[t] = nt;
+      c->tet_old[nt] = t;
+    }
+  }
+  std::vector<int> hx((size_t)8 * H);
+  for (int t = 0; t < H; ++t)
+    for (int l = 0; l < 8; ++l) hx[8 * (size_t)c->tet_new[t] + l] = c->node_new[ext[8 * (size_t)t + l]];
+  c->X.assign((size_t)3 * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d) c->X[3 * (size_t)c->node_new[i] + d] = X[3 * (size_t)i + d];
+  HexTopo h;
+  build_hex_topology(N, H, hx, h);
+
+  HIPCHK(c, hipSetDevice(c->opt.device));
+  if (!c->stream) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  c->mat = *mat;
+  c->mat.Gc = INFINITY;  // hexahedra do not split
+  Mesh& m = c->m;
+  m.T0 = m.T_cap = H;
+  m.N0 = m.N_cap = N;
+  m.E0 = m.E_cap = h.E0;
+  m.S_cap = 0;
+  m.mode = CEM_PHANTOM;
+  m.gsig = 0;
+  m.lam = mat->E * mat->nu / ((1 + mat->nu) * (1 - 2 * mat->nu));
+  m.mu = mat->E / (2 * (1 + mat->nu));
+  m.rho = mat->rho;
+  m.Gc = INFINITY;
+  m.grid_cap = kDefaultGridCap;
+  m.lanes = kDefaultLanes;
+  m.n_inst = 0;
+  m.etype = 8;
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], c->X[3 * (size_t)i + d]);
+        hi[d] = std::max(hi[d], c->X[3 * (size_t)i + d]);
+      }
+    m.umax = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                       (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  }
+  HIPCHK(c, hipHostMalloc((void**)&c->h_ctr, sizeof(Counters), hipHostMallocDefault));
+  std::memset(c->h_ctr, 0, sizeof(Counters));
+  c->stage = 1;
+  const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
+  int r;
+  ALLOC(c->d_ctr, 1, true);
+  ALLOC(m.hnodes, (size_t)2 * H, false);
+  ALLOC(m.he2e, (size_t)6 * H, false);
+  ALLOC(m.hpos, (size_t)2 * H, false);
+  ALLOC(m.hgrad, (size_t)6 * H, false);
+  ALLOC(m.X, m.N_cap, true);
+  ALLOC(m.poff, (size_t)m.E0 + 1, false);
+  ALLOC(m.pent, (size_t)12 * H, false);
+  ALLOC(m.noff, (size_t)N + 1, false);
+  ALLOC(m.nent, (size_t)8 * H, false);
+  ALLOC(m.invm, m.N_cap, true);
+  ALLOC(m.lslot, m.N_cap, true);
+  ALLOC(m.vol, m.T_cap, true);
+  ALLOC(m.splitlist, 1, false);
+  char* vb;
+  ALLOC(vb, RS * 6 * (size_t)H, false);
+  c->w.veps = vb;
+  ALLOC(vb, RS * 6 * (size_t)m.E0, false);
+  c->w.esig = vb;
+  ALLOC(vb, RS * (size_t)m.E0, true);
+  c->w.einvV = vb;
+  ALLOC(vb, RS * 4 * ((size_t)8 * H), false);
+  c->w.contrib = vb;
+  ALLOC(c->w.partial, c->n_partial, false);
+  ALLOC(c->d_out, 8, false);
+  ALLOC(c->d_iout, 8, false);
+  ALLOC(c->st.u, m.N_cap, true);
+  ALLOC(c->st.v, m.N_cap, true);
+  ALLOC(c->st.a, m.N_cap, true);
+  ALLOC(c->st.uh, m.N_cap, true);
+  ALLOC(c->d_tmp, m.N_cap, false);
+  ALLOC(c->d_tmp2, m.N_cap, false);
+  std::vector<int4> hn((size_t)2 * H), hp((size_t)2 * H);
+  for (size_t t = 0; t < (size_t)H; ++t) {
+    const int* q = &hx[8 * t];
+    hn[2 * t] = make_int4(q[0], q[1], q[2], q[3]);
+    hn[2 * t + 1] = make_int4(q[4], q[5], q[6], q[7]);
+    const int* p = &h.nodepos[8 * t];
+    hp[2 * t] = make_int4(p[0], p[1], p[2], p[3]);
+    hp[2 * t + 1] = make_int4(p[4], p[5], p[6], p[7]);
+  }
+  if ((r = upload(c, m.hnodes, hn.data(), hn.size()))) return r;
+  if ((r = upload(c, m.hpos, hp.data(), hp.size()))) return r;
+  std::vector<int2> e2((size_t)6 * H);
+  for (size_t i = 0; i < e2.size(); ++i) e2[i] = make_int2(h.he2e[2 * i], h.he2e[2 * i + 1]);
+  if ((r = upload(c, m.he2e, e2.data(), e2.size()))) return r;
+  std::vector<double4> Xp(N);
+  for (int i = 0; i < N; ++i) Xp[i] = make_double4(c->X[3 * (size_t)i], c->X[3 * (size_t)i + 1], c->X[3 * (size_t)i + 2], 0.0);
+  if ((r = upload(c, m.X, Xp.data(), Xp.size()))) return r;
+  if ((r = upload(c, m.poff, h.poff.data(), h.poff.size()))) return r;
+  if ((r = upload(c, m.pent, h.pent.data(), h.pent.size()))) return r;
+  if ((r = upload(c, m.noff, h.noff.data(), h.noff.size()))) return r;
+  if ((r = upload(c, m.nent, h.nent.data(), h.nent.size()))) return r;
+  std::vector<int> lsl(N, -1);
+  if ((r = upload(c, m.lslot, lsl.data(), lsl.size()))) return r;
+  HIPCHK(c, hipMemsetAsync(c->d_ctr, 0, sizeof(Counters), c->stream));
+  for (double4* p : {c->st.u, c->st.v, c->st.a, c->st.uh})
+    HIPCHK(c, hipMemsetAsync(p, 0, sizeof(double4) * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 4 * ((size_t)8 * H), c->stream));
+  HIPCHK(c, launch_masses(m, c->stream));  // hex geometry (G_i, V), then lumped masses
+  if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, -1, c->stream));
+  else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, -1, c->stream));
+  if ((r = sync(c))) return r;
+  c->split_host.assign(H, 0);
+  c->need_init = true;
+  return CEM_OK;
+}
+
 int cem_set_traction(cem_ctx* c, int32_t n_faces, const int32_t* tri, const double* t,
                      double ramp_t0) {
   if (!c) return CEM_EINVAL;
@@ -1137,6 +1382,7 @@ int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "hexahedra do not split");
   c->gen++;
   if (c->step_host != 0) return c->fail(CEM_ESTATE, "pre-splits must precede the first step");
   if (n < 0 || (n > 0 && (!tet || !side_mask))) return c->fail(CEM_EINVAL, "bad presplit arguments");
@@ -1299,6 +1545,7 @@ int cem_replay_splits(cem_ctx* c, int32_t n, const cem_split_event* ev) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "hexahedra do not split");
   c->gen++;
   if (n < 0 || (n > 0 && !ev)) return c->fail(CEM_EINVAL, "bad schedule");
   std::vector<std::array<int, 3>> s;
@@ -1401,6 +1648,7 @@ int cem_set_instances(cem_ctx* c, int32_t n, const int32_t* node_off, const int3
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "batches are built from tetrahedral meshes");
   c->gen++;
   Mesh& m = c->m;
   if (c->m.n_inst) return c->fail(CEM_ESTATE, "instances already declared");
@@ -1564,6 +1812,10 @@ int cem_read_front_G(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* n) {
   if (!c || !n) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  if (c->m.etype == 8) {
+    *n = 0;
+    return CEM_OK;  // hexahedra have no crack fronts
+  }
   if (c->need_init && c->dt_set && (r = initialize(c))) return r;
   if ((r = read_counters(c))) return r;
   int nc = c->h_ctr->n_cand;
@@ -1705,6 +1957,7 @@ int cem_set_modulus(cem_ctx* c, int32_t n_tets, const double* E) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "a per-element modulus is for tetrahedral meshes");
   c->gen++;
   Mesh& m = c->m;
   if (E) {
@@ -1879,6 +2132,7 @@ int cem_window_forward(cem_ctx* c, int32_t n, int32_t every) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, true);
   if (r) return r;
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "gradient windows are for tetrahedral meshes");
   if (n < 0 || every < 1) return c->fail(CEM_EINVAL, "window needs n_steps >= 0 and every >= 1");
   if (c->m.n_bc || c->m.n_grp)
     return c->fail(CEM_ESTATE, "gradient windows with prescribed velocities are not supported");
