@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="plate",
                     choices=["plate", "cube", "block8m", "block", "ensemble", "window",
-                             "dirichlet"])
+                             "dirichlet", "hex", "hexblock"])
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps for the CPU baseline (0: about 15 s of work)")
@@ -146,6 +146,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "window":
         return bench_window(args)
+    if args.workload in ("hex", "hexblock"):
+        return bench_hex(args)
     mesh, ramp, desc = workload(args.workload)
     T = mesh.n_tets
     log(f"workload {args.workload}: {T} tets, {mesh.n_nodes} nodes")
@@ -479,6 +481,116 @@ def window_cpu_baseline(mesh, mat, E, dt, gu, n_steps=8):
             "kind": "oracle",
             "sample": f"{n_steps}-step window forward + reverse on the same 202,800-tet mesh "
                       "(oracle setup excluded)"}
+
+
+# Algorithmic bytes per hex-step of the hexahedral passes (compulsory traffic,
+# FP64 / mixed), with E/H = 3 edges and N/H = 1 node per hex on a structured
+# grid: strain = ids 32 + G 192 + u gather 32 + write V eps 48; edge = CSR
+# 4 (E/H) + 48 + read V eps 48 + write sigma 48 (E/H) + einvV 8 (E/H);
+# force = ids 80 + G 192 + read sigma 48 (E/H) + u, v read+write 96 + 1/m 8.
+HEX_BYTES = {
+    "fp64": {"strain": 32 + 192 + 32 + 48, "edge_stress": 12 + 48 + 48 + 144 + 24,
+             "node": 80 + 192 + 144 + 96 + 8},
+    "mixed": {"strain": 32 + 192 + 32 + 24, "edge_stress": 12 + 48 + 24 + 72 + 12,
+              "node": 80 + 192 + 72 + 96 + 8},
+}
+
+
+def bench_hex(args):
+    """Trilinear hexahedra (ES-H-FEM, factor 1/12): the notched-plate geometry
+    at 200 x 80 x 8 hex cells (128,000 hexes, 1 MPa ramped over 1 us), or a
+    400 x 200 x 100 block (8,000,000 hexes).  No splitting (hexahedra do not
+    split).  A step: strain, edge stress, element force + node update."""
+    import torch
+    from paper_2508_04076_amd import meshgen as mg
+    from paper_2508_04076_amd.cem import Simulation
+
+    mat = dict(mg.BRANCHING_MATERIAL)
+    if args.workload == "hex":
+        mesh = mg.add_tension(mg.hex_box(200, 80, 8, 0.1, 0.04, 0.004), 1, 1e6)
+        desc = ("plate 100x40x4 mm as 200x80x8 trilinear hex cells (128,000 hexes), "
+                "1 MPa traction ramped over 1 us, no splitting")
+    else:
+        mesh = mg.add_tension(mg.hex_box(400, 200, 100, 0.2, 0.1, 0.05), 1, 1e6)
+        desc = ("block 200x100x50 mm as 400x200x100 trilinear hex cells (8,000,000 hexes), "
+                "1 MPa traction ramped over 1 us, no splitting")
+    H = mesh.n_hex
+    K, W = args.steps, args.warmup
+    log(f"hex workload {args.workload}: {H} hexes, {mesh.n_nodes} nodes")
+    out_runs = {}
+    for prec in ("fp64", "mixed"):
+        if prec == "mixed" and args.no_mixed:
+            continue
+        for graph in (False, True):
+            if graph and args.no_graph:
+                continue
+            sim = Simulation.from_hex_mesh(mesh, mat, ramp_t0=1e-6, precision=prec,
+                                           graph_steps=args.graph_steps if graph else 0)
+            dt = 0.5 * sim.critical_dt()
+            sim.set_dt(dt)
+            sim.set_profiling(not graph)
+            sim.step(W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(K)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            run = {"ms_per_step": wall * 1e3 / K, "hex_steps_per_s": H * K / wall, "dt_s": dt}
+            if not graph:
+                kt = sim.kernel_times()
+                run["kernels_ms_per_step"] = {k: kt[k] / K for k in
+                                              ("strain", "edge_stress", "node", "topology")}
+                run["u"] = sim.get_state()[0]
+            out_runs[(prec, graph)] = run
+            log(f"hex {prec} {'graphs' if graph else 'plain+events'}: {wall * 1e3 / K:.4f} ms/step, "
+                f"{H * K / wall:.4e} hex-steps/s")
+            sim.close()
+    base = out_runs[("fp64", False)]
+    per = base["kernels_ms_per_step"]
+    dom = max(("strain", "edge_stress", "node"), key=lambda k: per[k])
+    achieved = HEX_BYTES["fp64"][dom] * H / (per[dom] * 1e-3) / 1e9
+    names = {"strain": "k_strain_hex", "edge_stress": "k_edge_stress",
+             "node": "k_elem_force_hex+k_node"}
+    mixed = None
+    if ("mixed", False) in out_runs:
+        um, u64 = out_runs[("mixed", False)]["u"], base["u"]
+        mixed = {"hex_steps_per_s": out_runs[("mixed", False)]["hex_steps_per_s"],
+                 "ms_per_step": out_runs[("mixed", False)]["ms_per_step"],
+                 "graph_hex_steps_per_s": out_runs.get(("mixed", True), {}).get("hex_steps_per_s"),
+                 "rel_l2_u_vs_fp64": float(np.linalg.norm(um - u64) / np.linalg.norm(u64))}
+    cpu = None
+    if not args.no_cpu:
+        from oracle.oracle import Oracle
+        o = Oracle.hex_mesh(mesh, mat, ramp_t0=1e-6)
+        o.set_dt(base["dt_s"])
+        t0 = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t0
+        n_cpu = max(1, min(100, int(15.0 / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        o.step(n_cpu)
+        el = time.perf_counter() - t0
+        cpu = {"value": H * n_cpu / el, "unit": "hex-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_cpu} steps of the same hex workload after one warm-up step "
+                         f"(single-threaded FP64 oracle, {el:.1f} s)"}
+    out = {
+        "metric": "hex-steps/sec (ES-H-FEM), FP64 and FP32-mixed",
+        "value": base["hex_steps_per_s"], "unit": "hex-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": base["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "hexes": H, "nodes": mesh.n_nodes, "dt_s": base["dt_s"],
+                   "launch": "plain launches with per-pass HIP events"},
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_hex": HEX_BYTES["fp64"][dom],
+                     "avg_launch_ms": per[dom]},
+        "kernels_ms_per_step": per,
+        "graph_no_events": {"hex_steps_per_s": out_runs.get(("fp64", True), {}).get("hex_steps_per_s"),
+                            "ms_per_step": out_runs.get(("fp64", True), {}).get("ms_per_step")},
+        "mixed": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 
