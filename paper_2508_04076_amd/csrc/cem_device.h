@@ -129,7 +129,7 @@ struct Work {
   void* esig;               // [E_cap] Six<R>: smoothed edge stress
   void* einvV;              // [E_cap] R: kappa_k / sum of effective volumes of the patch,
                             // kappa_k the volume-averaged relative modulus (1 if uniform)
-  void* contrib;            // [T_cap][4] R4: nodal force terms, index (e << 2) | l
+  void* contrib;            // [entries][3] R: nodal force term of each node-list entry
   double* partial;          // reduction partials
 };
 
@@ -145,10 +145,10 @@ template <class R> struct Launch {
   static hipError_t strain(const Mesh& m, const double4* u, const Work& w, Counters* c,
                            hipStream_t s);
   static hipError_t edge_stress(const Mesh& m, const Work& w, Counters* c, hipStream_t s);
-  static hipError_t front(const Mesh& m, const State& st, const Work& w, Counters* c,
-                          int flagging, hipStream_t s);
+  // front: -1 no crack pass; 1 crack pass with flagging; 0 crack pass for the
+  // readbacks only, then the forced schedule's selection (replay)
   static hipError_t node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
-                         double4* fout, hipStream_t s, hipEvent_t mid = nullptr);
+                         double4* fout, hipStream_t s, hipEvent_t mid = nullptr, int front = -1);
   // einvV of the first `count` edges (count < 0: the original edges)
   static hipError_t edge_volumes(const Mesh& m, const Work& w, int count, hipStream_t s);
   static hipError_t front_eval(const Mesh& m, const State& st, const Work& w, Counters* c,

@@ -27,10 +27,12 @@ namespace cem {
 // on the device, so a captured graph stays valid as splits add elements.
 struct Chunks {
   int ch, hi, stride;
-  __device__ __forceinline__ Chunks(long long count) {
+  // nblocks: the workgroups that share the items (the first nblocks of the
+  // grid; default all of it)
+  __device__ __forceinline__ Chunks(long long count, int nblocks = 0) {
     long long nch = (count + kBlock - 1) / kBlock;
     int x = blockIdx.x % 8, j = blockIdx.x / 8;
-    stride = gridDim.x / 8;
+    stride = (nblocks > 0 ? nblocks : (int)gridDim.x) / 8;
     ch = (int)(nch * x / 8) + j;
     hi = (int)(nch * (x + 1) / 8);
   }
@@ -220,15 +222,45 @@ __device__ __forceinline__ void elem_terms(const Mesh& m, int e, int4 nd, int co
   }
 }
 
+// One nodal force term per node-list entry: CEM_TERM_STRIDE values of R
+// (3: packed, the default: a quarter less traffic than padding to 4 for the
+// float64 terms, the same speed for float32).
+#ifndef CEM_TERM_STRIDE
+#define CEM_TERM_STRIDE 3
+#endif
+template <class R>
+__device__ __forceinline__ void put_term(R* __restrict__ contrib, int p, R x, R y, R z) {
+#if CEM_TERM_STRIDE == 4
+  ((typename Vec4<R>::T*)contrib)[p] = Vec4<R>::make(x, y, z);
+#else
+  R* q = contrib + 3 * (size_t)p;
+  q[0] = x;
+  q[1] = y;
+  q[2] = z;
+#endif
+}
+template <class R>
+__device__ __forceinline__ void get_term(const R* __restrict__ contrib, int p, R& x, R& y, R& z) {
+#if CEM_TERM_STRIDE == 4
+  typename Vec4<R>::T q = ((const typename Vec4<R>::T*)contrib)[p];
+  x = q.x;
+  y = q.y;
+  z = q.z;
+#else
+  const R* q = contrib + 3 * (size_t)p;
+  x = q[0];
+  y = q[1];
+  z = q[2];
+#endif
+}
+
 // Store the four nodal terms at the element's positions in the node lists.
 template <class R>
 __device__ __forceinline__ void store_terms(R* __restrict__ contrib, int4 pos, const R out[4][3]) {
-  typedef typename Vec4<R>::T R4;
-  R4* o = (R4*)contrib;
-  o[pos.x] = Vec4<R>::make(out[0][0], out[0][1], out[0][2]);
-  o[pos.y] = Vec4<R>::make(out[1][0], out[1][1], out[1][2]);
-  o[pos.z] = Vec4<R>::make(out[2][0], out[2][1], out[2][2]);
-  o[pos.w] = Vec4<R>::make(out[3][0], out[3][1], out[3][2]);
+  put_term(contrib, pos.x, out[0][0], out[0][1], out[0][2]);
+  put_term(contrib, pos.y, out[1][0], out[1][1], out[1][2]);
+  put_term(contrib, pos.z, out[2][0], out[2][1], out[2][2]);
+  put_term(contrib, pos.w, out[3][0], out[3][1], out[3][2]);
 }
 
 // Sum of node i's contiguous terms by G lanes (lane g takes entries g, g + G,
@@ -240,12 +272,12 @@ __device__ __forceinline__ void node_gather(const Mesh& m, const R* __restrict__
                                             double& fz) {
   fx = fy = fz = 0;
   const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
-  typedef typename Vec4<R>::T R4;
   for (int p = p0 + g; p < p1; p += G) {
-    R4 q = ((const R4*)contrib)[p];
-    fx += (double)q.x;
-    fy += (double)q.y;
-    fz += (double)q.z;
+    R qx, qy, qz;
+    get_term(contrib, p, qx, qy, qz);
+    fx += (double)qx;
+    fy += (double)qy;
+    fz += (double)qz;
   }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) {

@@ -127,8 +127,6 @@ __global__ __launch_bounds__(kBlock) void k_elem_force_hex(Mesh m, const Six<R>*
                                                            Counters* __restrict__ c) {
   if (c->err) return;
   Chunks it(m.T0);
-  typedef typename Vec4<R>::T R4;
-  R4* o = (R4*)contrib;
   for (int e; it.next(e);) {
     if (e >= m.T0) continue;
     R sg[6] = {0, 0, 0, 0, 0, 0};
@@ -147,9 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_elem_force_hex(Mesh m, const Six<R>*
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       R gx = (R)G[3 * i], gy = (R)G[3 * i + 1], gz = (R)G[3 * i + 2];
-      o[pos[i]] = Vec4<R>::make(w * (gx * sg[0] + gy * sg[3] + gz * sg[5]),
-                                w * (gy * sg[1] + gx * sg[3] + gz * sg[4]),
-                                w * (gz * sg[2] + gy * sg[4] + gx * sg[5]));
+      put_term(contrib, pos[i], w * (gx * sg[0] + gy * sg[3] + gz * sg[5]),
+               w * (gy * sg[1] + gx * sg[3] + gz * sg[4]), w * (gz * sg[2] + gy * sg[4] + gx * sg[5]));
     }
   }
 }

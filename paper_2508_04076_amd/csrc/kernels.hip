@@ -4,11 +4,12 @@
 // atomics, so results are deterministic:
 //   strain      per element slot: V_eff * eps_e = V_eff B_e u_e          (6 values)
 //   edge_stress per edge: eps_k = sum_patch(V_eff eps) / sum_patch V_eff, sigma_k = C eps_k
-//   front       per crack-front candidate: G_I, G_II, Griffith test, flag
-//   compact     flagged tets -> ascending list (two kernels, last-block scan)
+//   elem_force  per element: its four nodal force terms; extra workgroups of
+//               the same launch take the crack-front candidates (G_I, G_II,
+//               Griffith test, flags appended to the split list)
 //   node        per node: f_i = sum_{(e,l) ni i} (V_eff,e / 6) B_{e,l}^T sum_{k in edges(e)} sigma_k,
 //               then the Newmark update
-//   topology    one workgroup applies the step's splits
+//   topology    one workgroup sorts the flags and applies the step's splits
 // The node force uses the identity
 //   sum_k V_k Bt_k^T sigma_k = sum_e (V_eff,e / 6) B_e^T sum_{k in edges(e)} sigma_k
 // (Bt_k = sum_patch w_ek B_e, V_k = (1/6) sum_patch V_eff, w_ek V_k = V_eff,e / 6),
@@ -150,12 +151,11 @@ __device__ __forceinline__ bool over_capacity(const Mesh& m, Counters* c) {
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force(Mesh m, const Six<R>* __restrict__ esig,
-                                                       R* __restrict__ contrib,
-                                                       Counters* __restrict__ c) {
-  if (c->err || over_capacity(m, c)) return;
+__device__ __forceinline__ void elem_force_items(const Mesh& m, const Six<R>* __restrict__ esig,
+                                                 R* __restrict__ contrib,
+                                                 const Counters* __restrict__ c, int nblocks) {
   const int Tn = elems_now(m, c);
-  Chunks it(Tn);
+  Chunks it(Tn, nblocks);
   for (int e; it.next(e);) {
   if (e >= Tn) continue;
   int4 nd = m.enodes[e];
@@ -170,6 +170,14 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force(Mesh m, con
   }
   store_terms(contrib, pos, out);
   }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force(Mesh m, const Six<R>* __restrict__ esig,
+                                                       R* __restrict__ contrib,
+                                                       Counters* __restrict__ c) {
+  if (c->err || over_capacity(m, c)) return;
+  elem_force_items(m, esig, contrib, c, 0);
 }
 
 // Prescribed components of constrained slot b at time t: velocity v0 V(t),
@@ -429,17 +437,15 @@ __device__ __forceinline__ void load_tet(const Mesh& m, int t, int* nd, int* ed)
 // order, ties to the lower face and to pattern I.  The Griffith test
 // G >= Gc flags the tet: it is appended to the (unordered) split list.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_front(Mesh m, const double4* __restrict__ u,
-                                                  const Six<R>* __restrict__ esig,
-                                                  Counters* __restrict__ c, int flagging) {
-  if (c->err) return;
-  __shared__ unsigned long long red[kBlock];
+__device__ void front_block(const Mesh& m, const double4* __restrict__ u,
+                            const Six<R>* __restrict__ esig, Counters* __restrict__ c,
+                            int flagging, int blk, int nblk, unsigned long long* red) {
   unsigned long long kmax = 0;
   const int nc = c->n_cand;
   const int room = m.S_cap - c->n_split;
   const int f = threadIdx.x & 3;
   constexpr int cpb = kBlock / 4;
-  for (int base = blockIdx.x * cpb; base < nc; base += gridDim.x * cpb) {
+  for (int base = blk * cpb; base < nc; base += nblk * cpb) {
     int idx = base + (int)threadIdx.x / 4;
     int t = idx < nc ? m.cand[idx] : -1;
     bool act = t >= 0 && m.smask[t] < 0;
@@ -491,6 +497,23 @@ __global__ __launch_bounds__(kBlock) void k_front(Mesh m, const double4* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0 && red[0] != 0) atomicMax(&c->gmax_key, red[0]);
+}
+
+// The element force pass and the crack-front pass in one launch: the first eg
+// workgroups take the elements, the others the crack-front candidates.  Both
+// read the edge stresses and write disjoint data; the capacity test on the
+// flags is left to the node pass, which runs after both.
+template <class R>
+__global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force_front(
+    Mesh m, const Six<R>* __restrict__ esig, R* __restrict__ contrib,
+    const double4* __restrict__ uh, Counters* __restrict__ c, int eg, int flagging) {
+  if (c->err) return;
+  __shared__ unsigned long long red[kBlock];
+  if ((int)blockIdx.x >= eg) {
+    front_block<R>(m, uh, esig, c, flagging, blockIdx.x - eg, gridDim.x - eg, red);
+    return;
+  }
+  elem_force_items(m, esig, contrib, c, eg);
 }
 
 // Readback of every front's G_I and G_II (unordered; the host sorts).
@@ -1199,14 +1222,6 @@ static int front_grid(const Mesh& m) {
 }
 
 template <class R>
-hipError_t Launch<R>::front(const Mesh& m, const State& st, const Work& w, Counters* c,
-                            int flagging, hipStream_t s) {
-  hipLaunchKernelGGL(k_front<R>, dim3(front_grid(m)), dim3(kBlock), 0, s, m,
-                     (const double4*)st.uh, (const Six<R>*)w.esig, c, flagging);
-  return hipGetLastError();
-}
-
-template <class R>
 hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, Counters* c,
                                  int* out_tfl, double* out_g, int* out_n, hipStream_t s) {
   hipLaunchKernelGGL(k_front_eval<R>, dim3(front_grid(m)), dim3(kBlock), 0, s, m,
@@ -1234,10 +1249,19 @@ static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const
 
 template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
-                           double4* fout, hipStream_t s, hipEvent_t mid) {
+                           double4* fout, hipStream_t s, hipEvent_t mid, int front) {
   if (m.etype == 8) {
     hipError_t e = launch_elem_force_hex<R>(m, w.esig, w.contrib, c, s);
     if (e != hipSuccess) return e;
+  } else if (front >= 0) {
+    // crack-front workgroups ride along with the element force launch
+    const int eg = persistent_grid(m, m.T_cap);
+    hipLaunchKernelGGL(k_elem_force_front<R>, dim3(eg + front_grid(m)), dim3(kBlock), 0, s, m,
+                       (const Six<R>*)w.esig, (R*)w.contrib, (const double4*)st.uh, c, eg, front);
+    if (front == 0) {  // forced schedule: select this step's entries
+      hipError_t e = launch_replay_select(m, c, s);
+      if (e != hipSuccess) return e;
+    }
   } else {
     hipLaunchKernelGGL(k_elem_force<R>, dim3(persistent_grid(m, m.T_cap)), dim3(kBlock), 0, s, m,
                        (const Six<R>*)w.esig, (R*)w.contrib, c);

@@ -551,9 +551,9 @@ int strain_stress(cem_ctx* c, const double4* u) {
   return c->mixed ? launch_strain_stress<float>(c, u) : launch_strain_stress<double>(c, u);
 }
 
-int node_pass(cem_ctx* c, int mode, double4* fout, hipEvent_t mid = nullptr) {
-  hipError_t e = c->mixed ? Launch<float>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream, mid)
-                          : Launch<double>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream, mid);
+int node_pass(cem_ctx* c, int mode, double4* fout, hipEvent_t mid = nullptr, int front = -1) {
+  hipError_t e = c->mixed ? Launch<float>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream, mid, front)
+                          : Launch<double>::node(c->m, c->st, c->w, c->d_ctr, mode, fout, c->stream, mid, front);
   HIPCHK(c, e);
   return CEM_OK;
 }
@@ -580,13 +580,9 @@ int enqueue_step(cem_ctx* c, hipEvent_t* ev) {
   else HIPCHK(c, Launch<double>::edge_stress(c->m, c->w, c->d_ctr, s));
   if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
   bool fracture = (std::isfinite(c->mat.Gc) || replay) && !c->frozen;
-  if (fracture) {
-    if (c->mixed) HIPCHK(c, Launch<float>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
-    else HIPCHK(c, Launch<double>::front(c->m, c->st, c->w, c->d_ctr, replay ? 0 : 1, s));
-    if (replay) HIPCHK(c, launch_replay_select(c->m, c->d_ctr, s));
-  }
+  // the crack pass runs inside the element force launch (its own workgroups)
   if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
-  int r = node_pass(c, NODE_STEP, nullptr, ev ? ev[4] : nullptr);
+  int r = node_pass(c, NODE_STEP, nullptr, ev ? ev[4] : nullptr, fracture ? (replay ? 0 : 1) : -1);
   if (r) return r;
   if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
   HIPCHK(c, launch_reaction(c->m, c->d_ctr, s));
