@@ -38,9 +38,10 @@ ALG_BYTES = {
     "fp64": {"strain": 149.0, "edge_stress": 146.0, "node": 200.0},
     "mixed": {"strain": 85.0, "edge_stress": 88.0, "node": 130.0},
 }
-# the node pass is two launches: per-element force terms, then per-node sums
+# the node pass is two launches: per-element force terms (with the crack-front
+# workgroups riding along), then per-node sums
 KERNEL_NAMES = {"strain": ["k_strain"], "edge_stress": ["k_edge_stress"],
-                "node": ["k_elem_force", "k_node"]}
+                "node": ["k_elem_force_front", "k_node"]}
 
 
 def log(msg):
@@ -275,7 +276,7 @@ def main():
             t0 = time.perf_counter()
             o.step(1)
             one = time.perf_counter() - t0
-            n_cpu = max(1, min(200, int(15.0 / max(one, 1e-6))))
+            n_cpu = max(1, min(200, int(20.0 / max(one, 1e-6))))
             done = 1
         else:
             done = 0
