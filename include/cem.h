@@ -288,6 +288,15 @@ int cem_window_forward(cem_ctx* ctx, int32_t n_steps, int32_t every);
 int cem_window_backward(cem_ctx* ctx, const double* gu, const double* gv, double* gu0,
                         double* gv0, double* gE);
 
+/* Strain energy SE = 1/2 sum_k V_k sigma_k . eps_k at displacement u
+ * ([n_nodes_now][3], caller's order; NULL: the current state) and its
+ * sensitivities: gu = dSE/du (the internal force, [n_nodes_now][3]) and
+ * gE = dSE/dE_j at fixed u ([n_tets], per Pa; copies add to their parent).
+ * With gu as the window's end sensitivity, gE plus the window's dJ/dE is the
+ * gradient of the end-of-window strain energy.  Any output may be NULL;
+ * tetrahedral meshes only. */
+int cem_strain_energy_grad(cem_ctx* ctx, const double* u, double* se, double* gu, double* gE);
+
 /* Time of the last cem_window_backward, in milliseconds: out[0] whole call,
  * out[1] forward recompute of the segments, out[2] reverse strain pass,
  * out[3] reverse edge pass, out[4] reverse element pass, out[5] reverse node

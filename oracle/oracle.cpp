@@ -1381,4 +1381,16 @@ int orc_reactions(orc_ctx* c, int group, int cap, double* rows6, int* n_out, dou
   return 0;
 }
 
+int orc_strain_energy_grad(orc_ctx* c, const double* u, double* gE) {
+  // explicit sensitivity of SE = 1/2 u^T K(E) u to each tet's modulus at fixed
+  // u: 1/2 u^T (dK/dE_j) u (the same edge sum as the window's modulus term)
+  std::vector<V3> uu = c->u;
+  if (u)
+    for (size_t i = 0; i < uu.size(); ++i) uu[i] = {u[3 * i], u[3 * i + 1], u[3 * i + 2]};
+  std::vector<double> out(c->T0, 0.0);
+  modulus_term(c, uu, uu, 0.5, out);
+  for (int t = 0; t < c->T0; ++t) gE[t] = out[t];
+  return 0;
+}
+
 }  // extern "C"

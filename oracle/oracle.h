@@ -78,6 +78,10 @@ int orc_add_velocity_bc(orc_ctx* c, int n, const int* node, const int* mask,
  * work: the group's reactions' accumulated work */
 int orc_reactions(orc_ctx* c, int group, int cap, double* rows6, int* n_out, double* work);
 
+/* dSE/dE_j at fixed displacement (u = NULL: the current state): the explicit
+ * part of the strain energy's sensitivity to each tet's modulus, [n_tets] */
+int orc_strain_energy_grad(orc_ctx* c, const double* u, double* gE);
+
 /* inspection */
 int orc_masses(orc_ctx* c, double* m);
 int orc_loads(orc_ctx* c, double* F);

@@ -74,6 +74,7 @@ def lib():
             ("orc_set_frozen", [_p, _i]),
             ("orc_window_gradient", [_p, _i, _p, _p, _p, _p, _p]),
             ("orc_add_velocity_bc", [_p, _i, _p, _p, _p, _d, _p]),
+            ("orc_strain_energy_grad", [_p, _p, _p]),
             ("orc_reactions", [_p, _i, _i, _p, _p, _p]),
         ]:
             fn = getattr(L, name)
@@ -261,6 +262,13 @@ class Oracle:
 
     def set_frozen(self, on=True):
         self._chk(lib().orc_set_frozen(self.c, int(bool(on))))
+
+    def strain_energy_grad(self, u=None):
+        """dSE/dE per tet at fixed u (the explicit part; dSE/du is the internal force)."""
+        uu = None if u is None else _f64(u, (self.n_nodes, 3))
+        gE = np.zeros(len(self._t))
+        self._chk(lib().orc_strain_energy_grad(self.c, _ptr(uu), _ptr(gE)))
+        return gE
 
     def window_gradient(self, n_steps, gu=None, gv=None):
         """Run n fixed-topology steps; return (dJ/du0, dJ/dv0, dJ/dE) for

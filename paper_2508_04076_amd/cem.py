@@ -31,7 +31,8 @@ EXPORTS = [
     "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
     "cem_set_profiling", "cem_kernel_times", "cem_set_instances", "cem_set_dt_instances",
     "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
-    "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step", "cem_window_forward", "cem_window_backward", "cem_window_times",
+    "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step",
+    "cem_window_forward", "cem_window_backward", "cem_window_times", "cem_strain_energy_grad",
 ]
 
 
@@ -122,6 +123,7 @@ def load_library(path=LIB_PATH):
         "cem_window_forward": [p, i32, i32],
         "cem_window_backward": [p, p, p, p, p, p],
         "cem_window_times": [p, p],
+        "cem_strain_energy_grad": [p, p, C.POINTER(C.c_double), p, p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -373,6 +375,15 @@ class Simulation:
         self._chk(self.lib.cem_window_backward(self.ctx, _p(gu), _p(gv), _p(gu0), _p(gv0),
                                                _p(gE)))
         return gu0, gv0, gE
+
+    def strain_energy_grad(self, u=None):
+        """(SE, dSE/du, dSE/dE at fixed u) at displacement u (None: the current state)."""
+        n = self.n_nodes
+        uu = None if u is None else _f64(u, (n, 3))
+        se = C.c_double()
+        gu, gE = np.zeros((n, 3)), np.zeros(self.n_tets)
+        self._chk(self.lib.cem_strain_energy_grad(self.ctx, _p(uu), C.byref(se), _p(gu), _p(gE)))
+        return se.value, gu, gE
 
     def window_times(self):
         out = np.zeros(6)

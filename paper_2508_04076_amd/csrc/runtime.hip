@@ -2225,6 +2225,74 @@ int cem_window_backward(cem_ctx* c, const double* gu, const double* gv, double* 
   return CEM_OK;
 }
 
+int cem_strain_energy_grad(cem_ctx* c, const double* u, double* se, double* gu, double* gE) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "a per-element modulus is for tetrahedral meshes");
+  Mesh& m = c->m;
+  if ((r = win_fixed(c))) return r;
+  int n = nodes_now_host(c);
+  const double4* src = c->st.u;
+  if (u) {
+    std::vector<double4> tmp;
+    pad3(c, u, tmp, n);
+    if ((r = upload(c, c->d_tmp, tmp.data(), n))) return r;
+    src = c->d_tmp;
+  }
+  const int np = c->n_partial;
+  // SE = 1/2 sum_k V_k sigma_k . eps_k
+  if (c->mixed) {
+    HIPCHK(c, Launch<float>::strain(m, src, c->w, c->d_ctr, c->stream));
+    HIPCHK(c, launch_strain_energy<float>(m, c->w, c->d_ctr, c->w.partial, np, -1, c->stream));
+  } else {
+    HIPCHK(c, Launch<double>::strain(m, src, c->w, c->d_ctr, c->stream));
+    HIPCHK(c, launch_strain_energy<double>(m, c->w, c->d_ctr, c->w.partial, np, -1, c->stream));
+  }
+  HIPCHK(c, launch_sum(c->w.partial, np, c->d_out, c->stream));
+  // dSE/du = f_int(u)
+  if ((r = strain_stress(c, src))) return r;
+  if ((r = node_pass(c, NODE_FORCE, c->d_tmp2))) return r;
+  // dSE/dE_j = 1/2 (V_j / 6) sum_{k in edges(j)} eps_k . Chat eps_k: the reverse
+  // kernels with lambda = u accumulate minus twice that
+  auto& W = c->win;
+  HIPCHK(c, hipMemsetAsync(W.gE, 0, sizeof(double) * m.T_cap, c->stream));
+  const int En = edges_now_host(c);
+  const double nu = c->mat.nu;
+  const double lh = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mh = 1.0 / (2.0 * (1.0 + nu));
+  if (c->mixed) {
+    HIPCHK(c, Adjoint<float>::inv_volumes(m, W.einv0, En, c->stream));
+    HIPCHK(c, Adjoint<float>::strain2(m, src, src, c->w.veps, W.vu, c->d_ctr, c->stream));
+    HIPCHK(c, Adjoint<float>::edge2(m, c->w.veps, W.vu, c->w.einvV, W.einv0, c->w.esig, W.z, lh, mh,
+                                    c->d_ctr, c->stream));
+    HIPCHK(c, Adjoint<float>::elem(m, c->w.esig, W.z, c->w.contrib, W.gE, c->d_ctr, c->stream));
+  } else {
+    HIPCHK(c, Adjoint<double>::inv_volumes(m, W.einv0, En, c->stream));
+    HIPCHK(c, Adjoint<double>::strain2(m, src, src, c->w.veps, W.vu, c->d_ctr, c->stream));
+    HIPCHK(c, Adjoint<double>::edge2(m, c->w.veps, W.vu, c->w.einvV, W.einv0, c->w.esig, W.z, lh, mh,
+                                     c->d_ctr, c->stream));
+    HIPCHK(c, Adjoint<double>::elem(m, c->w.esig, W.z, c->w.contrib, W.gE, c->d_ctr, c->stream));
+  }
+  double seh = 0;
+  HIPCHK(c, hipMemcpyAsync(&seh, c->d_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double4> fh(n);
+  HIPCHK(c, hipMemcpyAsync(fh.data(), c->d_tmp2, sizeof(double4) * n, hipMemcpyDeviceToHost, c->stream));
+  const int ns = m.mode == MODE_PHANTOM ? c->n_split_host : 0;
+  std::vector<double> g((size_t)m.T0 + ns);
+  std::vector<int> par(std::max(ns, 1));
+  HIPCHK(c, hipMemcpyAsync(g.data(), W.gE, sizeof(double) * g.size(), hipMemcpyDeviceToHost, c->stream));
+  if (ns) HIPCHK(c, hipMemcpyAsync(par.data(), m.rec_tet, sizeof(int) * ns, hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  if ((r = check_device_error(c))) return r;
+  if (se) *se = seh;
+  if (gu) unpad3(c, fh, gu, n);
+  if (gE) {
+    for (int s = 0; s < ns; ++s) g[par[s]] += g[(size_t)m.T0 + s];
+    for (int t = 0; t < m.T0; ++t) gE[t] = -0.5 * g[c->tet_new[t]];
+  }
+  return CEM_OK;
+}
+
 int cem_window_times(cem_ctx* c, double* out) {
   if (!c || !out) return CEM_EINVAL;
   for (int i = 0; i < 6; ++i) out[i] = c->win.times[i];

@@ -10,6 +10,12 @@ which recomputes each checkpoint segment of ``every`` steps and reverses it
 step by step on the GPU.  This module only moves arrays between torch and the
 library; every step of the computation runs in the library's kernels.
 
+``strain_energy(sim, E, u)`` is the strain energy at displacement u for the
+modulus the simulation holds (the E last given to ``window``), differentiable
+in E (at fixed u) and u; ``strain_energy(sim, E, window(...)[0])`` is the
+end-of-window strain energy, whose gradient in E sums the explicit term and
+the window's adjoint.
+
 The time step is an input of the window (set on the simulation), not a
 function of E.  Between the forward and the backward the simulation must not
 be stepped or modified (the library then refuses the backward).
@@ -49,3 +55,22 @@ def window(sim, E, u0, v0, n_steps, every=50, step0=0):
     """(u_n, v_n) after n_steps fixed-topology steps from step step0,
     differentiable in E, u0 and v0."""
     return ModulusWindow.apply(E, u0, v0, sim, int(n_steps), int(every), int(step0))
+
+
+class StrainEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, E, u, sim):
+        se, gu, gE = sim.strain_energy_grad(_host(u))
+        ctx.save_for_backward(torch.from_numpy(gu).to(u.device), torch.from_numpy(gE).to(E.device))
+        return torch.tensor(se, dtype=torch.float64, device=u.device)
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g):
+        gu, gE = ctx.saved_tensors
+        return g * gE, g * gu, None
+
+
+def strain_energy(sim, E, u):
+    """1/2 u^T K(E) u with E the modulus the simulation holds (differentiable)."""
+    return StrainEnergy.apply(E, u, sim)

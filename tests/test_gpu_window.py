@@ -132,6 +132,22 @@ def test_window_checkpoint_spacing_is_bitwise_neutral():
     del rng
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_strain_energy_gradient_parity(precision):
+    _case(f"strain energy gradient {precision}")
+    mesh = mg.cube_notched(6)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.2, seed=4)
+    sim, orc, u0, v0 = _setup(mesh, E, 6.0e-6, 0.0, seed=7, precision=precision)
+    u = np.random.default_rng(8).standard_normal(u0.shape) * 1e-6
+    se, gu, gE = sim.strain_energy_grad(u)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert _rel(gE, orc.strain_energy_grad(u)) < tol
+    assert _rel(gu, orc.internal_force(u)) < tol
+    orc.set_state(u, v0)
+    assert abs(se / orc.energy()["SE"] - 1) < tol
+    sim.close()
+
+
 def test_window_mixed_precision():
     _case("window gradient mixed precision")
     mesh = mg.cube_notched(6)
@@ -202,9 +218,42 @@ def test_autograd_window_matches_finite_differences():
     sim.close()
 
 
+def test_autograd_final_strain_energy():
+    # the cfg objective: strain energy at the end of the window, composed of
+    # the two differentiable pieces (explicit dSE/dE plus the window adjoint)
+    _case("autograd end-of-window strain energy vs central differences")
+    import torch
+    from paper_2508_04076_amd.window import strain_energy, window
+    mesh = mg.plate_notched(40, 16, 2, 0.01, 0.004, 0.0005, 0.005)
+    E0 = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    sim = _sim(mesh, ramp_t0=1e-7, graph_steps=8)
+    sim.set_dt(0.5 * sim.critical_dt())
+    n = sim.n_nodes
+    dev = torch.device("cuda:0")
+    E = torch.tensor(E0, device=dev, requires_grad=True)
+    u0 = torch.zeros((n, 3), dtype=torch.float64, device=dev, requires_grad=True)
+    v0 = torch.zeros((n, 3), dtype=torch.float64, device=dev, requires_grad=True)
+
+    def loss(E_, u_, v_):
+        u, _ = window(sim, E_, u_, v_, 150, 40)
+        return strain_energy(sim, E_, u)
+
+    L = loss(E, u0, v0)
+    L.backward()
+    gE = E.grad.clone()
+    rng = np.random.default_rng(11)
+    with torch.no_grad():
+        dE = torch.tensor(rng.choice([-1.0, 1.0], mesh.n_tets), device=dev) * E
+        h = 1e-5
+        fd = (loss(E + h * dE, u0, v0) - loss(E - h * dE, u0, v0)).item() / (2 * h)
+        assert abs(fd - (gE * dE).sum().item()) < 1e-6 * abs(fd), (fd, (gE * dE).sum().item())
+    sim.close()
+
+
 def test_window_full_size_plate_directional_derivative():
-    # 202,800-tet plate, 500 steps with a checkpoint every 50: the gradient's
-    # directional derivative against central differences of the forward
+    # 202,800-tet plate, 500 steps with a checkpoint every 50: the gradient of
+    # the final strain energy with respect to the per-tet modulus, against
+    # central differences of the forward
     _case("window 202,800-tet plate, 500 steps, every 50")
     mesh = mg.plate_window()
     E0 = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
@@ -213,7 +262,6 @@ def test_window_full_size_plate_directional_derivative():
     sim.set_dt(dt)
     n = sim.n_nodes
     rng = np.random.default_rng(9)
-    gu = rng.standard_normal((n, 3))
     zero = np.zeros((n, 3))
 
     def J(E):
@@ -221,10 +269,12 @@ def test_window_full_size_plate_directional_derivative():
         sim.set_state(zero, zero)
         sim.set_step(0)
         sim.window_forward(500, 50)
-        return float((gu * sim.get_state()[0]).sum())
+        return sim.strain_energy_grad()[0]
 
     J(E0)
+    _, gu, gE_explicit = sim.strain_energy_grad()
     _, _, gE = sim.window_backward(gu, None)
+    gE = gE + gE_explicit
     dE = rng.choice([-1.0, 1.0], mesh.n_tets) * E0
     h = 1e-5
     fd = (J(E0 + h * dE) - J(E0 - h * dE)) / (2 * h)

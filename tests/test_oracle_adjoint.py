@@ -198,3 +198,29 @@ def test_window_leaves_end_state_and_frozen_topology():
     u2, v2, _ = o2.get_state()
     assert (u == u2).all() and (v == v2).all()
     assert o.counts() == c0 and o.energy()["step"] == 10
+
+
+def test_strain_energy_modulus_gradient():
+    # explicit dSE/dE_j at fixed u against central differences of the
+    # oracle's strain energy, and Euler's identity sum_j E_j dSE/dE_j = SE
+    # (SE is linear in the moduli at fixed u)
+    m, pt, pm = _split_setup(n=3)
+    E = mg.modulus_field(len(m.tets), MAT["E"], 0.2, seed=4)
+    o, _, u0, _ = _window_case(m, pt, pm, E)
+    u = np.random.default_rng(5).standard_normal(u0.shape) * 1e-6
+    g = o.strain_energy_grad(u)
+
+    def se(E_):
+        oo, _, _, _ = _window_case(m, pt, pm, E_)
+        oo.set_state(u, np.zeros_like(u))
+        return oo.energy()["SE"]
+
+    assert abs(g @ E - se(E)) < 1e-12 * se(E)
+    # the internal force is dSE/du
+    f = o.internal_force(u)
+    assert abs(0.5 * (f * u).sum() - se(E)) < 1e-12 * se(E)
+    for t in (int(pt[0]), 5, int(np.argmax(g))):
+        e = np.zeros(len(E))
+        e[t] = 1e-4 * E[t]
+        fd = (se(E + e) - se(E - e)) / 2e-4
+        assert abs(fd - g[t] * E[t]) < 1e-8 * abs(se(E))
