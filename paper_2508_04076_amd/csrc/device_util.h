@@ -27,11 +27,12 @@ namespace cem {
 // on the device, so a captured graph stays valid as splits add elements.
 struct Chunks {
   int ch, hi, stride;
-  // nblocks: the workgroups that share the items (the first nblocks of the
-  // grid; default all of it)
-  __device__ __forceinline__ Chunks(long long count, int nblocks = 0) {
+  // nblocks: the workgroups that share the items, starting at workgroup b0
+  // (a multiple of 8, so that each keeps its XCD); default the whole grid
+  __device__ __forceinline__ Chunks(long long count, int nblocks = 0, int b0 = 0) {
     long long nch = (count + kBlock - 1) / kBlock;
-    int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    int b = (int)blockIdx.x - b0;
+    int x = b % 8, j = b / 8;
     stride = (nblocks > 0 ? nblocks : (int)gridDim.x) / 8;
     ch = (int)(nch * x / 8) + j;
     hi = (int)(nch * (x + 1) / 8);

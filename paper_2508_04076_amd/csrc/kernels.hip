@@ -153,9 +153,10 @@ __device__ __forceinline__ bool over_capacity(const Mesh& m, Counters* c) {
 template <class R>
 __device__ __forceinline__ void elem_force_items(const Mesh& m, const Six<R>* __restrict__ esig,
                                                  R* __restrict__ contrib,
-                                                 const Counters* __restrict__ c, int nblocks) {
+                                                 const Counters* __restrict__ c, int nblocks,
+                                                 int b0) {
   const int Tn = elems_now(m, c);
-  Chunks it(Tn, nblocks);
+  Chunks it(Tn, nblocks, b0);
   for (int e; it.next(e);) {
   if (e >= Tn) continue;
   int4 nd = m.enodes[e];
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force(Mesh m, con
                                                        R* __restrict__ contrib,
                                                        Counters* __restrict__ c) {
   if (c->err || over_capacity(m, c)) return;
-  elem_force_items(m, esig, contrib, c, 0);
+  elem_force_items(m, esig, contrib, c, 0, 0);
 }
 
 // Prescribed components of constrained slot b at time t: velocity v0 V(t),
@@ -499,21 +500,22 @@ __device__ void front_block(const Mesh& m, const double4* __restrict__ u,
   if (threadIdx.x == 0 && red[0] != 0) atomicMax(&c->gmax_key, red[0]);
 }
 
-// The element force pass and the crack-front pass in one launch: the first eg
-// workgroups take the elements, the others the crack-front candidates.  Both
-// read the edge stresses and write disjoint data; the capacity test on the
-// flags is left to the node pass, which runs after both.
+// The element force pass and the crack-front pass in one launch: the first fg
+// workgroups (dispatched first, so they run beside the element workgroups
+// instead of after them) take the crack-front candidates, the others the
+// elements.  Both read the edge stresses and write disjoint data; the
+// capacity test on the flags is left to the node pass, which runs after both.
 template <class R>
 __global__ __launch_bounds__(kBlock, CEM_WPE_ELEM) void k_elem_force_front(
     Mesh m, const Six<R>* __restrict__ esig, R* __restrict__ contrib,
-    const double4* __restrict__ uh, Counters* __restrict__ c, int eg, int flagging) {
+    const double4* __restrict__ uh, Counters* __restrict__ c, int fg, int flagging) {
   if (c->err) return;
   __shared__ unsigned long long red[kBlock];
-  if ((int)blockIdx.x >= eg) {
-    front_block<R>(m, uh, esig, c, flagging, blockIdx.x - eg, gridDim.x - eg, red);
+  if ((int)blockIdx.x < fg) {
+    front_block<R>(m, uh, esig, c, flagging, blockIdx.x, fg, red);
     return;
   }
-  elem_force_items(m, esig, contrib, c, eg);
+  elem_force_items(m, esig, contrib, c, (int)gridDim.x - fg, fg);
 }
 
 // Readback of every front's G_I and G_II (unordered; the host sorts).
@@ -681,9 +683,12 @@ __device__ void block_sort(int* list, int n, const int* key, int* shk, int* shv)
     }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+// Sum over groups of G consecutive lanes by a fixed butterfly (every lane of a
+// group must take part).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;
 }
 
@@ -699,7 +704,6 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
   __shared__ int s_n, s_base;
   __shared__ int shk[kSortLds], shv[kSortLds];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = kTopoBlock / 64;
   if (tid == 0) {
     s_n = c->err ? 0 : c->n_flag;
     s_base = c->n_split;
@@ -709,115 +713,158 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
   R* einvV = (R*)w.einvV;
   if (n > 0) {
     if (dynamic) block_sort(m.splitlist, n, m.tet_ext, shk, shv);
-    // phases 0 + 1, one thread per split: record the split, keep the parent's
-    // real nodes and edges, then rewrite elements, edges and node lists
-    for (int i = tid; i < n; i += kTopoBlock) {
-      int t = m.splitlist[i];
-      int mask = m.pmask[t];
-      int nd[4], ed[6];
-      load_tet<R>(m, t, nd, ed);
-      snodes[i] = make_int4(nd[0], nd[1], nd[2], nd[3]);
-      for (int q = 0; q < 6; ++q) sedges[6 * i + q] = ed[q];
-      m.smask[t] = mask;
-      int s = base + i;
-      m.rec_step[s] = dynamic ? (int)(c->step + 1) : (int)c->step;
-      m.rec_tet[s] = t;
-      m.rec_mask[s] = mask;
-      m.rec_pat[s] = dynamic ? m.ppat[t] : 0;
-      m.rec_G[s] = dynamic ? m.pG[t] : 0.0;
-      m.area[i] = dynamic ? crack_area(m, nd, mask) : 0.0;
-      m.rec_area[s] = m.area[i];
-      if (m.mode == MODE_ERODE) {
-        m.enodes[t] = make_int4(pack0(nd[0], FR_ZERO), nd[1], nd[2], nd[3]);
-        continue;
-      }
-      int tb = m.T0 + s;
-      int nb = __popc(mask);
-      int codeA = code_for_side(4 - nb), codeB = code_for_side(nb);
-      int4 op4 = m.epos[t];
-      const int op[4] = {op4.x, op4.y, op4.z, op4.w};
-      int na[4], nbn[4], pa[4], pb[4];
-      for (int l = 0; l < 4; ++l) {
-        int x = m.N0 + 4 * s + l;
-        int xe = 4 * m.T0 + 4 * s + l;  // the extra node's single list entry
-        m.X[x] = m.X[nd[l]];
-        st.u[x] = st.u[nd[l]];
-        st.v[x] = st.v[nd[l]];
-        st.a[x] = st.a[nd[l]];
-        st.uh[x] = st.uh[nd[l]];
-        m.lslot[x] = -1;
-        if (m.n_inst) m.inst[x] = m.inst[nd[l]];
-        bool onB = (mask >> l) & 1;
-        na[l] = onB ? x : nd[l];
-        nbn[l] = onB ? nd[l] : x;
-        pa[l] = onB ? xe : op[l];
-        pb[l] = onB ? op[l] : xe;
-        int owner = onB ? t : tb;  // the copy that holds the extra node
-        m.nent[xe] = (owner << 2) | l;
-        if (onB) m.nent[op[l]] = (tb << 2) | l;
-      }
-      m.enodes[t] = make_int4(pack0(na[0], codeA), na[1], na[2], na[3]);
-      m.enodes[tb] = make_int4(pack0(nbn[0], codeB), nbn[1], nbn[2], nbn[3]);
-      m.epos[t] = make_int4(pa[0], pa[1], pa[2], pa[3]);
-      m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
-      double V = m.vol[t];
-      m.vol[tb] = V;
-      double kp = 1.0;
-      if (m.kap) {
-        kp = m.kap[t];
-        m.kap[tb] = kp;
-      }
-      if (m.n_inst) {
-        int ti = m.tinst[t];
-        m.tinst[tb] = ti;
-        for (int r = 0; r < 10; ++r) m.einst[m.E0 + 10 * s + r] = ti;
-      }
-      // a new edge's patch is one copy: kappa_k is the parent's
-      R ivA = (R)(kp / (frac_of(codeA) * V)), ivB = (R)(kp / (frac_of(codeB) * V));
-      int eA[6], eB[6];
-      int r = 0;
-      int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
-      const int* pp = (const int*)&m.patchpos[3 * t];
-      for (int q = 0; q < 6; ++q) {
-        int k = ed[q];
-        int ba = (mask >> kEA[q]) & 1, bb = (mask >> kEB[q]) & 1;
-        if (!ba && !bb) {          // both nodes on side A: copy A keeps edge k
-          eA[q] = k;
-          eB[q] = ebase + r; m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; r++;
-        } else if (ba && bb) {     // both on side B: copy B takes edge k
-          eB[q] = k; m.pent[pp[q]] = tb;
-          eA[q] = ebase + r; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; r++;
-        } else {                   // cut edge: each copy gets a new one
-          m.pent[pp[q]] = -1;
-          eA[q] = ebase + r; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; r++;
-          eB[q] = ebase + r; m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; r++;
+    // phases 0 + 1, eight lanes per split: record the split, keep the parent's
+    // real nodes and edges, then rewrite elements, edges and node lists.
+    // Lane l < 4 copies extra node l and fixes its node-list entries, lane
+    // q < 6 rewrites edge q's patch entries, lane 0 the records and the two
+    // copies' element rows.  Everything a split reads of its parent is read
+    // before a block barrier, everything it writes after it.
+    constexpr int GS = 8;
+    const int sl = tid % GS;
+    for (int i0 = 0; i0 < n; i0 += kTopoBlock / GS) {
+      const int i = i0 + tid / GS;
+      const bool on = i < n;
+      int t = 0, mask = 0, nd[4] = {0, 0, 0, 0}, ed[6] = {0, 0, 0, 0, 0, 0}, pp[6];
+      int4 op4 = make_int4(0, 0, 0, 0);
+      double V = 0, kp = 1.0, area = 0, G = 0;
+      int ti = 0, pat = 0;
+      if (on) {
+        t = m.splitlist[i];
+        mask = m.pmask[t];
+        load_tet<R>(m, t, nd, ed);
+        if (m.mode == MODE_PHANTOM) {
+          op4 = m.epos[t];
+          V = m.vol[t];
+          if (m.kap) kp = m.kap[t];
+          if (m.n_inst) ti = m.tinst[t];
+          const int* p6 = (const int*)&m.patchpos[3 * t];
+          for (int q = 0; q < 6; ++q) pp[q] = p6[q];
+        }
+        if (sl == 0 && dynamic) {
+          pat = m.ppat[t];
+          G = m.pG[t];
+          area = crack_area(m, nd, mask);
         }
       }
-      for (; r < 10; ++r) { m.pent[pbase + r] = -1; einvV[ebase + r] = (R)0; }
-      m.et2e[3 * t] = make_int2(eA[0], eA[1]);
-      m.et2e[3 * t + 1] = make_int2(eA[2], eA[3]);
-      m.et2e[3 * t + 2] = make_int2(eA[4], eA[5]);
-      m.et2e[3 * tb] = make_int2(eB[0], eB[1]);
-      m.et2e[3 * tb + 1] = make_int2(eB[2], eB[3]);
-      m.et2e[3 * tb + 2] = make_int2(eB[4], eB[5]);
+      __syncthreads();
+      if (on) {
+        const int s = base + i;
+        if (sl == 0) {
+          snodes[i] = make_int4(nd[0], nd[1], nd[2], nd[3]);
+          for (int q = 0; q < 6; ++q) sedges[6 * i + q] = ed[q];
+          m.smask[t] = mask;
+          m.rec_step[s] = dynamic ? (int)(c->step + 1) : (int)c->step;
+          m.rec_tet[s] = t;
+          m.rec_mask[s] = mask;
+          m.rec_pat[s] = pat;
+          m.rec_G[s] = G;
+          m.area[i] = area;
+          m.rec_area[s] = area;
+          if (m.mode == MODE_ERODE) m.enodes[t] = make_int4(pack0(nd[0], FR_ZERO), nd[1], nd[2], nd[3]);
+        }
+        if (m.mode == MODE_PHANTOM) {
+          const int tb = m.T0 + s;
+          const int nb = __popc(mask);
+          const int codeA = code_for_side(4 - nb), codeB = code_for_side(nb);
+          const int op[4] = {op4.x, op4.y, op4.z, op4.w};
+          if (sl < 4) {
+            const int l = sl;
+            const int x = m.N0 + 4 * s + l;
+            const int xe = 4 * m.T0 + 4 * s + l;  // the extra node's single list entry
+            m.X[x] = m.X[nd[l]];
+            st.u[x] = st.u[nd[l]];
+            st.v[x] = st.v[nd[l]];
+            st.a[x] = st.a[nd[l]];
+            st.uh[x] = st.uh[nd[l]];
+            m.lslot[x] = -1;
+            if (m.n_inst) m.inst[x] = m.inst[nd[l]];
+            const bool onB = (mask >> l) & 1;
+            const int owner = onB ? t : tb;  // the copy that holds the extra node
+            m.nent[xe] = (owner << 2) | l;
+            if (onB) m.nent[op[l]] = (tb << 2) | l;
+          }
+          // a new edge's patch is one copy: kappa_k is the parent's
+          const R ivA = (R)(kp / (frac_of(codeA) * V)), ivB = (R)(kp / (frac_of(codeB) * V));
+          const int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
+          int eA[6], eB[6];
+          int r = 0;  // every edge makes one new edge, a cut edge two
+          for (int q = 0; q < 6; ++q) {
+            const int k = ed[q];
+            const int ba = (mask >> kEA[q]) & 1, bb = (mask >> kEB[q]) & 1;
+            const bool mine = sl == q;
+            if (!ba && !bb) {          // both nodes on side A: copy A keeps edge k
+              eA[q] = k;
+              eB[q] = ebase + r;
+              if (mine) { m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; }
+              r++;
+            } else if (ba && bb) {     // both on side B: copy B takes edge k
+              eB[q] = k;
+              eA[q] = ebase + r;
+              if (mine) { m.pent[pp[q]] = tb; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; }
+              r++;
+            } else {                   // cut edge: each copy gets a new one
+              eA[q] = ebase + r;
+              eB[q] = ebase + r + 1;
+              if (mine) {
+                m.pent[pp[q]] = -1;
+                m.pent[pbase + r] = t; einvV[ebase + r] = ivA;
+                m.pent[pbase + r + 1] = tb; einvV[ebase + r + 1] = ivB;
+              }
+              r += 2;
+            }
+          }
+          if (sl == 6)
+            for (int q = r; q < 10; ++q) { m.pent[pbase + q] = -1; einvV[ebase + q] = (R)0; }
+          if (sl == 7 && m.n_inst) {
+            m.tinst[tb] = ti;
+            for (int q = 0; q < 10; ++q) m.einst[ebase + q] = ti;
+          }
+          if (sl == 0) {
+            int na[4], nbn[4], pa[4], pb[4];
+            for (int l = 0; l < 4; ++l) {
+              const int x = m.N0 + 4 * s + l, xe = 4 * m.T0 + 4 * s + l;
+              const bool onB = (mask >> l) & 1;
+              na[l] = onB ? x : nd[l];
+              nbn[l] = onB ? nd[l] : x;
+              pa[l] = onB ? xe : op[l];
+              pb[l] = onB ? op[l] : xe;
+            }
+            m.enodes[t] = make_int4(pack0(na[0], codeA), na[1], na[2], na[3]);
+            m.enodes[tb] = make_int4(pack0(nbn[0], codeB), nbn[1], nbn[2], nbn[3]);
+            m.epos[t] = make_int4(pa[0], pa[1], pa[2], pa[3]);
+            m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
+            m.vol[tb] = V;
+            if (m.kap) m.kap[tb] = kp;
+            m.et2e[3 * t] = make_int2(eA[0], eA[1]);
+            m.et2e[3 * t + 1] = make_int2(eA[2], eA[3]);
+            m.et2e[3 * t + 2] = make_int2(eA[4], eA[5]);
+            m.et2e[3 * tb] = make_int2(eB[0], eB[1]);
+            m.et2e[3 * tb + 1] = make_int2(eB[2], eB[3]);
+            m.et2e[3 * tb + 2] = make_int2(eB[4], eB[5]);
+          }
+        }
+      }
+      __syncthreads();
     }
     __threadfence_block();
     __syncthreads();
-    // phase 2: lumped masses of touched nodes, volumes of touched edges; one
-    // wave per item, lanes over the list, fixed-order wave sum
+    // phase 2: lumped masses of touched nodes (16 lanes per node list) and
+    // volumes of touched edges (8 lanes per patch); fixed-order group sums
     if (m.mode == MODE_PHANTOM) {
-      for (int item = wave; item < 4 * n; item += nwaves) {
+      constexpr int GN = 16;
+      const int gl = tid % GN;
+      for (int item = tid / GN; item < 4 * n; item += kTopoBlock / GN) {
         int i = item >> 2, l = item & 3;
         int4 q4 = snodes[i];
         int node = l == 0 ? q4.x : l == 1 ? q4.y : l == 2 ? q4.z : q4.w;
         double part = 0;
-        for (int p = m.noff[node] + lane; p < m.noff[node + 1]; p += 64) {
+        for (int p = m.noff[node] + gl; p < m.noff[node + 1]; p += GN) {
           int e = m.nent[p] >> 2;
           part += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
         }
-        part = wave_sum(part);
-        if (lane == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
-        if (lane == 1) {
+        part = group_sum<GN>(part);
+        if (gl == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
+        if (gl == 1) {
           int t = m.splitlist[i];
           int mask = m.pmask[t];
           int nbB = __popc(mask);
@@ -828,42 +875,43 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
         }
       }
     }
-    for (int item = wave; item < 6 * n; item += nwaves) {
-      int k = sedges[item];
-      double part = 0, partk = 0;
-      for (int p = m.poff[k] + lane; p < m.poff[k + 1]; p += 64) {
-        int e = m.pent[p];
-        if (e < 0) continue;
-        double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
-        part += ve;
-        if (m.kap) partk += ve * m.kap[e];
+    {
+      constexpr int GE = 8;
+      const int gl = tid % GE;
+      for (int item = tid / GE; item < 6 * n; item += kTopoBlock / GE) {
+        int k = sedges[item];
+        double part = 0, partk = 0;
+        for (int p = m.poff[k] + gl; p < m.poff[k + 1]; p += GE) {
+          int e = m.pent[p];
+          if (e < 0) continue;
+          double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+          part += ve;
+          if (m.kap) partk += ve * m.kap[e];
+        }
+        part = group_sum<GE>(part);
+        if (m.kap) partk = group_sum<GE>(partk);
+        if (gl == 0)
+          einvV[k] = !(part > 0) ? (R)0 : m.kap ? (R)(partk / part / part) : (R)(1.0 / part);
       }
-      part = wave_sum(part);
-      if (m.kap) partk = wave_sum(partk);
-      if (lane == 0)
-        einvV[k] = !(part > 0) ? (R)0 : m.kap ? (R)(partk / part / part) : (R)(1.0 / part);
     }
-    // phase 3: new crack fronts on intact face neighbours
-    for (int i = tid; i < n; i += kTopoBlock) {
+    // phase 3: new crack fronts on intact face neighbours, one lane per face
+    for (int item = tid; item < 4 * n; item += kTopoBlock) {
+      const int i = item >> 2, f = item & 3;
       int t = m.splitlist[i];
       int mask = m.pmask[t];
+      int fl[3], k = 0;
+      for (int l = 0; l < 4; ++l)
+        if (l != f) fl[k++] = l;
+      int b0 = (mask >> fl[0]) & 1, b1 = (mask >> fl[1]) & 1, b2 = (mask >> fl[2]) & 1;
+      if (b0 == b1 && b1 == b2) continue;
+      int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];
+      int cn = ((const int*)&m.nbr[t])[f];
+      if (cn < 0 || m.smask[cn] >= 0) continue;
+      int fc = (m.nbrface[t] >> (8 * f)) & 0xff;
       int4 q4 = snodes[i];
-      int nd[4] = {q4.x, q4.y, q4.z, q4.w};
-      const int* nb4 = (const int*)&m.nbr[t];
-      int nf = m.nbrface[t];
-      for (int f = 0; f < 4; ++f) {
-        int fl[3], k = 0;
-        for (int l = 0; l < 4; ++l)
-          if (l != f) fl[k++] = l;
-        int b0 = (mask >> fl[0]) & 1, b1 = (mask >> fl[1]) & 1, b2 = (mask >> fl[2]) & 1;
-        if (b0 == b1 && b1 == b2) continue;
-        int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];
-        int cn = nb4[f];
-        if (cn < 0 || m.smask[cn] >= 0) continue;
-        int fc = (nf >> (8 * f)) & 0xff;
-        ((int*)m.front)[4 * cn + fc] = nd[lone];
-        if (atomicCAS(&m.candf[cn], 0, 1) == 0) m.cand[atomicAdd(&c->n_cand, 1)] = cn;
-      }
+      const int nd[4] = {q4.x, q4.y, q4.z, q4.w};
+      ((int*)m.front)[4 * cn + fc] = nd[lone];
+      if (atomicCAS(&m.candf[cn], 0, 1) == 0) m.cand[atomicAdd(&c->n_cand, 1)] = cn;
     }
     __syncthreads();
   }
@@ -1255,9 +1303,9 @@ hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counte
     if (e != hipSuccess) return e;
   } else if (front >= 0) {
     // crack-front workgroups ride along with the element force launch
-    const int eg = persistent_grid(m, m.T_cap);
-    hipLaunchKernelGGL(k_elem_force_front<R>, dim3(eg + front_grid(m)), dim3(kBlock), 0, s, m,
-                       (const Six<R>*)w.esig, (R*)w.contrib, (const double4*)st.uh, c, eg, front);
+    const int fg = (front_grid(m) + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_elem_force_front<R>, dim3(fg + persistent_grid(m, m.T_cap)), dim3(kBlock), 0,
+                       s, m, (const Six<R>*)w.esig, (R*)w.contrib, (const double4*)st.uh, c, fg, front);
     if (front == 0) {  // forced schedule: select this step's entries
       hipError_t e = launch_replay_select(m, c, s);
       if (e != hipSuccess) return e;
