@@ -86,6 +86,7 @@ struct cem_ctx {
   int graph_replay = -1;
 
   // profiling
+  hipEvent_t tev[2] = {nullptr, nullptr};  // whole-call timing (created once)
   int profiling = 0;
   double times[7] = {0, 0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> evpool;
@@ -697,6 +698,14 @@ int ensure_events(cem_ctx* c, size_t n) {
   return CEM_OK;
 }
 
+// The two events that time a whole call (created on first use, destroyed
+// with the context).
+int timing_events(cem_ctx* c) {
+  for (int q = 0; q < 2; ++q)
+    if (!c->tev[q]) HIPCHK(c, hipEventCreate(&c->tev[q]));
+  return CEM_OK;
+}
+
 // Sum the per-pass intervals of k recorded steps (kEvents events per step).
 int accumulate_times(cem_ctx* c, int k) {
   for (int i = 0; i < k; ++i)
@@ -768,9 +777,8 @@ int nodes_now_host(cem_ctx* c) {
 int run_steps(cem_ctx* c, int32_t n_steps) {
   int r;
   if (n_steps == 0) return CEM_OK;
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
+  if ((r = timing_events(c))) return r;
+  hipEvent_t e0 = c->tev[0], e1 = c->tev[1];
   HIPCHK(c, hipEventRecord(e0, c->stream));
   if (c->need_init && (r = initialize(c))) return r;
   for (int q = 0; q < 7; ++q) c->times[q] = 0;
@@ -807,8 +815,6 @@ int run_steps(cem_ctx* c, int32_t n_steps) {
   float ms = 0;
   (void)hipEventElapsedTime(&ms, e0, e1);
   c->times[0] = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return r;
 }
 
@@ -994,6 +1000,8 @@ void cem_destroy(cem_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
+    for (auto e : c->tev)
+      if (e) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     for (void* p : c->win.fixed) (void)hipFree(p);
     (void)hipFree(c->win.ck);
@@ -2267,9 +2275,8 @@ int cem_window_backward(cem_ctx* c, const double* gu, const double* gv, double* 
   if (W.gen != c->gen) return c->fail(CEM_ESTATE, "no gradient window pending (cem_window_forward)");
   Mesh& m = c->m;
   for (double& t : W.times) t = 0;
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
+  if ((r = timing_events(c))) return r;
+  hipEvent_t e0 = c->tev[0], e1 = c->tev[1];
   HIPCHK(c, hipEventRecord(e0, c->stream));
   // sensitivities at the window's end
   std::vector<double4> tmp(W.nodes, make_double4(0, 0, 0, 0));
@@ -2294,8 +2301,6 @@ int cem_window_backward(cem_ctx* c, const double* gu, const double* gv, double* 
   float ms = 0;
   (void)hipEventElapsedTime(&ms, e0, e1);
   W.times[0] = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   // read back in the caller's numbering
   std::vector<double4> h(W.nodes);
   double4* src[2] = {W.p, W.q};
