@@ -489,12 +489,14 @@ def window_cpu_baseline(mesh, mat, E, dt, gu, n_steps=8):
 # FP64 / mixed), with E/H = 3 edges and N/H = 1 node per hex on a structured
 # grid: strain = ids 32 + G 192 + u gather 32 + write V eps 48; edge = CSR
 # 4 (E/H) + 48 + read V eps 48 + write sigma 48 (E/H) + einvV 8 (E/H);
-# force = ids 80 + G 192 + read sigma 48 (E/H) + u, v read+write 96 + 1/m 8.
+# force = ids 84 (12 edge ids 48, node lists 36) + G 192 + read sigma 48 (E/H)
+# + u, v read+write 96 + 1/m 8.  The per-hex stress sum handed from the element
+# pass to the node pass is an intermediate, not counted.
 HEX_BYTES = {
     "fp64": {"strain": 32 + 192 + 32 + 48, "edge_stress": 12 + 48 + 48 + 144 + 24,
-             "node": 80 + 192 + 144 + 96 + 8},
+             "node": 84 + 192 + 144 + 96 + 8},
     "mixed": {"strain": 32 + 192 + 32 + 24, "edge_stress": 12 + 48 + 24 + 72 + 12,
-              "node": 80 + 192 + 72 + 96 + 8},
+              "node": 84 + 192 + 72 + 96 + 8},
 }
 
 

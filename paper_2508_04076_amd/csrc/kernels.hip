@@ -212,7 +212,7 @@ __device__ __forceinline__ void bc_override(const Mesh& m, int b, double t, doub
 // Node pass: G lanes per node sum the node's contributions (lane g takes
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
-template <class R, int MODE, int G, bool BC>
+template <class R, int MODE, int G, bool BC, bool HX>
 __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st, const R* __restrict__ contrib,
                                                  double4* __restrict__ fout,
                                                  Counters* __restrict__ c) {
@@ -224,7 +224,8 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st,
   const int i = item / G;
   const bool active = i < Nn;
   double fx, fy, fz;
-  node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
+  if (HX) node_gather_hex<R, G>(m, contrib, i, active, g, fx, fy, fz);
+  else node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
   if (!active || g != 0) continue;
   if (MODE == NODE_FORCE) {
     fout[i] = make_double4(fx, fy, fz, 0.0);
@@ -1277,22 +1278,29 @@ hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, 
   return hipGetLastError();
 }
 
-template <class R, int G>
-static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
-                              Counters* c, int mode, double4* fout, hipStream_t s) {
+template <class R, int G, bool HX>
+static void launch_node_kind(const Mesh& m, const State& st, const R* ct, Counters* c, int mode,
+                             double4* fout, hipStream_t s) {
   dim3 g(persistent_grid(m, (long long)m.N_cap * G)), b(kBlock);
   // constrained nodes take their own kernel variant, so that a mesh without
   // prescribed velocities pays nothing for them
   if (mode == NODE_FORCE)
-    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false, HX>), g, b, 0, s, m, st, ct, fout, c);
   else if (mode == NODE_INIT && m.n_bc)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true, HX>), g, b, 0, s, m, st, ct, fout, c);
   else if (mode == NODE_INIT)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false, HX>), g, b, 0, s, m, st, ct, fout, c);
   else if (m.n_bc)
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true, HX>), g, b, 0, s, m, st, ct, fout, c);
   else
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false, HX>), g, b, 0, s, m, st, ct, fout, c);
+}
+
+template <class R, int G>
+static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
+                              Counters* c, int mode, double4* fout, hipStream_t s) {
+  if (CEM_HEX_GATHER && m.etype == 8) launch_node_kind<R, G, true>(m, st, ct, c, mode, fout, s);
+  else launch_node_kind<R, G, false>(m, st, ct, c, mode, fout, s);
 }
 
 template <class R>
