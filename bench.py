@@ -86,6 +86,38 @@ def velocity_groups(name, mesh):
             (bot, np.full(len(bot), 2), np.zeros((len(bot), 3)), 0.0)]
 
 
+def kernel_source_hash():
+    """SHA-256 over every HIP source and header of the library (file name and
+    contents, in name order): the kernels, their helpers and the host runtime,
+    whose node and element order also set the traffic."""
+    d = os.path.join(ROOT, "paper_2508_04076_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode() + b"\0" + open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def copy_peak_gbs(nbytes=1 << 30, reps=10):
+    """Read+write GB/s of a plain device-to-device copy of nbytes (torch's
+    current stream, timed with events after three untimed copies)."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def counters_for(kernel_src_hash):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source."""
@@ -116,6 +148,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--launch", default="",
+                    help="fixed launch shape grid_cap,lanes,layout (e.g. 2048,4,stress_sums) "
+                         "instead of the autotuner")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="ensemble workload only (default mixed)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -165,14 +200,19 @@ def main():
         for g_ in groups:
             s_.add_velocity_bc(*g_)
         if tuned:
-            s_.set_launch(tuned["grid_cap"], tuned["lanes"])
+            s_.set_launch(tuned["grid_cap"], tuned["lanes"], tuned["layout"])
         return s_
 
     # ---- 0. launch shape from the library's autotuner, on a warmed-up copy
     gs = 0 if args.no_graph else args.graph_steps
     sim = make("fp64", 0)
     dt = 0.5 * sim.critical_dt()
-    if not args.no_tune:
+    if args.launch:
+        g_, l_, lay_ = args.launch.split(",")
+        tuned.update(grid_cap=int(g_), lanes=int(l_), layout=lay_)
+        sim.close()
+        sim = make("fp64", 0)
+    elif not args.no_tune:
         sim.set_dt(dt)
         sim.step(W)
         tuned.update(sim.autotune(trial_steps=10))
@@ -233,6 +273,11 @@ def main():
         if len(sched):
             mx.replay_splits(sched)
         mx.step(W)
+        tuned_mx = None
+        if not args.launch and not args.no_tune:
+            # its own launch shape (the tuner restores the state after each trial)
+            tuned_mx = mx.autotune(trial_steps=10)
+            log(f"autotuned launch (mixed): {tuned_mx}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mx.step(K)
@@ -242,7 +287,8 @@ def main():
         err = float(np.linalg.norm(um - u64) / np.linalg.norm(u64))
         mixed = {"tet_steps_per_s": T * K / mw, "ms_per_step": mw * 1e3 / K,
                  "rel_l2_u_vs_fp64": err, "steps_compared": W + K,
-                 "split_schedule": "fp64 run replayed", "dtype": "f32 force / f64 state"}
+                 "split_schedule": "fp64 run replayed", "dtype": "f32 force / f64 state",
+                 "autotune": tuned_mx}
         log(f"mixed: {mw * 1e3 / K:.4f} ms/step, {T * K / mw:.4e} tet-steps/s, "
             f"rel L2 u err {err:.3e}")
         mx.close()
@@ -252,8 +298,9 @@ def main():
     dur_s = per_launch[dom] * 1e-3
     alg = ALG_BYTES["fp64"][dom] * T
     achieved = alg / dur_s / 1e9
-    src = open(os.path.join(ROOT, "paper_2508_04076_amd", "csrc", "kernels.hip"), "rb").read()
-    cnt = counters_for(hashlib.sha256(src).hexdigest())
+    cnt = counters_for(kernel_source_hash())
+    if cnt and cnt.get("layout", "terms") != tuned.get("layout", "terms"):
+        cnt = None  # counters of the other force layout
     traffic = None
     if cnt and cnt.get("workload") == args.workload and \
             all(k in cnt.get("kernels", {}) for k in KERNEL_NAMES[dom]):
@@ -262,6 +309,29 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic, "alg_bytes_per_tet": ALG_BYTES["fp64"][dom],
                 "avg_launch_ms": per_launch[dom]}
+
+    # ---- HBM GB/s of the step: model bytes x rate ("effective"), and counted
+    # bytes (rocprofv3 counters of this source) over each pass's event time,
+    # against the spec and a device copy measured here
+    hbm = {"spec_gbs": HBM_PEAK_GBS, "copy_peak_gbs": copy_peak_gbs(),
+           "effective_gbs_fp64": sum(ALG_BYTES["fp64"].values()) * value / 1e9,
+           "alg_bytes_per_tet_fp64": sum(ALG_BYTES["fp64"].values())}
+    if graph:
+        hbm["effective_gbs_fp64_graphs"] = sum(ALG_BYTES["fp64"].values()) * graph["tet_steps_per_s"] / 1e9
+    if mixed:
+        hbm["effective_gbs_mixed"] = sum(ALG_BYTES["mixed"].values()) * mixed["tet_steps_per_s"] / 1e9
+    if cnt and cnt.get("workload") == args.workload and \
+            all(k in cnt.get("kernels", {}) for p_ in KERNEL_NAMES for k in KERNEL_NAMES[p_]):
+        counted, tb, tt = {}, 0.0, 0.0
+        for p_, names in KERNEL_NAMES.items():
+            b_ = sum(cnt["kernels"][k]["hbm_bytes_per_launch"] for k in names)
+            counted[p_] = {"bytes_per_launch": b_, "gbs": b_ / (per_launch[p_] * 1e-3) / 1e9}
+            tb += b_
+            tt += per_launch[p_] * 1e-3
+        hbm["counted"] = counted
+        hbm["counted_gbs_s_e_f"] = tb / tt / 1e9
+        hbm["counted_note"] = ("bytes from FETCH_SIZE and WRITE_SIZE (scaled by a plain copy) at "
+                               "the library's default launch shape; times from this run's events")
 
     # ---- 4. CPU oracle on a bounded sample
     cpu = None
@@ -302,6 +372,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": per_launch,
+        "hbm": hbm,
         "autotune": tuned or None,
         "graph_no_events": graph,
         "mixed": mixed,

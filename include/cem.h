@@ -55,6 +55,8 @@ enum {
 enum { CEM_FP64 = 0, CEM_MIXED = 1 };          /* force arithmetic precision */
 enum { CEM_PHANTOM = 0, CEM_ERODE = 1 };       /* what a split does to the tet */
 enum { CEM_GSIG_PRINCIPAL = 0, CEM_GSIG_NORMAL = 1 };
+/* what the tet element force pass hands to the node pass (cem_set_launch) */
+enum { CEM_LAYOUT_TERMS = 0, CEM_LAYOUT_STRESS_SUMS = 1 };
 
 typedef struct cem_ctx cem_ctx;
 
@@ -218,14 +220,22 @@ int cem_critical_dt_instances(cem_ctx* ctx, double* dt_crit);
 int cem_read_energy_instances(cem_ctx* ctx, int32_t n, cem_energy* out);
 
 /* Launch shape of the step passes: persistent grid size (a positive multiple
- * of 8 workgroups) and lanes per node in the node pass (4, 8 or 16).  The
- * lane count sets the order of the node sums, hence the rounding. */
-int cem_set_launch(cem_ctx* ctx, int32_t grid_cap, int32_t lanes);
+ * of 8 workgroups), lanes per node in the node pass (4, 8 or 16) and the tet
+ * force layout: CEM_LAYOUT_TERMS (default) stores the four nodal terms
+ * (f/36) G_l^T s of each tet (s = sum of its six edge stresses, G_l = 6 V grad
+ * N_l, Eq. fint_discretization in its element form) at the node-list
+ * positions; CEM_LAYOUT_STRESS_SUMS stores (f/36) s once per tet and the node
+ * pass forms G_l^T from the corner coordinates.  The same forces either way,
+ * up to rounding; which is faster depends on the mesh size and precision.
+ * Hexahedra always use per-hex stress sums and ignore the layout.  Lanes and
+ * layout set the order of the node sums, hence the rounding. */
+int cem_set_launch(cem_ctx* ctx, int32_t grid_cap, int32_t lanes, int32_t layout);
 /* Autotuner of the launch shape: times trial_steps steps of the live
- * simulation for each candidate (grid 1024..8192 x lanes 4, 8, 16), restores
- * the state after every trial and keeps the fastest (any output may be NULL). */
+ * simulation for each candidate (layout x grid 1024..8192 x lanes 4, 8, 16),
+ * restores the state after every trial and keeps the fastest (any output may
+ * be NULL). */
 int cem_autotune(cem_ctx* ctx, int32_t trial_steps, int32_t* best_grid, int32_t* best_lanes,
-                 double* best_ms_per_step);
+                 int32_t* best_layout, double* best_ms_per_step);
 
 /* ---- Heterogeneous modulus and fixed-topology gradient windows
  *

@@ -334,6 +334,11 @@ void rebuild_masses(orc_ctx* c) {
     for (int l = 0; l < e.nn; ++l) c->m[e.n[l]] += c->rho * e.Veff / e.nn;
 }
 
+// Acceleration of node i under the net force g: g / m_i.  A node that no
+// element holds has no mass, no internal force and no load; it is given zero
+// acceleration and so keeps its velocity.
+double accel(const orc_ctx* c, size_t i, double g) { return c->m[i] > 0 ? g / c->m[i] : 0.0; }
+
 // Smoothed strain and stress of every edge (Eqs. strain_discretization and
 // CSTet_strain_discretization): eps_k = sum_j w_jk B_j u_j with
 // w_jk = V_j / sum V over the elements sharing edge k; sigma_k = C eps_k.
@@ -600,7 +605,7 @@ int initialize(orc_ctx* c) {
   internal_force(c, c->u, f);
   double r = ramp(c, t);
   for (size_t i = 0; i < c->X.size(); ++i)
-    for (int d = 0; d < 3; ++d) c->a[i][d] = (r * c->F[i][d] - f[i][d]) / c->m[i];
+    for (int d = 0; d < 3; ++d) c->a[i][d] = accel(c, i, r * c->F[i][d] - f[i][d]);
   apply_bc(c, t, c->u, false);
   bc_reactions(c, f, r, c->bc_R);
   c->need_init = false;
@@ -677,7 +682,7 @@ void one_step(orc_ctx* c) {
   std::vector<V3> u0 = c->u;
   for (size_t i = 0; i < N; ++i) {
     for (int d = 0; d < 3; ++d) {
-      double an1 = (rn1 * c->F[i][d] - f[i][d]) / c->m[i];
+      double an1 = accel(c, i, rn1 * c->F[i][d] - f[i][d]);
       c->W += 0.5 * (rn + rn1) * c->F[i][d] * (u1[i][d] - c->u[i][d]);
       c->v[i][d] = c->v[i][d] + 0.5 * dt * (c->a[i][d] + an1);
       c->a[i][d] = an1;

@@ -22,6 +22,7 @@ ERROR_NAMES = {-1: "CEM_EINVAL", -2: "CEM_ENOMEM", -3: "CEM_EHIP", -4: "CEM_EMES
 PRECISION = {"fp64": 0, "mixed": 1}
 SPLIT_MODE = {"phantom": 0, "erode": 1}
 GSIG = {"principal": 0, "normal": 1}
+LAYOUT = {"terms": 0, "stress_sums": 1}
 
 EXPORTS = [
     "cem_create", "cem_destroy", "cem_last_error", "cem_upload_mesh", "cem_upload_hex_mesh",
@@ -113,9 +114,9 @@ def load_library(path=LIB_PATH):
         "cem_set_dt_instances": [p, p],
         "cem_critical_dt_instances": [p, p],
         "cem_read_energy_instances": [p, i32, p],
-        "cem_set_launch": [p, i32, i32],
+        "cem_set_launch": [p, i32, i32, i32],
         "cem_autotune": [p, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                         C.POINTER(C.c_double)],
+                         C.POINTER(C.c_int32), C.POINTER(C.c_double)],
         "cem_set_modulus": [p, i32, p],
         "cem_set_step": [p, i64],
         "cem_add_velocity_bc": [p, i32, p, p, p, d, C.POINTER(C.c_int32)],
@@ -341,14 +342,16 @@ class Simulation:
                                                      C.cast(arr, C.c_void_p)))
         return [{k: getattr(e, k) for k, _ in cem_energy._fields_} for e in arr]
 
-    def set_launch(self, grid_cap, lanes):
-        self._chk(self.lib.cem_set_launch(self.ctx, int(grid_cap), int(lanes)))
+    def set_launch(self, grid_cap, lanes, layout="terms"):
+        """Launch shape; layout "terms" or "stress_sums" (tet force hand-over)."""
+        self._chk(self.lib.cem_set_launch(self.ctx, int(grid_cap), int(lanes), LAYOUT[layout]))
 
     def autotune(self, trial_steps=10):
-        g, l, ms = C.c_int32(), C.c_int32(), C.c_double()
+        g, l, lay, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         self._chk(self.lib.cem_autotune(self.ctx, int(trial_steps), C.byref(g), C.byref(l),
-                                        C.byref(ms)))
-        return dict(grid_cap=g.value, lanes=l.value, ms_per_step=ms.value)
+                                        C.byref(lay), C.byref(ms)))
+        name = {v: k for k, v in LAYOUT.items()}[lay.value]
+        return dict(grid_cap=g.value, lanes=l.value, layout=name, ms_per_step=ms.value)
 
     # ---- heterogeneous modulus and gradient windows
     def set_modulus(self, E_tet):

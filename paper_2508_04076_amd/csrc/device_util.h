@@ -186,6 +186,19 @@ __device__ __forceinline__ void hooke(R lam, R mu, const R* eps, R* sig) {
   sig[5] = mu * eps[5];
 }
 
+// Weighted stress sum of element e: s_e = (f / 36) sum_{k in edges(e)} sigma_k
+// (f = V_eff / V), so that the nodal term is c_{e,l} = G_l^T s_e.
+template <class R>
+__device__ __forceinline__ void elem_ssum(const Mesh& m, int e, int code,
+                                          const Six<R>* __restrict__ esig, R sg[6]) {
+  int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
+  Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
+  Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
+  const R w = (R)(frac_of(code) / 36.0);
+#pragma unroll
+  for (int r = 0; r < 6; ++r) sg[r] = w * (s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r]);
+}
+
 // Nodal terms of element e: c_{e,l} = (V_eff / 6) B_l^T sum_{k in edges(e)} sigma_k
 // = (f / 36) G_l^T s with G_l = 6 V grad N_l (G_0 = -(G_1 + G_2 + G_3)).
 template <class R>
@@ -267,6 +280,42 @@ __device__ __forceinline__ void store_terms(R* __restrict__ contrib, int4 pos, c
   put_term(contrib, pos.y, out[1][0], out[1][1], out[1][2]);
   put_term(contrib, pos.z, out[2][0], out[2][1], out[2][2]);
   put_term(contrib, pos.w, out[3][0], out[3][1], out[3][2]);
+}
+
+// Tetrahedra: node i's force from its (tet, local) entries, each term
+// G_l^T s_e formed from the tet's weighted stress sum s_e and
+// G_l = 6 V grad N_l = (X_b - X_a) x (X_c - X_a) over the face (a, b, c)
+// opposite corner l, oriented as G_1 = c2 x c3, G_2 = c3 x c1, G_3 = c1 x c2
+// (c_j = X_j - X_0) and G_0 = (X_3 - X_1) x (X_2 - X_1).  Coordinate
+// differences in float64; lanes and sum order as node_gather.
+template <class R, int G>
+__device__ __forceinline__ void node_gather_tet(const Mesh& m, const R* __restrict__ ts, int i,
+                                                bool active, int g, double& fx, double& fy,
+                                                double& fz) {
+  fx = fy = fz = 0;
+  const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
+  for (int p = p0 + g; p < p1; p += G) {
+    const int ent = m.nent[p], e = ent >> 2, l = ent & 3;
+    const int4 nd = m.enodes[e];
+    const int n0 = nd.x & kNodeMask;
+    const int na = l == 0 ? nd.y : n0;
+    const int nb = l == 0 ? nd.w : l == 1 ? nd.z : l == 2 ? nd.w : nd.y;
+    const int nc = l == 0 ? nd.z : l == 1 ? nd.w : l == 2 ? nd.y : nd.z;
+    const double4 xa = m.X[na], xb = m.X[nb], xc = m.X[nc];
+    Six<R> s = load6((const Six<R>*)ts + e);
+    const R bx = (R)(xb.x - xa.x), by = (R)(xb.y - xa.y), bz = (R)(xb.z - xa.z);
+    const R cx = (R)(xc.x - xa.x), cy = (R)(xc.y - xa.y), cz = (R)(xc.z - xa.z);
+    const R gx = by * cz - bz * cy, gy = bz * cx - bx * cz, gz = bx * cy - by * cx;
+    fx += (double)(gx * s.v[0] + gy * s.v[3] + gz * s.v[5]);
+    fy += (double)(gy * s.v[1] + gx * s.v[3] + gz * s.v[4]);
+    fz += (double)(gz * s.v[2] + gy * s.v[4] + gx * s.v[5]);
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    fx += __shfl_xor(fx, off, G);
+    fy += __shfl_xor(fy, off, G);
+    fz += __shfl_xor(fz, off, G);
+  }
 }
 
 // Hexahedra: node i's force from its (hex, local) entries, each term

@@ -139,9 +139,14 @@ __global__ __launch_bounds__(kBlock) void k_strain_energy(Mesh m, const Six<R>* 
 
 // Element force pass: for element e with effective volume fraction f,
 //   c_{e,l} = (V_eff / 6) B_l^T sum_{k in edges(e)} sigma_k = (f / 36) G_l^T s,
-// G_l = 6 V grad N_l (face cross products; G_0 = -(G_1 + G_2 + G_3)).  The
-// four 3-vectors (padded to 4) are stored at the element's positions in the
-// node lists (epos), so the node pass reads each node's terms contiguously.
+// G_l = 6 V grad N_l (face cross products).  Two layouts of what the node
+// pass receives (chosen per context, Mesh::ssum):
+//  - terms (default): the four 3-vectors at the element's positions in the
+//    node lists (epos), so the node pass reads each node's terms contiguously;
+//  - stress sums: s_e = (f / 36) s, one coalesced row per element, and the
+//    node pass forms G_l^T s_e itself from the corner coordinates.  Fewer
+//    bytes written, more gathered: faster where the coordinates and element
+//    rows stay in cache and the terms are wide (float64).
 // More tets flagged than split capacity left: raise the error before the
 // force passes touch the state, so it stays at the start of the step.
 __device__ __forceinline__ bool over_capacity(const Mesh& m, Counters* c) {
@@ -160,8 +165,14 @@ __device__ __forceinline__ void elem_force_items(const Mesh& m, const Six<R>* __
   for (int e; it.next(e);) {
   if (e >= Tn) continue;
   int4 nd = m.enodes[e];
-  int4 pos = m.epos[e];
   int code = (unsigned)nd.x >> kNodeBits;
+  if (m.ssum) {
+    R sg[6] = {0, 0, 0, 0, 0, 0};
+    if (code != FR_ZERO) elem_ssum(m, e, code, esig, sg);
+    store6((Six<R>*)contrib + e, sg);
+    continue;
+  }
+  int4 pos = m.epos[e];
   R out[4][3];
   if (code == FR_ZERO) {
 #pragma unroll
@@ -212,7 +223,8 @@ __device__ __forceinline__ void bc_override(const Mesh& m, int b, double t, doub
 // Node pass: G lanes per node sum the node's contributions (lane g takes
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
-template <class R, int MODE, int G, bool BC, bool HX>
+// KIND: 0 = contiguous terms, 1 = hex stress sums, 2 = tet stress sums
+template <class R, int MODE, int G, bool BC, int KIND>
 __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st, const R* __restrict__ contrib,
                                                  double4* __restrict__ fout,
                                                  Counters* __restrict__ c) {
@@ -224,7 +236,8 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st,
   const int i = item / G;
   const bool active = i < Nn;
   double fx, fy, fz;
-  if (HX) node_gather_hex<R, G>(m, contrib, i, active, g, fx, fy, fz);
+  if (KIND == 1) node_gather_hex<R, G>(m, contrib, i, active, g, fx, fy, fz);
+  else if (KIND == 2) node_gather_tet<R, G>(m, contrib, i, active, g, fx, fy, fz);
   else node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
   if (!active || g != 0) continue;
   if (MODE == NODE_FORCE) {
@@ -1278,29 +1291,34 @@ hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, 
   return hipGetLastError();
 }
 
-template <class R, int G, bool HX>
+template <class R, int G, int KIND>
 static void launch_node_kind(const Mesh& m, const State& st, const R* ct, Counters* c, int mode,
                              double4* fout, hipStream_t s) {
   dim3 g(persistent_grid(m, (long long)m.N_cap * G)), b(kBlock);
   // constrained nodes take their own kernel variant, so that a mesh without
   // prescribed velocities pays nothing for them
   if (mode == NODE_FORCE)
-    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false, HX>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c);
   else if (mode == NODE_INIT && m.n_bc)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true, HX>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true, KIND>), g, b, 0, s, m, st, ct, fout, c);
   else if (mode == NODE_INIT)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false, HX>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c);
   else if (m.n_bc)
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true, HX>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true, KIND>), g, b, 0, s, m, st, ct, fout, c);
   else
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false, HX>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c);
 }
 
 template <class R, int G>
 static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
                               Counters* c, int mode, double4* fout, hipStream_t s) {
-  if (CEM_HEX_GATHER && m.etype == 8) launch_node_kind<R, G, true>(m, st, ct, c, mode, fout, s);
-  else launch_node_kind<R, G, false>(m, st, ct, c, mode, fout, s);
+  if (m.etype == 8) {
+    if (CEM_HEX_GATHER) launch_node_kind<R, G, 1>(m, st, ct, c, mode, fout, s);
+    else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);
+  } else {
+    if (m.ssum) launch_node_kind<R, G, 2>(m, st, ct, c, mode, fout, s);
+    else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);
+  }
 }
 
 template <class R>

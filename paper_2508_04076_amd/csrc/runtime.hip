@@ -1095,6 +1095,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   m.dt = 0;
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
+  m.ssum = 0;
   m.n_inst = 0;
   m.etype = 4;
   m.inst = m.tinst = m.einst = nullptr;
@@ -1315,6 +1316,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.Gc = INFINITY;
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
+  m.ssum = 0;
   m.n_inst = 0;
   m.etype = 8;
   {
@@ -1824,25 +1826,28 @@ int cem_critical_dt_instances(cem_ctx* c, double* out) {
   return sync(c);
 }
 
-int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes) {
+int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes, int32_t layout) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
   c->gen++;
   if (grid_cap < 8 || grid_cap % 8 || (lanes != 4 && lanes != 8 && lanes != 16))
     return c->fail(CEM_EINVAL, "grid_cap must be a positive multiple of 8, lanes 4, 8 or 16");
+  if (layout != CEM_LAYOUT_TERMS && layout != CEM_LAYOUT_STRESS_SUMS)
+    return c->fail(CEM_EINVAL, "layout must be CEM_LAYOUT_TERMS or CEM_LAYOUT_STRESS_SUMS");
   c->m.grid_cap = grid_cap;
   c->m.lanes = lanes;
+  c->m.ssum = c->m.etype == 8 ? 0 : layout;
   drop_graph(c);
   return CEM_OK;
 }
 
 // Launch-shape autotuner: times trial_steps steps of the live simulation for
-// each candidate (persistent grid size x lanes per node), restoring the state
-// after every trial, and keeps the fastest.  Lanes change the order of the
-// node sums, hence the rounding of the results.
+// each candidate (force layout x persistent grid size x lanes per node),
+// restoring the state after every trial, and keeps the fastest.  Lanes and
+// layout change the order of the node sums, hence the rounding of the results.
 int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* best_lanes,
-                 double* best_ms) {
+                 int32_t* best_layout, double* best_ms) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, true);
   if (r) return r;
@@ -1853,34 +1858,40 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
   if ((r = cem_save_state(c, buf.data(), used, &used))) return r;
   const int grids[4] = {1024, 2048, 4096, 8192};
   const int lanes[3] = {4, 8, 16};
-  int g0 = c->m.grid_cap, l0 = c->m.lanes;
+  const int nlay = c->m.etype == 8 ? 1 : 2;  // hexes have one layout
+  int g0 = c->m.grid_cap, l0 = c->m.lanes, s0 = c->m.ssum;
   double best = 1e300;
-  int bg = g0, bl = l0;
+  int bg = g0, bl = l0, bs = s0;
   int saved_prof = c->profiling;
   c->profiling = 0;
   // one warm-up trial, then every candidate
   if ((r = cem_step(c, trial_steps)) == CEM_OK) r = cem_load_state(c, buf.data(), used);
-  for (int gi = 0; gi < 4 && r == CEM_OK; ++gi)
-    for (int li = 0; li < 3 && r == CEM_OK; ++li) {
-      c->m.grid_cap = grids[gi];
-      c->m.lanes = lanes[li];
-      drop_graph(c);
-      if ((r = cem_step(c, trial_steps))) break;
-      double ms = c->times[0] / trial_steps;
-      if (ms < best) {
-        best = ms;
-        bg = grids[gi];
-        bl = lanes[li];
+  for (int si = 0; si < nlay && r == CEM_OK; ++si)
+    for (int gi = 0; gi < 4 && r == CEM_OK; ++gi)
+      for (int li = 0; li < 3 && r == CEM_OK; ++li) {
+        c->m.grid_cap = grids[gi];
+        c->m.lanes = lanes[li];
+        c->m.ssum = si;
+        drop_graph(c);
+        if ((r = cem_step(c, trial_steps))) break;
+        double ms = c->times[0] / trial_steps;
+        if (ms < best) {
+          best = ms;
+          bg = grids[gi];
+          bl = lanes[li];
+          bs = si;
+        }
+        r = cem_load_state(c, buf.data(), used);
       }
-      r = cem_load_state(c, buf.data(), used);
-    }
   c->profiling = saved_prof;
   c->m.grid_cap = r ? g0 : bg;
   c->m.lanes = r ? l0 : bl;
+  c->m.ssum = r ? s0 : bs;
   drop_graph(c);
   if (r) return r;
   if (best_grid) *best_grid = bg;
   if (best_lanes) *best_lanes = bl;
+  if (best_layout) *best_layout = bs;
   if (best_ms) *best_ms = best;
   return CEM_OK;
 }

@@ -105,9 +105,43 @@ def test_mesh_errors_found_on_the_host(lib):
     t5 = m.tets.copy()
     t5[0, 0] = 10 ** 6
     assert _upload(lib, m.X, t5)[0] == cem.CEM_EMESH
+    # empty inputs and a non-finite coordinate
+    none = np.zeros((0, 4), np.int32)
+    assert _upload(lib, m.X, none)[0] == cem.CEM_EINVAL
+    assert _upload(lib, m.X[:3], m.tets[:0])[0] == cem.CEM_EINVAL
+    X6 = m.X.copy()
+    X6[3, 1] = np.nan
+    r, msg = _upload(lib, X6, m.tets)
+    assert r == cem.CEM_EINVAL and b"finite" in msg
     # bad material
     assert _upload(lib, m.X, m.tets, dict(E=-1.0, nu=0.2, rho=1.0, Gc=1.0))[0] == cem.CEM_EINVAL
     assert _upload(lib, m.X, m.tets, dict(E=1.0, nu=0.5, rho=1.0, Gc=1.0))[0] == cem.CEM_EINVAL
+
+
+def test_hex_mesh_errors_found_on_the_host(lib):
+    m = mg.hex_box(2, 2, 2)
+
+    def up(X, h):
+        r, ctx = _create(lib, max_splits=0)
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        h = np.ascontiguousarray(h, dtype=np.int32)
+        mat = cem.cem_material(E=32e9, nu=0.2, rho=2450.0, Gc=3.0)
+        r = lib.cem_upload_hex_mesh(ctx, len(X), X.ctypes.data_as(C.c_void_p), len(h),
+                                    h.ctypes.data_as(C.c_void_p), C.byref(mat))
+        msg = lib.cem_last_error(ctx)
+        lib.cem_destroy(ctx)
+        return r, msg
+
+    assert up(m.X, m.hexes[:0])[0] == cem.CEM_EINVAL
+    h = m.hexes.copy()
+    h[0, 0] = len(m.X)
+    assert up(m.X, h)[0] == cem.CEM_EMESH
+    # a degenerate hexahedron (two corners merged); a wholly inverted one is
+    # mirrored, not refused
+    h = m.hexes.copy()
+    h[0, 6] = h[0, 0]
+    r, msg = up(m.X, h)
+    assert r == cem.CEM_EMESH and b"hexahedron" in msg
 
 
 def test_valid_mesh_needs_a_device(lib):

@@ -1,0 +1,107 @@
+"""The stress-sum force layout (the element pass hands (f/36) sum sigma per tet
+to the node pass, which forms G_l^T s itself) against the oracle and against
+the default term layout, through the C-ABI.
+
+Tolerances as the other parity tests: FP64 forces 1e-12 normwise relative,
+FP64 trajectories 1e-9 relative L2 after splitting, identical split events;
+mixed precision 1e-5 on forces.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2508_04076_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+MAT = dict(mg.BRANCHING_MATERIAL)
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _sim(mesh, layout="stress_sums", lanes=8, **kw):
+    from paper_2508_04076_amd.cem import Simulation
+    kw.setdefault("max_splits", max(mesh.n_tets // 4, 64))
+    sim = Simulation.from_mesh(mesh, MAT, **kw)
+    sim.set_launch(1024, lanes, layout)
+    return sim
+
+
+@pytest.mark.parametrize("name", ["cube10_notched", "jitter5"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_parity(name, precision):
+    _case(f"stress-sum layout force parity {name} {precision}")
+    if name == "cube10_notched":
+        mesh = mg.cube_notched(10)
+    else:
+        mesh = mg.cube_notched(5)
+        mesh.X = mg.jitter(mg.kuhn_box(5, 5, 5), 0.2, seed=0).X
+    sim = _sim(mesh, precision=precision)
+    orc = Oracle.from_mesh(mesh, MAT)
+    for seed in range(2):
+        u = mg.random_displacement(sim.n_nodes, 1e-6, seed=seed)
+        err = _rel(sim.internal_force(u), orc.internal_force(u))
+        assert err < (1e-12 if precision == "fp64" else 1e-5), err
+    sim.close()
+
+
+@pytest.mark.parametrize("mode", ["phantom", "erode"])
+def test_split_events(mode):
+    _case(f"stress-sum layout split events cube 6 {mode}")
+    mesh = mg.cube_notched(6)
+    sim = _sim(mesh, split_mode=mode, lanes=4)
+    orc = Oracle.from_mesh(mesh, MAT, split_mode=mode)
+    dt = 0.5 * orc.critical_dt()
+    sim.set_dt(dt)
+    orc.set_dt(dt)
+    for _ in range(4):
+        sim.step(60)
+        orc.step(60)
+    eg, Gg = sim.splits()
+    eo, Go = orc.splits()
+    assert np.array_equal(eg, eo)
+    dyn = eo[:, 3] > 0
+    assert dyn.sum() > 0
+    assert np.allclose(Gg[dyn], Go[dyn], rtol=1e-9, atol=0)
+    ug, vg, _ = sim.get_state()
+    uo, vo, _ = orc.get_state()
+    assert _rel(ug, uo) < 1e-9 and _rel(vg, vo) < 1e-9
+    sim.close()
+
+
+def test_layouts_agree_on_the_plate():
+    # the 768k-tet plate, ramped load, through the onset of dynamic splitting
+    _case("plate 768k: stress-sum vs term layout, 500 steps, graphs")
+    mesh = mg.plate_notched()
+    out = {}
+    for layout in ("terms", "stress_sums"):
+        sim = _sim(mesh, layout=layout, lanes=4, ramp_t0=1e-6, max_splits=96000, graph_steps=50)
+        sim.set_dt(0.5 * sim.critical_dt())
+        sim.step(500)
+        out[layout] = (sim.get_state()[0], sim.splits()[0])
+        sim.close()
+    (ua, ea), (ub, eb) = out["terms"], out["stress_sums"]
+    assert np.array_equal(ea, eb) and (ea[:, 3] > 0).any()
+    assert _rel(ub, ua) < 1e-10
+
+
+def test_hexes_ignore_the_layout():
+    _case("hex: layout ignored")
+    from paper_2508_04076_amd.cem import Simulation
+    mesh = mg.add_tension(mg.jitter(mg.hex_box(4, 3, 3), 0.2, seed=5), 1, 1e6)
+    us = []
+    for layout in ("terms", "stress_sums"):
+        sim = Simulation.from_hex_mesh(mesh, MAT)
+        sim.set_launch(1024, 8, layout)
+        sim.set_dt(0.5 * sim.critical_dt())
+        sim.step(30)
+        us.append(sim.get_state()[0])
+        sim.close()
+    assert np.array_equal(us[0], us[1])
