@@ -7,13 +7,16 @@ A step is the whole hot path: strain pass, edge stress pass, crack-front pass
 with flag compaction, node force + Newmark pass, topology update.
 
 Prints one JSON line (rank 0).  Phases:
-  1. FP64 run, plain launches with per-pass HIP events: warmup, then the timed
-     region of --steps steps (value, ms_per_step, per-pass durations, roofline
-     of the dominant pass);
-  2. the same region length as captured HIP graphs without events (reported
-     as "graph_no_events");
-  3. mixed precision with the FP64 split schedule replayed: throughput and
-     relative L2 error of u against the FP64 run;
+  0. the library's autotuner picks the launch shape (force layout, grid,
+     lanes) on a warmed-up copy;
+  1. FP64 run, plain launches with per-pass HIP events on the library's
+     stream: warmup, then --steps steps (per-pass durations and the roofline
+     of the dominant pass; reported as "per_pass_run");
+  2. the same steps as captured HIP graphs without events: the timed region
+     of value and ms_per_step (tet-steps/s over graph replays), bitwise equal
+     to run 1;
+  3. mixed precision with the FP64 split schedule replayed (its own tuned
+     shape): throughput and relative L2 error of u against the FP64 run;
   4. the CPU oracle on a bounded sample (cpu_baseline).
 """
 from __future__ import annotations
@@ -188,6 +191,8 @@ def main():
     T = mesh.n_tets
     log(f"workload {args.workload}: {T} tets, {mesh.n_nodes} nodes")
     K, W = args.steps, args.warmup
+    if not args.no_graph:
+        W = max(W, args.graph_steps)  # the first graph is captured in the warm-up
     max_splits = max(T // 8, len(mesh.presplit_tets) + 20000)
 
     tuned = {}
@@ -220,7 +225,9 @@ def main():
         sim.close()
         sim = make("fp64", 0)
 
-    # ---- 1. FP64, plain launches with per-pass HIP events (the timed region)
+    # ---- 1. FP64, plain launches with per-pass HIP events on the library's
+    # stream: the kernel times of the roofline (and the timed region when
+    # graphs are off)
     sim.set_dt(dt)
     log(f"dt = {dt:.6e} s; warmup {W} steps")
     sim.set_profiling(True)
@@ -239,14 +246,14 @@ def main():
     u64, _, _ = sim.get_state()
     e64 = sim.energy()
     ev64, _ = sim.splits()
-    value = T * K / wall
     log(f"fp64 (plain launches, per-pass events): "
-        f"{wall * 1e3 / K:.4f} ms/step, {value:.4e} tet-steps/s, splits {e64['n_split']}")
+        f"{wall * 1e3 / K:.4f} ms/step, {T * K / wall:.4e} tet-steps/s, splits {e64['n_split']}")
     per_launch = {k: kt[k] / K for k in ("strain", "edge_stress", "front", "elem_force",
                                           "node_sum", "node", "topology")}
     sim.close()
 
-    # ---- 2. FP64 as captured HIP graphs without events, same region length
+    # ---- 2. FP64 as captured HIP graphs without events, same steps: the
+    # timed region of `value` (tet-steps/s over graph replays)
     graph = None
     if not args.no_graph and gs > 0:
         g = make("fp64", gs)
@@ -260,7 +267,7 @@ def main():
         ug, _, _ = g.get_state()
         graph = {"ms_per_step": gw * 1e3 / K, "tet_steps_per_s": T * K / gw,
                  "graph_steps": gs,
-                 "bitwise_equal_to_timed_run": bool(np.array_equal(ug, u64))}
+                 "bitwise_equal_to_per_pass_run": bool(np.array_equal(ug, u64))}
         log(f"fp64 graphs without events: {gw * 1e3 / K:.4f} ms/step, {T * K / gw:.4e} tet-steps/s")
         g.close()
 
@@ -313,11 +320,17 @@ def main():
     # ---- HBM GB/s of the step: model bytes x rate ("effective"), and counted
     # bytes (rocprofv3 counters of this source) over each pass's event time,
     # against the spec and a device copy measured here
+    per_pass_run = {"ms_per_step": wall * 1e3 / K, "tet_steps_per_s": T * K / wall,
+                    "launch": "plain launches with per-pass HIP events (the kernel times above)"}
+    if graph:
+        value, ms_step = graph["tet_steps_per_s"], graph["ms_per_step"]
+        launch_desc = f"HIP graphs of {gs} steps, no events"
+    else:
+        value, ms_step = per_pass_run["tet_steps_per_s"], per_pass_run["ms_per_step"]
+        launch_desc = per_pass_run["launch"]
     hbm = {"spec_gbs": HBM_PEAK_GBS, "copy_peak_gbs": copy_peak_gbs(),
            "effective_gbs_fp64": sum(ALG_BYTES["fp64"].values()) * value / 1e9,
            "alg_bytes_per_tet_fp64": sum(ALG_BYTES["fp64"].values())}
-    if graph:
-        hbm["effective_gbs_fp64_graphs"] = sum(ALG_BYTES["fp64"].values()) * graph["tet_steps_per_s"] / 1e9
     if mixed:
         hbm["effective_gbs_mixed"] = sum(ALG_BYTES["mixed"].values()) * mixed["tet_steps_per_s"] / 1e9
     if cnt and cnt.get("workload") == args.workload and \
@@ -364,17 +377,17 @@ def main():
 
     out = {
         "metric": METRIC, "value": value, "unit": "tet-steps/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": wall * 1e3 / K, "higher_is_better": True,
+        "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "tets": T, "nodes": mesh.n_nodes,
                    "dt_s": dt, "splits_after_run": int(e64["n_split"]),
-                   "launch": "plain launches with per-pass HIP events"},
+                   "launch": launch_desc},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": per_launch,
         "hbm": hbm,
         "autotune": tuned or None,
-        "graph_no_events": graph,
+        "per_pass_run": per_pass_run,
         "mixed": mixed,
     }
     if reaction:
@@ -396,8 +409,12 @@ def bench_ensemble(args):
     T = un.n_tets
     log(f"ensemble: 64 plates, {T} tets, {un.n_nodes} nodes, precision {prec}")
     K, W = args.steps, args.warmup
+    if not args.no_graph:
+        W = max(W, args.graph_steps)  # the first graph is captured in the warm-up
     gs = 0 if args.no_graph else args.graph_steps
-    sim = Simulation(un.X, un.tets, mat, precision=prec, max_splits=T // 8, graph_steps=gs)
+    # every tet splits at most once: capacity T can never run out, however far
+    # the high-traction members fragment
+    sim = Simulation(un.X, un.tets, mat, precision=prec, max_splits=T, graph_steps=gs)
     sim.set_instances(node_off, tet_off)
     sim.set_traction(un.load_tris, un.load_trac, 1e-6)
     sim.presplit(un.presplit_tets, un.presplit_masks)
@@ -591,6 +608,8 @@ def bench_hex(args):
                 "1 MPa traction ramped over 1 us, no splitting")
     H = mesh.n_hex
     K, W = args.steps, args.warmup
+    if not args.no_graph:
+        W = max(W, args.graph_steps)  # the first graph is captured in the warm-up
     log(f"hex workload {args.workload}: {H} hexes, {mesh.n_nodes} nodes")
     out_runs = {}
     for prec in ("fp64", "mixed"):
@@ -648,20 +667,22 @@ def bench_hex(args):
         cpu = {"value": H * n_cpu / el, "unit": "hex-steps/s", "cores": 1, "kind": "oracle",
                "sample": f"{n_cpu} steps of the same hex workload after one warm-up step "
                          f"(single-threaded FP64 oracle, {el:.1f} s)"}
+    timed = out_runs.get(("fp64", True), base)
     out = {
         "metric": "hex-steps/sec (ES-H-FEM), FP64 and FP32-mixed",
-        "value": base["hex_steps_per_s"], "unit": "hex-steps/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": base["ms_per_step"], "higher_is_better": True,
+        "value": timed["hex_steps_per_s"], "unit": "hex-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": timed["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "hexes": H, "nodes": mesh.n_nodes, "dt_s": base["dt_s"],
-                   "launch": "plain launches with per-pass HIP events"},
+                   "launch": (f"HIP graphs of {args.graph_steps} steps, no events"
+                              if timed is not base else "plain launches with per-pass HIP events")},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "alg_bytes_per_hex": HEX_BYTES["fp64"][dom],
                      "avg_launch_ms": per[dom]},
         "kernels_ms_per_step": per,
-        "graph_no_events": {"hex_steps_per_s": out_runs.get(("fp64", True), {}).get("hex_steps_per_s"),
-                            "ms_per_step": out_runs.get(("fp64", True), {}).get("ms_per_step")},
+        "per_pass_run": {"hex_steps_per_s": base["hex_steps_per_s"], "ms_per_step": base["ms_per_step"],
+                         "launch": "plain launches with per-pass HIP events (the kernel times above)"},
         "mixed": mixed,
         "cpu_baseline": cpu,
     }

@@ -343,7 +343,8 @@ class Simulation:
         return [{k: getattr(e, k) for k, _ in cem_energy._fields_} for e in arr]
 
     def set_launch(self, grid_cap, lanes, layout="terms"):
-        """Launch shape; layout "terms" or "stress_sums" (tet force hand-over)."""
+        """Launch shape; layout "terms" or "stress_sums" (what the tet force
+        pass hands to the node pass)."""
         self._chk(self.lib.cem_set_launch(self.ctx, int(grid_cap), int(lanes), LAYOUT[layout]))
 
     def autotune(self, trial_steps=10):

@@ -54,8 +54,9 @@ struct Mesh {
   double umax;              // runaway bound on |u|
   int grid_cap;             // workgroups of the persistent step launches (multiple of 8)
   int lanes;                // lanes per node in the node pass (4, 8 or 16)
-  int ssum;                 // tets: 1 = force pass hands per-tet stress sums to the node
-                            // pass, 0 = nodal terms at node-list positions
+  int ssum;                 // tets: what the force pass hands to the node pass: 0 = nodal
+                            // terms at node-list positions, 1 = per-tet stress sums (the
+                            // node pass forms G_l from the corner coordinates)
   int n_inst;               // independent instances of a batch (0: one simulation)
   int etype;                // nodes per element: 4 (tetrahedra) or 8 (hexahedra)
 

@@ -1,6 +1,6 @@
 """The stress-sum force layout (the element pass hands (f/36) sum sigma per tet
-to the node pass, which forms G_l^T s itself) against the oracle and against
-the default term layout, through the C-ABI.
+to the node pass, which forms G_l^T s itself from the corner coordinates)
+against the oracle and against the default term layout, through the C-ABI.
 
 Tolerances as the other parity tests: FP64 forces 1e-12 normwise relative,
 FP64 trajectories 1e-9 relative L2 after splitting, identical split events;
@@ -34,16 +34,20 @@ def _sim(mesh, layout="stress_sums", lanes=8, **kw):
     return sim
 
 
+LAYOUTS = ["stress_sums"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name", ["cube10_notched", "jitter5"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_force_parity(name, precision):
-    _case(f"stress-sum layout force parity {name} {precision}")
+def test_force_parity(name, precision, layout):
+    _case(f"{layout} force parity {name} {precision}")
     if name == "cube10_notched":
         mesh = mg.cube_notched(10)
     else:
         mesh = mg.cube_notched(5)
         mesh.X = mg.jitter(mg.kuhn_box(5, 5, 5), 0.2, seed=0).X
-    sim = _sim(mesh, precision=precision)
+    sim = _sim(mesh, layout=layout, precision=precision)
     orc = Oracle.from_mesh(mesh, MAT)
     for seed in range(2):
         u = mg.random_displacement(sim.n_nodes, 1e-6, seed=seed)
@@ -52,11 +56,12 @@ def test_force_parity(name, precision):
     sim.close()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("mode", ["phantom", "erode"])
-def test_split_events(mode):
-    _case(f"stress-sum layout split events cube 6 {mode}")
+def test_split_events(mode, layout):
+    _case(f"{layout} split events cube 6 {mode}")
     mesh = mg.cube_notched(6)
-    sim = _sim(mesh, split_mode=mode, lanes=4)
+    sim = _sim(mesh, layout=layout, split_mode=mode, lanes=4)
     orc = Oracle.from_mesh(mesh, MAT, split_mode=mode)
     dt = 0.5 * orc.critical_dt()
     sim.set_dt(dt)
@@ -81,15 +86,48 @@ def test_layouts_agree_on_the_plate():
     _case("plate 768k: stress-sum vs term layout, 500 steps, graphs")
     mesh = mg.plate_notched()
     out = {}
-    for layout in ("terms", "stress_sums"):
+    for layout in ["terms"] + LAYOUTS:
         sim = _sim(mesh, layout=layout, lanes=4, ramp_t0=1e-6, max_splits=96000, graph_steps=50)
         sim.set_dt(0.5 * sim.critical_dt())
         sim.step(500)
         out[layout] = (sim.get_state()[0], sim.splits()[0])
         sim.close()
-    (ua, ea), (ub, eb) = out["terms"], out["stress_sums"]
-    assert np.array_equal(ea, eb) and (ea[:, 3] > 0).any()
-    assert _rel(ub, ua) < 1e-10
+    ua, ea = out["terms"]
+    assert (ea[:, 3] > 0).any()
+    for layout in LAYOUTS:
+        ub, eb = out[layout]
+        assert np.array_equal(ea, eb) and _rel(ub, ua) < 1e-10, layout
+
+
+def test_checkpoint_and_layout_switch():
+    _case("stress_sums: checkpoint before the dynamic splits, restore, rerun, switch layout")
+    mesh = mg.cube_notched(6)
+    sim = _sim(mesh, lanes=4, graph_steps=20)
+    sim.set_dt(0.5 * sim.critical_dt())
+    sim.step(10)
+    buf = sim.save_state()
+    n0 = sim.counts()["splits"]
+    sim.step(200)
+    u1, e1 = sim.get_state()[0], sim.splits()[0]
+    assert len(e1) > n0  # the run split after the checkpoint
+    sim.load_state(buf)
+    sim.step(200)
+    assert np.array_equal(sim.get_state()[0], u1) and np.array_equal(sim.splits()[0], e1)
+    # a checkpoint taken after splits, restored into a fresh context
+    buf2 = sim.save_state()
+    sim.step(100)
+    u2 = sim.get_state()[0]
+    fresh = _sim(mesh, lanes=4, graph_steps=20)
+    fresh.load_state(buf2)
+    fresh.step(100)
+    assert np.array_equal(fresh.get_state()[0], u2)
+    fresh.close()
+    # switching layouts mid-run keeps the physics (rounding order aside)
+    sim.load_state(buf)
+    sim.set_launch(1024, 4, "terms")
+    sim.step(200)
+    assert np.array_equal(sim.splits()[0], e1) and _rel(sim.get_state()[0], u1) < 1e-10
+    sim.close()
 
 
 def test_hexes_ignore_the_layout():
