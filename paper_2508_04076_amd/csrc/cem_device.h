@@ -33,7 +33,7 @@ struct Counters {
   int replay_cursor;              // next entry of the forced schedule
   int ticket;                     // crack pass last-block ticket
   int n_sched;                    // forced schedule length (0: G test decides)
-  int pad;
+  int n_cand_dead;                // candidate-list entries whose tet has split since
   unsigned long long lam_key;     // ordered key of max element eigenvalue (setup)
   double dt_crit;
 };

@@ -11,6 +11,10 @@
 #ifndef CEM_EDGE_BATCH
 #define CEM_EDGE_BATCH 6
 #endif
+// fewest dead entries before the crack-front candidate list is compacted
+#ifndef CEM_CAND_COMPACT_MIN
+#define CEM_CAND_COMPACT_MIN 64
+#endif
 // hexahedra: 1 = the node pass forms the nodal terms from the per-hex stress
 // sum and G (gathered per node-list entry); 0 = the element pass writes them
 #ifndef CEM_HEX_GATHER

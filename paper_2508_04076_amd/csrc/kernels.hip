@@ -908,6 +908,62 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
           einvV[k] = !(part > 0) ? (R)0 : m.kap ? (R)(partk / part / part) : (R)(1.0 / part);
       }
     }
+    // the candidate list drops the tets that have split once they are the
+    // majority (and at least 64): an order-keeping compaction in place (each
+    // chunk is read in full before any of it is written, and writes land at or
+    // below it).  Its work over a run is at most twice the entries ever
+    // appended.
+    {
+      __shared__ int s_dead, s_nc, s_nd, s_wtot[kTopoBlock / 64], s_total;
+      if (tid == 0) s_dead = 0;
+      __syncthreads();
+      int dead = 0;
+      for (int i = tid; i < n; i += kTopoBlock) dead += m.candf[m.splitlist[i]] != 0;
+      if (dead) atomicAdd(&s_dead, dead);
+      __syncthreads();
+      // one thread reads the counters, so that every thread takes the same branch
+      if (tid == 0) {
+        s_nc = c->n_cand;
+        s_nd = c->n_cand_dead + s_dead;
+      }
+      __syncthreads();
+      const int nc = s_nc, nd_all = s_nd;
+      if (nd_all >= CEM_CAND_COMPACT_MIN && 2 * nd_all > nc) {
+        const int lane = tid & 63, wv = tid >> 6;
+        int out = 0;
+        for (int b0 = 0; b0 < nc; b0 += kTopoBlock) {
+          const int idx = b0 + tid;
+          const int t = idx < nc ? m.cand[idx] : -1;
+          const bool alive = t >= 0 && m.smask[t] < 0;
+          const unsigned long long bal = __ballot(alive);
+          const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+          if (lane == 0) s_wtot[wv] = __popcll(bal);
+          __syncthreads();
+          if (tid == 0) {
+            int acc = 0;
+            for (int w = 0; w < kTopoBlock / 64; ++w) {
+              const int x = s_wtot[w];
+              s_wtot[w] = acc;
+              acc += x;
+            }
+            s_total = acc;
+          }
+          __syncthreads();
+          if (alive) m.cand[out + s_wtot[wv] + pre] = t;
+          out += s_total;
+          __threadfence_block();
+          __syncthreads();
+        }
+        if (tid == 0) {
+          c->n_cand = out;
+          c->n_cand_dead = 0;
+        }
+      } else if (tid == 0) {
+        c->n_cand_dead = nd_all;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
     // phase 3: new crack fronts on intact face neighbours, one lane per face
     for (int item = tid; item < 4 * n; item += kTopoBlock) {
       const int i = item >> 2, f = item & 3;
