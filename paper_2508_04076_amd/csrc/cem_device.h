@@ -9,6 +9,10 @@ namespace cem {
 
 constexpr int kBlock = 256;          // 4 wave64 per workgroup
 constexpr int kTopoBlock = 1024;     // single-workgroup topology update
+#ifndef CEM_TOPO_INLINE
+#define CEM_TOPO_INLINE 128
+#endif
+constexpr int kTopoInline = CEM_TOPO_INLINE;  // larger batches sum masses and volumes in k_topo_sums
 constexpr int kDefaultLanes = 8;         // lanes per node in the node pass
 constexpr int kDefaultGridCap = 2048;    // workgroups of the persistent step launches
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
@@ -36,6 +40,8 @@ struct Counters {
   int n_cand_dead;                // candidate-list entries whose tet has split since
   unsigned long long lam_key;     // ordered key of max element eigenvalue (setup)
   double dt_crit;
+  int batch_base;                 // first split of a batch whose masses and edge
+  int batch_n;                    // volumes are left to k_topo_sums (0: none)
 };
 
 // Six float values of a symmetric tensor in Voigt order

@@ -706,6 +706,69 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Phase 2 of a split batch (global split indices base .. base + n): lumped
+// masses of the touched nodes (16 lanes per node list) and volumes of the
+// touched edges (8 lanes per patch), each a fixed-order group sum, so the
+// result does not depend on which threads run it.  Thread gtid of gthreads
+// (a multiple of 64).
+template <class R>
+__device__ void topo_sums(const Mesh& m, R* __restrict__ einvV, const int4* __restrict__ snodes,
+                          const int* __restrict__ sedges, int base, int n, int gtid, int gthreads) {
+  if (m.mode == MODE_PHANTOM) {
+    constexpr int GN = 16;
+    const int gl = gtid % GN;
+    for (int item = gtid / GN; item < 4 * n; item += gthreads / GN) {
+      int i = item >> 2, l = item & 3;
+      int4 q4 = snodes[i];
+      int node = l == 0 ? q4.x : l == 1 ? q4.y : l == 2 ? q4.z : q4.w;
+      double part = 0;
+      for (int p = m.noff[node] + gl; p < m.noff[node + 1]; p += GN) {
+        int e = m.nent[p] >> 2;
+        part += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
+      }
+      part = group_sum<GN>(part);
+      if (gl == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
+      if (gl == 1) {
+        int t = m.splitlist[i];
+        int mask = m.pmask[t];
+        int nbB = __popc(mask);
+        bool onB = (mask >> l) & 1;
+        // the extra node of l belongs to the copy of the other side
+        double fo = frac_of(code_for_side(onB ? 4 - nbB : nbB));
+        m.invm[m.N0 + 4 * (base + i) + l] = 1.0 / (m.rho * fo * m.vol[t] / 4.0);
+      }
+    }
+  }
+  constexpr int GE = 8;
+  const int gl = gtid % GE;
+  for (int item = gtid / GE; item < 6 * n; item += gthreads / GE) {
+    int k = sedges[item];
+    double part = 0, partk = 0;
+    for (int p = m.poff[k] + gl; p < m.poff[k + 1]; p += GE) {
+      int e = m.pent[p];
+      if (e < 0) continue;
+      double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+      part += ve;
+      if (m.kap) partk += ve * m.kap[e];
+    }
+    part = group_sum<GE>(part);
+    if (m.kap) partk = group_sum<GE>(partk);
+    if (gl == 0)
+      einvV[k] = !(part > 0) ? (R)0 : m.kap ? (R)(partk / part / part) : (R)(1.0 / part);
+  }
+}
+
+// Phase 2 of a large batch, over the whole chip, after k_topology.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_topo_sums(Mesh m, Work w, const Counters* __restrict__ c,
+                                                      const int4* __restrict__ snodes,
+                                                      const int* __restrict__ sedges) {
+  const int n = c->batch_n;
+  if (n == 0) return;
+  topo_sums<R>(m, (R*)w.einvV, snodes, sedges, c->batch_base, n,
+               (int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x));
+}
+
 // All splits of one step, applied by one workgroup in phases separated by
 // barriers.  Split i of this batch gets global index s = n_split + i; its
 // copy B takes element slot T0 + s, its extra nodes N0 + 4 s + l and its new
@@ -862,52 +925,9 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
     }
     __threadfence_block();
     __syncthreads();
-    // phase 2: lumped masses of touched nodes (16 lanes per node list) and
-    // volumes of touched edges (8 lanes per patch); fixed-order group sums
-    if (m.mode == MODE_PHANTOM) {
-      constexpr int GN = 16;
-      const int gl = tid % GN;
-      for (int item = tid / GN; item < 4 * n; item += kTopoBlock / GN) {
-        int i = item >> 2, l = item & 3;
-        int4 q4 = snodes[i];
-        int node = l == 0 ? q4.x : l == 1 ? q4.y : l == 2 ? q4.z : q4.w;
-        double part = 0;
-        for (int p = m.noff[node] + gl; p < m.noff[node + 1]; p += GN) {
-          int e = m.nent[p] >> 2;
-          part += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
-        }
-        part = group_sum<GN>(part);
-        if (gl == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
-        if (gl == 1) {
-          int t = m.splitlist[i];
-          int mask = m.pmask[t];
-          int nbB = __popc(mask);
-          bool onB = (mask >> l) & 1;
-          // the extra node of l belongs to the copy of the other side
-          double fo = frac_of(code_for_side(onB ? 4 - nbB : nbB));
-          m.invm[m.N0 + 4 * (base + i) + l] = 1.0 / (m.rho * fo * m.vol[t] / 4.0);
-        }
-      }
-    }
-    {
-      constexpr int GE = 8;
-      const int gl = tid % GE;
-      for (int item = tid / GE; item < 6 * n; item += kTopoBlock / GE) {
-        int k = sedges[item];
-        double part = 0, partk = 0;
-        for (int p = m.poff[k] + gl; p < m.poff[k + 1]; p += GE) {
-          int e = m.pent[p];
-          if (e < 0) continue;
-          double ve = frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
-          part += ve;
-          if (m.kap) partk += ve * m.kap[e];
-        }
-        part = group_sum<GE>(part);
-        if (m.kap) partk = group_sum<GE>(partk);
-        if (gl == 0)
-          einvV[k] = !(part > 0) ? (R)0 : m.kap ? (R)(partk / part / part) : (R)(1.0 / part);
-      }
-    }
+    // phase 2: masses and edge volumes touched by the batch, here for small
+    // batches, else by k_topo_sums after this kernel (nothing below reads them)
+    if (n <= kTopoInline) topo_sums<R>(m, einvV, snodes, sedges, base, n, tid, kTopoBlock);
     // the candidate list drops the tets that have split once they are the
     // majority (and at least 64): an order-keeping compaction in place (each
     // chunk is read in full before any of it is written, and writes land at or
@@ -993,6 +1013,8 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
         c->Ud = ud;
       }
       c->n_split = base + n;
+      c->batch_base = base;
+      c->batch_n = n > kTopoInline ? n : 0;
       if (advance) {
         c->step += 1;
         c->gmax_last = c->gmax_key;
@@ -1000,6 +1022,7 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       }
     }
     c->n_flag = 0;
+    if (c->err) c->batch_n = 0;
   }
   if (advance && m.n_inst) {
     for (int i = tid; i < m.n_inst; i += kTopoBlock) {
@@ -1455,6 +1478,8 @@ hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Coun
                              int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s) {
   hipLaunchKernelGGL(k_topology<R>, dim3(1), dim3(kTopoBlock), 0, s, m, st, w, c, dynamic, advance,
                      snodes, sedges);
+  if (m.etype != 8)  // hexahedra do not split
+    hipLaunchKernelGGL(k_topo_sums<R>, dim3(256), dim3(kBlock), 0, s, m, w, c, snodes, sedges);
   return hipGetLastError();
 }
 template hipError_t launch_topology_t<double>(const Mesh&, const State&, const Work&, Counters*,
