@@ -501,6 +501,16 @@ def bench_window(args):
     sim.set_dt(dt)
     n = sim.n_nodes
     zero = np.zeros((n, 3))
+    # launch shape (force layout, grid, lanes) for the forward and reverse passes
+    tuned = None
+    if args.launch:
+        g_, l_, lay_ = args.launch.split(",")
+        sim.set_launch(int(g_), int(l_), lay_)
+        tuned = {"grid_cap": int(g_), "lanes": int(l_), "layout": lay_}
+    elif not args.no_tune:
+        sim.step(every)
+        tuned = sim.autotune(trial_steps=10)
+        log(f"autotuned launch: {tuned}")
 
     def one(n_steps, profiled):
         sim.set_profiling(profiled)
@@ -551,6 +561,7 @@ def bench_window(args):
                      "avg_launch_ms": per[dom]},
         "reverse_kernels_ms_per_step": per,
         "reverse_kernels_gbs": rows,
+        "autotune": tuned,
         "cpu_baseline": cpu,
     }
     sim.close()

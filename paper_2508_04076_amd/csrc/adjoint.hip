@@ -79,8 +79,10 @@ __global__ __launch_bounds__(kBlock) void k_edge2(Mesh m, const Six<R>* __restri
   }
 }
 
-// Nodal terms of K lambda (as in the forward element pass) and the modulus
-// sensitivity of the element slot, accumulated over the reverse steps.
+// Nodal terms of K lambda (as in the forward element pass, in the context's
+// force layout: terms at node-list positions or per-element stress sums) and
+// the modulus sensitivity of the element slot, accumulated over the reverse
+// steps.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_elem_adj(Mesh m, const Six<R>* __restrict__ esig,
                                                      const R* __restrict__ z,
@@ -93,18 +95,26 @@ __global__ __launch_bounds__(kBlock) void k_elem_adj(Mesh m, const Six<R>* __res
   for (int e; it.next(e);) {
     if (e >= Tn) continue;
     int4 nd = m.enodes[e];
-    int4 pos = m.epos[e];
     int code = (unsigned)nd.x >> kNodeBits;
+    if (code != FR_ZERO) {
+      int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
+      double zs = (double)z[q01.x] + (double)z[q01.y] + (double)z[q23.x] + (double)z[q23.y] +
+                  (double)z[q45.x] + (double)z[q45.y];
+      gE[e] -= frac_of(code) * m.vol[e] / 6.0 * zs;
+    }
+    if (m.ssum) {
+      R sg[6] = {0, 0, 0, 0, 0, 0};
+      if (code != FR_ZERO) elem_ssum(m, e, code, esig, sg);
+      store6((Six<R>*)contrib + e, sg);
+      continue;
+    }
+    int4 pos = m.epos[e];
     R out[4][3];
     if (code == FR_ZERO) {
 #pragma unroll
       for (int l = 0; l < 4; ++l) out[l][0] = out[l][1] = out[l][2] = 0;
     } else {
       elem_terms(m, e, nd, code, esig, out);
-      int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
-      double zs = (double)z[q01.x] + (double)z[q01.y] + (double)z[q23.x] + (double)z[q23.y] +
-                  (double)z[q45.x] + (double)z[q45.y];
-      gE[e] -= frac_of(code) * m.vol[e] / 6.0 * zs;
     }
     store_terms(contrib, pos, out);
   }
@@ -113,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_elem_adj(Mesh m, const Six<R>* __res
 // Node update of one reverse step.  last: only p <- p - f (the initial
 // acceleration's term).  half: the new lambda's index is >= 1, so it also
 // holds dt/2 q from the step before it.
-template <class R, int G>
+template <class R, int G, bool SSUM>
 __global__ __launch_bounds__(kBlock) void k_node_adj(Mesh m, const R* __restrict__ contrib,
                                                      double4* __restrict__ p,
                                                      double4* __restrict__ q,
@@ -127,7 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_node_adj(Mesh m, const R* __restrict
     const int i = item / G;
     const bool active = i < Nn;
     double fx, fy, fz;
-    node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
+    if (SSUM) node_gather_tet<R, G>(m, contrib, i, active, g, fx, fy, fz);
+    else node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
     if (!active || g != 0) continue;
     double4 p0 = p[i];
     double px = p0.x - fx, py = p0.y - fy, pz = p0.z - fz;
@@ -205,8 +216,12 @@ hipError_t Adjoint<R>::elem(const Mesh& m, const void* esig, const void* z, void
 template <class R, int G>
 static void launch_node_adj(const Mesh& m, const R* ct, double4* p, double4* q, double4* lam,
                             int last, int half, const Counters* c, hipStream_t s) {
-  hipLaunchKernelGGL((k_node_adj<R, G>), dim3(persistent_grid(m, (long long)m.N_cap * G)),
-                     dim3(kBlock), 0, s, m, ct, p, q, lam, last, half, c);
+  if (m.ssum)
+    hipLaunchKernelGGL((k_node_adj<R, G, true>), dim3(persistent_grid(m, (long long)m.N_cap * G)),
+                       dim3(kBlock), 0, s, m, ct, p, q, lam, last, half, c);
+  else
+    hipLaunchKernelGGL((k_node_adj<R, G, false>), dim3(persistent_grid(m, (long long)m.N_cap * G)),
+                       dim3(kBlock), 0, s, m, ct, p, q, lam, last, half, c);
 }
 
 template <class R>

@@ -113,6 +113,32 @@ def test_window_gradient_parity(n, every):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_window_gradient_stress_sum_layout(precision):
+    # the reverse force pass in the stress-sum layout: the same gradients
+    _case(f"window gradient, stress-sum layout, {precision}")
+    mesh = mg.cube_notched(6)
+    E = mg.modulus_field(mesh.n_tets, MAT["E"], 0.1, seed=3)
+    dt = 6.0e-6
+    sim, orc, u0, v0 = _setup(mesh, E, dt, 5 * dt, seed=11, precision=precision)
+    sim.set_launch(1024, 8, "stress_sums")
+    rng = np.random.default_rng(12)
+    gu = rng.standard_normal(u0.shape)
+    gv = rng.standard_normal(u0.shape) * 1e-4
+    sim.window_forward(23, 5)
+    g_sim = sim.window_backward(gu, gv)
+    g_orc = orc.window_gradient(23, gu, gv)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    for a, b, name in zip(g_sim, g_orc, ["u0", "v0", "E"]):
+        assert _rel(a, b) < tol, (name, _rel(a, b))
+    u = np.random.default_rng(8).standard_normal(u0.shape) * 1e-6
+    _, gu2, gE2 = sim.strain_energy_grad(u)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert _rel(gE2, orc.strain_energy_grad(u)) < tol
+    assert _rel(gu2, orc.internal_force(u)) < tol
+    sim.close()
+
+
 def test_window_checkpoint_spacing_is_bitwise_neutral():
     _case("window checkpoint spacing")
     mesh = mg.cube_notched(6)
