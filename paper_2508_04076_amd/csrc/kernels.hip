@@ -709,36 +709,40 @@ __device__ __forceinline__ double group_sum(double v) {
 // Phase 2 of a split batch (global split indices base .. base + n): lumped
 // masses of the touched nodes (16 lanes per node list) and volumes of the
 // touched edges (8 lanes per patch), each a fixed-order group sum, so the
-// result does not depend on which threads run it.  Thread gtid of gthreads
-// (a multiple of 64).
+// result does not depend on which threads run it.  Thread gtid of gthreads (a
+// multiple of the group width; every lane of a group takes part).
 template <class R>
-__device__ void topo_sums(const Mesh& m, R* __restrict__ einvV, const int4* __restrict__ snodes,
-                          const int* __restrict__ sedges, int base, int n, int gtid, int gthreads) {
-  if (m.mode == MODE_PHANTOM) {
-    constexpr int GN = 16;
-    const int gl = gtid % GN;
-    for (int item = gtid / GN; item < 4 * n; item += gthreads / GN) {
-      int i = item >> 2, l = item & 3;
-      int4 q4 = snodes[i];
-      int node = l == 0 ? q4.x : l == 1 ? q4.y : l == 2 ? q4.z : q4.w;
-      double part = 0;
-      for (int p = m.noff[node] + gl; p < m.noff[node + 1]; p += GN) {
-        int e = m.nent[p] >> 2;
-        part += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
-      }
-      part = group_sum<GN>(part);
-      if (gl == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
-      if (gl == 1) {
-        int t = m.splitlist[i];
-        int mask = m.pmask[t];
-        int nbB = __popc(mask);
-        bool onB = (mask >> l) & 1;
-        // the extra node of l belongs to the copy of the other side
-        double fo = frac_of(code_for_side(onB ? 4 - nbB : nbB));
-        m.invm[m.N0 + 4 * (base + i) + l] = 1.0 / (m.rho * fo * m.vol[t] / 4.0);
-      }
+__device__ void topo_masses(const Mesh& m, const int4* __restrict__ snodes, int base, int n,
+                            int gtid, int gthreads) {
+  if (m.mode != MODE_PHANTOM) return;
+  constexpr int GN = 16;
+  const int gl = gtid % GN;
+  for (int item = gtid / GN; item < 4 * n; item += gthreads / GN) {
+    int i = item >> 2, l = item & 3;
+    int4 q4 = snodes[i];
+    int node = l == 0 ? q4.x : l == 1 ? q4.y : l == 2 ? q4.z : q4.w;
+    double part = 0;
+    for (int p = m.noff[node] + gl; p < m.noff[node + 1]; p += GN) {
+      int e = m.nent[p] >> 2;
+      part += m.rho * frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e] / 4.0;
+    }
+    part = group_sum<GN>(part);
+    if (gl == 0) m.invm[node] = part > 0 ? 1.0 / part : 0.0;
+    if (gl == 1) {
+      int t = m.splitlist[i];
+      int mask = m.pmask[t];
+      int nbB = __popc(mask);
+      bool onB = (mask >> l) & 1;
+      // the extra node of l belongs to the copy of the other side
+      double fo = frac_of(code_for_side(onB ? 4 - nbB : nbB));
+      m.invm[m.N0 + 4 * (base + i) + l] = 1.0 / (m.rho * fo * m.vol[t] / 4.0);
     }
   }
+}
+
+template <class R>
+__device__ void topo_volumes(const Mesh& m, R* __restrict__ einvV, const int* __restrict__ sedges,
+                             int n, int gtid, int gthreads) {
   constexpr int GE = 8;
   const int gl = gtid % GE;
   for (int item = gtid / GE; item < 6 * n; item += gthreads / GE) {
@@ -758,6 +762,29 @@ __device__ void topo_sums(const Mesh& m, R* __restrict__ einvV, const int4* __re
   }
 }
 
+// Phase 3: new crack fronts on intact face neighbours, one lane per face.
+__device__ void topo_fronts(const Mesh& m, Counters* __restrict__ c,
+                            const int4* __restrict__ snodes, int n, int gtid, int gthreads) {
+  for (int item = gtid; item < 4 * n; item += gthreads) {
+    const int i = item >> 2, f = item & 3;
+    int t = m.splitlist[i];
+    int mask = m.pmask[t];
+    int fl[3], k = 0;
+    for (int l = 0; l < 4; ++l)
+      if (l != f) fl[k++] = l;
+    int b0 = (mask >> fl[0]) & 1, b1 = (mask >> fl[1]) & 1, b2 = (mask >> fl[2]) & 1;
+    if (b0 == b1 && b1 == b2) continue;
+    int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];
+    int cn = ((const int*)&m.nbr[t])[f];
+    if (cn < 0 || m.smask[cn] >= 0) continue;
+    int fc = (m.nbrface[t] >> (8 * f)) & 0xff;
+    int4 q4 = snodes[i];
+    const int nd[4] = {q4.x, q4.y, q4.z, q4.w};
+    ((int*)m.front)[4 * cn + fc] = nd[lone];
+    if (atomicCAS(&m.candf[cn], 0, 1) == 0) m.cand[atomicAdd(&c->n_cand, 1)] = cn;
+  }
+}
+
 // Phase 2 of a large batch, over the whole chip, after k_topology.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_topo_sums(Mesh m, Work w, const Counters* __restrict__ c,
@@ -765,8 +792,9 @@ __global__ __launch_bounds__(kBlock) void k_topo_sums(Mesh m, Work w, const Coun
                                                       const int* __restrict__ sedges) {
   const int n = c->batch_n;
   if (n == 0) return;
-  topo_sums<R>(m, (R*)w.einvV, snodes, sedges, c->batch_base, n,
-               (int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x));
+  const int gtid = (int)(blockIdx.x * blockDim.x + threadIdx.x), gthreads = (int)(gridDim.x * blockDim.x);
+  topo_masses<R>(m, snodes, c->batch_base, n, gtid, gthreads);
+  topo_volumes<R>(m, (R*)w.einvV, sedges, n, gtid, gthreads);
 }
 
 // All splits of one step, applied by one workgroup in phases separated by
@@ -778,12 +806,13 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
                                                          Counters* __restrict__ c, int dynamic,
                                                          int advance, int4* __restrict__ snodes,
                                                          int* __restrict__ sedges) {
-  __shared__ int s_n, s_base;
+  __shared__ int s_n, s_base, s_dead;
   __shared__ int shk[kSortLds], shv[kSortLds];
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_n = c->err ? 0 : c->n_flag;
     s_base = c->n_split;
+    s_dead = 0;
   }
   __syncthreads();
   const int n = s_n, base = s_base;
@@ -822,6 +851,20 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
           G = m.pG[t];
           area = crack_area(m, nd, mask);
         }
+        // candidates that split now leave dead entries in the candidate list
+        if (sl == 0 && m.candf[t]) atomicAdd(&s_dead, 1);
+      }
+      // the real twin's state for extra node sl (real nodes are not written here)
+      double4 xr = make_double4(0, 0, 0, 0), ur = xr, vr = xr, ar = xr, uhr = xr;
+      int insr = 0;
+      if (on && sl < 4 && m.mode == MODE_PHANTOM) {
+        const int nr = nd[sl];
+        xr = m.X[nr];
+        ur = st.u[nr];
+        vr = st.v[nr];
+        ar = st.a[nr];
+        uhr = st.uh[nr];
+        if (m.n_inst) insr = m.inst[nr];
       }
       __syncthreads();
       if (on) {
@@ -848,13 +891,13 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
             const int l = sl;
             const int x = m.N0 + 4 * s + l;
             const int xe = 4 * m.T0 + 4 * s + l;  // the extra node's single list entry
-            m.X[x] = m.X[nd[l]];
-            st.u[x] = st.u[nd[l]];
-            st.v[x] = st.v[nd[l]];
-            st.a[x] = st.a[nd[l]];
-            st.uh[x] = st.uh[nd[l]];
+            m.X[x] = xr;
+            st.u[x] = ur;
+            st.v[x] = vr;
+            st.a[x] = ar;
+            st.uh[x] = uhr;
             m.lslot[x] = -1;
-            if (m.n_inst) m.inst[x] = m.inst[nd[l]];
+            if (m.n_inst) m.inst[x] = insr;
             const bool onB = (mask >> l) & 1;
             const int owner = onB ? t : tb;  // the copy that holds the extra node
             m.nent[xe] = (owner << 2) | l;
@@ -925,22 +968,13 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
     }
     __threadfence_block();
     __syncthreads();
-    // phase 2: masses and edge volumes touched by the batch, here for small
-    // batches, else by k_topo_sums after this kernel (nothing below reads them)
-    if (n <= kTopoInline) topo_sums<R>(m, einvV, snodes, sedges, base, n, tid, kTopoBlock);
     // the candidate list drops the tets that have split once they are the
     // majority (and at least 64): an order-keeping compaction in place (each
     // chunk is read in full before any of it is written, and writes land at or
     // below it).  Its work over a run is at most twice the entries ever
-    // appended.
+    // appended.  It comes before phase 3, which appends.
     {
-      __shared__ int s_dead, s_nc, s_nd, s_wtot[kTopoBlock / 64], s_total;
-      if (tid == 0) s_dead = 0;
-      __syncthreads();
-      int dead = 0;
-      for (int i = tid; i < n; i += kTopoBlock) dead += m.candf[m.splitlist[i]] != 0;
-      if (dead) atomicAdd(&s_dead, dead);
-      __syncthreads();
+      __shared__ int s_nc, s_nd, s_wtot[kTopoBlock / 64], s_total;
       // one thread reads the counters, so that every thread takes the same branch
       if (tid == 0) {
         s_nc = c->n_cand;
@@ -984,24 +1018,21 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
       __threadfence_block();
       __syncthreads();
     }
-    // phase 3: new crack fronts on intact face neighbours, one lane per face
-    for (int item = tid; item < 4 * n; item += kTopoBlock) {
-      const int i = item >> 2, f = item & 3;
-      int t = m.splitlist[i];
-      int mask = m.pmask[t];
-      int fl[3], k = 0;
-      for (int l = 0; l < 4; ++l)
-        if (l != f) fl[k++] = l;
-      int b0 = (mask >> fl[0]) & 1, b1 = (mask >> fl[1]) & 1, b2 = (mask >> fl[2]) & 1;
-      if (b0 == b1 && b1 == b2) continue;
-      int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];
-      int cn = ((const int*)&m.nbr[t])[f];
-      if (cn < 0 || m.smask[cn] >= 0) continue;
-      int fc = (m.nbrface[t] >> (8 * f)) & 0xff;
-      int4 q4 = snodes[i];
-      const int nd[4] = {q4.x, q4.y, q4.z, q4.w};
-      ((int*)m.front)[4 * cn + fc] = nd[lone];
-      if (atomicCAS(&m.candf[cn], 0, 1) == 0) m.cand[atomicAdd(&c->n_cand, 1)] = cn;
+    // phases 2 and 3 read what phase 1 wrote and nothing of each other.
+    // Phase 2 (masses and edge volumes touched by the batch) runs here for
+    // batches up to kTopoInline, else in k_topo_sums after this kernel;
+    // phase 3 appends the new crack fronts.  A batch of up to 8 splits runs
+    // the three item sets side by side on disjoint threads.
+    if (n <= 8) {
+      if (tid < 64 * n) topo_masses<R>(m, snodes, base, n, tid, 64 * n);
+      else if (tid < 112 * n) topo_volumes<R>(m, einvV, sedges, n, tid - 64 * n, 48 * n);
+      else if (tid < 116 * n) topo_fronts(m, c, snodes, n, tid - 112 * n, 4 * n);
+    } else {
+      if (n <= kTopoInline) {
+        topo_masses<R>(m, snodes, base, n, tid, kTopoBlock);
+        topo_volumes<R>(m, einvV, sedges, n, tid, kTopoBlock);
+      }
+      topo_fronts(m, c, snodes, n, tid, kTopoBlock);
     }
     __syncthreads();
   }
