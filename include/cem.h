@@ -321,6 +321,14 @@ int cem_window_times(cem_ctx* ctx, double* out);
  * then run as plain launches (HIP cannot time events recorded inside a
  * graph). */
 int cem_set_profiling(cem_ctx* ctx, int32_t on);
+
+/* How a step's splits are applied (Section 3, split elements): 0 = automatic
+ * (default: the whole chip for batches over 128 splits while the run splits
+ * more than 64 tets per step, until it drops below 16), 1 = one workgroup
+ * always, 2 = the whole chip for every batch over 128 splits.  The results
+ * are the same in every mode; only the launches differ (the whole-chip path
+ * takes two more per step).  CEM_EINVAL for another value. */
+int cem_set_topology_mode(cem_ctx* ctx, int32_t mode);
 int cem_kernel_times(cem_ctx* ctx, double* out);
 
 #ifdef __cplusplus

@@ -30,7 +30,7 @@ EXPORTS = [
     "cem_presplit", "cem_critical_dt", "cem_set_dt", "cem_bind_state", "cem_set_state",
     "cem_get_state", "cem_internal_force", "cem_step", "cem_replay_splits", "cem_read_energy",
     "cem_read_splits", "cem_read_front_G", "cem_save_state", "cem_load_state", "cem_counts",
-    "cem_set_profiling", "cem_kernel_times", "cem_set_instances", "cem_set_dt_instances",
+    "cem_set_profiling", "cem_set_topology_mode", "cem_kernel_times", "cem_set_instances", "cem_set_dt_instances",
     "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
     "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step",
     "cem_window_forward", "cem_window_backward", "cem_window_times", "cem_strain_energy_grad",
@@ -109,6 +109,7 @@ def load_library(path=LIB_PATH):
         "cem_load_state": [p, p, i64],
         "cem_counts": [p, p],
         "cem_set_profiling": [p, i32],
+        "cem_set_topology_mode": [p, i32],
         "cem_kernel_times": [p, p],
         "cem_set_instances": [p, i32, p, p],
         "cem_set_dt_instances": [p, p],
@@ -308,6 +309,10 @@ class Simulation:
     def load_state(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._chk(self.lib.cem_load_state(self.ctx, _p(buf), len(buf)))
+
+    def set_topology_mode(self, mode):
+        """0 automatic, 1 one workgroup, 2 whole chip for split batches over 128."""
+        self._chk(self.lib.cem_set_topology_mode(self.ctx, {"auto": 0, "single": 1, "chip": 2}.get(mode, mode)))
 
     def set_profiling(self, on=True):
         self._chk(self.lib.cem_set_profiling(self.ctx, 1 if on else 0))

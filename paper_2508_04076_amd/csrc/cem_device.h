@@ -42,6 +42,8 @@ struct Counters {
   double dt_crit;
   int batch_base;                 // first split of a batch whose masses and edge
   int batch_n;                    // volumes are left to k_topo_sums (0: none)
+  int batch_apply_n;              // splits left to k_topo_apply / k_topo_finish (0: none)
+  int dead_pending;               // candidates among them (dead list entries)
 };
 
 // Six float values of a symmetric tensor in Voigt order
@@ -60,6 +62,7 @@ struct Mesh {
   double umax;              // runaway bound on |u|
   int grid_cap;             // workgroups of the persistent step launches (multiple of 8)
   int lanes;                // lanes per node in the node pass (4, 8 or 16)
+  int topo_multi;           // 1: split batches over kTopoInline are applied by the whole chip
   int ssum;                 // tets: what the force pass hands to the node pass: 0 = nodal
                             // terms at node-list positions, 1 = per-tet stress sums (the
                             // node pass forms G_l from the corner coordinates)

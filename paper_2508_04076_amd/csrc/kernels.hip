@@ -618,32 +618,43 @@ __device__ __forceinline__ int code_for_side(int nodes_on_side) {
   return nodes_on_side == 1 ? FR_EIGHTH : nodes_on_side == 3 ? FR_SEVEN8 : FR_HALF;
 }
 
+// Element l of four values (select chain: no indexed local array).
+template <class T>
+__device__ __forceinline__ T pick4(T a, T b, T c, T d, int l) {
+  return l == 0 ? a : l == 1 ? b : l == 2 ? c : d;
+}
+
 // Area of the midpoint crack surface of a 2|2 cut (Varignon parallelogram) or
-// a 1|3 cut (corner triangle).
-__device__ double crack_area(const Mesh& m, const int* nd, int mask) {
-  int nb = __popc(mask);
-  double4 x[4];
-  for (int l = 0; l < 4; ++l) x[l] = m.X[nd[l]];
-  double ax, ay, az, bx, by, bz;
+// a 1|3 cut (corner triangle).  Corner indices from the mask's bits.
+__device__ __forceinline__ double crack_area(const Mesh& m, const int* nd, int mask) {
+  const double4 x0 = m.X[nd[0]], x1 = m.X[nd[1]], x2 = m.X[nd[2]], x3 = m.X[nd[3]];
+  const int nb = __popc(mask);
+  int i0, i1, j0, j1;
   double f;
   if (nb == 2) {
-    int A[2], B[2], ia = 0, ib = 0;
-    for (int l = 0; l < 4; ++l) {
-      if ((mask >> l) & 1) B[ib++] = l; else A[ia++] = l;
-    }
-    ax = x[A[1]].x - x[A[0]].x; ay = x[A[1]].y - x[A[0]].y; az = x[A[1]].z - x[A[0]].z;
-    bx = x[B[1]].x - x[B[0]].x; by = x[B[1]].y - x[B[0]].y; bz = x[B[1]].z - x[B[0]].z;
+    // edge A0A1 (nodes off the mask) and edge B0B1 (nodes on it)
+    const int a = ~mask & 15;
+    i0 = __ffs(a) - 1;
+    i1 = 31 - __clz(a);
+    j0 = __ffs(mask) - 1;
+    j1 = 31 - __clz(mask);
     f = 0.25;
   } else {
-    int big = nb == 1 ? 0 : 1;
-    int q[3], iq = 0;
-    for (int l = 0; l < 4; ++l)
-      if ((((mask >> l) & 1) ? 1 : 0) == big) q[iq++] = l;
-    ax = x[q[1]].x - x[q[0]].x; ay = x[q[1]].y - x[q[0]].y; az = x[q[1]].z - x[q[0]].z;
-    bx = x[q[2]].x - x[q[0]].x; by = x[q[2]].y - x[q[0]].y; bz = x[q[2]].z - x[q[0]].z;
+    // the three corners of the larger side: q0 q1 and q0 q2
+    int big = nb == 1 ? (~mask & 15) : mask;
+    i0 = __ffs(big) - 1;
+    big &= big - 1;
+    i1 = __ffs(big) - 1;
+    big &= big - 1;
+    j1 = __ffs(big) - 1;
+    j0 = i0;
     f = 0.125;
   }
-  double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+  const double4 p0 = pick4(x0, x1, x2, x3, i0), p1 = pick4(x0, x1, x2, x3, i1);
+  const double4 r0 = pick4(x0, x1, x2, x3, j0), r1 = pick4(x0, x1, x2, x3, j1);
+  const double ax = p1.x - p0.x, ay = p1.y - p0.y, az = p1.z - p0.z;
+  const double bx = r1.x - r0.x, by = r1.y - r0.y, bz = r1.z - r0.z;
+  const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
   return f * sqrt(cx * cx + cy * cy + cz * cz);
 }
 
@@ -797,10 +808,263 @@ __global__ __launch_bounds__(kBlock) void k_topo_sums(Mesh m, Work w, const Coun
   topo_volumes<R>(m, (R*)w.einvV, sedges, n, gtid, gthreads);
 }
 
+// What a split reads of its parent (phase 0), and writes (phase 1).  Eight
+// lanes per split: lane l < 4 copies extra node l and fixes its node-list
+// entries, lane q < 6 rewrites edge q's patch entries, lane 0 the records and
+// the two copies' element rows.  A workgroup reads every split it holds
+// before a barrier and writes after it, so a split never sees its own
+// writes; splits of one batch touch disjoint data (their own tet, copy slot,
+// extra nodes, new edges and list entries), so any grouping of splits into
+// workgroups gives the same result.
+struct SplitIn {
+  int t, mask, nd[4], ed[6], pp[6];
+  int4 op4;
+  double V, kp, area, G;
+  int ti, pat;
+  double4 xr, ur, vr, ar, uhr;  // the real twin's state for extra node sl
+  int insr;
+};
+
+template <class R>
+__device__ __forceinline__ void split_read(const Mesh& m, const State& st, int i, int sl,
+                                           int dynamic, int* dead, SplitIn& q) {
+  q.t = m.splitlist[i];
+  q.mask = m.pmask[q.t];
+  load_tet<R>(m, q.t, q.nd, q.ed);
+  q.op4 = make_int4(0, 0, 0, 0);
+  q.V = 0;
+  q.kp = 1.0;
+  q.area = 0;
+  q.G = 0;
+  q.ti = 0;
+  q.pat = 0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) q.pp[r] = 0;
+  if (m.mode == MODE_PHANTOM) {
+    q.op4 = m.epos[q.t];
+    q.V = m.vol[q.t];
+    if (m.kap) q.kp = m.kap[q.t];
+    if (m.n_inst) q.ti = m.tinst[q.t];
+    const int* p6 = (const int*)&m.patchpos[3 * q.t];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) q.pp[r] = p6[r];
+  }
+  if (sl == 0 && dynamic) {
+    q.pat = m.ppat[q.t];
+    q.G = m.pG[q.t];
+    q.area = crack_area(m, q.nd, q.mask);
+  }
+  // candidates that split now leave dead entries in the candidate list
+  if (sl == 0 && m.candf[q.t]) atomicAdd(dead, 1);
+  // the real twin's state (real nodes are not written by any split)
+  q.xr = make_double4(0, 0, 0, 0);
+  q.ur = q.vr = q.ar = q.uhr = q.xr;
+  q.insr = 0;
+  if (sl < 4 && m.mode == MODE_PHANTOM) {
+    const int nr = pick4(q.nd[0], q.nd[1], q.nd[2], q.nd[3], sl);
+    q.xr = m.X[nr];
+    q.ur = st.u[nr];
+    q.vr = st.v[nr];
+    q.ar = st.a[nr];
+    q.uhr = st.uh[nr];
+    if (m.n_inst) q.insr = m.inst[nr];
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void split_write(const Mesh& m, const State& st, R* __restrict__ einvV,
+                                            const Counters* __restrict__ c, int base, int i,
+                                            int sl, int dynamic, const SplitIn& q,
+                                            int4* __restrict__ snodes, int* __restrict__ sedges) {
+  const int s = base + i, t = q.t, mask = q.mask;
+  if (sl == 0) {
+    snodes[i] = make_int4(q.nd[0], q.nd[1], q.nd[2], q.nd[3]);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) sedges[6 * i + r] = q.ed[r];
+    m.smask[t] = mask;
+    m.rec_step[s] = dynamic ? (int)(c->step + 1) : (int)c->step;
+    m.rec_tet[s] = t;
+    m.rec_mask[s] = mask;
+    m.rec_pat[s] = q.pat;
+    m.rec_G[s] = q.G;
+    m.area[i] = q.area;
+    m.rec_area[s] = q.area;
+    if (m.mode == MODE_ERODE)
+      m.enodes[t] = make_int4(pack0(q.nd[0], FR_ZERO), q.nd[1], q.nd[2], q.nd[3]);
+  }
+  if (m.mode != MODE_PHANTOM) return;
+  const int tb = m.T0 + s;
+  const int nb = __popc(mask);
+  const int codeA = code_for_side(4 - nb), codeB = code_for_side(nb);
+  if (sl < 4) {
+    const int l = sl;
+    const int opl = pick4(q.op4.x, q.op4.y, q.op4.z, q.op4.w, l);
+    const int x = m.N0 + 4 * s + l;
+    const int xe = 4 * m.T0 + 4 * s + l;  // the extra node's single list entry
+    m.X[x] = q.xr;
+    st.u[x] = q.ur;
+    st.v[x] = q.vr;
+    st.a[x] = q.ar;
+    st.uh[x] = q.uhr;
+    m.lslot[x] = -1;
+    if (m.n_inst) m.inst[x] = q.insr;
+    const bool onB = (mask >> l) & 1;
+    const int owner = onB ? t : tb;  // the copy that holds the extra node
+    m.nent[xe] = (owner << 2) | l;
+    if (onB) m.nent[opl] = (tb << 2) | l;
+  }
+  // a new edge's patch is one copy: kappa_k is the parent's
+  const R ivA = (R)(q.kp / (frac_of(codeA) * q.V)), ivB = (R)(q.kp / (frac_of(codeB) * q.V));
+  const int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
+  int eA[6], eB[6];
+  int r = 0;  // every edge makes one new edge, a cut edge two
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int k = q.ed[e];
+    const int ba = (mask >> kEA[e]) & 1, bb = (mask >> kEB[e]) & 1;
+    const bool mine = sl == e;
+    if (!ba && !bb) {          // both nodes on side A: copy A keeps edge k
+      eA[e] = k;
+      eB[e] = ebase + r;
+      if (mine) { m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; }
+      r++;
+    } else if (ba && bb) {     // both on side B: copy B takes edge k
+      eB[e] = k;
+      eA[e] = ebase + r;
+      if (mine) { m.pent[q.pp[e]] = tb; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; }
+      r++;
+    } else {                   // cut edge: each copy gets a new one
+      eA[e] = ebase + r;
+      eB[e] = ebase + r + 1;
+      if (mine) {
+        m.pent[q.pp[e]] = -1;
+        m.pent[pbase + r] = t; einvV[ebase + r] = ivA;
+        m.pent[pbase + r + 1] = tb; einvV[ebase + r + 1] = ivB;
+      }
+      r += 2;
+    }
+  }
+  if (sl == 6)
+    for (int e = r; e < 10; ++e) { m.pent[pbase + e] = -1; einvV[ebase + e] = (R)0; }
+  if (sl == 7 && m.n_inst) {
+    m.tinst[tb] = q.ti;
+    for (int e = 0; e < 10; ++e) m.einst[ebase + e] = q.ti;
+  }
+  if (sl == 0) {
+    const int op[4] = {q.op4.x, q.op4.y, q.op4.z, q.op4.w};
+    int na[4], nbn[4], pa[4], pb[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int x = m.N0 + 4 * s + l, xe = 4 * m.T0 + 4 * s + l;
+      const bool onB = (mask >> l) & 1;
+      na[l] = onB ? x : q.nd[l];
+      nbn[l] = onB ? q.nd[l] : x;
+      pa[l] = onB ? xe : op[l];
+      pb[l] = onB ? op[l] : xe;
+    }
+    m.enodes[t] = make_int4(pack0(na[0], codeA), na[1], na[2], na[3]);
+    m.enodes[tb] = make_int4(pack0(nbn[0], codeB), nbn[1], nbn[2], nbn[3]);
+    m.epos[t] = make_int4(pa[0], pa[1], pa[2], pa[3]);
+    m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
+    m.vol[tb] = q.V;
+    if (m.kap) m.kap[tb] = q.kp;
+    m.et2e[3 * t] = make_int2(eA[0], eA[1]);
+    m.et2e[3 * t + 1] = make_int2(eA[2], eA[3]);
+    m.et2e[3 * t + 2] = make_int2(eA[4], eA[5]);
+    m.et2e[3 * tb] = make_int2(eB[0], eB[1]);
+    m.et2e[3 * tb + 1] = make_int2(eB[2], eB[3]);
+    m.et2e[3 * tb + 2] = make_int2(eB[4], eB[5]);
+  }
+}
+
+// The candidate list drops the tets that have split once they are the
+// majority (and at least CEM_CAND_COMPACT_MIN): an order-keeping compaction in
+// place by one workgroup of kTopoBlock threads (each chunk is read in full
+// before any of it is written, and writes land at or below it).  Its work
+// over a run is at most twice the entries ever appended.  new_dead: the
+// batch's candidates, the same value in every thread.
+__device__ void compact_candidates(const Mesh& m, Counters* __restrict__ c, int new_dead) {
+  __shared__ int s_nc, s_nd, s_wtot[kTopoBlock / 64], s_total;
+  const int tid = threadIdx.x;
+  // one thread reads the counters, so that every thread takes the same branch
+  if (tid == 0) {
+    s_nc = c->n_cand;
+    s_nd = c->n_cand_dead + new_dead;
+  }
+  __syncthreads();
+  const int nc = s_nc, nd_all = s_nd;
+  if (nd_all >= CEM_CAND_COMPACT_MIN && 2 * nd_all > nc) {
+    const int lane = tid & 63, wv = tid >> 6;
+    int out = 0;
+    for (int b0 = 0; b0 < nc; b0 += kTopoBlock) {
+      const int idx = b0 + tid;
+      const int t = idx < nc ? m.cand[idx] : -1;
+      const bool alive = t >= 0 && m.smask[t] < 0;
+      const unsigned long long bal = __ballot(alive);
+      const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wtot[wv] = __popcll(bal);
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < kTopoBlock / 64; ++w) {
+          const int x = s_wtot[w];
+          s_wtot[w] = acc;
+          acc += x;
+        }
+        s_total = acc;
+      }
+      __syncthreads();
+      if (alive) m.cand[out + s_wtot[wv] + pre] = t;
+      out += s_total;
+      __threadfence_block();
+      __syncthreads();
+    }
+    if (tid == 0) {
+      c->n_cand = out;
+      c->n_cand_dead = 0;
+    }
+  } else if (tid == 0) {
+    c->n_cand_dead = nd_all;
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+// Counters after a batch of n splits from global index base (thread 0), and
+// the per-instance G maxima (all threads).
+__device__ void topo_tail(const Mesh& m, Counters* __restrict__ c, int base, int n, int dynamic,
+                          int advance) {
+  if (threadIdx.x == 0) {
+    if (!c->err) {
+      if (n > 0 && dynamic) {
+        double ud = c->Ud;
+        for (int i = 0; i < n; ++i) ud += m.Gc * m.area[i];
+        c->Ud = ud;
+      }
+      c->n_split = base + n;
+      if (advance) {
+        c->step += 1;
+        c->gmax_last = c->gmax_key;
+        c->gmax_key = 0;
+      }
+    }
+    c->n_flag = 0;
+  }
+  if (advance && m.n_inst) {
+    for (int i = threadIdx.x; i < m.n_inst; i += blockDim.x) {
+      m.gmax_inst[m.n_inst + i] = m.gmax_inst[i];
+      m.gmax_inst[i] = 0;
+    }
+  }
+}
+
 // All splits of one step, applied by one workgroup in phases separated by
 // barriers.  Split i of this batch gets global index s = n_split + i; its
 // copy B takes element slot T0 + s, its extra nodes N0 + 4 s + l and its new
-// edges E0 + 10 s + r.  Copy A stays in the parent's slot.
+// edges E0 + 10 s + r.  Copy A stays in the parent's slot.  With topo_multi
+// (or for a host pre-split), a batch over kTopoInline is only sorted here:
+// k_topo_apply, k_topo_sums and k_topo_finish complete it on the whole chip,
+// with the same per-split code and sums.
 template <class R>
 __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work w,
                                                          Counters* __restrict__ c, int dynamic,
@@ -819,205 +1083,31 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
   R* einvV = (R*)w.einvV;
   if (n > 0) {
     if (dynamic) block_sort(m.splitlist, n, m.tet_ext, shk, shv);
-    // phases 0 + 1, eight lanes per split: record the split, keep the parent's
-    // real nodes and edges, then rewrite elements, edges and node lists.
-    // Lane l < 4 copies extra node l and fixes its node-list entries, lane
-    // q < 6 rewrites edge q's patch entries, lane 0 the records and the two
-    // copies' element rows.  Everything a split reads of its parent is read
-    // before a block barrier, everything it writes after it.
+    if (m.topo_multi && n > kTopoInline) {
+      if (tid == 0) {
+        c->batch_base = base;
+        c->batch_n = n;
+        c->batch_apply_n = n;
+        c->dead_pending = 0;
+      }
+      return;
+    }
+    // phases 0 + 1, eight lanes per split (split_read, split_write)
     constexpr int GS = 8;
     const int sl = tid % GS;
     for (int i0 = 0; i0 < n; i0 += kTopoBlock / GS) {
       const int i = i0 + tid / GS;
       const bool on = i < n;
-      int t = 0, mask = 0, nd[4] = {0, 0, 0, 0}, ed[6] = {0, 0, 0, 0, 0, 0}, pp[6];
-      int4 op4 = make_int4(0, 0, 0, 0);
-      double V = 0, kp = 1.0, area = 0, G = 0;
-      int ti = 0, pat = 0;
-      if (on) {
-        t = m.splitlist[i];
-        mask = m.pmask[t];
-        load_tet<R>(m, t, nd, ed);
-        if (m.mode == MODE_PHANTOM) {
-          op4 = m.epos[t];
-          V = m.vol[t];
-          if (m.kap) kp = m.kap[t];
-          if (m.n_inst) ti = m.tinst[t];
-          const int* p6 = (const int*)&m.patchpos[3 * t];
-          for (int q = 0; q < 6; ++q) pp[q] = p6[q];
-        }
-        if (sl == 0 && dynamic) {
-          pat = m.ppat[t];
-          G = m.pG[t];
-          area = crack_area(m, nd, mask);
-        }
-        // candidates that split now leave dead entries in the candidate list
-        if (sl == 0 && m.candf[t]) atomicAdd(&s_dead, 1);
-      }
-      // the real twin's state for extra node sl (real nodes are not written here)
-      double4 xr = make_double4(0, 0, 0, 0), ur = xr, vr = xr, ar = xr, uhr = xr;
-      int insr = 0;
-      if (on && sl < 4 && m.mode == MODE_PHANTOM) {
-        const int nr = nd[sl];
-        xr = m.X[nr];
-        ur = st.u[nr];
-        vr = st.v[nr];
-        ar = st.a[nr];
-        uhr = st.uh[nr];
-        if (m.n_inst) insr = m.inst[nr];
-      }
+      SplitIn q;
+      if (on) split_read<R>(m, st, i, sl, dynamic, &s_dead, q);
       __syncthreads();
-      if (on) {
-        const int s = base + i;
-        if (sl == 0) {
-          snodes[i] = make_int4(nd[0], nd[1], nd[2], nd[3]);
-          for (int q = 0; q < 6; ++q) sedges[6 * i + q] = ed[q];
-          m.smask[t] = mask;
-          m.rec_step[s] = dynamic ? (int)(c->step + 1) : (int)c->step;
-          m.rec_tet[s] = t;
-          m.rec_mask[s] = mask;
-          m.rec_pat[s] = pat;
-          m.rec_G[s] = G;
-          m.area[i] = area;
-          m.rec_area[s] = area;
-          if (m.mode == MODE_ERODE) m.enodes[t] = make_int4(pack0(nd[0], FR_ZERO), nd[1], nd[2], nd[3]);
-        }
-        if (m.mode == MODE_PHANTOM) {
-          const int tb = m.T0 + s;
-          const int nb = __popc(mask);
-          const int codeA = code_for_side(4 - nb), codeB = code_for_side(nb);
-          const int op[4] = {op4.x, op4.y, op4.z, op4.w};
-          if (sl < 4) {
-            const int l = sl;
-            const int x = m.N0 + 4 * s + l;
-            const int xe = 4 * m.T0 + 4 * s + l;  // the extra node's single list entry
-            m.X[x] = xr;
-            st.u[x] = ur;
-            st.v[x] = vr;
-            st.a[x] = ar;
-            st.uh[x] = uhr;
-            m.lslot[x] = -1;
-            if (m.n_inst) m.inst[x] = insr;
-            const bool onB = (mask >> l) & 1;
-            const int owner = onB ? t : tb;  // the copy that holds the extra node
-            m.nent[xe] = (owner << 2) | l;
-            if (onB) m.nent[op[l]] = (tb << 2) | l;
-          }
-          // a new edge's patch is one copy: kappa_k is the parent's
-          const R ivA = (R)(kp / (frac_of(codeA) * V)), ivB = (R)(kp / (frac_of(codeB) * V));
-          const int ebase = m.E0 + 10 * s, pbase = 6 * m.T0 + 10 * s;
-          int eA[6], eB[6];
-          int r = 0;  // every edge makes one new edge, a cut edge two
-          for (int q = 0; q < 6; ++q) {
-            const int k = ed[q];
-            const int ba = (mask >> kEA[q]) & 1, bb = (mask >> kEB[q]) & 1;
-            const bool mine = sl == q;
-            if (!ba && !bb) {          // both nodes on side A: copy A keeps edge k
-              eA[q] = k;
-              eB[q] = ebase + r;
-              if (mine) { m.pent[pbase + r] = tb; einvV[ebase + r] = ivB; }
-              r++;
-            } else if (ba && bb) {     // both on side B: copy B takes edge k
-              eB[q] = k;
-              eA[q] = ebase + r;
-              if (mine) { m.pent[pp[q]] = tb; m.pent[pbase + r] = t; einvV[ebase + r] = ivA; }
-              r++;
-            } else {                   // cut edge: each copy gets a new one
-              eA[q] = ebase + r;
-              eB[q] = ebase + r + 1;
-              if (mine) {
-                m.pent[pp[q]] = -1;
-                m.pent[pbase + r] = t; einvV[ebase + r] = ivA;
-                m.pent[pbase + r + 1] = tb; einvV[ebase + r + 1] = ivB;
-              }
-              r += 2;
-            }
-          }
-          if (sl == 6)
-            for (int q = r; q < 10; ++q) { m.pent[pbase + q] = -1; einvV[ebase + q] = (R)0; }
-          if (sl == 7 && m.n_inst) {
-            m.tinst[tb] = ti;
-            for (int q = 0; q < 10; ++q) m.einst[ebase + q] = ti;
-          }
-          if (sl == 0) {
-            int na[4], nbn[4], pa[4], pb[4];
-            for (int l = 0; l < 4; ++l) {
-              const int x = m.N0 + 4 * s + l, xe = 4 * m.T0 + 4 * s + l;
-              const bool onB = (mask >> l) & 1;
-              na[l] = onB ? x : nd[l];
-              nbn[l] = onB ? nd[l] : x;
-              pa[l] = onB ? xe : op[l];
-              pb[l] = onB ? op[l] : xe;
-            }
-            m.enodes[t] = make_int4(pack0(na[0], codeA), na[1], na[2], na[3]);
-            m.enodes[tb] = make_int4(pack0(nbn[0], codeB), nbn[1], nbn[2], nbn[3]);
-            m.epos[t] = make_int4(pa[0], pa[1], pa[2], pa[3]);
-            m.epos[tb] = make_int4(pb[0], pb[1], pb[2], pb[3]);
-            m.vol[tb] = V;
-            if (m.kap) m.kap[tb] = kp;
-            m.et2e[3 * t] = make_int2(eA[0], eA[1]);
-            m.et2e[3 * t + 1] = make_int2(eA[2], eA[3]);
-            m.et2e[3 * t + 2] = make_int2(eA[4], eA[5]);
-            m.et2e[3 * tb] = make_int2(eB[0], eB[1]);
-            m.et2e[3 * tb + 1] = make_int2(eB[2], eB[3]);
-            m.et2e[3 * tb + 2] = make_int2(eB[4], eB[5]);
-          }
-        }
-      }
+      if (on) split_write<R>(m, st, einvV, c, base, i, sl, dynamic, q, snodes, sedges);
       __syncthreads();
     }
     __threadfence_block();
     __syncthreads();
-    // the candidate list drops the tets that have split once they are the
-    // majority (and at least 64): an order-keeping compaction in place (each
-    // chunk is read in full before any of it is written, and writes land at or
-    // below it).  Its work over a run is at most twice the entries ever
-    // appended.  It comes before phase 3, which appends.
-    {
-      __shared__ int s_nc, s_nd, s_wtot[kTopoBlock / 64], s_total;
-      // one thread reads the counters, so that every thread takes the same branch
-      if (tid == 0) {
-        s_nc = c->n_cand;
-        s_nd = c->n_cand_dead + s_dead;
-      }
-      __syncthreads();
-      const int nc = s_nc, nd_all = s_nd;
-      if (nd_all >= CEM_CAND_COMPACT_MIN && 2 * nd_all > nc) {
-        const int lane = tid & 63, wv = tid >> 6;
-        int out = 0;
-        for (int b0 = 0; b0 < nc; b0 += kTopoBlock) {
-          const int idx = b0 + tid;
-          const int t = idx < nc ? m.cand[idx] : -1;
-          const bool alive = t >= 0 && m.smask[t] < 0;
-          const unsigned long long bal = __ballot(alive);
-          const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-          if (lane == 0) s_wtot[wv] = __popcll(bal);
-          __syncthreads();
-          if (tid == 0) {
-            int acc = 0;
-            for (int w = 0; w < kTopoBlock / 64; ++w) {
-              const int x = s_wtot[w];
-              s_wtot[w] = acc;
-              acc += x;
-            }
-            s_total = acc;
-          }
-          __syncthreads();
-          if (alive) m.cand[out + s_wtot[wv] + pre] = t;
-          out += s_total;
-          __threadfence_block();
-          __syncthreads();
-        }
-        if (tid == 0) {
-          c->n_cand = out;
-          c->n_cand_dead = 0;
-        }
-      } else if (tid == 0) {
-        c->n_cand_dead = nd_all;
-      }
-      __threadfence_block();
-      __syncthreads();
-    }
+    // the compaction comes before phase 3, which appends
+    compact_candidates(m, c, s_dead);
     // phases 2 and 3 read what phase 1 wrote and nothing of each other.
     // Phase 2 (masses and edge volumes touched by the batch) runs here for
     // batches up to kTopoInline, else in k_topo_sums after this kernel;
@@ -1037,30 +1127,61 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
     __syncthreads();
   }
   if (tid == 0) {
-    if (!c->err) {
-      if (n > 0 && dynamic) {
-        double ud = c->Ud;
-        for (int i = 0; i < n; ++i) ud += m.Gc * m.area[i];
-        c->Ud = ud;
-      }
-      c->n_split = base + n;
-      c->batch_base = base;
-      c->batch_n = n > kTopoInline ? n : 0;
-      if (advance) {
-        c->step += 1;
-        c->gmax_last = c->gmax_key;
-        c->gmax_key = 0;
-      }
-    }
-    c->n_flag = 0;
-    if (c->err) c->batch_n = 0;
+    c->batch_base = base;
+    c->batch_n = (!c->err && n > kTopoInline) ? n : 0;
+    c->batch_apply_n = 0;
   }
-  if (advance && m.n_inst) {
-    for (int i = tid; i < m.n_inst; i += kTopoBlock) {
-      m.gmax_inst[m.n_inst + i] = m.gmax_inst[i];
-      m.gmax_inst[i] = 0;
-    }
+  topo_tail(m, c, base, n, dynamic, advance);
+}
+
+// Phases 0 + 1 of a deferred batch over the whole chip: 32 splits per
+// workgroup pass, the same read / barrier / write as k_topology.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_topo_apply(Mesh m, State st, Work w,
+                                                       Counters* __restrict__ c, int dynamic,
+                                                       int4* __restrict__ snodes,
+                                                       int* __restrict__ sedges) {
+  const int n = c->batch_apply_n;
+  if (n == 0) return;
+  const int base = c->batch_base;
+  R* einvV = (R*)w.einvV;
+  constexpr int GS = 8, PER = kBlock / GS;
+  const int sl = threadIdx.x % GS;
+  for (int i0 = blockIdx.x * PER; i0 < n; i0 += gridDim.x * PER) {
+    const int i = i0 + threadIdx.x / GS;
+    const bool on = i < n;
+    SplitIn q;
+    if (on) split_read<R>(m, st, i, sl, dynamic, &c->dead_pending, q);
+    __syncthreads();
+    if (on) split_write<R>(m, st, einvV, c, base, i, sl, dynamic, q, snodes, sedges);
+    __syncthreads();
   }
+}
+
+// The rest of a deferred batch, by one workgroup after k_topo_apply:
+// candidate compaction, new crack fronts, counters.
+template <class R>
+__global__ __launch_bounds__(kTopoBlock) void k_topo_finish(Mesh m, Counters* __restrict__ c,
+                                                            int dynamic, int advance,
+                                                            const int4* __restrict__ snodes) {
+  __shared__ int s_n, s_base, s_dead;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_n = c->batch_apply_n;
+    s_base = c->batch_base;
+    s_dead = c->dead_pending;
+  }
+  __syncthreads();
+  const int n = s_n, base = s_base;
+  if (n == 0) return;
+  compact_candidates(m, c, s_dead);
+  topo_fronts(m, c, snodes, n, tid, kTopoBlock);
+  __syncthreads();
+  if (tid == 0) {
+    c->batch_apply_n = 0;
+    c->dead_pending = 0;
+  }
+  topo_tail(m, c, base, n, dynamic, advance);
 }
 
 // ---------------------------------------------------------------- prescribed velocities
@@ -1507,10 +1628,19 @@ template hipError_t launch_strain_energy<float>(const Mesh&, const Work&, Counte
 template <class R>
 hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Counters* c,
                              int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s) {
-  hipLaunchKernelGGL(k_topology<R>, dim3(1), dim3(kTopoBlock), 0, s, m, st, w, c, dynamic, advance,
+  // a host pre-split (dynamic 0) always takes the whole-chip path for large batches
+  Mesh mm = m;
+  if (!dynamic) mm.topo_multi = 1;
+  hipLaunchKernelGGL(k_topology<R>, dim3(1), dim3(kTopoBlock), 0, s, mm, st, w, c, dynamic, advance,
                      snodes, sedges);
-  if (m.etype != 8)  // hexahedra do not split
-    hipLaunchKernelGGL(k_topo_sums<R>, dim3(256), dim3(kBlock), 0, s, m, w, c, snodes, sedges);
+  if (mm.etype == 8) return hipGetLastError();  // hexahedra do not split
+  if (mm.topo_multi)
+    hipLaunchKernelGGL(k_topo_apply<R>, dim3(256), dim3(kBlock), 0, s, mm, st, w, c, dynamic, snodes,
+                       sedges);
+  hipLaunchKernelGGL(k_topo_sums<R>, dim3(256), dim3(kBlock), 0, s, mm, w, c, snodes, sedges);
+  if (mm.topo_multi)
+    hipLaunchKernelGGL(k_topo_finish<R>, dim3(1), dim3(kTopoBlock), 0, s, mm, c, dynamic, advance,
+                       (const int4*)snodes);
   return hipGetLastError();
 }
 template hipError_t launch_topology_t<double>(const Mesh&, const State&, const Work&, Counters*,

@@ -107,6 +107,7 @@ struct cem_ctx {
   // any change of state, mesh or launch shape bumps gen (discards a window)
   long long gen = 0;
   int frozen = 0;        // steps skip the crack pass
+  int topo_mode = 0;     // 0 auto, 1 one workgroup, 2 whole chip for large split batches
   int graph_frozen = -1;
 
   // fixed-topology gradient window
@@ -782,6 +783,7 @@ int run_steps(cem_ctx* c, int32_t n_steps) {
   HIPCHK(c, hipEventRecord(e0, c->stream));
   if (c->need_init && (r = initialize(c))) return r;
   for (int q = 0; q < 7; ++q) c->times[q] = 0;
+  const int splits0 = c->h_ctr->n_split;
   int K = c->opt.graph_steps;
   int done = 0;
   // HIP cannot time events recorded inside a graph: profiling uses plain launches
@@ -815,6 +817,17 @@ int run_steps(cem_ctx* c, int32_t n_steps) {
   float ms = 0;
   (void)hipEventElapsedTime(&ms, e0, e1);
   c->times[0] = ms;
+  if (r == CEM_OK && c->topo_mode == 0) {
+    // automatic topology mode: large split batches over the whole chip while
+    // the run splits more than 64 tets per step, one workgroup again below 16
+    // (the same results either way; only the launches differ)
+    const double rate = (double)(c->h_ctr->n_split - splits0) / n_steps;
+    const int want = c->m.topo_multi ? (rate >= 16.0) : (rate > 64.0);
+    if (want != c->m.topo_multi) {
+      c->m.topo_multi = want;
+      drop_graph(c);
+    }
+  }
   return r;
 }
 
@@ -1096,6 +1109,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
   m.ssum = 0;
+  m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 4;
   m.inst = m.tinst = m.einst = nullptr;
@@ -1317,6 +1331,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
   m.ssum = 0;
+  m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 8;
   {
@@ -2406,6 +2421,18 @@ int cem_strain_energy_grad(cem_ctx* c, const double* u, double* se, double* gu, 
 int cem_window_times(cem_ctx* c, double* out) {
   if (!c || !out) return CEM_EINVAL;
   for (int i = 0; i < 6; ++i) out[i] = c->win.times[i];
+  return CEM_OK;
+}
+
+int cem_set_topology_mode(cem_ctx* c, int32_t mode) {
+  if (!c) return CEM_EINVAL;
+  if (mode < 0 || mode > 2) return c->fail(CEM_EINVAL, "topology mode must be 0, 1 or 2");
+  c->topo_mode = mode;
+  const int multi = mode == 2 ? 1 : 0;
+  if (mode != 0 && multi != c->m.topo_multi) {
+    c->m.topo_multi = multi;
+    drop_graph(c);
+  }
   return CEM_OK;
 }
 
