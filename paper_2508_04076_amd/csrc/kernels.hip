@@ -1109,26 +1109,23 @@ __global__ __launch_bounds__(kTopoBlock) void k_topology(Mesh m, State st, Work 
     // the compaction comes before phase 3, which appends
     compact_candidates(m, c, s_dead);
     // phases 2 and 3 read what phase 1 wrote and nothing of each other.
-    // Phase 2 (masses and edge volumes touched by the batch) runs here for
-    // batches up to kTopoInline, else in k_topo_sums after this kernel;
-    // phase 3 appends the new crack fronts.  A batch of up to 8 splits runs
-    // the three item sets side by side on disjoint threads.
+    // Phase 2 (masses and edge volumes touched by the batch) and phase 3 (new
+    // crack fronts) of a batch not left to the whole chip.  A batch of up to 8
+    // splits runs the three item sets side by side on disjoint threads.
     if (n <= 8) {
       if (tid < 64 * n) topo_masses<R>(m, snodes, base, n, tid, 64 * n);
       else if (tid < 112 * n) topo_volumes<R>(m, einvV, sedges, n, tid - 64 * n, 48 * n);
       else if (tid < 116 * n) topo_fronts(m, c, snodes, n, tid - 112 * n, 4 * n);
     } else {
-      if (n <= kTopoInline) {
-        topo_masses<R>(m, snodes, base, n, tid, kTopoBlock);
-        topo_volumes<R>(m, einvV, sedges, n, tid, kTopoBlock);
-      }
+      topo_masses<R>(m, snodes, base, n, tid, kTopoBlock);
+      topo_volumes<R>(m, einvV, sedges, n, tid, kTopoBlock);
       topo_fronts(m, c, snodes, n, tid, kTopoBlock);
     }
     __syncthreads();
   }
   if (tid == 0) {
     c->batch_base = base;
-    c->batch_n = (!c->err && n > kTopoInline) ? n : 0;
+    c->batch_n = 0;
     c->batch_apply_n = 0;
   }
   topo_tail(m, c, base, n, dynamic, advance);
@@ -1634,13 +1631,13 @@ hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Coun
   hipLaunchKernelGGL(k_topology<R>, dim3(1), dim3(kTopoBlock), 0, s, mm, st, w, c, dynamic, advance,
                      snodes, sedges);
   if (mm.etype == 8) return hipGetLastError();  // hexahedra do not split
-  if (mm.topo_multi)
-    hipLaunchKernelGGL(k_topo_apply<R>, dim3(256), dim3(kBlock), 0, s, mm, st, w, c, dynamic, snodes,
-                       sedges);
+  // one-workgroup mode: everything happened in k_topology
+  if (!mm.topo_multi) return hipGetLastError();
+  hipLaunchKernelGGL(k_topo_apply<R>, dim3(256), dim3(kBlock), 0, s, mm, st, w, c, dynamic, snodes,
+                     sedges);
   hipLaunchKernelGGL(k_topo_sums<R>, dim3(256), dim3(kBlock), 0, s, mm, w, c, snodes, sedges);
-  if (mm.topo_multi)
-    hipLaunchKernelGGL(k_topo_finish<R>, dim3(1), dim3(kTopoBlock), 0, s, mm, c, dynamic, advance,
-                       (const int4*)snodes);
+  hipLaunchKernelGGL(k_topo_finish<R>, dim3(1), dim3(kTopoBlock), 0, s, mm, c, dynamic, advance,
+                     (const int4*)snodes);
   return hipGetLastError();
 }
 template hipError_t launch_topology_t<double>(const Mesh&, const State&, const Work&, Counters*,
