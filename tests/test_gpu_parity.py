@@ -155,9 +155,9 @@ def test_front_G_readback():
     sim.close()
 
 
-def test_split_events_cfg0_full_run():
+def test_split_events_cube10_full_run():
     # 10^3-cell cube, 6,000 tets, notch z = 0.5 over x < 0.3, 2,000 steps
-    _case("split events cfg0 full 2000 steps, graphs of 100 steps")
+    _case("split events 10^3-cell cube, 2000 steps, graphs of 100 steps")
     mesh = mg.cube_notched(10)
     sim, orc = _run_pair(mesh, 2000, chunks=4, sim_kw=dict(graph_steps=100))
     ev = _events_equal(sim, orc)

@@ -245,7 +245,7 @@ def test_autograd_window_matches_finite_differences():
 
 
 def test_autograd_final_strain_energy():
-    # the cfg objective: strain energy at the end of the window, composed of
+    # the gradient-window objective: strain energy at the end of the window, composed of
     # the two differentiable pieces (explicit dSE/dE plus the window adjoint)
     _case("autograd end-of-window strain energy vs central differences")
     import torch
