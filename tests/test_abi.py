@@ -67,6 +67,14 @@ def test_calls_out_of_order(lib):
     assert lib.cem_read_energy(ctx, C.byref(e)) == cem.CEM_ESTATE
     n = C.c_int32()
     assert lib.cem_read_splits(ctx, 0, None, C.byref(n)) == cem.CEM_ESTATE
+    assert lib.cem_set_launch(ctx, 1024, 8, 0) == cem.CEM_ESTATE
+    g, l, lay, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    assert lib.cem_autotune(ctx, 5, C.byref(g), C.byref(l), C.byref(lay), C.byref(ms)) == cem.CEM_ESTATE
+    # the topology mode is a host setting: checked without a mesh or a device
+    for bad in (-1, 3):
+        assert lib.cem_set_topology_mode(ctx, bad) == cem.CEM_EINVAL
+    for ok in (0, 1, 2):
+        assert lib.cem_set_topology_mode(ctx, ok) == cem.CEM_OK
     lib.cem_destroy(ctx)
 
 
