@@ -109,7 +109,6 @@ struct Mesh {
   // trilinear hexahedra (etype 8; no splitting, T_cap = T0)
   int4* hnodes;             // [2 T0] node ids 0-3, 4-7
   int2* he2e;               // [6 T0] twelve edge ids
-  int4* hpos;               // [2 T0] positions of the eight (hex, local) entries in the node lists
   double4* hgrad;           // [6 T0] G_i = integral of grad N_i over the hex, 8 x 3 row-major
 
   // prescribed velocities in groups (all null, counts 0, when there are none)
@@ -141,7 +140,8 @@ struct Work {
   void* esig;               // [E_cap] Six<R>: smoothed edge stress
   void* einvV;              // [E_cap] R: kappa_k / sum of effective volumes of the patch,
                             // kappa_k the volume-averaged relative modulus (1 if uniform)
-  void* contrib;            // [entries][3] R: nodal force term of each node-list entry
+  void* contrib;            // [4 T_cap][3] R: nodal force term of each node-list entry, or
+                            // [T_cap] Six<R>: (f/36) sum sigma per element (per hex: (1/12) sum sigma)
   double* partial;          // reduction partials
 };
 

@@ -23,15 +23,6 @@
 #ifndef CEM_CAND_COMPACT_MIN
 #define CEM_CAND_COMPACT_MIN 64
 #endif
-// hexahedra: 1 = the node pass forms the nodal terms from the per-hex stress
-// sum and G (gathered per node-list entry); 0 = the element pass writes them
-#ifndef CEM_HEX_GATHER
-#define CEM_HEX_GATHER 1
-#endif
-// edge stresses gathered together by the element force pass (6 or 3)
-#ifndef CEM_ELEM_GATHER
-#define CEM_ELEM_GATHER 6
-#endif
 
 namespace cem {
 
@@ -87,20 +78,6 @@ template <class R> __device__ __forceinline__ void store6(Six<R>* p, const R* v)
   for (int i = 0; i < 6; ++i) s.v[i] = v[i];
   *p = s;
 }
-
-template <class R> struct Vec4;
-template <> struct Vec4<double> {
-  typedef double4 T;
-  static __device__ __forceinline__ double4 make(double x, double y, double z) {
-    return make_double4(x, y, z, 0.0);
-  }
-};
-template <> struct Vec4<float> {
-  typedef float4 T;
-  static __device__ __forceinline__ float4 make(float x, float y, float z) {
-    return make_float4(x, y, z, 0.0f);
-  }
-};
 
 // Time step of node i (one per instance in a batch).
 __device__ __forceinline__ double node_dt(const Mesh& m, int i) {
@@ -219,26 +196,12 @@ __device__ __forceinline__ void elem_terms(const Mesh& m, int e, int4 nd, int co
   int2 q01 = m.et2e[3 * e], q23 = m.et2e[3 * e + 1], q45 = m.et2e[3 * e + 2];
   double4 x0 = m.X[nd.x & kNodeMask], x1 = m.X[nd.y], x2 = m.X[nd.z], x3 = m.X[nd.w];
   R sg[6];
-#if CEM_ELEM_GATHER == 3
-  {
-    Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
-#pragma unroll
-    for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r];
-  }
-  __asm__ volatile("" ::: "memory");  // the second three loads after the first sums
-  {
-    Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
-#pragma unroll
-    for (int r = 0; r < 6; ++r) sg[r] = sg[r] + s3.v[r] + s4.v[r] + s5.v[r];
-  }
-#else
   {
     Six<R> s0 = load6(esig + q01.x), s1 = load6(esig + q01.y), s2 = load6(esig + q23.x);
     Six<R> s3 = load6(esig + q23.y), s4 = load6(esig + q45.x), s5 = load6(esig + q45.y);
 #pragma unroll
     for (int r = 0; r < 6; ++r) sg[r] = s0.v[r] + s1.v[r] + s2.v[r] + s3.v[r] + s4.v[r] + s5.v[r];
   }
-#endif
   R g[4][3];
   face_normals(x0, x1, x2, x3, g + 1);
 #pragma unroll
@@ -253,36 +216,22 @@ __device__ __forceinline__ void elem_terms(const Mesh& m, int e, int4 nd, int co
   }
 }
 
-// One nodal force term per node-list entry: CEM_TERM_STRIDE values of R
-// (3: packed, the default: a quarter less traffic than padding to 4 for the
-// float64 terms, the same speed for float32).
-#ifndef CEM_TERM_STRIDE
-#define CEM_TERM_STRIDE 3
-#endif
+// One nodal force term per node-list entry: three values of R, packed (a
+// quarter less traffic than padding to four for the float64 terms, the same
+// speed for float32).
 template <class R>
 __device__ __forceinline__ void put_term(R* __restrict__ contrib, int p, R x, R y, R z) {
-#if CEM_TERM_STRIDE == 4
-  ((typename Vec4<R>::T*)contrib)[p] = Vec4<R>::make(x, y, z);
-#else
   R* q = contrib + 3 * (size_t)p;
   q[0] = x;
   q[1] = y;
   q[2] = z;
-#endif
 }
 template <class R>
 __device__ __forceinline__ void get_term(const R* __restrict__ contrib, int p, R& x, R& y, R& z) {
-#if CEM_TERM_STRIDE == 4
-  typename Vec4<R>::T q = ((const typename Vec4<R>::T*)contrib)[p];
-  x = q.x;
-  y = q.y;
-  z = q.z;
-#else
   const R* q = contrib + 3 * (size_t)p;
   x = q[0];
   y = q[1];
   z = q[2];
-#endif
 }
 
 // Store the four nodal terms at the element's positions in the node lists.

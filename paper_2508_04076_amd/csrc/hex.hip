@@ -140,22 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_elem_force_hex(Mesh m, const Six<R>*
       for (int r = 0; r < 6; ++r) sg[r] += a.v[r] + b.v[r];
     }
     const R w = (R)(1.0 / 12.0);
-#if CEM_HEX_GATHER
 #pragma unroll
     for (int r = 0; r < 6; ++r) sg[r] *= w;
     store6((Six<R>*)contrib + e, sg);
-#else
-    double G[24];
-    load_hgrad(m, e, G);
-    int4 p0 = m.hpos[2 * e], p1 = m.hpos[2 * e + 1];
-    const int pos[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      R gx = (R)G[3 * i], gy = (R)G[3 * i + 1], gz = (R)G[3 * i + 2];
-      put_term(contrib, pos[i], w * (gx * sg[0] + gy * sg[3] + gz * sg[5]),
-               w * (gy * sg[1] + gx * sg[3] + gz * sg[4]), w * (gz * sg[2] + gy * sg[4] + gx * sg[5]));
-    }
-#endif
   }
 }
 

@@ -1541,8 +1541,7 @@ template <class R, int G>
 static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
                               Counters* c, int mode, double4* fout, hipStream_t s) {
   if (m.etype == 8) {
-    if (CEM_HEX_GATHER) launch_node_kind<R, G, 1>(m, st, ct, c, mode, fout, s);
-    else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);
+    launch_node_kind<R, G, 1>(m, st, ct, c, mode, fout, s);
   } else {
     if (m.ssum) launch_node_kind<R, G, 2>(m, st, ct, c, mode, fout, s);
     else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);

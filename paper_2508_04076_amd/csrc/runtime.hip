@@ -3,12 +3,6 @@
 #include "../../include/cem.h"
 #include "cem_device.h"
 
-// node order of the internal numbering: 2 Hilbert curve (default), 0 reverse
-// Cuthill-McKee (measured: the curve is 7% faster on the 768k-tet plate and
-// 14% on the 8M-tet block, whose RCM levels are too wide for the L2)
-#ifndef CEM_NODE_ORDER
-#define CEM_NODE_ORDER 2
-#endif
 
 #include <algorithm>
 #include <array>
@@ -237,107 +231,6 @@ int check_orient(cem_ctx* c, int N, const double* X, int T, std::vector<int>& te
   return CEM_OK;
 }
 
-// Reverse Cuthill-McKee order of the node graph (nodes joined by tet edges),
-// one component at a time from a pseudo-peripheral node, neighbours visited by
-// increasing degree.  Gives every tet nearby node ids, so the gathers of the
-// step kernels reuse cache lines.
-void rcm_order(int N, int T, int K, const int (*le)[2], int nle, const std::vector<int>& elems,
-               std::vector<int>& new_of_old) {
-  size_t M = (size_t)nle * T;
-  std::vector<uint64_t> key(M);
-  std::vector<uint32_t> val(M, 0);
-  for (int t = 0; t < T; ++t)
-    for (int q = 0; q < nle; ++q) {
-      uint64_t a = (uint32_t)elems[(size_t)K * t + le[q][0]], b = (uint32_t)elems[(size_t)K * t + le[q][1]];
-      if (a > b) std::swap(a, b);
-      key[(size_t)nle * t + q] = (a << 32) | b;
-    }
-  int nb = bits_for((uint64_t)std::max(N - 1, 1));
-  for (size_t i = 0; i < M; ++i) key[i] = (key[i] >> 32 << nb) | (key[i] & 0xffffffffull);
-  radix_sort(key, val, 2 * nb);
-  std::vector<int> deg(N, 0);
-  size_t E = 0;
-  for (size_t i = 0; i < M; ++i) {
-    if (i > 0 && key[i] == key[i - 1]) continue;
-    key[E++] = key[i];
-  }
-  key.resize(E);
-  const uint64_t lo_mask = (1ull << nb) - 1;
-  for (size_t i = 0; i < E; ++i) {
-    deg[key[i] >> nb]++;
-    deg[key[i] & lo_mask]++;
-  }
-  std::vector<size_t> off(N + 1, 0);
-  for (int i = 0; i < N; ++i) off[i + 1] = off[i] + deg[i];
-  std::vector<int> adj(off[N]);
-  std::vector<size_t> fill(off.begin(), off.end() - 1);
-  for (size_t i = 0; i < E; ++i) {
-    int a = (int)(key[i] >> nb), b = (int)(key[i] & lo_mask);
-    adj[fill[a]++] = b;
-    adj[fill[b]++] = a;
-  }
-  std::vector<int> level(N, -1), order;
-  order.reserve(N);
-  std::vector<char> done(N, 0);
-  std::vector<int> queue;
-  queue.reserve(N);
-  // BFS levels from s over unvisited nodes; returns the last node of the
-  // deepest level with the smallest degree, and the depth
-  auto bfs = [&](int s0, int& depth) {
-    queue.clear();
-    queue.push_back(s0);
-    level[s0] = 0;
-    size_t h = 0;
-    while (h < queue.size()) {
-      int v = queue[h++];
-      for (size_t p = off[v]; p < off[v + 1]; ++p) {
-        int w = adj[p];
-        if (level[w] < 0 && !done[w]) {
-          level[w] = level[v] + 1;
-          queue.push_back(w);
-        }
-      }
-    }
-    depth = level[queue.back()];
-    int best = queue.back();
-    for (int v : queue)
-      if (level[v] == depth && deg[v] < deg[best]) best = v;
-    for (int v : queue) level[v] = -1;
-    return best;
-  };
-  std::vector<int> nbrs;
-  for (int s0 = 0; s0 < N; ++s0) {
-    if (done[s0]) continue;
-    int depth = 0, d2 = 0;
-    int start = bfs(s0, depth);
-    for (int it = 0; it < 4; ++it) {
-      int nxt = bfs(start, d2);
-      if (d2 <= depth) break;
-      depth = d2;
-      start = nxt;
-    }
-    // Cuthill-McKee sweep
-    size_t h = order.size();
-    order.push_back(start);
-    done[start] = 1;
-    while (h < order.size()) {
-      int v = order[h++];
-      nbrs.clear();
-      for (size_t p = off[v]; p < off[v + 1]; ++p)
-        if (!done[adj[p]]) nbrs.push_back(adj[p]);
-      std::sort(nbrs.begin(), nbrs.end(), [&](int x, int y) {
-        return deg[x] != deg[y] ? deg[x] < deg[y] : x < y;
-      });
-      for (int w : nbrs) {
-        done[w] = 1;
-        order.push_back(w);
-      }
-    }
-  }
-  new_of_old.assign(N, 0);
-  for (int k = 0; k < N; ++k) new_of_old[order[N - 1 - k]] = k;
-}
-
 // Hilbert-curve node order (3D, 21 bits per axis), one connected component
 // after another (components in the order of their first node, each on its own
 // bounding box, so a batch of meshes is ordered exactly as its members would
@@ -517,7 +410,6 @@ struct HexTopo {
   std::vector<int> pent;     // 12 H
   std::vector<int> noff;     // N + 1
   std::vector<int> nent;     // 8 H: hex << 3 | local
-  std::vector<int> nodepos;  // 8 H
 };
 
 void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
@@ -552,13 +444,8 @@ void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
   for (int i = 0; i < N; ++i) h.noff[i + 1] += h.noff[i];
   std::vector<int> fill(h.noff.begin(), h.noff.end() - 1);
   h.nent.assign((size_t)8 * H, 0);
-  h.nodepos.assign((size_t)8 * H, 0);
   for (int t = 0; t < H; ++t)
-    for (int l = 0; l < 8; ++l) {
-      int p = fill[hx[8 * (size_t)t + l]]++;
-      h.nent[p] = (t << 3) | l;
-      h.nodepos[8 * (size_t)t + l] = p;
-    }
+    for (int l = 0; l < 8; ++l) h.nent[fill[hx[8 * (size_t)t + l]]++] = (t << 3) | l;
 }
 
 // Jacobian determinants of a trilinear hex at its 2 x 2 x 2 Gauss points:
@@ -1045,11 +932,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   if (r) return r;
   // internal numbering: nodes along a Hilbert curve per component, tets by their
   // smallest new node id (stable in the caller's order)
-#if CEM_NODE_ORDER == 2
   hilbert_order(N, T, 4, ext, X, c->node_new);
-#else
-  rcm_order(N, T, 4, kLE, 6, ext, c->node_new);
-#endif
   c->node_old.assign(N, 0);
   for (int i = 0; i < N; ++i) c->node_old[c->node_new[i]] = i;
   {
@@ -1175,7 +1058,9 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   c->w.esig = vb;
   ALLOC(vb, RS * (size_t)m.E_cap, true);
   c->w.einvV = vb;
-  ALLOC(vb, RS * 4 * ((size_t)4 * m.T_cap), false);
+  // three values per node-list entry, four entries per element slot (the
+  // stress sums take six per slot)
+  ALLOC(vb, RS * 12 * (size_t)m.T_cap, false);
   c->w.contrib = vb;
   ALLOC(c->w.partial, c->n_partial, false);
   ALLOC(c->d_out, 8, false);
@@ -1239,7 +1124,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   HIPCHK(c, hipMemsetAsync(c->w.veps, 0, RS * 6 * (size_t)m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(c->w.esig, 0, RS * 6 * (size_t)m.E_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(c->w.einvV, 0, RS * (size_t)m.E_cap, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 4 * ((size_t)4 * m.T_cap), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 12 * (size_t)m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(m.vol, 0, sizeof(double) * m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(m.invm, 0, sizeof(double) * m.N_cap, c->stream));
   HIPCHK(c, launch_masses(m, c->stream));
@@ -1277,11 +1162,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
     }
     if (!(lo > 0)) return c->fail(CEM_EMESH, "degenerate or inverted hexahedron " + std::to_string(t));
   }
-#if CEM_NODE_ORDER == 2
   hilbert_order(N, H, 8, ext, X, c->node_new);
-#else
-  rcm_order(N, H, 8, kHexLE, 12, ext, c->node_new);
-#endif
   c->node_old.assign(N, 0);
   for (int i = 0; i < N; ++i) c->node_old[c->node_new[i]] = i;
   {
@@ -1352,7 +1233,6 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   ALLOC(c->d_ctr, 1, true);
   ALLOC(m.hnodes, (size_t)2 * H, false);
   ALLOC(m.he2e, (size_t)6 * H, false);
-  ALLOC(m.hpos, (size_t)2 * H, false);
   ALLOC(m.hgrad, (size_t)6 * H, false);
   ALLOC(m.X, m.N_cap, true);
   ALLOC(m.poff, (size_t)m.E0 + 1, false);
@@ -1370,7 +1250,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   c->w.esig = vb;
   ALLOC(vb, RS * (size_t)m.E0, true);
   c->w.einvV = vb;
-  ALLOC(vb, RS * 4 * ((size_t)8 * H), false);
+  ALLOC(vb, RS * 6 * (size_t)H, false);  // the per-hex stress sums
   c->w.contrib = vb;
   ALLOC(c->w.partial, c->n_partial, false);
   ALLOC(c->d_out, 8, false);
@@ -1381,17 +1261,13 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   ALLOC(c->st.uh, m.N_cap, true);
   ALLOC(c->d_tmp, m.N_cap, false);
   ALLOC(c->d_tmp2, m.N_cap, false);
-  std::vector<int4> hn((size_t)2 * H), hp((size_t)2 * H);
+  std::vector<int4> hn((size_t)2 * H);
   for (size_t t = 0; t < (size_t)H; ++t) {
     const int* q = &hx[8 * t];
     hn[2 * t] = make_int4(q[0], q[1], q[2], q[3]);
     hn[2 * t + 1] = make_int4(q[4], q[5], q[6], q[7]);
-    const int* p = &h.nodepos[8 * t];
-    hp[2 * t] = make_int4(p[0], p[1], p[2], p[3]);
-    hp[2 * t + 1] = make_int4(p[4], p[5], p[6], p[7]);
   }
   if ((r = upload(c, m.hnodes, hn.data(), hn.size()))) return r;
-  if ((r = upload(c, m.hpos, hp.data(), hp.size()))) return r;
   std::vector<int2> e2((size_t)6 * H);
   for (size_t i = 0; i < e2.size(); ++i) e2[i] = make_int2(h.he2e[2 * i], h.he2e[2 * i + 1]);
   if ((r = upload(c, m.he2e, e2.data(), e2.size()))) return r;
@@ -1407,7 +1283,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   HIPCHK(c, hipMemsetAsync(c->d_ctr, 0, sizeof(Counters), c->stream));
   for (double4* p : {c->st.u, c->st.v, c->st.a, c->st.uh})
     HIPCHK(c, hipMemsetAsync(p, 0, sizeof(double4) * N, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 4 * ((size_t)8 * H), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 6 * (size_t)H, c->stream));
   HIPCHK(c, launch_masses(m, c->stream));  // hex geometry (G_i, V), then lumped masses
   if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, -1, c->stream));
   else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, -1, c->stream));
