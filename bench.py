@@ -254,9 +254,13 @@ def main():
 
     # ---- 2. FP64 as captured HIP graphs without events, same steps: the
     # timed region of `value` (tet-steps/s over graph replays)
-    graph = None
+    graph, handover = None, None
     if not args.no_graph and gs > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         g = make("fp64", gs)
+        torch.cuda.synchronize()
+        t_up = time.perf_counter() - t0
         g.set_dt(dt)
         g.step(W)
         torch.cuda.synchronize()
@@ -264,11 +268,28 @@ def main():
         g.step(K)
         torch.cuda.synchronize()
         gw = time.perf_counter() - t0
-        ug, _, _ = g.get_state()
+        t0 = time.perf_counter()
+        ug, vg, _ = g.get_state()
+        t_rd = time.perf_counter() - t0
         graph = {"ms_per_step": gw * 1e3 / K, "tet_steps_per_s": T * K / gw,
                  "graph_steps": gs,
                  "bitwise_equal_to_per_pass_run": bool(np.array_equal(ug, u64))}
         log(f"fp64 graphs without events: {gw * 1e3 / K:.4f} ms/step, {T * K / gw:.4e} tet-steps/s")
+        t0 = time.perf_counter()
+        g.set_state(ug, vg)
+        torch.cuda.synchronize()
+        t_wr = time.perf_counter() - t0
+        # the boundary's host hand-overs, outside the timed region of `value`
+        handover = {
+            "mesh_upload_s": t_up, "state_readback_ms": t_rd * 1e3, "state_set_ms": t_wr * 1e3,
+            "tet_steps_per_s_with_readback": T * K / (gw + t_rd),
+            "tet_steps_per_s_with_upload_and_readback": T * K / (t_up + gw + t_rd),
+            "note": ("mesh upload = host preprocessing (order, edges, patches, node lists) plus "
+                     "host-to-device copies, once per run; readback = u, v, a to host; "
+                     f"rates over the {K} timed graph steps"),
+        }
+        log(f"host hand-over: upload {t_up:.2f} s, state readback {t_rd * 1e3:.2f} ms, "
+            f"set {t_wr * 1e3:.2f} ms")
         g.close()
 
     # ---- 3. mixed precision, FP64 split schedule replayed
@@ -389,6 +410,7 @@ def main():
         "autotune": tuned or None,
         "per_pass_run": per_pass_run,
         "mixed": mixed,
+        "host_handover": handover,
     }
     if reaction:
         out["reactions"] = reaction
