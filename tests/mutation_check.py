@@ -1,0 +1,123 @@
+"""Planted-mistake check of the oracle's pins (CPU only; not collected by pytest).
+
+Each mutant plants one plausible mistake in a copy of oracle/oracle.cpp (a
+dropped term, a wrong factor, sign, index or operand, a swapped side), builds
+it, and runs the oracle's CPU tests (tests/test_oracle_*.py) on the copy.  A
+mutant is caught when any test fails.  The GPU library is not involved.
+
+    python tests/mutation_check.py [--workers 6] [name,name,...]
+
+About 17 minutes on 8 cores for the full list.
+"""
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, text in oracle.cpp, replacement); each text occurs exactly once
+MUTANTS = [
+ ("lame mu factor", "*mu = E / (2.0 * (1.0 + nu));", "*mu = E / (1.0 + nu);"),
+ ("lame lambda denominator", "((1.0 + nu) * (1.0 - 2.0 * nu))", "((1.0 + nu) * (1.0 - nu))"),
+ ("C shear = 2 mu", "for (int i = 3; i < 6; ++i) C[i][i] = mu;", "for (int i = 3; i < 6; ++i) C[i][i] = 2.0 * mu;"),
+ ("grad N0 dropped term", "g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);\n  return det / 6.0;", "g[0][d] = -(g[1][d] + g[2][d]);\n  return det / 6.0;"),
+ ("tet volume factor", "  return det / 6.0;\n}", "  return det / 2.0;\n}"),
+ ("B row 4 index", "B[4][c + 1] = gz;", "B[4][c + 1] = gy;"),
+ ("B row 5 operand", "B[5][c + 0] = gz;", "B[5][c + 0] = gx;"),
+ ("inverse transposed", "for (int d = 0; d < 3; ++d) g[l][d] = inv[l - 1][d];", "for (int d = 0; d < 3; ++d) g[l][d] = inv[d][l - 1];"),
+ ("smoothing weight V not Veff", "    for (int j : c->patch[k]) {\n      double w = c->el[j].Veff / S;\n      for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];",
+  "    for (int j : c->patch[k]) {\n      double w = c->el[j].V / S;\n      for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];"),
+ ("smoothing overwrite", "eps[k][r] += w * eps_el[j][r];", "eps[k][r] = w * eps_el[j][r];"),
+ ("V_k missing 1/D", "    if (S == 0.0) continue;\n    double Vk = S / c->D;\n    for (int j : c->patch[k]) {\n      double w = c->el[j].Veff / S;\n      double B[6][24];", "    if (S == 0.0) continue;\n    double Vk = S;\n    for (int j : c->patch[k]) {\n      double w = c->el[j].Veff / S;\n      double B[6][24];"),
+ ("force sign", "f[c->el[j].n[q / 3]][q % 3] += Vk * w * s;", "f[c->el[j].n[q / 3]][q % 3] -= Vk * w * s;"),
+ ("force uses B^T eps", "for (int r = 0; r < 6; ++r) s += B[r][q] * sig[k][r];", "for (int r = 0; r < 6; ++r) s += B[r][q] * eps[k][r];"),
+ ("mass from V", "c->m[e.n[l]] += c->rho * e.Veff / e.nn;", "c->m[e.n[l]] += c->rho * e.V / e.nn;"),
+ ("mass split 1/3", "c->m[e.n[l]] += c->rho * e.Veff / e.nn;", "c->m[e.n[l]] += c->rho * e.Veff / 3.0;"),
+ ("side fraction 1/8 <-> 7/8", "if (nodes_on_side == 1) return 0.125;", "if (nodes_on_side == 1) return 0.875;"),
+ ("copy fraction side swapped", "c->el[t].Veff = side_fraction(4 - nb) * c->el[t].V;", "c->el[t].Veff = side_fraction(nb) * c->el[t].V;"),
+ ("extra node starts at rest", "c->u.push_back(c->u[real]);", "c->u.push_back({0, 0, 0});"),
+ ("crack area 2|2 factor", "return 0.25 * norm(cross(sub(x[A[1]], x[A[0]]), sub(x[Bn[1]], x[Bn[0]])));", "return 0.5 * norm(cross(sub(x[A[1]], x[A[0]]), sub(x[Bn[1]], x[Bn[0]])));"),
+ ("crack area 1|3 factor", "return 0.125 * norm(cross(sub(x[q[1]], x[q[0]]), sub(x[q[2]], x[q[0]])));", "return 0.25 * norm(cross(sub(x[q[1]], x[q[0]]), sub(x[q[2]], x[q[0]])));"),
+ ("delta_2 wrong nodes", "V3 d1 = stretch(N1, N2), d2 = stretch(N2, N3);", "V3 d1 = stretch(N1, N2), d2 = stretch(N1, N3);"),
+ ("stretch test off", "if (d > 0.0) return du;", "if (d > -1e300) return du;"),
+ ("G_I without 1/2", "*GI = 0.5 * (s3 * std::fabs(dot(d1, nI)) + s4 * std::fabs(dot(d2, nI)));", "*GI = (s3 * std::fabs(dot(d1, nI)) + s4 * std::fabs(dot(d2, nI)));"),
+ ("sigma_G4 wrong edge", "double s4 = stress_term(sig[edge(N3, N4)].data(), nI, c->gsig);", "double s4 = stress_term(sig[edge(N1, N4)].data(), nI, c->gsig);"),
+ ("n_I wrong vector", "V3 nI = unit(cross(sub(X3, X1), sub(X4, X2)));", "V3 nI = unit(cross(sub(X3, X1), sub(X4, X1)));"),
+ ("principal projector not square-rooted", "return lmax * std::sqrt(p2);", "return lmax * p2;"),
+ ("lone node wrong", "int lone = (b1 == b2) ? fl[0] : (b0 == b2) ? fl[1] : fl[2];", "int lone = (b1 == b2) ? fl[1] : (b0 == b2) ? fl[0] : fl[2];"),
+ ("predictor a term", "u1[i][d] = c->u[i][d] + dt * c->v[i][d] + 0.5 * dt * dt * c->a[i][d];", "u1[i][d] = c->u[i][d] + dt * c->v[i][d] + dt * dt * c->a[i][d];"),
+ ("velocity update explicit", "c->v[i][d] = c->v[i][d] + 0.5 * dt * (c->a[i][d] + an1);", "c->v[i][d] = c->v[i][d] + dt * an1;"),
+ ("external work rule", "c->W += 0.5 * (rn + rn1) * c->F[i][d] * (u1[i][d] - c->u[i][d]);", "c->W += rn1 * c->F[i][d] * (u1[i][d] - c->u[i][d]);"),
+ ("strain energy factor", "se += 0.5 * (Vsum[k] / c->D) * s;", "se += (Vsum[k] / c->D) * s;"),
+ ("dissipation without Gc", "c->Ud += c->Gc * crack_area(x, e.mask);", "c->Ud += crack_area(x, e.mask);"),
+ ("load ramp inverted", "if (c->ramp_t0 > 0.0 && t < c->ramp_t0) return t / c->ramp_t0;", "if (c->ramp_t0 > 0.0 && t < c->ramp_t0) return 1.0 - t / c->ramp_t0;"),
+ ("bc displacement integral", "if (t0 > 0 && t <= t0) return t * t / (2.0 * t0);", "if (t0 > 0 && t <= t0) return t * t / t0;"),
+ ("reaction sign of load", "R[b][d] = c->m[i] * c->a[i][d] + f[i][d] - r * c->F[i][d];", "R[b][d] = c->m[i] * c->a[i][d] + f[i][d] + r * c->F[i][d];"),
+ ("hex smoothing 1/12 -> 1/6", "  c->D = 12.0;", "  c->D = 6.0;"),
+ ("hex dN factor", "dN[i][1] = f[0] * sg[i][1] * f[2] / 8.0;", "dN[i][1] = f[0] * sg[i][1] * f[2] / 4.0;"),
+]
+
+
+def make_copy(dst):
+    skip = shutil.ignore_patterns("*.so", "__pycache__", "csrc")
+    for d in ("oracle", "tests", "paper_2508_04076_amd"):
+        shutil.copytree(os.path.join(ROOT, d), os.path.join(dst, d), ignore=skip)
+
+
+def run_one(mutant, work, src, tests):
+    name, a, b = mutant
+    if src.count(a) != 1:
+        return name, f"NOT APPLIED (text found {src.count(a)} times)"
+    open(os.path.join(work, "oracle", "oracle.cpp"), "w").write(src.replace(a, b))
+    lib = os.path.join(work, "oracle", "liboracle.so")
+    if os.path.exists(lib):
+        os.remove(lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *tests],
+                       cwd=work, capture_output=True, text=True, timeout=900)
+    if r.returncode == 0:
+        return name, "SURVIVED"
+    failed = [l for l in r.stdout.splitlines() if l.startswith("FAILED")]
+    which = failed[0].split("::")[-1].split(" ")[0] if failed else f"exit {r.returncode}"
+    return name, f"caught by {which}"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="?", help="comma-separated mutant names (default: all)")
+    ap.add_argument("--workers", type=int, default=6)
+    args = ap.parse_args()
+    muts = MUTANTS
+    if args.names:
+        want = args.names.split(",")
+        muts = [m for m in MUTANTS if m[0] in want]
+    src = open(os.path.join(ROOT, "oracle", "oracle.cpp")).read()
+    tests = sorted(os.path.join("tests", f) for f in os.listdir(os.path.join(ROOT, "tests"))
+                   if f.startswith("test_oracle") and f.endswith(".py"))
+    W = max(1, min(args.workers, len(muts)))
+    out = {}
+    with tempfile.TemporaryDirectory(prefix="oracle_mutants_") as tmp:
+        works = []
+        for w in range(W):
+            d = os.path.join(tmp, f"w{w}")
+            make_copy(d)
+            works.append(d)
+
+        def worker(w):
+            return [run_one(m, works[w], src, tests) for m in muts[w::W]]
+
+        with cf.ThreadPoolExecutor(W) as ex:
+            for res in ex.map(worker, range(W)):
+                out.update(res)
+    for name, _, _ in muts:
+        print(f"{name:42s} {out[name]}", flush=True)
+    caught = sum(v.startswith("caught") for v in out.values())
+    print(f"caught {caught} of {len(muts)}")
+    return 0 if caught == len(muts) else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())
