@@ -67,3 +67,39 @@ def test_plate_in_the_benchmark_launch(plate, precision, launch):
         assert _rel(ug, uo) < 1e-5
         assert np.array_equal(eg[:, :3], eo[:, :3])
     sim.close()
+
+
+def test_plate_modified_energy_in_the_benchmark_launch():
+    """A property at the full size: central differences keep
+    KE + SE - W - (dt^2/8) a^T M a constant for any load history (trapezoid
+    work per step).  The 768k-tet plate without its notch (no splits), the
+    1 us load ramp, stress-sum launch at grid 8192, graphs of 50 steps."""
+    _case("plate 768k (no notch), modified energy over 600 steps, stress sums 8192/8, graphs")
+    from paper_2508_04076_amd.cem import Simulation
+    mesh = mg.plate_notched()
+    sim = Simulation.from_mesh(mesh, MAT, presplit=False, ramp_t0=1e-6, Gc=np.inf,
+                               max_splits=64, graph_steps=50)
+    sim.set_launch(8192, 8, "stress_sums")
+    dt = 0.5 * sim.critical_dt()
+    sim.set_dt(dt)
+    # lumped masses rho V / 4 of the unsplit mesh, from the coordinates
+    x = mesh.X[mesh.tets]
+    V = np.abs(np.einsum("ij,ij->i", x[:, 1] - x[:, 0],
+                         np.cross(x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]))) / 6.0
+    mass = np.zeros(len(mesh.X))
+    np.add.at(mass, mesh.tets.ravel(), np.repeat(MAT["rho"] * V / 4.0, 4))
+
+    def modified():
+        e = sim.energy()
+        _, _, a = sim.get_state()
+        return e["KE"] + e["SE"] - e["Wext"] - dt * dt / 8 * (mass[:, None] * a * a).sum(), e["Wext"]
+
+    b0, _ = modified()
+    drift = []
+    for _ in range(6):
+        sim.step(100)
+        b, W = modified()
+        drift.append(b - b0)
+    assert sim.energy()["n_split"] == 0 and W > 0
+    assert np.abs(drift).max() < 1e-9 * W, (drift, W)
+    sim.close()
