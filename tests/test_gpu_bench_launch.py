@@ -103,3 +103,35 @@ def test_plate_modified_energy_in_the_benchmark_launch():
     assert sim.energy()["n_split"] == 0 and W > 0
     assert np.abs(drift).max() < 1e-9 * W, (drift, W)
     sim.close()
+
+
+def _cut_area(x, mask):
+    """Area of the plane polygon through the midpoints of the edges joining the
+    two sides of the partition (convex hull in the polygon's plane)."""
+    from scipy.spatial import ConvexHull
+    side = [(mask >> l) & 1 for l in range(4)]
+    mids = np.array([(x[a] + x[b]) / 2 for a in range(4) for b in range(a + 1, 4)
+                     if side[a] != side[b]])
+    c = mids - mids.mean(axis=0)
+    _, _, vt = np.linalg.svd(c)
+    return ConvexHull(c @ vt[:2].T).volume
+
+
+def test_plate_dissipation_is_Gc_times_the_opened_area():
+    """A property at the full size with dynamic splitting: U_d is Gc times the
+    area of the crack surfaces the G test opened (the pre-split notch excluded),
+    the areas measured from the split records and the input coordinates."""
+    _case("plate 768k, 2,200 steps through the onset of splitting, stress sums 8192/8, graphs")
+    from paper_2508_04076_amd.cem import Simulation
+    mesh = mg.plate_notched()
+    sim = Simulation.from_mesh(mesh, MAT, ramp_t0=1e-6, max_splits=96000, graph_steps=50)
+    sim.set_launch(8192, 8, "stress_sums")
+    sim.set_dt(0.5 * sim.critical_dt())
+    sim.step(2200)
+    ev = sim.splits()[0]
+    dyn = ev[ev[:, 3] > 0]
+    assert len(dyn) > 1000
+    area = sum(_cut_area(mesh.X[mesh.tets[t]], int(k)) for t, k in dyn[:, 1:3])
+    Ud = sim.energy()["Ud"]
+    assert abs(Ud / (MAT["Gc"] * area) - 1) < 1e-12, (Ud, MAT["Gc"] * area)
+    sim.close()
