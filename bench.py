@@ -121,19 +121,22 @@ def copy_peak_gbs(nbytes=1 << 30, reps=10):
     return gbs
 
 
-def counters_for(kernel_src_hash):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "hbm_counters.json")
-    if not os.path.exists(p):
-        return None
-    try:
-        d = json.load(open(p))
-    except Exception:
-        return None
-    if d.get("kernel_source_sha256") != kernel_src_hash:
-        return None
-    return d
+def counters_for(kernel_src_hash, workload="plate"):
+    """HBM traffic per launch of `workload` from the committed rocprofv3 counter
+    summaries (profiles/hbm_counters.json, else hbm_counters_<workload>.json),
+    if they were taken on the current kernel source."""
+    for name in ("hbm_counters.json", f"hbm_counters_{workload}.json"):
+        p = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(p):
+            continue
+        try:
+            d = json.load(open(p))
+        except Exception:
+            continue
+        if d.get("workload") != workload:
+            continue
+        return d if d.get("kernel_source_sha256") == kernel_src_hash else None
+    return None
 
 
 def main():
@@ -215,8 +218,7 @@ def main():
     if args.launch:
         g_, l_, lay_ = args.launch.split(",")
         tuned.update(grid_cap=int(g_), lanes=int(l_), layout=lay_)
-        sim.close()
-        sim = make("fp64", 0)
+        sim.set_launch(tuned["grid_cap"], tuned["lanes"], tuned["layout"])
     elif not args.no_tune:
         sim.set_dt(dt)
         sim.step(W)
@@ -326,7 +328,7 @@ def main():
     dur_s = per_launch[dom] * 1e-3
     alg = ALG_BYTES["fp64"][dom] * T
     achieved = alg / dur_s / 1e9
-    cnt = counters_for(kernel_source_hash())
+    cnt = counters_for(kernel_source_hash(), args.workload)
     if cnt and cnt.get("layout", "terms") != tuned.get("layout", "terms"):
         cnt = None  # counters of the other force layout
     traffic = None

@@ -38,9 +38,17 @@ def test_source_hash_covers_every_hip_file(tmp_path, monkeypatch):
 def test_counters_of_other_sources_are_not_used(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "hbm_counters.json").write_text(json.dumps({"kernel_source_sha256": "0" * 64,
+    (prof / "hbm_counters.json").write_text(json.dumps({"workload": "plate",
+                                                        "kernel_source_sha256": "0" * 64,
                                                         "kernels": {}}))
+    (prof / "hbm_counters_block.json").write_text(json.dumps({"workload": "block",
+                                                              "kernel_source_sha256": "1" * 64,
+                                                              "kernels": {}}))
     live = bench.kernel_source_hash()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.counters_for(live) is None
-    assert bench.counters_for("0" * 64) is not None
+    assert bench.counters_for("0" * 64)["workload"] == "plate"
+    # another workload's summary is found by name, and only for that workload
+    assert bench.counters_for("1" * 64, "block")["workload"] == "block"
+    assert bench.counters_for("0" * 64, "block") is None
+    assert bench.counters_for("1" * 64, "hex") is None
