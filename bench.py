@@ -14,7 +14,8 @@ Prints one JSON line (rank 0).  Phases:
      of the dominant pass; reported as "per_pass_run");
   2. the same steps as captured HIP graphs, and again as plain launches,
      both without events: value and ms_per_step are the faster of the two
-     (which one wins varies between boxes; both are reported under "modes"),
+     (which one wins varies from one machine to another; both are reported
+     under "modes"),
      each bitwise equal to run 1;
   3. mixed precision with the FP64 split schedule replayed (its own tuned
      shape): throughput and relative L2 error of u against the FP64 run;
