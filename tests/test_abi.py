@@ -168,3 +168,19 @@ def test_binding_fails_loudly_without_library(tmp_path):
             cem.load_library(str(tmp_path / "nope.so"))
         finally:
             cem._lib = saved
+
+
+def test_plain_c_caller_compiles_and_links(tmp_path):
+    """include/cem.h is a C header: a C99 program (tests/c_abi/cube_force.c)
+    compiles against it with -pedantic -Werror and links to libcem.so alone."""
+    import importlib.util
+    import subprocess
+    here = os.path.join(ROOT, "tests", "c_abi", "build.py")
+    spec = importlib.util.spec_from_file_location("c_abi_build", here)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    out = str(tmp_path / "cube_force")
+    r = subprocess.run(mod.command(out), capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    dyn = subprocess.run(["readelf", "-d", out], capture_output=True, text=True).stdout
+    assert "[libcem.so]" in dyn and "libstdc++" not in dyn and "torch" not in dyn
