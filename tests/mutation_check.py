@@ -59,6 +59,13 @@ MUTANTS = [
  ("reaction sign of load", "R[b][d] = c->m[i] * c->a[i][d] + f[i][d] - r * c->F[i][d];", "R[b][d] = c->m[i] * c->a[i][d] + f[i][d] + r * c->F[i][d];"),
  ("hex smoothing 1/12 -> 1/6", "  c->D = 12.0;", "  c->D = 6.0;"),
  ("hex dN factor", "dN[i][1] = f[0] * sg[i][1] * f[2] / 8.0;", "dN[i][1] = f[0] * sg[i][1] * f[2] / 4.0;"),
+ ("uncut faces made fronts", "if (b0 == b1 && b1 == b2) continue;  // face not cut", "if (b0 == b1 && b1 == b2 && false) continue;"),
+ ("front face index of the splitter", "r.face = c->nbr_face[s][f];", "r.face = f;"),
+ ("erosion keeps half the volume", "par.Veff = 0.0;", "par.Veff = 0.5 * par.V;"),
+ ("bc acceleration zero on the ramp", "? 1.0 / t0 : 0.0; }", "? 0.0 : 0.0; }"),
+ ("critical step factor", "*dt_crit = 2.0 / std::sqrt(", "*dt_crit = 1.0 / std::sqrt("),
+ ("replayed tet split twice", "      if (c->smask[e.tet] >= 0) continue;\n      e.pattern", "      e.pattern"),
+ ("masses not rebuilt after splits", "  if (!evs.empty() && c->mode == 0) rebuild_masses(c);", "  (void)evs;"),
 ]
 
 

@@ -14,6 +14,9 @@ step, stated without the oracle's own formulas.
   area measured here by an independent planar-polygon routine.
 - Newton's law summed over all nodes, with the internal forces in equilibrium
   (sum f_int = 0): the supports' total force is sum_i m_i a_i - r(t) sum_i F_i.
+- A tet splits once, and splitting moves mass between nodes without creating
+  or losing any (total mass = rho x mesh volume); a notch cut before the run
+  releases no energy.
 """
 import numpy as np
 from scipy.spatial import ConvexHull
@@ -146,3 +149,35 @@ def test_support_forces_balance_the_motion_and_the_loads():
         expect = (mass[:, None] * a).sum(axis=0) - r * F.sum(axis=0)
         scale = r * np.abs(F[:, 2]).sum()
         assert np.allclose(rows[-1, 2:5], expect, rtol=0, atol=1e-10 * scale), (n, rows[-1], expect)
+
+
+def _volume(X, tets):
+    x = X[tets]
+    return np.abs(np.einsum("ij,ij->i", x[:, 1] - x[:, 0],
+                            np.cross(x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]))).sum() / 6.0
+
+
+def test_replayed_splits_split_once_and_keep_the_mass():
+    # a tet splits once (a second entry for it is ignored), and splitting
+    # moves mass between nodes without creating or losing any
+    m = mg.jitter(mg.kuhn_box(4, 4, 4), 0.2, seed=8)
+    o = Oracle(m.X, m.tets, MAT["E"], MAT["nu"], MAT["rho"], Gc=3.0)
+    o.set_dt(0.5 * o.critical_dt())
+    a, b, c = 17, 101, 230
+    o.replay([[2, a, 3], [2, b, 1], [4, a, 6], [5, c, 9]])
+    o.step(6)
+    ev = o.splits()[0]
+    assert ev[:, 1].tolist() == [a, b, c] and ev[:, 2].tolist() == [3, 1, 9]
+    mass = o.masses()
+    assert len(mass) == len(m.X) + 12 and (mass > 0).all()
+    assert _rel(mass.sum(), MAT["rho"] * _volume(m.X, m.tets)) < 1e-13
+
+
+def test_pre_splits_do_not_dissipate():
+    # the notch is cut before the run: no energy is released by it
+    m = mg.cube_notched(6)
+    o = Oracle.from_mesh(m, MAT, Gc=np.inf)
+    o.set_dt(0.5 * o.critical_dt())
+    o.step(20)
+    e = o.energy()
+    assert e["n_split"] == len(m.presplit_tets) > 0 and e["Ud"] == 0.0
