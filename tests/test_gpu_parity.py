@@ -309,3 +309,29 @@ def test_permuted_input_numbering():
     u = mg.random_displacement(sim.n_nodes, 1e-6, seed=9)
     assert _rel(sim.internal_force(u), orc.internal_force(u)) < 1e-12
     sim.close()
+
+
+def test_replay_with_a_repeated_tet_splits_it_once():
+    _case("replay schedule naming one tet twice, jittered 4^3 cube")
+    m = mg.jitter(mg.kuhn_box(4, 4, 4), 0.2, seed=8)
+    m.presplit_tets = None
+    sched = np.array([[2, 17, 3], [2, 101, 1], [4, 17, 6], [5, 230, 9]], dtype=np.int32)
+    sim = _sim(m, Gc=3.0)
+    orc = Oracle(m.X, m.tets, MAT["E"], MAT["nu"], MAT["rho"], Gc=3.0)
+    dt = 0.5 * orc.critical_dt()
+    sim.set_dt(dt)
+    orc.set_dt(dt)
+    rng = np.random.default_rng(3)
+    v0 = rng.standard_normal((len(m.X), 3)) * 1e-3
+    sim.set_state(None, v0)
+    orc.set_state(None, v0)
+    sim.replay_splits(sched)
+    orc.replay(sched)
+    sim.step(8)
+    orc.step(8)
+    eg, eo = sim.splits()[0], orc.splits()[0]
+    assert eg[:, 1].tolist() == [17, 101, 230] and np.array_equal(eg[:, :3], eo[:, :3])
+    ug, vg, _ = sim.get_state()
+    uo, vo, _ = orc.get_state()
+    assert _rel(ug, uo) < 1e-10 and _rel(vg, vo) < 1e-10
+    sim.close()
