@@ -66,6 +66,12 @@ MUTANTS = [
  ("critical step factor", "*dt_crit = 2.0 / std::sqrt(", "*dt_crit = 1.0 / std::sqrt("),
  ("replayed tet split twice", "      if (c->smask[e.tet] >= 0) continue;\n      e.pattern", "      e.pattern"),
  ("masses not rebuilt after splits", "  if (!evs.empty() && c->mode == 0) rebuild_masses(c);", "  (void)evs;"),
+ ("adjoint: v sensitivity misses dt ub", "vb[i][d] = v1 + dt * u1;", "vb[i][d] = v1;"),
+ ("adjoint: a sensitivity misses dt^2/2 ub", "ab[i][d] = 0.5 * dt * v1 + 0.5 * dt * dt * u1;", "ab[i][d] = 0.5 * dt * v1;"),
+ ("adjoint: modulus term sign", "modulus_term(c, lam, us[s + 1], -1.0, Eb);", "modulus_term(c, lam, us[s + 1], 1.0, Eb);"),
+ ("adjoint: modulus term at the final state", "modulus_term(c, lam, us[s + 1], -1.0, Eb);", "modulus_term(c, lam, us.back(), -1.0, Eb);"),
+ ("adjoint: K term sign", "for (int d = 0; d < 3; ++d) ub[i][d] -= f[i][d];", "for (int d = 0; d < 3; ++d) ub[i][d] += f[i][d];"),
+ ("adjoint: modulus weight dropped", "out[c->el[j].parent] += scale * Vk * (c->el[j].Veff / S) * q;", "out[c->el[j].parent] += scale * Vk * q;"),
 ]
 
 
