@@ -72,6 +72,10 @@ MUTANTS = [
  ("adjoint: modulus term at the final state", "modulus_term(c, lam, us[s + 1], -1.0, Eb);", "modulus_term(c, lam, us.back(), -1.0, Eb);"),
  ("adjoint: K term sign", "for (int d = 0; d < 3; ++d) ub[i][d] -= f[i][d];", "for (int d = 0; d < 3; ++d) ub[i][d] += f[i][d];"),
  ("adjoint: modulus weight dropped", "out[c->el[j].parent] += scale * Vk * (c->el[j].Veff / S) * q;", "out[c->el[j].parent] += scale * Vk * q;"),
+ ("traction face area factor", "double A = 0.5 * norm(cross(sub(c->X[b], c->X[a]), sub(c->X[d], c->X[a])));", "double A = norm(cross(sub(c->X[b], c->X[a]), sub(c->X[d], c->X[a])));"),
+ ("traction on one vertex only", "for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + k] * A / 3.0;", "for (int k = 0; k < 3; ++k) c->F[n][k] += q == 0 ? t[3 * f + k] * A : 0.0;"),
+ ("traction components swapped", "for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + k] * A / 3.0;", "for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + (k + 1) % 3] * A / 3.0;"),
+ ("bc velocity without its ramp", "double bc_vel(double t0, double t) { return (t0 > 0 && t <= t0) ? t / t0 : 1.0; }", "double bc_vel(double t0, double t) { return 1.0; }"),
 ]
 
 

@@ -145,3 +145,27 @@ def test_bc_argument_checks():
         o.add_velocity_bc([2], [1], np.zeros((1, 3)))
     with pytest.raises(OracleError):
         o.window_gradient(2)
+
+
+def test_prescribed_velocity_is_the_rate_of_the_prescribed_displacement():
+    # on the ramp the prescribed displacement is quadratic in t, so its central
+    # difference over two steps is its derivative exactly: it must equal the
+    # prescribed velocity at the middle step
+    m = mg.jitter(mg.kuhn_box(3, 3, 2), 0.2, seed=4)
+    o = Oracle(m.X, m.tets, MAT["E"], MAT["nu"], MAT["rho"])
+    dt = 0.5 * o.critical_dt()
+    o.set_dt(dt)
+    n = len(m.X)
+    v0 = np.array([0.8, -0.3, 0.5])
+    o.add_velocity_bc(np.arange(n), np.full(n, 7), np.tile(v0, (n, 1)), 40 * dt)
+    us, vs = [], []
+    for _ in range(30):
+        o.step(1)
+        u, v, _ = o.get_state()
+        us.append(u)
+        vs.append(v)
+    for k in range(1, 29):
+        rate = (us[k + 1] - us[k - 1]) / (2 * dt)
+        assert np.allclose(vs[k], rate, rtol=1e-9, atol=1e-12), k
+    # and it ramps: at step k + 1 (time (k + 1) dt) the velocity is v0 (k + 1) / 40
+    assert np.allclose(vs[9], v0 * 10 / 40, rtol=1e-12, atol=0)
