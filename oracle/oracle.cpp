@@ -644,14 +644,14 @@ std::vector<Event> decide_splits(orc_ctx* c) {
   return out;
 }
 
-void apply_events(orc_ctx* c, const std::vector<Event>& evs, bool dynamic) {
+// Apply the splits decided in a step.  Each opens a crack surface and so
+// dissipates Gc times its area (pre-splits, applied by orc_presplit, do not).
+void apply_events(orc_ctx* c, const std::vector<Event>& evs) {
   const auto& on = c->orig;
   for (const Event& e : evs) {
-    if (dynamic) {
-      V3 x[4];
-      for (int l = 0; l < 4; ++l) x[l] = c->X[on[e.tet][l]];
-      c->Ud += c->Gc * crack_area(x, e.mask);
-    }
+    V3 x[4];
+    for (int l = 0; l < 4; ++l) x[l] = c->X[on[e.tet][l]];
+    c->Ud += c->Gc * crack_area(x, e.mask);
     apply_split(c, e.tet, e.mask);
     c->events.push_back(e);
     c->events.back().step = (int)c->step;
@@ -727,7 +727,7 @@ void one_step(orc_ctx* c) {
   } else {
     c->nfront = (int)fronts(c).size();
   }
-  apply_events(c, evs, true);
+  apply_events(c, evs);
 }
 
 double strain_energy(const orc_ctx* c) {
