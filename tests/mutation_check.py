@@ -76,6 +76,12 @@ MUTANTS = [
  ("traction on one vertex only", "for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + k] * A / 3.0;", "for (int k = 0; k < 3; ++k) c->F[n][k] += q == 0 ? t[3 * f + k] * A : 0.0;"),
  ("traction components swapped", "for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + k] * A / 3.0;", "for (int k = 0; k < 3; ++k) c->F[n][k] += t[3 * f + (k + 1) % 3] * A / 3.0;"),
  ("bc velocity without its ramp", "double bc_vel(double t0, double t) { return (t0 > 0 && t <= t0) ? t / t0 : 1.0; }", "double bc_vel(double t0, double t) { return 1.0; }"),
+ ("split neighbours taken as fronts", "if (nbt < 0 || c->smask[nbt] >= 0) continue;", "if (nbt < 0) continue;"),
+ ("G_max is the last rather than the largest", "if (!any || best > c->Gmax) c->Gmax = best;", "c->Gmax = best;"),
+ ("pattern I cuts off the wrong pair", "*maskI = (1 << lN2) | (1 << lN4);", "*maskI = (1 << lN2) | (1 << lN1);"),
+ ("pattern II cuts off the wrong node", "*maskII = (1 << lN2);", "*maskII = (1 << lN4);"),
+ ("initial acceleration ignores the ramp", "for (int d = 0; d < 3; ++d) c->a[i][d] = accel(c, i, r * c->F[i][d] - f[i][d]);", "for (int d = 0; d < 3; ++d) c->a[i][d] = accel(c, i, c->F[i][d] - f[i][d]);"),
+ ("kinetic energy factor", "ke += 0.5 * c->m[i] * dot(c->v[i], c->v[i]);", "ke += c->m[i] * dot(c->v[i], c->v[i]);"),
 ]
 
 

@@ -17,6 +17,8 @@ step, stated without the oracle's own formulas.
 - A tet splits once, and splitting moves mass between nodes without creating
   or losing any (total mass = rho x mesh volume); a notch cut before the run
   releases no energy.
+- The crack grows continuously: each split continues a neighbour's crack
+  across their shared face (Section 3); G_max is the largest front rate.
 """
 import numpy as np
 from scipy.spatial import ConvexHull
@@ -181,3 +183,57 @@ def test_pre_splits_do_not_dissipate():
     o.step(20)
     e = o.energy()
     assert e["n_split"] == len(m.presplit_tets) > 0 and e["Ud"] == 0.0
+
+
+def test_crack_grows_continuously_across_front_faces():
+    # every split decided in a run continues the crack of a neighbour split
+    # earlier: on a face they share, the new partition groups the three face
+    # nodes as the neighbour's does, and that face is cut (the crack surface
+    # passes through it)
+    m = mg.cube_notched(6)
+    o = Oracle.from_mesh(m, MAT)
+    o.set_dt(0.5 * o.critical_dt())
+    o.step(240)
+    ev = o.splits()[0]
+    dyn = ev[ev[:, 3] > 0]
+    assert len(dyn) > 5
+    tets = m.tets
+    faces = {}
+    for t in range(len(tets)):
+        for f in range(4):
+            key = tuple(sorted(int(x) for k, x in enumerate(tets[t]) if k != f))
+            faces.setdefault(key, []).append(t)
+    split_at = {int(t): (int(s), int(k)) for s, t, k, _ in ev}
+
+    def side(t, k, node):
+        return (k >> list(tets[t]).index(node)) & 1
+
+    for s, t, k, _ in dyn:
+        ok = False
+        for key, owners in faces.items():
+            if t not in owners or len(owners) != 2:
+                continue
+            nb = owners[0] if owners[1] == t else owners[1]
+            if nb not in split_at or split_at[nb][0] >= s:
+                continue
+            kn = split_at[nb][1]
+            cut = len({side(nb, kn, x) for x in key}) == 2
+            same = all((side(t, k, a) == side(t, k, b)) == (side(nb, kn, a) == side(nb, kn, b))
+                       for a in key for b in key)
+            ok = ok or (cut and same)
+        assert ok, (s, t, k)
+
+
+def test_Gmax_is_the_largest_front_release_rate():
+    # with a toughness no front reaches, the crack pass runs but splits nothing:
+    # the step's G_max is then the largest G_I or G_II among the fronts of the
+    # same state, as the per-front readback reports them
+    m = mg.cube_notched(6)
+    o = Oracle.from_mesh(m, MAT, Gc=1e12)
+    o.set_dt(0.5 * o.critical_dt())
+    for n in (20, 60, 120):
+        o.step(n - int(o.energy()["step"]))
+        e = o.energy()
+        _, g = o.front_G()
+        assert len(g) > 10 and e["n_split"] == len(m.presplit_tets)
+        assert e["Gmax"] == g.max() and e["Gmax"] > 0
