@@ -118,9 +118,11 @@ def _cut_area(x, mask):
 
 
 def test_plate_dissipation_is_Gc_times_the_opened_area():
-    """A property at the full size with dynamic splitting: U_d is Gc times the
+    """Properties at the full size with dynamic splitting: U_d is Gc times the
     area of the crack surfaces the G test opened (the pre-split notch excluded),
-    the areas measured from the split records and the input coordinates."""
+    the areas measured from the split records and the input coordinates; and
+    the crack grows continuously, each split continuing an earlier one across
+    a shared face."""
     _case("plate 768k, 2,200 steps through the onset of splitting, stress sums 8192/8, graphs")
     from paper_2508_04076_amd.cem import Simulation
     mesh = mg.plate_notched()
@@ -135,3 +137,43 @@ def test_plate_dissipation_is_Gc_times_the_opened_area():
     Ud = sim.energy()["Ud"]
     assert abs(Ud / (MAT["Gc"] * area) - 1) < 1e-12, (Ud, MAT["Gc"] * area)
     sim.close()
+    _assert_crack_continues(mesh.tets, ev)
+
+
+def _assert_crack_continues(tets, ev):
+    """Every split decided in the run cuts a face it shares with a tet split in
+    an earlier step, grouping that face's three nodes as the neighbour does."""
+    T = len(tets)
+    fl = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
+    fn = np.sort(tets[:, fl].reshape(-1, 3), axis=1)  # (4T, 3): face f of tet t at 4t + f
+    _, fid = np.unique(fn, axis=0, return_inverse=True)
+    fid = fid.ravel()
+    order = np.argsort(fid, kind="stable")
+    owner_of = {}
+    for i in range(0, len(order) - 1):
+        a_, b_ = order[i], order[i + 1]
+        if fid[a_] == fid[b_]:
+            owner_of[int(a_)] = int(b_) // 4
+            owner_of[int(b_)] = int(a_) // 4
+    split_at = {int(t): (int(s), int(k)) for s, t, k, _ in ev}
+
+    def side(t, k, node):
+        return (k >> int(np.nonzero(tets[t] == node)[0][0])) & 1
+
+    dyn = ev[ev[:, 3] > 0]
+    for s, t, k, _ in dyn:
+        ok = False
+        for f in range(4):
+            nb = owner_of.get(4 * int(t) + f)
+            if nb is None or nb not in split_at or split_at[nb][0] >= s:
+                continue
+            kn = split_at[nb][1]
+            key = tets[t][fl[f]]
+            cut = len({side(nb, kn, x) for x in key}) == 2
+            same = all((side(t, k, a) == side(t, k, b)) == (side(nb, kn, a) == side(nb, kn, b))
+                       for a in key for b in key)
+            if cut and same:
+                ok = True
+                break
+        assert ok, (s, t, k)
+    assert T > 0
