@@ -82,6 +82,11 @@ MUTANTS = [
  ("pattern II cuts off the wrong node", "*maskII = (1 << lN2);", "*maskII = (1 << lN4);"),
  ("initial acceleration ignores the ramp", "for (int d = 0; d < 3; ++d) c->a[i][d] = accel(c, i, r * c->F[i][d] - f[i][d]);", "for (int d = 0; d < 3; ++d) c->a[i][d] = accel(c, i, c->F[i][d] - f[i][d]);"),
  ("kinetic energy factor", "ke += 0.5 * c->m[i] * dot(c->v[i], c->v[i]);", "ke += c->m[i] * dot(c->v[i], c->v[i]);"),
+ ("modulus smoothing weight by V", "    double w = c->el[j].Veff / S;\n    for (int r = 0; r < 6; ++r)\n      for (int q = 0; q < 6; ++q) Ck[r][q] += w * Cj[r][q];", "    double w = c->el[j].V / S;\n    for (int r = 0; r < 6; ++r)\n      for (int q = 0; q < 6; ++q) Ck[r][q] += w * Cj[r][q];"),
+ ("copy takes a slot's modulus", "lame(c->Et[c->el[j].parent], c->nu, &lam, &mu);", "lame(c->Et[j < c->T0 ? j : 0], c->nu, &lam, &mu);"),
+ ("reaction work without the trapezoid", "c->grp_W[g] += 0.5 * (c->bc_R[b][d] + R[b][d]) * (c->u[i][d] - u0[i][d]);", "c->grp_W[g] += R[b][d] * (c->u[i][d] - u0[i][d]);"),
+ ("bc predictor one step late", "c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn1);", "c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn);"),
+ ("no gap for equal principal stresses", "double gap = 1e-10 * amax;", "double gap = 0.0;"),
 ]
 
 

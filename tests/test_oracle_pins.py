@@ -257,6 +257,17 @@ def test_stress_term_special_cases():
     TR = R @ T @ R.T
     tR = [TR[0, 0], TR[1, 1], TR[2, 2], TR[0, 1], TR[1, 2], TR[0, 2]]
     assert abs(stress_term(tR, R @ n) - stress_term(t, n)) < 1e-13
+    # tied largest eigenvalue in a rotated frame, where the solver's two equal
+    # eigenvalues come out differing by rounding: still the whole eigenspace,
+    # sigma_1 sqrt(1 - (e3 . n)^2) with e3 the direction of the smaller one
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        Q = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+        S = Q @ np.diag([3.0, 3.0, -1.0]) @ Q.T
+        sv = [S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[1, 2], S[0, 2]]
+        m = rng.standard_normal(3)
+        m /= np.linalg.norm(m)
+        assert abs(stress_term(sv, m) - 3.0 * np.sqrt(1 - (Q[:, 2] @ m) ** 2)) < 1e-12
 
 
 def test_midpoint_cut_geometry():
