@@ -87,6 +87,9 @@ MUTANTS = [
  ("reaction work without the trapezoid", "c->grp_W[g] += 0.5 * (c->bc_R[b][d] + R[b][d]) * (c->u[i][d] - u0[i][d]);", "c->grp_W[g] += R[b][d] * (c->u[i][d] - u0[i][d]);"),
  ("bc predictor one step late", "c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn1);", "c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn);"),
  ("no gap for equal principal stresses", "double gap = 1e-10 * amax;", "double gap = 0.0;"),
+ ("hex Gauss points at the wrong abscissa", "const double a = 1.0 / std::sqrt(3.0);", "const double a = 0.5;"),
+ ("1|3 crack area from the wrong side", "int big = (nb == 1) ? 0 : 1;", "int big = (nb == 1) ? 1 : 0;"),
+ ("hex inverse Jacobian entry transposed", "    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "    inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
 ]
 
 
