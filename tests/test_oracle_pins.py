@@ -352,6 +352,25 @@ def test_front_G_uniaxial_hand_case():
     o.set_state(uc, None)
     _, g3 = o.front_G()
     assert np.all(g3 == 0)
+    # a quarter turn about z with a 1% stretch lengthens every edge although
+    # each edge's displacement points against the edge (dX . du < 0): the
+    # stretch test keeps delta = du, so G_I does not vanish (G_II does here for
+    # another reason: the largest principal stress is along z and n_II lies in
+    # the x-y plane)
+    Rz = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    ur = X @ (1.01 * Rz - np.eye(3)).T
+    for i, j in ((N1, N2), (N2, N3)):
+        assert (X[j] - X[i]) @ (ur[j] - ur[i]) < 0 and stretched_by(X, ur, i, j)
+    uq = np.zeros_like(uu)
+    uq[:5] = ur
+    uq[5:9] = ur[[0, 1, 2, 3]]
+    o.set_state(uq, None)
+    _, g4 = o.front_G()
+    assert g4[0, 0] != 0 and g4[0, 1] == 0
+
+
+def stretched_by(X, u, i, j):
+    return np.linalg.norm(X[j] + u[j] - X[i] - u[i]) > np.linalg.norm(X[j] - X[i])
 
 
 def test_front_G_rotation_and_relabel_invariance():
