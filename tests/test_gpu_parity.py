@@ -335,3 +335,32 @@ def test_replay_with_a_repeated_tet_splits_it_once():
     uo, vo, _ = orc.get_state()
     assert _rel(ug, uo) < 1e-10 and _rel(vg, vo) < 1e-10
     sim.close()
+
+
+def test_front_G_under_a_quarter_turn():
+    # two tets sharing a face, the first pre-split with node 1 alone: the
+    # second is a front.  A quarter turn about z with a 1% stretch lengthens
+    # every edge although each displacement points against its edge, so the
+    # stretch test must keep delta = du (the quadratic term decides)
+    _case("front G, two tets, quarter turn + 1% stretch")
+    from paper_2508_04076_amd.cem import Simulation
+    X = np.array([[0.2, -1.0, 0.1], [0.0, 0.0, 0.0], [0.0, 1.0, 0.0], [1.0, 0.0, 0.0],
+                  [0.0, 1.0, 1.0]])
+    t = np.array([[0, 1, 2, 3], [1, 2, 3, 4]])
+    mat = dict(MAT, Gc=1e30)
+    sim = Simulation(X, t, mat, max_splits=8)
+    orc = Oracle(X, t, mat["E"], mat["nu"], mat["rho"], Gc=1e30)
+    sim.presplit([0], [2])
+    orc.presplit([0], [2])
+    Rz = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    ur = X @ (1.01 * Rz - np.eye(3)).T
+    uq = np.zeros((sim.n_nodes, 3))
+    uq[:5] = ur
+    uq[5:9] = ur[[0, 1, 2, 3]]
+    sim.set_state(uq, None)
+    orc.set_state(uq, None)
+    tg, gg = sim.front_G()
+    to, go = orc.front_G()
+    assert np.array_equal(tg, to) and go[0, 0] != 0
+    assert np.abs(gg - go).max() <= 1e-10 * np.abs(go).max()
+    sim.close()
