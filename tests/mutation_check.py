@@ -89,6 +89,9 @@ MUTANTS = [
  ("no gap for equal principal stresses", "double gap = 1e-10 * amax;", "double gap = 0.0;"),
  ("hex Gauss points at the wrong abscissa", "const double a = 1.0 / std::sqrt(3.0);", "const double a = 0.5;"),
  ("1|3 crack area from the wrong side", "int big = (nb == 1) ? 0 : 1;", "int big = (nb == 1) ? 1 : 0;"),
+ ("strain energy without 1/D", "se += 0.5 * (Vsum[k] / c->D) * s;", "se += 0.5 * Vsum[k] * s;"),
+ ("masses not rebuilt after pre-splits", "  if (c->mode == 0) rebuild_masses(c);\n  c->need_init = true;", "  c->need_init = true;"),
+ ("2|2 crack area from the wrong diagonals", "return 0.25 * norm(cross(sub(x[A[1]], x[A[0]]), sub(x[Bn[1]], x[Bn[0]])));", "return 0.25 * norm(cross(sub(x[A[1]], x[Bn[0]]), sub(x[Bn[1]], x[A[0]])));"),
  ("stretch test without its quadratic term", "double d = 2.0 * dot(dX, du) + dot(du, du);", "double d = 2.0 * dot(dX, du);"),
  ("hex inverse Jacobian entry transposed", "    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "    inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
 ]
