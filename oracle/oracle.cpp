@@ -16,7 +16,10 @@
 //     2 dX.du + |du|^2 > 0; the Heaviside step at 0 is 0;
 //   * the "maximum principal stress vector" projected on n is taken as
 //     sigma_1 |P_1 n| (P_1: projector on the eigenspace of the largest
-//     eigenvalue, ties within 1e-10 max|lambda|), or n.sigma.n (gsig = 1);
+//     eigenvalue; eigenvalues within 1e-6 max|lambda| of the largest count as
+//     tied, because stresses computed in two different summation orders
+//     differ by rounding and the eigenvector of a closer pair moves by that
+//     rounding over the gap), or n.sigma.n (gsig = 1);
 //     projected stretches enter as |delta.n|;
 //   * crack front: a face of an intact tet shared with a split tet whose
 //     partition cuts that face; the node alone on its side is N2, the other
@@ -272,7 +275,7 @@ double stress_term(const double* s6, const V3& n, int gsig) {
   jacobi_eig(3, A, w, vec);
   double lmax = std::max(w[0], std::max(w[1], w[2]));
   double amax = std::max(std::fabs(w[0]), std::max(std::fabs(w[1]), std::fabs(w[2])));
-  double gap = 1e-10 * amax;
+  double gap = 1e-6 * amax;
   double p2 = 0.0;
   for (int i = 0; i < 3; ++i) {
     if (w[i] >= lmax - gap) {

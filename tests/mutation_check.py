@@ -7,7 +7,7 @@ mutant is caught when any test fails.  The GPU library is not involved.
 
     python tests/mutation_check.py [--workers 6] [name,name,...]
 
-About 17 minutes on 8 cores for the full list.
+About 30 minutes on 8 cores for the full list.
 """
 import argparse
 import concurrent.futures as cf
@@ -86,13 +86,19 @@ MUTANTS = [
  ("copy takes a slot's modulus", "lame(c->Et[c->el[j].parent], c->nu, &lam, &mu);", "lame(c->Et[j < c->T0 ? j : 0], c->nu, &lam, &mu);"),
  ("reaction work without the trapezoid", "c->grp_W[g] += 0.5 * (c->bc_R[b][d] + R[b][d]) * (c->u[i][d] - u0[i][d]);", "c->grp_W[g] += R[b][d] * (c->u[i][d] - u0[i][d]);"),
  ("bc predictor one step late", "c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn1);", "c->bc_uref[b][d] + c->bc_v0[b][d] * bc_disp(c->grp_t0[c->bc_group[b]], tn);"),
- ("no gap for equal principal stresses", "double gap = 1e-10 * amax;", "double gap = 0.0;"),
+ ("no gap for equal principal stresses", "double gap = 1e-6 * amax;", "double gap = 0.0;"),
  ("hex Gauss points at the wrong abscissa", "const double a = 1.0 / std::sqrt(3.0);", "const double a = 0.5;"),
  ("1|3 crack area from the wrong side", "int big = (nb == 1) ? 0 : 1;", "int big = (nb == 1) ? 1 : 0;"),
  ("strain energy without 1/D", "se += 0.5 * (Vsum[k] / c->D) * s;", "se += 0.5 * Vsum[k] * s;"),
  ("masses not rebuilt after pre-splits", "  if (c->mode == 0) rebuild_masses(c);\n  c->need_init = true;", "  c->need_init = true;"),
  ("2|2 crack area from the wrong diagonals", "return 0.25 * norm(cross(sub(x[A[1]], x[A[0]]), sub(x[Bn[1]], x[Bn[0]])));", "return 0.25 * norm(cross(sub(x[A[1]], x[Bn[0]]), sub(x[Bn[1]], x[A[0]])));"),
  ("stretch test without its quadratic term", "double d = 2.0 * dot(dX, du) + dot(du, du);", "double d = 2.0 * dot(dX, du);"),
+ ("pattern II wins ties", "if (GII > best) { best = GII; bmask = mII; bpat = 2; }", "if (GII >= best) { best = GII; bmask = mII; bpat = 2; }"),
+ ("later face wins ties", "if (GI > best) { best = GI; bmask = mI; bpat = 1; }", "if (GI >= best) { best = GI; bmask = mI; bpat = 1; }"),
+ ("fronts visited in reverse face order", "return x.c != y.c ? x.c < y.c : x.face < y.face;", "return x.c != y.c ? x.c < y.c : x.face > y.face;"),
+ ("Griffith test strict", "if (best >= c->Gc) out.push_back", "if (best > c->Gc) out.push_back"),
+ ("tie gap too narrow", "double gap = 1e-6 * amax;", "double gap = 1e-10 * amax;"),
+ ("tie gap too wide", "double gap = 1e-6 * amax;", "double gap = 1e-5 * amax;"),
  ("hex inverse Jacobian entry transposed", "    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "    inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
 ]
 
