@@ -307,67 +307,67 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st,
 
 // ---------------------------------------------------------------- crack pass
 
+// One Jacobi rotation in the (p, q) plane of the symmetric 3x3 tensor a, with
+// the tangent of the stable 2x2 symmetric Schur decomposition (Golub and Van
+// Loan, the classical Jacobi method): a_pq becomes 0, the diagonal moves by
+// t a_pq, the third row/column and the columns p, q of v rotate.
+template <int p, int q>
+__device__ __forceinline__ void jacobi_rot(double (&a)[3][3], double (&v)[3][3]) {
+  constexpr int r = 3 - p - q;
+  double apq = a[p][q];
+  if (apq == 0.0) return;
+  double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+  double t = fabs(th) > 1e150 ? 0.5 / th
+                               : (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+  double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+  a[p][p] -= t * apq;
+  a[q][q] += t * apq;
+  a[p][q] = a[q][p] = 0.0;
+  double arp = a[r][p], arq = a[r][q];
+  a[r][p] = a[p][r] = c * arp - s * arq;
+  a[r][q] = a[q][r] = s * arp + c * arq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double vp = v[k][p], vq = v[k][q];
+    v[k][p] = c * vp - s * vq;
+    v[k][q] = s * vp + c * vq;
+  }
+}
+
 // Stress term of Eqs. G-I / G-II for the smoothed edge stress s (Voigt) and the
 // unit crack normal n.  gsig 0: sigma_1 |P_1 n|, P_1 the projector on the
-// eigenspace of the largest eigenvalue (eigenvalues within 1e-10 max|lambda|
-// count as equal); gsig 1: n . sigma . n.
+// eigenspace of the largest eigenvalue; eigenvalues within 1e-6 max|lambda| of
+// it count as equal (two evaluations of one edge stress in different summation
+// orders differ by rounding, and the eigenvector of a closer pair moves by that
+// rounding over the gap).  The eigenpairs come from cyclic Jacobi sweeps,
+// accurate to rounding for the eigenvalues and to rounding over the gap for
+// the eigenvectors.  gsig 1: n . sigma . n.
 __device__ double stress_term(const double* s, double nx, double ny, double nz, int gsig) {
-  double a11 = s[0], a22 = s[1], a33 = s[2], a12 = s[3], a23 = s[4], a13 = s[5];
   if (gsig == 1) {
-    return nx * (a11 * nx + a12 * ny + a13 * nz) + ny * (a12 * nx + a22 * ny + a23 * nz) +
-           nz * (a13 * nx + a23 * ny + a33 * nz);
+    return nx * (s[0] * nx + s[3] * ny + s[5] * nz) + ny * (s[3] * nx + s[1] * ny + s[4] * nz) +
+           nz * (s[5] * nx + s[4] * ny + s[2] * nz);
   }
-  double p1 = a12 * a12 + a13 * a13 + a23 * a23;
-  double l1, l2, l3;  // l1 >= l2 >= l3
-  if (p1 == 0.0) {
-    // diagonal: eigenvectors are the axes
-    double d[3] = {a11, a22, a33};
-    double lmax = fmax(a11, fmax(a22, a33));
-    double amax = fmax(fabs(a11), fmax(fabs(a22), fabs(a33)));
-    double gap = 1e-10 * amax;
-    double nn[3] = {nx, ny, nz};
-    double p2 = 0;
-    for (int i = 0; i < 3; ++i)
-      if (d[i] >= lmax - gap) p2 += nn[i] * nn[i];
-    return lmax * sqrt(p2);
+  double a[3][3] = {{s[0], s[3], s[5]}, {s[3], s[1], s[4]}, {s[5], s[4], s[2]}};
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-36 * dia)) break;
+    jacobi_rot<0, 1>(a, v);
+    jacobi_rot<0, 2>(a, v);
+    jacobi_rot<1, 2>(a, v);
   }
-  // trigonometric solution of the characteristic cubic
-  double q = (a11 + a22 + a33) / 3.0;
-  double b11 = a11 - q, b22 = a22 - q, b33 = a33 - q;
-  double p2 = b11 * b11 + b22 * b22 + b33 * b33 + 2.0 * p1;
-  double p = sqrt(p2 / 6.0);
-  double detB = b11 * (b22 * b33 - a23 * a23) - a12 * (a12 * b33 - a23 * a13) +
-                a13 * (a12 * a23 - b22 * a13);
-  double r = detB / (2.0 * p * p * p);
-  r = fmin(1.0, fmax(-1.0, r));
-  double phi = acos(r) / 3.0;
-  l1 = q + 2.0 * p * cos(phi);
-  l3 = q + 2.0 * p * cos(phi + 2.0943951023931954923);  // + 2 pi / 3
-  l2 = 3.0 * q - l1 - l3;
-  double amax = fmax(fabs(l1), fmax(fabs(l2), fabs(l3)));
-  double gap = 1e-10 * amax;
-  int mult = 1 + (l2 >= l1 - gap) + (l3 >= l1 - gap);
-  if (mult == 3) return l1;  // |P n| = |n| = 1
-  // eigenvector of the simple eigenvalue (l1 if mult == 1, else l3) from the
-  // largest cross product of two rows of (A - lambda I)
-  double lam = (mult == 1) ? l1 : l3;
-  double r0x = a11 - lam, r0y = a12, r0z = a13;
-  double r1x = a12, r1y = a22 - lam, r1z = a23;
-  double r2x = a13, r2y = a23, r2z = a33 - lam;
-  double c01x = r0y * r1z - r0z * r1y, c01y = r0z * r1x - r0x * r1z, c01z = r0x * r1y - r0y * r1x;
-  double c02x = r0y * r2z - r0z * r2y, c02y = r0z * r2x - r0x * r2z, c02z = r0x * r2y - r0y * r2x;
-  double c12x = r1y * r2z - r1z * r2y, c12y = r1z * r2x - r1x * r2z, c12z = r1x * r2y - r1y * r2x;
-  double d01 = c01x * c01x + c01y * c01y + c01z * c01z;
-  double d02 = c02x * c02x + c02y * c02y + c02z * c02z;
-  double d12 = c12x * c12x + c12y * c12y + c12z * c12z;
-  double vx, vy, vz, dd;
-  if (d01 >= d02 && d01 >= d12) { vx = c01x; vy = c01y; vz = c01z; dd = d01; }
-  else if (d02 >= d12) { vx = c02x; vy = c02y; vz = c02z; dd = d02; }
-  else { vx = c12x; vy = c12y; vz = c12z; dd = d12; }
-  double proj = (vx * nx + vy * ny + vz * nz);
-  double c2 = dd > 0 ? proj * proj / dd : 0.0;  // (v . n)^2 for unit v
-  if (mult == 1) return l1 * sqrt(c2);
-  return l1 * sqrt(fmax(0.0, 1.0 - c2));      // eigenspace of l1 is the plane normal to v3
+  double w[3] = {a[0][0], a[1][1], a[2][2]};
+  double lmax = fmax(w[0], fmax(w[1], w[2]));
+  double amax = fmax(fabs(w[0]), fmax(fabs(w[1]), fabs(w[2])));
+  double gap = 1e-6 * amax;
+  double p2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double c = v[0][i] * nx + v[1][i] * ny + v[2][i] * nz;
+    if (w[i] >= lmax - gap) p2 += c * c;
+  }
+  return lmax * sqrt(p2);
 }
 
 template <class R> __device__ __forceinline__ void load_sig(const Six<R>* esig, int k, double* s) {
