@@ -63,6 +63,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -76,6 +77,24 @@ V3 cross(const V3& a, const V3& b) {
   return {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
 }
 double norm(const V3& a) { return std::sqrt(dot(a, a)); }
+
+// Runs fn(lo, hi) over nt contiguous pieces of [0, n) on nt threads (the
+// calling thread alone when nt <= 1).  Callers give each item to exactly one
+// piece and keep every per-item sum in the serial order, so results do not
+// depend on nt.
+template <class Fn>
+void par_range(int nt, size_t n, Fn fn) {
+  if (nt <= 1 || n < 2) {
+    fn((size_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    size_t lo = n * t / nt, hi = n * (t + 1) / nt;
+    th.emplace_back([=] { fn(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
 
 // Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major).
 // On return w holds the eigenvalues and column i of vec the i-th eigenvector.
@@ -162,6 +181,7 @@ struct orc_ctx {
   std::vector<double> Et;  // Young's modulus of each original tet
   bool hetero = false;     // Et differs from the scalar E
   bool frozen = false;     // topology frozen: no crack pass
+  int nthreads = 1;        // threads of the element, edge and node loops
   // prescribed velocities (Dirichlet), in groups: per constrained node its
   // group, dof mask (bit d), v0, u_ref and current reaction; per group the
   // ramp time, the reactions' work and a history row per step
@@ -373,39 +393,43 @@ void edge_cmat(const orc_ctx* c, int k, double S, double Ck[6][6]) {
 void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::array<double, 6>>& eps,
                  std::vector<std::array<double, 6>>& sig, std::vector<double>& Vsum) {
   std::vector<std::array<double, 6>> eps_el(c->el.size());
-  for (size_t j = 0; j < c->el.size(); ++j) {
-    double B[6][24], ue[24];
-    bmat(c->el[j], B);
-    const int nc = 3 * c->el[j].nn;
-    for (int l = 0; l < c->el[j].nn; ++l)
-      for (int d = 0; d < 3; ++d) ue[3 * l + d] = u[c->el[j].n[l]][d];
-    for (int r = 0; r < 6; ++r) {
-      double s = 0;
-      for (int q = 0; q < nc; ++q) s += B[r][q] * ue[q];
-      eps_el[j][r] = s;
+  par_range(c->nthreads, c->el.size(), [&](size_t j0, size_t j1) {
+    for (size_t j = j0; j < j1; ++j) {
+      double B[6][24], ue[24];
+      bmat(c->el[j], B);
+      const int nc = 3 * c->el[j].nn;
+      for (int l = 0; l < c->el[j].nn; ++l)
+        for (int d = 0; d < 3; ++d) ue[3 * l + d] = u[c->el[j].n[l]][d];
+      for (int r = 0; r < 6; ++r) {
+        double s = 0;
+        for (int q = 0; q < nc; ++q) s += B[r][q] * ue[q];
+        eps_el[j][r] = s;
+      }
     }
-  }
+  });
   size_t nE = c->edge_nodes.size();
   eps.assign(nE, {0, 0, 0, 0, 0, 0});
   sig.assign(nE, {0, 0, 0, 0, 0, 0});
   Vsum.assign(nE, 0.0);
-  for (size_t k = 0; k < nE; ++k) {
-    double S = 0;
-    for (int j : c->patch[k]) S += c->el[j].Veff;
-    Vsum[k] = S;
-    if (S == 0.0) continue;  // every element on the edge removed: no stress
-    for (int j : c->patch[k]) {
-      double w = c->el[j].Veff / S;
-      for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];
+  par_range(c->nthreads, nE, [&](size_t k0, size_t k1) {
+    for (size_t k = k0; k < k1; ++k) {
+      double S = 0;
+      for (int j : c->patch[k]) S += c->el[j].Veff;
+      Vsum[k] = S;
+      if (S == 0.0) continue;  // every element on the edge removed: no stress
+      for (int j : c->patch[k]) {
+        double w = c->el[j].Veff / S;
+        for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];
+      }
+      double C[6][6];
+      edge_cmat(c, (int)k, S, C);
+      for (int r = 0; r < 6; ++r) {
+        double s = 0;
+        for (int q = 0; q < 6; ++q) s += C[r][q] * eps[k][q];
+        sig[k][r] = s;
+      }
     }
-    double C[6][6];
-    edge_cmat(c, (int)k, S, C);
-    for (int r = 0; r < 6; ++r) {
-      double s = 0;
-      for (int q = 0; q < 6; ++q) s += C[r][q] * eps[k][q];
-      sig[k][r] = s;
-    }
-  }
+  });
 }
 
 // Internal force, Eqs. fint_discretization / CSTet_fint_discretization in the
@@ -416,21 +440,31 @@ void internal_force(const orc_ctx* c, const std::vector<V3>& u, std::vector<V3>&
   std::vector<double> Vsum;
   edge_fields(c, u, eps, sig, Vsum);
   f.assign(c->X.size(), {0, 0, 0});
-  for (size_t k = 0; k < c->edge_nodes.size(); ++k) {
-    double S = Vsum[k];
-    if (S == 0.0) continue;
-    double Vk = S / c->D;
-    for (int j : c->patch[k]) {
-      double w = c->el[j].Veff / S;
-      double B[6][24];
-      bmat(c->el[j], B);
-      for (int q = 0; q < 3 * c->el[j].nn; ++q) {
-        double s = 0;
-        for (int r = 0; r < 6; ++r) s += B[r][q] * sig[k][r];
-        f[c->el[j].n[q / 3]][q % 3] += Vk * w * s;
+  // each thread owns a range of nodes and runs the whole edge loop, adding
+  // only to its own nodes: every nodal sum keeps the serial order
+  par_range(c->nthreads, c->X.size(), [&](size_t n0, size_t n1) {
+    auto own = [&](int i) { return (size_t)i >= n0 && (size_t)i < n1; };
+    for (size_t k = 0; k < c->edge_nodes.size(); ++k) {
+      double S = Vsum[k];
+      if (S == 0.0) continue;
+      double Vk = S / c->D;
+      for (int j : c->patch[k]) {
+        const Elem& e = c->el[j];
+        bool any = false;
+        for (int l = 0; l < e.nn; ++l) any = any || own(e.n[l]);
+        if (!any) continue;
+        double w = e.Veff / S;
+        double B[6][24];
+        bmat(e, B);
+        for (int q = 0; q < 3 * e.nn; ++q) {
+          if (!own(e.n[q / 3])) continue;
+          double s = 0;
+          for (int r = 0; r < 6; ++r) s += B[r][q] * sig[k][r];
+          f[e.n[q / 3]][q % 3] += Vk * w * s;
+        }
       }
     }
-  }
+  });
 }
 
 // Fraction of the parent volume carried by the copy holding the nodes of one
@@ -683,15 +717,18 @@ void one_step(orc_ctx* c) {
   std::vector<V3> f;
   internal_force(c, u1, f);
   std::vector<V3> u0 = c->u;
-  for (size_t i = 0; i < N; ++i) {
-    for (int d = 0; d < 3; ++d) {
-      double an1 = accel(c, i, rn1 * c->F[i][d] - f[i][d]);
-      c->W += 0.5 * (rn + rn1) * c->F[i][d] * (u1[i][d] - c->u[i][d]);
-      c->v[i][d] = c->v[i][d] + 0.5 * dt * (c->a[i][d] + an1);
-      c->a[i][d] = an1;
-      c->u[i][d] = u1[i][d];
+  for (size_t i = 0; i < N; ++i)
+    for (int d = 0; d < 3; ++d) c->W += 0.5 * (rn + rn1) * c->F[i][d] * (u1[i][d] - c->u[i][d]);
+  par_range(c->nthreads, N, [&](size_t i0, size_t i1) {
+    for (size_t i = i0; i < i1; ++i) {
+      for (int d = 0; d < 3; ++d) {
+        double an1 = accel(c, i, rn1 * c->F[i][d] - f[i][d]);
+        c->v[i][d] = c->v[i][d] + 0.5 * dt * (c->a[i][d] + an1);
+        c->a[i][d] = an1;
+        c->u[i][d] = u1[i][d];
+      }
     }
-  }
+  });
   if (!c->grp_t0.empty()) {
     apply_bc(c, tn1, c->u, false);
     std::vector<V3> R;
@@ -1338,6 +1375,12 @@ int orc_set_modulus(orc_ctx* c, const double* E_tet) {
 
 int orc_set_frozen(orc_ctx* c, int on) {
   c->frozen = on != 0;
+  return 0;
+}
+
+int orc_set_threads(orc_ctx* c, int n) {
+  if (n < 1) return c->fail(-1, "thread count must be positive");
+  c->nthreads = n;
   return 0;
 }
 

@@ -62,6 +62,10 @@ int orc_replay(orc_ctx* c, int n, const int* ev3);
 int orc_set_modulus(orc_ctx* c, const double* E_tet);
 /* 1: steps skip the crack pass (fixed topology) */
 int orc_set_frozen(orc_ctx* c, int on);
+/* Threads of the element, edge and node loops (default 1).  Each thread owns
+ * a contiguous range of elements, edges or nodes and every sum keeps the
+ * serial order, so results are bitwise the same at any count. */
+int orc_set_threads(orc_ctx* c, int n);
 /* Runs n fixed-topology steps from the current state and returns the
  * sensitivities of J = gu . u_n + gv . v_n (either may be NULL = 0) to the
  * initial u and v ([n_nodes_now][3]) and to each tet's modulus ([n_tets]).

@@ -25,7 +25,7 @@ def build(force=False):
     stale = not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
         os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "oracle.h")))
     if force or stale:
-        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-ffp-contract=off",
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-ffp-contract=off",
                "-o", LIB + ".tmp", SRC]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
@@ -72,6 +72,7 @@ def lib():
             ("orc_sym_eig3", [_p, _p, _p]),
             ("orc_set_modulus", [_p, _p]),
             ("orc_set_frozen", [_p, _i]),
+            ("orc_set_threads", [_p, _i]),
             ("orc_window_gradient", [_p, _i, _p, _p, _p, _p, _p]),
             ("orc_add_velocity_bc", [_p, _i, _p, _p, _p, _d, _p]),
             ("orc_strain_energy_grad", [_p, _p, _p]),
@@ -259,6 +260,11 @@ class Oracle:
         if E.shape != (len(self._t),):
             raise OracleError("one modulus per tet")
         self._chk(lib().orc_set_modulus(self.c, _ptr(E)))
+
+    def set_threads(self, n):
+        """Threads of the element, edge and node loops; results are bitwise
+        the same at any count."""
+        self._chk(lib().orc_set_threads(self.c, int(n)))
 
     def set_frozen(self, on=True):
         self._chk(lib().orc_set_frozen(self.c, int(bool(on))))
