@@ -139,10 +139,12 @@ int cem_upload_mesh(cem_ctx* ctx, int32_t n_nodes, const double* X, int32_t n_te
  * family, Eqs. hex_strain_discretization and hex_fint_discretization): hexes
  * [H][8] with nodes 0-1-2-3 counter-clockwise on the bottom face (seen from
  * above) and 4-7 above them; a hex inverted throughout is mirrored, one whose
- * Jacobian changes sign inside is CEM_EMESH.  Each hex enters the edge
- * smoothing with its volume-averaged gradients (2 x 2 x 2 Gauss points), the
- * 12 hex edges form the smoothing domains with V_k = (1/12) sum of the patch
- * volumes, and the lumped mass is rho V / 8 per node.  Hexes do not split:
+ * Jacobian determinant changes sign over its Gauss points and edge midpoints
+ * is CEM_EMESH.  Each hex enters the smoothing domain of each of its
+ * 12 edges with its shape-function gradients at that edge's midpoint G_k
+ * (Eq. strain_discretization evaluates dN/dx at G_k), the smoothing domains
+ * have V_k = (1/12) sum of the patch volumes (volumes by 2 x 2 x 2 Gauss
+ * points), and the lumped mass is rho V / 8 per node.  Hexes do not split:
  * the crack pass is off (Gc is ignored) and the splitting, batch, modulus and
  * gradient-window calls return CEM_ESTATE.  Tractions (triangles), prescribed
  * velocities, steps, energies and checkpoints work as for tetrahedra. */
@@ -165,6 +167,23 @@ int cem_presplit(cem_ctx* ctx, int32_t n, const int32_t* tet, const uint8_t* sid
  * bound on the largest frequency of M^-1 K, valid for every split state. */
 int cem_critical_dt(cem_ctx* ctx, double* dt_crit);
 int cem_set_dt(cem_ctx* ctx, double dt);
+
+/* Switch the force arithmetic (CEM_FP64 or CEM_MIXED) of an uploaded
+ * context, keeping its mesh, topology and state (u, v, a and the predictor
+ * carry over as they are): the per-edge inverse patch volumes are recomputed
+ * in the new type and a captured graph is dropped.  Checkpoints name the
+ * precision they were taken at and load only into a context at that
+ * precision. */
+int cem_set_precision(cem_ctx* ctx, int32_t precision);
+
+/* Steps per captured HIP graph in cem_step from now on (0 = plain launches);
+ * drops a captured graph. */
+int cem_set_graph_steps(cem_ctx* ctx, int32_t graph_steps);
+
+/* How the last cem_step call ran: out[0] steps, out[1] graph launches,
+ * out[2] steps per graph, out[3] steps enqueued as plain launches (a call
+ * with fewer steps than a graph, a remainder, or profiling on). */
+int cem_last_run(cem_ctx* ctx, int64_t* out);
 
 /* Use caller device buffers (each at least capacity_nodes * 4 float64,
  * rows padded to 4) for u and v.  The current state is copied into them. */

@@ -34,6 +34,7 @@ EXPORTS = [
     "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
     "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step",
     "cem_window_forward", "cem_window_backward", "cem_window_times", "cem_strain_energy_grad",
+    "cem_set_precision", "cem_set_graph_steps", "cem_last_run",
 ]
 
 
@@ -126,6 +127,9 @@ def load_library(path=LIB_PATH):
         "cem_window_backward": [p, p, p, p, p, p],
         "cem_window_times": [p, p],
         "cem_strain_energy_grad": [p, p, C.POINTER(C.c_double), p, p],
+        "cem_set_precision": [p, i32],
+        "cem_set_graph_steps": [p, i32],
+        "cem_last_run": [p, p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -234,6 +238,23 @@ class Simulation:
 
     def set_dt(self, dt):
         self._chk(self.lib.cem_set_dt(self.ctx, float(dt)))
+
+    def set_precision(self, precision):
+        """Switch the force arithmetic ("fp64" or "mixed") keeping mesh and state."""
+        self._chk(self.lib.cem_set_precision(self.ctx, PRECISION[precision]))
+        self.precision = precision
+
+    def set_graph_steps(self, k):
+        """Steps per captured HIP graph from now on (0: plain launches)."""
+        self._chk(self.lib.cem_set_graph_steps(self.ctx, int(k)))
+
+    def last_run(self):
+        """How the last step() call ran: steps, graph launches, steps per graph,
+        steps as plain launches."""
+        out = np.zeros(4, dtype=np.int64)
+        self._chk(self.lib.cem_last_run(self.ctx, _p(out)))
+        return dict(steps=int(out[0]), graph_launches=int(out[1]), graph_steps=int(out[2]),
+                    plain_steps=int(out[3]))
 
     def counts(self):
         out = np.zeros(6, dtype=np.int32)

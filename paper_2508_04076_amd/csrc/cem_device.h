@@ -109,7 +109,6 @@ struct Mesh {
   // trilinear hexahedra (etype 8; no splitting, T_cap = T0)
   int4* hnodes;             // [2 T0] node ids 0-3, 4-7
   int2* he2e;               // [6 T0] twelve edge ids
-  double4* hgrad;           // [6 T0] G_i = integral of grad N_i over the hex, 8 x 3 row-major
 
   // prescribed velocities in groups (all null, counts 0, when there are none)
   int n_bc, n_grp, hist_cap;

@@ -280,33 +280,6 @@ __device__ __forceinline__ void node_gather_tet(const Mesh& m, const R* __restri
   }
 }
 
-// Hexahedra: node i's force from its (hex, local) entries, each term
-// G_l^T s_e formed from the hex's stress sum s_e and gradient G_l; lanes and
-// sum order as node_gather.
-template <class R, int G>
-__device__ __forceinline__ void node_gather_hex(const Mesh& m, const R* __restrict__ hs, int i,
-                                                bool active, int g, double& fx, double& fy,
-                                                double& fz) {
-  fx = fy = fz = 0;
-  const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
-  CEM_PRAGMA(unroll CEM_NODE_UNROLL)
-  for (int p = p0 + g; p < p1; p += G) {
-    const int ent = m.nent[p], e = ent >> 3, l = ent & 7;
-    Six<R> s = load6((const Six<R>*)hs + e);
-    const double* gp = (const double*)(m.hgrad + 6 * (size_t)e) + 3 * l;
-    R gx = (R)gp[0], gy = (R)gp[1], gz = (R)gp[2];
-    fx += (double)(gx * s.v[0] + gy * s.v[3] + gz * s.v[5]);
-    fy += (double)(gy * s.v[1] + gx * s.v[3] + gz * s.v[4]);
-    fz += (double)(gz * s.v[2] + gy * s.v[4] + gx * s.v[5]);
-  }
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) {
-    fx += __shfl_xor(fx, off, G);
-    fy += __shfl_xor(fy, off, G);
-    fz += __shfl_xor(fz, off, G);
-  }
-}
-
 // Sum of node i's contiguous terms by G lanes (lane g takes entries g, g + G,
 // ...), combined by a fixed butterfly of shuffles, so the sum is the same on
 // every run.  Every lane of the group must call it.

@@ -223,7 +223,7 @@ __device__ __forceinline__ void bc_override(const Mesh& m, int b, double t, doub
 // Node pass: G lanes per node sum the node's contributions (lane g takes
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
-// KIND: 0 = contiguous terms, 1 = hex stress sums, 2 = tet stress sums
+// KIND: 0 = contiguous terms (tets or hexes), 2 = tet stress sums
 template <class R, int MODE, int G, bool BC, int KIND>
 __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st, const R* __restrict__ contrib,
                                                  double4* __restrict__ fout,
@@ -236,8 +236,7 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st,
   const int i = item / G;
   const bool active = i < Nn;
   double fx, fy, fz;
-  if (KIND == 1) node_gather_hex<R, G>(m, contrib, i, active, g, fx, fy, fz);
-  else if (KIND == 2) node_gather_tet<R, G>(m, contrib, i, active, g, fx, fy, fz);
+  if (KIND == 2) node_gather_tet<R, G>(m, contrib, i, active, g, fx, fy, fz);
   else node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
   if (!active || g != 0) continue;
   if (MODE == NODE_FORCE) {
@@ -1273,7 +1272,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_volumes(Mesh m, R* einvV, int c
   for (int p = m.poff[k]; p < m.poff[k + 1]; ++p) {
     int e = m.pent[p];
     if (e < 0) continue;
-    double ve = m.etype == 8 ? m.vol[e] : frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
+    // a hex mesh's entries name (hex, edge point) as 12 hex + q
+    double ve = m.etype == 8 ? m.vol[e / 12] : frac_of((unsigned)m.enodes[e].x >> kNodeBits) * m.vol[e];
     S += ve;
     if (m.kap) SK += ve * m.kap[e];
   }
@@ -1540,12 +1540,10 @@ static void launch_node_kind(const Mesh& m, const State& st, const R* ct, Counte
 template <class R, int G>
 static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
                               Counters* c, int mode, double4* fout, hipStream_t s) {
-  if (m.etype == 8) {
-    launch_node_kind<R, G, 1>(m, st, ct, c, mode, fout, s);
-  } else {
-    if (m.ssum) launch_node_kind<R, G, 2>(m, st, ct, c, mode, fout, s);
-    else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);
-  }
+  // hexes hand over their nodal terms at node-list positions, like the
+  // tetrahedra's term layout
+  if (m.etype != 8 && m.ssum) launch_node_kind<R, G, 2>(m, st, ct, c, mode, fout, s);
+  else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);
 }
 
 template <class R>

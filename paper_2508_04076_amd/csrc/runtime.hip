@@ -78,6 +78,9 @@ struct cem_ctx {
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0;
   int graph_replay = -1;
+  // how the last cem_step call ran: steps, graph launches, steps per graph,
+  // steps as plain launches
+  int64_t last_run[4] = {0, 0, 0, 0};
 
   // profiling
   hipEvent_t tev[2] = {nullptr, nullptr};  // whole-call timing (created once)
@@ -407,9 +410,10 @@ struct HexTopo {
   int E0 = 0;
   std::vector<int> he2e;     // 12 H
   std::vector<int> poff;     // E0 + 1
-  std::vector<int> pent;     // 12 H
+  std::vector<int> pent;     // 12 H: 12 hex + local edge (the hex's record at that edge's point)
   std::vector<int> noff;     // N + 1
   std::vector<int> nent;     // 8 H: hex << 3 | local
+  std::vector<int> nodepos;  // 8 H: position of entry (hex, local) in the node lists
 };
 
 void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
@@ -435,7 +439,7 @@ void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
       E++;
     }
     h.he2e[val[i]] = E - 1;
-    h.pent[i] = (int)(val[i] / 12);
+    h.pent[i] = (int)val[i];
   }
   h.poff.push_back((int)M);
   h.E0 = E;
@@ -444,8 +448,13 @@ void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
   for (int i = 0; i < N; ++i) h.noff[i + 1] += h.noff[i];
   std::vector<int> fill(h.noff.begin(), h.noff.end() - 1);
   h.nent.assign((size_t)8 * H, 0);
+  h.nodepos.assign((size_t)8 * H, 0);
   for (int t = 0; t < H; ++t)
-    for (int l = 0; l < 8; ++l) h.nent[fill[hx[8 * (size_t)t + l]]++] = (t << 3) | l;
+    for (int l = 0; l < 8; ++l) {
+      int p = fill[hx[8 * (size_t)t + l]]++;
+      h.nent[p] = (t << 3) | l;
+      h.nodepos[8 * (size_t)t + l] = p;
+    }
 }
 
 // Jacobian determinants of a trilinear hex at its 2 x 2 x 2 Gauss points:
@@ -456,11 +465,15 @@ void hex_det_range(const double* X, const int* nd, double* dmin, double* dmax) {
   const double a = 1.0 / std::sqrt(3.0);
   *dmin = INFINITY;
   *dmax = -INFINITY;
-  for (int gp = 0; gp < 8; ++gp) {
+  // the eight Gauss points, then the twelve edge midpoints
+  for (int pt = 0; pt < 20; ++pt) {
+    double xi[3];
+    for (int d = 0; d < 3; ++d)
+      xi[d] = pt < 8 ? a * sg[pt][d] : 0.5 * (sg[kHexLE[pt - 8][0]][d] + sg[kHexLE[pt - 8][1]][d]);
     double J[3][3] = {};
     for (int i = 0; i < 8; ++i) {
       double f[3];
-      for (int d = 0; d < 3; ++d) f[d] = 1.0 + a * sg[gp][d] * sg[i][d];
+      for (int d = 0; d < 3; ++d) f[d] = 1.0 + xi[d] * sg[i][d];
       double dN[3] = {0.125 * sg[i][0] * f[1] * f[2], 0.125 * f[0] * sg[i][1] * f[2],
                       0.125 * f[0] * f[1] * sg[i][2]};
       const double* x = X + 3 * (size_t)nd[i];
@@ -673,6 +686,8 @@ int run_steps(cem_ctx* c, int32_t n_steps) {
   const int splits0 = c->h_ctr->n_split;
   int K = c->opt.graph_steps;
   int done = 0;
+  c->last_run[0] = n_steps;
+  c->last_run[1] = c->last_run[2] = c->last_run[3] = 0;
   // HIP cannot time events recorded inside a graph: profiling uses plain launches
   if (!c->profiling && K > 0 && n_steps >= K) {
     int replay = c->h_ctr->n_sched > 0;
@@ -683,7 +698,9 @@ int run_steps(cem_ctx* c, int32_t n_steps) {
     while (n_steps - done >= K) {
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
       done += K;
+      c->last_run[1]++;
     }
+    c->last_run[2] = K;
   }
   if (c->profiling) {
     const int chunk = 64;
@@ -697,6 +714,7 @@ int run_steps(cem_ctx* c, int32_t n_steps) {
       done += k;
     }
   }
+  c->last_run[3] = n_steps - (int64_t)c->last_run[1] * c->last_run[2];
   for (; done < n_steps; ++done)
     if ((r = enqueue_step(c, nullptr))) return r;
   HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -734,7 +752,8 @@ int win_fixed(cem_ctx* c) {
   auto& W = c->win;
   if (W.p) return CEM_OK;
   const Mesh& m = c->m;
-  const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
+  // float64-sized whatever the precision (cem_set_precision can change it)
+  const size_t RS = sizeof(double);
   void* b[7] = {};
   size_t sz[7] = {sizeof(double4) * m.N_cap, sizeof(double4) * m.N_cap, sizeof(double4) * m.N_cap,
                   sizeof(double) * m.T_cap, RS * 6 * (size_t)m.T_cap, RS * (size_t)m.E_cap,
@@ -1013,7 +1032,9 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   std::memset(c->h_ctr, 0, sizeof(Counters));
   c->stage = 1;  // allocations from here are released by cem_destroy
 
-  const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
+  // the float-typed work arrays are sized for float64 in either precision, so
+  // that cem_set_precision can switch the arithmetic without reallocating
+  const size_t RS = sizeof(double);
   size_t nsplit_list = 1;  // a power of two >= S (room for the bitonic sort)
   while (nsplit_list < (size_t)std::max(S, 1)) nsplit_list <<= 1;
 #define ALLOC(ptr, n, ck) \
@@ -1228,12 +1249,12 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   HIPCHK(c, hipHostMalloc((void**)&c->h_ctr, sizeof(Counters), hipHostMallocDefault));
   std::memset(c->h_ctr, 0, sizeof(Counters));
   c->stage = 1;
-  const size_t RS = c->mixed ? sizeof(float) : sizeof(double);
+  const size_t RS = sizeof(double);  // either precision (cem_set_precision)
   int r;
   ALLOC(c->d_ctr, 1, true);
   ALLOC(m.hnodes, (size_t)2 * H, false);
   ALLOC(m.he2e, (size_t)6 * H, false);
-  ALLOC(m.hgrad, (size_t)6 * H, false);
+  ALLOC(m.epos, (size_t)2 * H, false);  // node-list positions of the eight (hex, local) entries
   ALLOC(m.X, m.N_cap, true);
   ALLOC(m.poff, (size_t)m.E0 + 1, false);
   ALLOC(m.pent, (size_t)12 * H, false);
@@ -1244,13 +1265,13 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   ALLOC(m.vol, m.T_cap, true);
   ALLOC(m.splitlist, 1, false);
   char* vb;
-  ALLOC(vb, RS * 6 * (size_t)H, false);
+  ALLOC(vb, RS * 6 * 12 * (size_t)H, false);  // one V eps record per (hex, edge point)
   c->w.veps = vb;
   ALLOC(vb, RS * 6 * (size_t)m.E0, false);
   c->w.esig = vb;
   ALLOC(vb, RS * (size_t)m.E0, true);
   c->w.einvV = vb;
-  ALLOC(vb, RS * 6 * (size_t)H, false);  // the per-hex stress sums
+  ALLOC(vb, RS * 3 * 8 * (size_t)H, false);  // the nodal terms at node-list positions
   c->w.contrib = vb;
   ALLOC(c->w.partial, c->n_partial, false);
   ALLOC(c->d_out, 8, false);
@@ -1278,12 +1299,13 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   if ((r = upload(c, m.pent, h.pent.data(), h.pent.size()))) return r;
   if ((r = upload(c, m.noff, h.noff.data(), h.noff.size()))) return r;
   if ((r = upload(c, m.nent, h.nent.data(), h.nent.size()))) return r;
+  if ((r = upload(c, (int*)m.epos, h.nodepos.data(), h.nodepos.size()))) return r;
   std::vector<int> lsl(N, -1);
   if ((r = upload(c, m.lslot, lsl.data(), lsl.size()))) return r;
   HIPCHK(c, hipMemsetAsync(c->d_ctr, 0, sizeof(Counters), c->stream));
   for (double4* p : {c->st.u, c->st.v, c->st.a, c->st.uh})
     HIPCHK(c, hipMemsetAsync(p, 0, sizeof(double4) * N, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 6 * (size_t)H, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->w.contrib, 0, RS * 3 * 8 * (size_t)H, c->stream));
   HIPCHK(c, launch_masses(m, c->stream));  // hex geometry (G_i, V), then lumped masses
   if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, -1, c->stream));
   else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, -1, c->stream));
@@ -1442,6 +1464,42 @@ int cem_set_dt(cem_ctx* c, double dt) {
   c->dt_set = true;
   c->need_init = true;
   drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_set_precision(cem_ctx* c, int32_t precision) {
+  if (!c) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (precision != CEM_FP64 && precision != CEM_MIXED) return c->fail(CEM_EINVAL, "unknown precision");
+  const int mixed = precision == CEM_MIXED;
+  if (mixed == c->mixed) return CEM_OK;
+  c->mixed = mixed;
+  c->opt.precision = precision;
+  c->gen++;
+  drop_graph(c);
+  // 1 / patch volume in the new arithmetic, from the current element volumes,
+  // for every edge now (split copies add ten each)
+  nodes_now_host(c);
+  const int En = edges_now_host(c);
+  if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(c->m, c->w, En, c->stream));
+  else HIPCHK(c, Launch<double>::edge_volumes(c->m, c->w, En, c->stream));
+  // the state (u, v, a and the predictor) carries over as it is: a
+  // recomputed here would see a topology changed by the last step's splits
+  return sync(c);
+}
+
+int cem_set_graph_steps(cem_ctx* c, int32_t k) {
+  if (!c) return CEM_EINVAL;
+  if (k < 0) return c->fail(CEM_EINVAL, "graph_steps must be >= 0");
+  c->opt.graph_steps = k;
+  drop_graph(c);
+  return CEM_OK;
+}
+
+int cem_last_run(cem_ctx* c, int64_t* out) {
+  if (!c || !out) return CEM_EINVAL;
+  for (int q = 0; q < 4; ++q) out[q] = c->last_run[q];
   return CEM_OK;
 }
 

@@ -70,6 +70,13 @@ def test_calls_out_of_order(lib):
     assert lib.cem_set_launch(ctx, 1024, 8, 0) == cem.CEM_ESTATE
     g, l, lay, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
     assert lib.cem_autotune(ctx, 5, C.byref(g), C.byref(l), C.byref(lay), C.byref(ms)) == cem.CEM_ESTATE
+    assert lib.cem_set_precision(ctx, 1) == cem.CEM_ESTATE
+    # graph size and the last-run record are host settings
+    assert lib.cem_set_graph_steps(ctx, -1) == cem.CEM_EINVAL
+    assert lib.cem_set_graph_steps(ctx, 25) == cem.CEM_OK
+    run = np.ones(4, dtype=np.int64)
+    assert lib.cem_last_run(ctx, run.ctypes.data_as(C.c_void_p)) == cem.CEM_OK
+    assert run.tolist() == [0, 0, 0, 0]
     # the topology mode is a host setting: checked without a mesh or a device
     for bad in (-1, 3):
         assert lib.cem_set_topology_mode(ctx, bad) == cem.CEM_EINVAL
