@@ -154,38 +154,55 @@ def hex_surface_integrals(x):
     return G, V
 
 
+def hex_gradients_at(x, xi):
+    """Gradients of the eight trilinear shape functions of the hex x [8, 3] at
+    the natural point xi, by solving J^T g_i = dN_i/dxi (numpy)."""
+    x = np.asarray(x, float)
+    f = 1.0 + _HEX_SIGN * np.asarray(xi, float)          # [8, 3]
+    dN = np.empty((8, 3))
+    dN[:, 0] = _HEX_SIGN[:, 0] * f[:, 1] * f[:, 2] / 8.0
+    dN[:, 1] = f[:, 0] * _HEX_SIGN[:, 1] * f[:, 2] / 8.0
+    dN[:, 2] = f[:, 0] * f[:, 1] * _HEX_SIGN[:, 2] / 8.0
+    J = x.T @ dN                                        # J[r, c] = dx_r / dxi_c
+    return np.linalg.solve(J.T, dN.T).T
+
+
+def _hex_B(g):
+    B = np.zeros((6, 24))
+    for l in range(8):
+        gx, gy, gz = g[l]
+        c = 3 * l
+        B[0, c], B[1, c + 1], B[2, c + 2] = gx, gy, gz
+        B[3, c], B[3, c + 1] = gy, gx
+        B[4, c + 1], B[4, c + 2] = gz, gy
+        B[5, c], B[5, c + 2] = gz, gx
+    return B
+
+
 def assemble_hex(X, hexes, E, nu):
-    """Dense ES-H-FEM stiffness: each hex enters with its volume-averaged
-    gradients, edges are the 12 hex edges, V_k = (1/12) sum of the patch
-    volumes, K = sum_k V_k Bt_k^T C Bt_k."""
+    """Dense ES-H-FEM stiffness straight from Eq. strain_discretization: the
+    smoothing domain of hex edge k collects the hexes j sharing it, each with
+    its shape-function gradients at G_k, the edge's midpoint, and weight
+    w_jk = V_j / S_k (S_k = sum of their volumes); V_k = S_k / 12 and
+    K = sum_k V_k Bt_k^T C Bt_k with Bt_k = sum_j w_jk B_j(G_k).  Volumes from
+    surface integrals (divergence theorem)."""
     X = np.asarray(X, float)
     hexes = np.asarray(hexes)
     N = len(X)
     C = cmat(E, nu)
-    Bs, Vs = [], []
-    for h in hexes:
-        G, V = hex_surface_integrals(X[h])
-        g = G / V
-        B = np.zeros((6, 24))
-        for l in range(8):
-            gx, gy, gz = g[l]
-            c = 3 * l
-            B[0, c], B[1, c + 1], B[2, c + 2] = gx, gy, gz
-            B[3, c], B[3, c + 1] = gy, gx
-            B[4, c + 1], B[4, c + 2] = gz, gy
-            B[5, c], B[5, c + 2] = gz, gx
-        Bs.append(B)
-        Vs.append(V)
+    Vs = [hex_surface_integrals(X[h])[1] for h in hexes]
     patches = {}
     for j, h in enumerate(hexes):
-        for a, b in _HEX_EDGES:
-            patches.setdefault(tuple(sorted((int(h[a]), int(h[b])))), []).append(j)
+        for q, (a, b) in enumerate(_HEX_EDGES):
+            patches.setdefault(tuple(sorted((int(h[a]), int(h[b])))), []).append((j, q))
     dof = lambda nd: np.array([[3 * n, 3 * n + 1, 3 * n + 2] for n in nd]).ravel()
     K = np.zeros((3 * N, 3 * N))
     for pj in patches.values():
-        S = sum(Vs[j] for j in pj)
+        S = sum(Vs[j] for j, _ in pj)
         Bt = np.zeros((6, 3 * N))
-        for j in pj:
-            Bt[:, dof(hexes[j])] += (Vs[j] / S) * Bs[j]
+        for j, q in pj:
+            a, b = _HEX_EDGES[q]
+            G = 0.5 * (_HEX_SIGN[a] + _HEX_SIGN[b])   # midpoint of the edge
+            Bt[:, dof(hexes[j])] += (Vs[j] / S) * _hex_B(hex_gradients_at(X[hexes[j]], G))
         K += (S / 12.0) * Bt.T @ C @ Bt
     return K, np.array(Vs)

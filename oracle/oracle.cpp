@@ -41,11 +41,16 @@
 //     volume average of the element matrices over the domain, so that
 //     sigma_k = C_k eps_k;
 //   * trilinear hexahedra (Eqs. hex_strain_discretization and
-//     hex_fint_discretization): each hex enters with one gradient per node,
-//     the volume average (1/V) integral of grad N_i over the element (exact with
-//     2 x 2 x 2 Gauss points); edges are the 12 hex edges and the smoothing
-//     domain of edge k has V_k = (1/12) sum of the volumes sharing it; the
-//     lumped mass is rho V / 8 per node; hexes do not split;
+//     hex_fint_discretization): as Eq. strain_discretization states, hex j
+//     enters the smoothing domain of edge k with its shape-function gradients
+//     evaluated at that edge's point G_k, the midpoint of the hex edge; edges
+//     are the 12 hex edges, the smoothing domain of edge k has
+//     V_k = (1/12) sum of the volumes sharing it and the volume weights
+//     w_jk = V_j / sum V; the hex volume is exact with 2 x 2 x 2 Gauss points;
+//     the lumped mass is rho V / 8 per node; hexes do not split;
+//   * hex critical step: the element bound takes the largest stiffness over
+//     the hex's edge points, (8 / rho) max_q lambda_max(B_q^T C B_q), which is
+//     at least lambda_max of its edge-averaged stiffness;
 //   * a prescribed velocity v0 r_v(t) on listed degrees of freedom, with the
 //     ramp r_v = t / t0 up to t0 and 1 after (Section 4 examples), fixes the
 //     displacement to u_ref + v0 S(t), S the integral of r_v, the velocity to
@@ -141,7 +146,7 @@ void jacobi_eig(int n, std::vector<double> A, double* w, double* vec) {
 struct Elem {
   int nn = 4;        // nodes: 4 (tet) or 8 (hex)
   int n[8];          // node ids (real or extra)
-  double g[8][3];    // dN_l/dx, Section 2.2 (constant per tet; volume average per hex)
+  double g[8][3];    // dN_l/dx of a tet, Section 2.2 (constant; hexes: per edge point, orc_ctx::hexg)
   double V;          // volume of the parent tetrahedron
   double Veff;       // volume the element carries (V, a fraction of V, or 0)
   int parent;        // original tet id
@@ -173,6 +178,9 @@ struct orc_ctx {
   std::map<std::pair<int, int>, int> edge_of;
   std::vector<std::pair<int, int>> edge_nodes;
   std::vector<std::vector<int>> patch;
+  std::vector<std::vector<int>> patch_q;  // local edge of each patch element on that edge
+  // hexes: grad N_i at the midpoint of local edge q, [(q * 8 + i) * 3 + d]
+  std::vector<std::array<double, 288>> hexg;
   std::vector<std::array<int, 4>> orig;  // original (oriented) connectivity
   std::vector<std::array<int, 4>> nbr, nbr_face;
   std::vector<int> smask;  // per original tet: -1 intact, else side mask
@@ -252,11 +260,10 @@ double tet_geometry(const V3 x[4], double g[4][3]) {
 
 // Strain-displacement matrix B (6 x 3nn) of Eqs. CSTet_strain_discretization
 // and hex_strain_discretization, columns ordered (u_0, v_0, w_0, u_1, ...).
-void bmat(const Elem& e, double B[6][24]) {
-  const double(*g)[3] = e.g;
+void bmat_of(const double (*g)[3], int nn, double B[6][24]) {
   for (int r = 0; r < 6; ++r)
     for (int c = 0; c < 24; ++c) B[r][c] = 0.0;
-  for (int l = 0; l < e.nn; ++l) {
+  for (int l = 0; l < nn; ++l) {
     double gx = g[l][0], gy = g[l][1], gz = g[l][2];
     int c = 3 * l;
     B[0][c + 0] = gx;
@@ -269,6 +276,18 @@ void bmat(const Elem& e, double B[6][24]) {
     B[5][c + 0] = gz;
     B[5][c + 2] = gx;
   }
+}
+
+void bmat(const Elem& e, double B[6][24]) { bmat_of(e.g, e.nn, B); }
+
+// Strain-displacement matrix of element j in the smoothing domain of its local
+// edge q: tets have one (constant gradients); a hex uses its gradients at the
+// midpoint of edge q (Eq. strain_discretization evaluates them at G_k).
+void elem_bmat(const orc_ctx* c, int j, int q, double B[6][24]) {
+  if (c->el[j].nn == 8)
+    bmat_of(reinterpret_cast<const double(*)[3]>(c->hexg[j].data() + 24 * q), 8, B);
+  else
+    bmat(c->el[j], B);
 }
 
 // Voigt stress vector (s11, s22, s33, s12, s23, s13) -> symmetric 3x3 tensor.
@@ -319,6 +338,7 @@ int find_or_add_edge(orc_ctx* c, int a, int b) {
   c->edge_of[key] = id;
   c->edge_nodes.push_back(key);
   c->patch.push_back({});
+  c->patch_q.push_back({});
   return id;
 }
 
@@ -338,6 +358,7 @@ void add_elem_to_edges(orc_ctx* c, int e) {
   for (int q = 0; q < ne; ++q) {
     int k = find_or_add_edge(c, c->el[e].n[tab[q][0]], c->el[e].n[tab[q][1]]);
     c->patch[k].push_back(e);
+    c->patch_q[k].push_back(q);
   }
 }
 
@@ -346,7 +367,10 @@ void remove_elem_from_edges(orc_ctx* c, int e) {
     int a = c->el[e].n[kEdgeLocal[q][0]], b = c->el[e].n[kEdgeLocal[q][1]];
     int k = c->edge_of.at(std::make_pair(std::min(a, b), std::max(a, b)));
     auto& p = c->patch[k];
-    p.erase(std::find(p.begin(), p.end(), e));
+    auto& pq = c->patch_q[k];
+    size_t at = std::find(p.begin(), p.end(), e) - p.begin();
+    p.erase(p.begin() + at);
+    pq.erase(pq.begin() + at);
   }
 }
 
@@ -392,18 +416,24 @@ void edge_cmat(const orc_ctx* c, int k, double S, double Ck[6][6]) {
 
 void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::array<double, 6>>& eps,
                  std::vector<std::array<double, 6>>& sig, std::vector<double>& Vsum) {
-  std::vector<std::array<double, 6>> eps_el(c->el.size());
+  // strain of each element at the point of each of its smoothing domains:
+  // one per tet (constant gradients), one per local edge of a hex
+  const int per = c->D == 12.0 ? 12 : 1;
+  std::vector<std::array<double, 6>> eps_el(c->el.size() * per);
   par_range(c->nthreads, c->el.size(), [&](size_t j0, size_t j1) {
     for (size_t j = j0; j < j1; ++j) {
-      double B[6][24], ue[24];
-      bmat(c->el[j], B);
+      double ue[24];
       const int nc = 3 * c->el[j].nn;
       for (int l = 0; l < c->el[j].nn; ++l)
         for (int d = 0; d < 3; ++d) ue[3 * l + d] = u[c->el[j].n[l]][d];
-      for (int r = 0; r < 6; ++r) {
-        double s = 0;
-        for (int q = 0; q < nc; ++q) s += B[r][q] * ue[q];
-        eps_el[j][r] = s;
+      for (int pq = 0; pq < per; ++pq) {
+        double B[6][24];
+        elem_bmat(c, (int)j, pq, B);
+        for (int r = 0; r < 6; ++r) {
+          double s = 0;
+          for (int q = 0; q < nc; ++q) s += B[r][q] * ue[q];
+          eps_el[per * j + pq][r] = s;
+        }
       }
     }
   });
@@ -417,9 +447,11 @@ void edge_fields(const orc_ctx* c, const std::vector<V3>& u, std::vector<std::ar
       for (int j : c->patch[k]) S += c->el[j].Veff;
       Vsum[k] = S;
       if (S == 0.0) continue;  // every element on the edge removed: no stress
-      for (int j : c->patch[k]) {
+      for (size_t i = 0; i < c->patch[k].size(); ++i) {
+        int j = c->patch[k][i];
+        int q = per == 1 ? 0 : c->patch_q[k][i];
         double w = c->el[j].Veff / S;
-        for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];
+        for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[per * j + q][r];
       }
       double C[6][6];
       edge_cmat(c, (int)k, S, C);
@@ -448,14 +480,15 @@ void internal_force(const orc_ctx* c, const std::vector<V3>& u, std::vector<V3>&
       double S = Vsum[k];
       if (S == 0.0) continue;
       double Vk = S / c->D;
-      for (int j : c->patch[k]) {
+      for (size_t i = 0; i < c->patch[k].size(); ++i) {
+        int j = c->patch[k][i];
         const Elem& e = c->el[j];
         bool any = false;
         for (int l = 0; l < e.nn; ++l) any = any || own(e.n[l]);
         if (!any) continue;
         double w = e.Veff / S;
         double B[6][24];
-        bmat(e, B);
+        elem_bmat(c, j, c->patch_q[k][i], B);
         for (int q = 0; q < 3 * e.nn; ++q) {
           if (!own(e.n[q / 3])) continue;
           double s = 0;
@@ -874,58 +907,72 @@ int window_gradient(orc_ctx* c, int n, const double* gu, const double* gv, doubl
   return 0;
 }
 
-// Trilinear hexahedron (Eq. hex_strain_discretization): volume and the
-// volume-averaged gradients g_i = (1/V) int grad N_i dV, with
-// N_i = (1 + xi xi_i)(1 + eta eta_i)(1 + zeta zeta_i) / 8 on [-1, 1]^3 and
-// 2 x 2 x 2 Gauss points (exact: the integrand adj(J)^T grad_xi N_i is a
-// polynomial of degree at most 3 in each reference coordinate).  Returns V;
-// *min_det receives the smallest Jacobian determinant at the Gauss points.
-double hex_geometry(const V3 x[8], double g[8][3], double* min_det) {
-  static const int sg[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
-                               {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+// Trilinear hexahedron (Eq. hex_strain_discretization), reference corner
+// signs of the local nodes: bottom face 0-1-2-3 counter-clockwise, top 4-7.
+const int kHexSign[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                            {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+// grad N_i = J^{-T} grad_xi N_i of the eight shape functions at the natural
+// point xi (J[r][c] = dx_r / dxi_c); returns det J.
+double hex_point_gradients(const V3 x[8], const double xi[3], double g[8][3]) {
+  const int(*sg)[3] = kHexSign;
+  double dN[8][3];  // dN_i / d(xi, eta, zeta)
+  for (int i = 0; i < 8; ++i) {
+    double f[3];
+    for (int d = 0; d < 3; ++d) f[d] = 1.0 + xi[d] * sg[i][d];
+    dN[i][0] = sg[i][0] * f[1] * f[2] / 8.0;
+    dN[i][1] = f[0] * sg[i][1] * f[2] / 8.0;
+    dN[i][2] = f[0] * f[1] * sg[i][2] / 8.0;
+  }
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int i = 0; i < 8; ++i)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] += x[i][r] * dN[i][c];
+  double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+               J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  double inv[3][3];  // J^{-1}
+  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  for (int i = 0; i < 8; ++i)
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int c = 0; c < 3; ++c) s += inv[c][d] * dN[i][c];
+      g[i][d] = s;
+    }
+  return det;
+}
+
+// Volume (2 x 2 x 2 Gauss points, exact for the trilinear map), the
+// smallest Jacobian determinant over the Gauss and edge points, and the
+// gradients at the midpoint of each local edge q (ge[(q * 8 + i) * 3 + d]).
+double hex_geometry(const V3 x[8], double* ge, double* min_det) {
+  const int(*sg)[3] = kHexSign;
   const double a = 1.0 / std::sqrt(3.0);
-  double V = 0;
-  for (int i = 0; i < 8; ++i) g[i][0] = g[i][1] = g[i][2] = 0;
+  double V = 0, g[8][3];
   *min_det = INFINITY;
   for (int p = 0; p < 8; ++p) {
     double xi[3] = {sg[p][0] * a, sg[p][1] * a, sg[p][2] * a};
-    double dN[8][3];  // dN_i / d(xi, eta, zeta)
-    for (int i = 0; i < 8; ++i) {
-      double f[3];
-      for (int d = 0; d < 3; ++d) f[d] = 1.0 + xi[d] * sg[i][d];
-      dN[i][0] = sg[i][0] * f[1] * f[2] / 8.0;
-      dN[i][1] = f[0] * sg[i][1] * f[2] / 8.0;
-      dN[i][2] = f[0] * f[1] * sg[i][2] / 8.0;
-    }
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // J[r][c] = dx_r / dxi_c
-    for (int i = 0; i < 8; ++i)
-      for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) J[r][c] += x[i][r] * dN[i][c];
-    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double det = hex_point_gradients(x, xi, g);
     *min_det = std::min(*min_det, det);
-    double inv[3][3];  // J^{-1}
-    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
-    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
-    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
-    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-    // grad N_i = J^{-T} grad_xi N_i, weighted by det J (Gauss weights 1)
-    for (int i = 0; i < 8; ++i)
-      for (int d = 0; d < 3; ++d) {
-        double s = 0;
-        for (int c = 0; c < 3; ++c) s += inv[c][d] * dN[i][c];
-        g[i][d] += s * det;
-      }
-    V += det;
+    V += det;  // Gauss weights 1
   }
-  for (int i = 0; i < 8; ++i)
-    for (int d = 0; d < 3; ++d) g[i][d] /= V;
+  for (int q = 0; q < 12; ++q) {
+    int p0 = kHexEdge[q][0], p1 = kHexEdge[q][1];
+    double xi[3];
+    for (int d = 0; d < 3; ++d) xi[d] = 0.5 * (sg[p0][d] + sg[p1][d]);
+    double det = hex_point_gradients(x, xi, g);
+    *min_det = std::min(*min_det, det);
+    for (int i = 0; i < 8; ++i)
+      for (int d = 0; d < 3; ++d) ge[(q * 8 + i) * 3 + d] = g[i][d];
+  }
   return V;
 }
 
@@ -1037,9 +1084,12 @@ orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex,
   c->X.resize(n_nodes);
   for (int i = 0; i < n_nodes; ++i) c->X[i] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
   c->el.resize(n_hex);
+  c->hexg.resize(n_hex);
   for (int t = 0; t < n_hex; ++t) {
     Elem& e = c->el[t];
     e.nn = 8;
+    for (int l = 0; l < 8; ++l)
+      for (int d = 0; d < 3; ++d) e.g[l][d] = 0.0;  // hexes use their edge-point gradients
     for (int l = 0; l < 8; ++l) {
       e.n[l] = hex[8 * t + l];
       if (e.n[l] < 0 || e.n[l] >= n_nodes) {
@@ -1051,12 +1101,12 @@ orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex,
     V3 x[8];
     for (int l = 0; l < 8; ++l) x[l] = c->X[e.n[l]];
     double mind;
-    double V = hex_geometry(x, e.g, &mind);
+    double V = hex_geometry(x, c->hexg[t].data(), &mind);
     if (V < 0) {
       std::swap(e.n[1], e.n[3]);
       std::swap(e.n[5], e.n[7]);
       for (int l = 0; l < 8; ++l) x[l] = c->X[e.n[l]];
-      V = hex_geometry(x, e.g, &mind);
+      V = hex_geometry(x, c->hexg[t].data(), &mind);
     }
     if (!(mind > 0)) {
       c->status = -5;
@@ -1137,9 +1187,48 @@ int orc_critical_dt(orc_ctx* c, double* dt_crit) {
   return 0;
 }
 
+// Largest eigenvalue of B^T C B for one strain-displacement matrix of nc
+// columns (dense cyclic Jacobi).
+double lambda_max_btcb(const double B[6][24], int nc, const double C[6][6]) {
+  std::vector<double> K(nc * nc, 0.0);
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) {
+      double s = 0;
+      for (int r = 0; r < 6; ++r)
+        for (int q = 0; q < 6; ++q) s += B[r][i] * C[r][q] * B[q][j];
+      K[nc * i + j] = s;
+    }
+  double w[24];
+  jacobi_eig(nc, K, w, nullptr);
+  double lm = w[0];
+  for (int i = 1; i < nc; ++i) lm = std::max(lm, w[i]);
+  return lm;
+}
+
 int orc_elem_lambda_max(orc_ctx* c, double* lam) {
   double C[6][6];
   cmat(c->lam, c->mu, C);
+  if (c->D == 12.0) {
+    // hexes: the largest over the edge points, max_q lambda_max(B_q^T C B_q),
+    // bounds lambda_max of the edge-averaged (1/12) sum_q B_q^T C B_q
+    std::map<std::array<double, 288>, double> hmemo;
+    for (int t = 0; t < c->T0; ++t) {
+      auto it = hmemo.find(c->hexg[t]);
+      if (it != hmemo.end()) {
+        lam[t] = it->second;
+        continue;
+      }
+      double lm = 0;
+      for (int q = 0; q < 12; ++q) {
+        double B[6][24];
+        elem_bmat(c, t, q, B);
+        lm = std::max(lm, lambda_max_btcb(B, 24, C));
+      }
+      hmemo[c->hexg[t]] = lm;
+      lam[t] = lm;
+    }
+    return 0;
+  }
   std::map<std::array<double, 24>, double> memo;  // identical shapes repeat
   for (int t = 0; t < c->T0; ++t) {
     const int nc = 3 * c->el[t].nn;

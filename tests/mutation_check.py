@@ -99,7 +99,9 @@ MUTANTS = [
  ("Griffith test strict", "if (best >= c->Gc) out.push_back", "if (best > c->Gc) out.push_back"),
  ("tie gap too narrow", "double gap = 1e-6 * amax;", "double gap = 1e-10 * amax;"),
  ("tie gap too wide", "double gap = 1e-6 * amax;", "double gap = 1e-5 * amax;"),
- ("hex inverse Jacobian entry transposed", "    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "    inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
+ ("hex inverse Jacobian entry transposed", "  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "  inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
+ ("hex edge point at the element centre", "for (int d = 0; d < 3; ++d) xi[d] = 0.5 * (sg[p0][d] + sg[p1][d]);", "for (int d = 0; d < 3; ++d) xi[d] = 0.0 * (sg[p0][d] + sg[p1][d]);"),
+ ("hex patch entries on the wrong edge point", "int q = per == 1 ? 0 : c->patch_q[k][i];", "int q = per == 1 ? 0 : (c->patch_q[k][i] + 1) % 12;"),
 ]
 
 
