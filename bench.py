@@ -1,25 +1,28 @@
 """Throughput of the ES-T-FEM crack-element step on one MI355X.
 
-Default workload: the notched plate of the paper's crack-branching example
-(Section 4.4) on a synthetic structured mesh, 100 x 40 x 4 mm at 200 x 80 x 8
-cells x 6 tets = 768,000 tets, 1 MPa traction ramped over 1 us, splitting on.
-A step is the whole hot path: strain pass, edge stress pass, crack-front pass
-with flag compaction, node force + Newmark pass, topology update.
+Default workload: the large notched block, 400 x 200 x 100 cells of 0.5 mm x
+6 tets = 48,000,000 tets (8,140,701 nodes), notch plane y = 50 mm over
+x < 100 mm with 960,000 pre-split tets (2%), +-1 MPa traction in y ramped
+over 1 us, splitting on; the headline precision is FP32 forces with FP64
+state, FP64 is reported beside it.  A step is the whole hot path: strain
+pass, edge stress pass, crack-front pass with flag compaction, node force +
+Newmark pass, topology update.  `--workload plate` is the 768,000-tet notched
+plate of the crack-branching example (Section 4.4), FP64 headline.
 
-Prints one JSON line (rank 0).  Phases:
-  0. the library's autotuner picks the launch shape (force layout, grid,
-     lanes) on a warmed-up copy;
-  1. FP64 run, plain launches with per-pass HIP events on the library's
-     stream: warmup, then --steps steps (per-pass durations and the roofline
-     of the dominant pass; reported as "per_pass_run");
-  2. the same steps as captured HIP graphs, and again as plain launches,
-     both without events: value and ms_per_step are the faster of the two
-     (which one wins varies from one machine to another; both are reported
-     under "modes"),
-     each bitwise equal to run 1;
-  3. mixed precision with the FP64 split schedule replayed (its own tuned
-     shape): throughput and relative L2 error of u against the FP64 run;
-  4. the CPU oracle on a bounded sample (cpu_baseline).
+Prints one JSON line.  The mesh is uploaded once; every timed run starts
+from one checkpoint:
+  0. FP64 from t = 0 through --advance steps (past the onset of dynamic
+     splitting) and --warmup steps: checkpoint C0;
+  1. per precision (FP64, then mixed on the same state): the library's
+     autotuner picks the launch shape from C0; then --steps steps from C0
+     three times: plain launches with per-pass HIP events on the library's
+     stream (kernel durations, roofline), HIP graphs of min(--graph-steps,
+     --steps) steps, plain launches; `value` is the faster of the last two
+     in the headline precision, each bitwise equal to the events run;
+  2. mixed precision from t = 0 to the end of the window with the FP64 split
+     schedule replayed (relative L2 error of u), and free-running (split
+     events that differ);
+  3. the CPU oracle on a bounded sample at one thread and every core.
 """
 from __future__ import annotations
 
@@ -47,6 +50,8 @@ ALG_BYTES = {
 # workgroups riding along), then per-node sums
 KERNEL_NAMES = {"strain": ["k_strain"], "edge_stress": ["k_edge_stress"],
                 "node": ["k_elem_force_front", "k_node"]}
+# steps before the warm-up by default: past the onset of dynamic splitting
+DEFAULT_ADVANCE = {"block": 1000, "block8m": 600, "plate": 600, "dirichlet": 600, "cube": 200}
 
 
 def log(msg):
@@ -123,35 +128,42 @@ def copy_peak_gbs(nbytes=1 << 30, reps=10):
     return gbs
 
 
-def counters_for(kernel_src_hash, workload="plate"):
-    """HBM traffic per launch of `workload` from the committed rocprofv3 counter
-    summaries (profiles/hbm_counters.json, else hbm_counters_<workload>.json),
-    if they were taken on the current kernel source."""
-    for name in ("hbm_counters.json", f"hbm_counters_{workload}.json"):
-        p = os.path.join(ROOT, "profiles", name)
-        if not os.path.exists(p):
-            continue
-        try:
-            d = json.load(open(p))
-        except Exception:
-            continue
-        if d.get("workload") != workload:
-            continue
-        return d if d.get("kernel_source_sha256") == kernel_src_hash else None
-    return None
+def counters_for(kernel_src_hash, workload, precision, layout):
+    """HBM traffic per launch from the committed rocprofv3 counter summary
+    profiles/hbm_counters_<workload>_<precision>.json, if it was taken on the
+    current kernel source in the same force layout."""
+    p = os.path.join(ROOT, "profiles", f"hbm_counters_{workload}_{precision}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("workload") != workload or d.get("precision") != precision:
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_hash or d.get("layout", "terms") != layout:
+        return None
+    return d
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="plate",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="block",
                     choices=["plate", "cube", "block8m", "block", "ensemble", "window",
                              "dirichlet", "hex", "hexblock"])
-    ap.add_argument("--graph-steps", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=0,
-                    help="oracle steps for the CPU baseline (0: about 15 s of work)")
+    ap.add_argument("--advance", type=int, default=-1,
+                    help="steps before the warm-up, to put the timed window past the onset of "
+                         "dynamic splitting (-1: the workload's default)")
+    ap.add_argument("--headline", default=None, choices=["fp64", "mixed"],
+                    help="precision of `value` (default: mixed for the blocks, else fp64)")
+    ap.add_argument("--graph-steps", type=int, default=50,
+                    help="steps per HIP graph (capped at --steps)")
+    ap.add_argument("--error-steps", type=int, default=0,
+                    help="length of the mixed-versus-FP64 error runs from t = 0 (default: to the "
+                         "end of the timed window)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -194,256 +206,278 @@ def main():
         return bench_hex(args)
     mesh, ramp, desc = workload(args.workload)
     T = mesh.n_tets
-    log(f"workload {args.workload}: {T} tets, {mesh.n_nodes} nodes")
     K, W = args.steps, args.warmup
-    if not args.no_graph:
-        W = max(W, args.graph_steps)  # the first graph is captured in the warm-up
-    max_splits = max(T // 8, len(mesh.presplit_tets) + 20000)
-
-    tuned = {}
-
+    head = args.headline or ("mixed" if args.workload in ("block", "block8m") else "fp64")
+    if args.no_mixed:
+        head = "fp64"
+    adv = args.advance if args.advance >= 0 else DEFAULT_ADVANCE.get(args.workload, 0)
+    gs = 0 if args.no_graph else min(args.graph_steps, K)
+    n_pre = len(mesh.presplit_tets) if mesh.presplit_tets is not None else 0
+    max_splits = n_pre + max(T // 50, 20000)
+    log(f"workload {args.workload}: {T} tets, {mesh.n_nodes} nodes; headline {head}; "
+        f"advance {adv}, warmup {W}, timed {K} steps, graphs of {gs}")
     groups = velocity_groups(args.workload, mesh)
 
-    def make(precision, graph):
-        s_ = Simulation.from_mesh(mesh, mat, ramp_t0=ramp, precision=precision,
-                                  max_splits=max_splits, graph_steps=graph, device=0)
-        for g_ in groups:
-            s_.add_velocity_bc(*g_)
-        if tuned:
-            s_.set_launch(tuned["grid_cap"], tuned["lanes"], tuned["layout"])
-        return s_
-
-    # ---- 0. launch shape from the library's autotuner, on a warmed-up copy
-    gs = 0 if args.no_graph else args.graph_steps
-    sim = make("fp64", 0)
-    dt = 0.5 * sim.critical_dt()
-    if args.launch:
-        g_, l_, lay_ = args.launch.split(",")
-        tuned.update(grid_cap=int(g_), lanes=int(l_), layout=lay_)
-        sim.set_launch(tuned["grid_cap"], tuned["lanes"], tuned["layout"])
-    elif not args.no_tune:
-        sim.set_dt(dt)
-        sim.step(W)
-        tuned.update(sim.autotune(trial_steps=10))
-        log(f"autotuned launch: {tuned}")
-        sim.close()
-        sim = make("fp64", 0)
-
-    # ---- 1. FP64, plain launches with per-pass HIP events on the library's
-    # stream: the kernel times of the roofline (and the timed region when
-    # graphs are off)
-    sim.set_dt(dt)
-    log(f"dt = {dt:.6e} s; warmup {W} steps")
-    sim.set_profiling(True)
-    sim.step(W)
+    # ---- one upload; every run below rewinds to a checkpoint
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(K)
+    sim = Simulation.from_mesh(mesh, mat, ramp_t0=ramp, precision="fp64",
+                               max_splits=max_splits, graph_steps=0, device=0)
+    for g_ in groups:
+        sim.add_velocity_bc(*g_)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = sim.kernel_times()
-    reaction = None
-    if groups:
-        rows, work = sim.reactions(0)
-        reaction = {"driven_face_reaction_N_last": rows[-1, 2:5].tolist(),
-                    "driven_face_work_J": work, "rows": len(rows)}
-    u64, _, _ = sim.get_state()
-    e64 = sim.energy()
+    t_up = time.perf_counter() - t0
+    log(f"mesh upload {t_up:.1f} s")
+    dt = 0.5 * sim.critical_dt()
+    sim.set_dt(dt)
+    ck_init = sim.save_state() if not args.no_mixed else None
+    # run up to the timed window (past the onset of dynamic splitting where the
+    # load reaches the notch in time), then the warm-up steps
+    done = 0
+    while done < adv:
+        n = min(250, adv - done)
+        sim.step(n)
+        done += n
+        e = sim.energy()
+        log(f"advance: step {done}, splits {e['n_split']} ({e['n_split'] - n_pre} dynamic), "
+            f"fronts {e['n_front']}, Gmax {e['Gmax']:.3g}")
+    sim.step(W)
+    ck0 = sim.save_state()
+    step0 = int(sim.energy()["step"])
+
+    def timed(prec_ck, graph, profiled=False):
+        """K steps from the checkpoint; returns seconds, final u, energy, last-run record."""
+        sim.load_state(prec_ck)
+        sim.set_graph_steps(graph)
+        sim.set_profiling(profiled)
+        torch.cuda.synchronize()
+        t0_ = time.perf_counter()
+        sim.step(K)
+        torch.cuda.synchronize()
+        wall_ = time.perf_counter() - t0_
+        sim.set_profiling(False)
+        return wall_, sim.get_state()[0], sim.energy(), sim.last_run()
+
+    def one_precision(prec, ck):
+        """Autotuned shape, per-pass events run, graph run, plain run."""
+        res = {}
+        tuned_ = None
+        if args.launch:
+            g_, l_, lay_ = args.launch.split(",")
+            sim.set_launch(int(g_), int(l_), lay_)
+            tuned_ = {"grid_cap": int(g_), "lanes": int(l_), "layout": lay_, "source": "--launch"}
+        elif not args.no_tune:
+            sim.load_state(ck)
+            sim.set_graph_steps(0)
+            tuned_ = sim.autotune(trial_steps=10)
+            log(f"autotuned launch ({prec}): {tuned_}")
+        wall_, u_pp, e_, _ = timed(ck, 0, profiled=True)
+        kt = sim.kernel_times()
+        res["per_pass"] = {"ms_per_step": wall_ * 1e3 / K, "tet_steps_per_s": T * K / wall_,
+                           "launch": "plain launches with per-pass HIP events"}
+        res["kernels_ms_per_step"] = {k: kt[k] / K for k in ("strain", "edge_stress", "front",
+                                                             "elem_force", "node_sum", "node",
+                                                             "topology")}
+        log(f"{prec} per-pass events: {wall_ * 1e3 / K:.4f} ms/step")
+        modes_ = {}
+        for name, graph in (("graphs", gs), ("plain", 0)):
+            if name == "graphs" and gs == 0:
+                continue
+            w_, u_, e2, lr = timed(ck, graph)
+            modes_[name] = {"ms_per_step": w_ * 1e3 / K, "tet_steps_per_s": T * K / w_,
+                            "graph_launches": lr["graph_launches"], "graph_steps": lr["graph_steps"],
+                            "plain_steps": lr["plain_steps"],
+                            "bitwise_equal_to_per_pass_run": bool(np.array_equal(u_, u_pp))}
+            log(f"{prec} {name}: {w_ * 1e3 / K:.4f} ms/step, {T * K / w_:.4e} tet-steps/s ({lr})")
+        best_ = max(modes_, key=lambda k: modes_[k]["tet_steps_per_s"])
+        res.update(modes=modes_, best=best_, autotune=tuned_, u_end=u_pp,
+                   splits_in_window=int(e_["n_split"]) - n_split0, energy=e_)
+        return res
+
+    n_split0 = int(sim.energy()["n_split"])
+    runs = {"fp64": one_precision("fp64", ck0)}
     ev64, _ = sim.splits()
-    log(f"fp64 (plain launches, per-pass events): "
-        f"{wall * 1e3 / K:.4f} ms/step, {T * K / wall:.4e} tet-steps/s, splits {e64['n_split']}")
-    per_launch = {k: kt[k] / K for k in ("strain", "edge_stress", "front", "elem_force",
-                                          "node_sum", "node", "topology")}
-    sim.close()
-
-    # ---- 2. FP64 as captured HIP graphs without events, same steps: the
-    # timed region of `value` (tet-steps/s over graph replays)
-    graph, handover = None, None
-    if not args.no_graph and gs > 0:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g = make("fp64", gs)
-        torch.cuda.synchronize()
-        t_up = time.perf_counter() - t0
-        g.set_dt(dt)
-        g.step(W)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.step(K)
-        torch.cuda.synchronize()
-        gw = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        ug, vg, _ = g.get_state()
-        t_rd = time.perf_counter() - t0
-        graph = {"ms_per_step": gw * 1e3 / K, "tet_steps_per_s": T * K / gw,
-                 "graph_steps": gs,
-                 "bitwise_equal_to_per_pass_run": bool(np.array_equal(ug, u64))}
-        log(f"fp64 graphs without events: {gw * 1e3 / K:.4f} ms/step, {T * K / gw:.4e} tet-steps/s")
-        t0 = time.perf_counter()
-        g.set_state(ug, vg)
-        torch.cuda.synchronize()
-        t_wr = time.perf_counter() - t0
-        # the boundary's host hand-overs, outside the timed region of `value`
-        handover = {
-            "mesh_upload_s": t_up, "state_readback_ms": t_rd * 1e3, "state_set_ms": t_wr * 1e3,
-            "tet_steps_per_s_with_readback": T * K / (gw + t_rd),
-            "tet_steps_per_s_with_upload_and_readback": T * K / (t_up + gw + t_rd),
-            "note": ("mesh upload = host preprocessing (order, edges, patches, node lists) plus "
-                     "host-to-device copies, once per run; readback = u, v, a to host; "
-                     f"rates over the {K} timed graph steps"),
-        }
-        log(f"host hand-over: upload {t_up:.2f} s, state readback {t_rd * 1e3:.2f} ms, "
-            f"set {t_wr * 1e3:.2f} ms")
-        g.close()
-
-    # ---- 2b. the same steps as plain launches without events: the library's
-    # other execution mode (graph_steps 0)
-    plain = None
-    if not args.no_graph and gs > 0:
-        p_ = make("fp64", 0)
-        p_.set_dt(dt)
-        p_.step(W)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p_.step(K)
-        torch.cuda.synchronize()
-        pw = time.perf_counter() - t0
-        up, _, _ = p_.get_state()
-        plain = {"ms_per_step": pw * 1e3 / K, "tet_steps_per_s": T * K / pw,
-                 "bitwise_equal_to_per_pass_run": bool(np.array_equal(up, u64))}
-        log(f"fp64 plain launches without events: {pw * 1e3 / K:.4f} ms/step, "
-            f"{T * K / pw:.4e} tet-steps/s")
-        p_.close()
-
-    # ---- 3. mixed precision, FP64 split schedule replayed
-    mixed = None
+    u64_end = runs["fp64"]["u_end"]
+    host = {"mesh_upload_s": t_up}
+    t0 = time.perf_counter()
+    ug, _, _ = sim.get_state()
+    host["state_readback_ms"] = (time.perf_counter() - t0) * 1e3
+    mixed_err = None
     if not args.no_mixed:
-        mx = make("mixed", args.graph_steps if not args.no_graph else 0)
-        mx.set_dt(dt)
+        # the same state in mixed precision: switch the arithmetic, keep the rest
+        sim.load_state(ck0)
+        sim.set_precision("mixed")
+        ck0m = sim.save_state()
+        runs["mixed"] = one_precision("mixed", ck0m)
+        um = runs["mixed"]["u_end"]
+        win_err = float(np.linalg.norm(um - u64_end) / np.linalg.norm(u64_end))
+        # from t = 0 with the FP64 split schedule replayed, and free-running
+        n_all = max(step0 + K, args.error_steps)
+        sim.set_graph_steps(gs)
+        if n_all > step0 + K:
+            # a longer FP64 reference run from t = 0
+            sim.set_precision("fp64")
+            sim.load_state(ck_init)
+            t0 = time.perf_counter()
+            sim.step(n_all)
+            log(f"fp64 reference: {n_all} steps from t = 0 in {time.perf_counter() - t0:.1f} s")
+            ev64, _ = sim.splits()
+            u64_end = sim.get_state()[0]
+        sim.set_precision("fp64")
+        sim.load_state(ck_init)
+        sim.set_precision("mixed")
         sched = ev64[ev64[:, 3] > 0][:, :3]
         if len(sched):
-            mx.replay_splits(sched)
-        mx.step(W)
-        tuned_mx = None
-        if not args.launch and not args.no_tune:
-            # its own launch shape (the tuner restores the state after each trial)
-            tuned_mx = mx.autotune(trial_steps=10)
-            log(f"autotuned launch (mixed): {tuned_mx}")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mx.step(K)
-        torch.cuda.synchronize()
-        mw = time.perf_counter() - t0
-        um, _, _ = mx.get_state()
-        err = float(np.linalg.norm(um - u64) / np.linalg.norm(u64))
-        mixed = {"tet_steps_per_s": T * K / mw, "ms_per_step": mw * 1e3 / K,
-                 "rel_l2_u_vs_fp64": err, "steps_compared": W + K,
-                 "split_schedule": "fp64 run replayed", "dtype": "f32 force / f64 state",
-                 "autotune": tuned_mx}
-        log(f"mixed: {mw * 1e3 / K:.4f} ms/step, {T * K / mw:.4e} tet-steps/s, "
-            f"rel L2 u err {err:.3e}")
-        mx.close()
+            sim.replay_splits(sched)
+        sim.step(n_all)
+        ur, _, _ = sim.get_state()
+        rep_err = float(np.linalg.norm(ur - u64_end) / np.linalg.norm(u64_end))
+        sim.set_precision("fp64")
+        sim.load_state(ck_init)
+        sim.set_precision("mixed")
+        sim.step(n_all)
+        evf, _ = sim.splits()
+        a64 = {tuple(r) for r in ev64[:, :3].tolist()}
+        af = {tuple(r) for r in evf[:, :3].tolist()}
+        mixed_err = {"rel_l2_u_vs_fp64_from_t0_schedule_replayed": rep_err,
+                     "steps_from_t0": n_all,
+                     "rel_l2_u_vs_fp64_over_timed_window_same_start": win_err,
+                     "free_running_split_events": {"fp64": len(a64), "mixed": len(af),
+                                                   "only_fp64": len(a64 - af),
+                                                   "only_mixed": len(af - a64)}}
+        log(f"mixed error: {mixed_err}")
+    sim.close()
+    del ck_init, ck0
 
-    # ---- roofline of the dominant pass (largest average time per step)
-    dom = max(("strain", "edge_stress", "node"), key=lambda k: per_launch[k])
-    dur_s = per_launch[dom] * 1e-3
-    alg = ALG_BYTES["fp64"][dom] * T
-    achieved = alg / dur_s / 1e9
-    cnt = counters_for(kernel_source_hash(), args.workload)
-    if cnt and cnt.get("layout", "terms") != tuned.get("layout", "terms"):
-        cnt = None  # counters of the other force layout
-    traffic = None
-    if cnt and cnt.get("workload") == args.workload and \
-            all(k in cnt.get("kernels", {}) for k in KERNEL_NAMES[dom]):
-        traffic = sum(cnt["kernels"][k]["hbm_bytes_per_launch"] for k in KERNEL_NAMES[dom])
-    roofline = {"bound": "hbm", "kernel": "+".join(KERNEL_NAMES[dom]), "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic, "alg_bytes_per_tet": ALG_BYTES["fp64"][dom],
-                "avg_launch_ms": per_launch[dom]}
+    # ---- roofline of the dominant pass of the headline precision
+    hr = runs[head]
+    per = hr["kernels_ms_per_step"]
+    dom = max(("strain", "edge_stress", "node"), key=lambda k: per[k])
 
-    # ---- HBM GB/s of the step: model bytes x rate ("effective"), and counted
-    # bytes (rocprofv3 counters of this source) over each pass's event time,
-    # against the spec and a device copy measured here
-    per_pass_run = {"ms_per_step": wall * 1e3 / K, "tet_steps_per_s": T * K / wall,
-                    "launch": "plain launches with per-pass HIP events (the kernel times above)"}
-    modes = {k: v for k, v in (("graphs", graph), ("plain", plain)) if v}
-    if modes:
-        best = max(modes, key=lambda k: modes[k]["tet_steps_per_s"])
-        value, ms_step = modes[best]["tet_steps_per_s"], modes[best]["ms_per_step"]
-        launch_desc = (f"HIP graphs of {gs} steps, no events" if best == "graphs"
-                       else "plain launches, no events")
-        if len(modes) > 1:
-            launch_desc += " (the faster of graphs and plain launches here; both under 'modes')"
-    else:
-        value, ms_step = per_pass_run["tet_steps_per_s"], per_pass_run["ms_per_step"]
-        launch_desc = per_pass_run["launch"]
-    hbm = {"spec_gbs": HBM_PEAK_GBS, "copy_peak_gbs": copy_peak_gbs(),
-           "effective_gbs_fp64": sum(ALG_BYTES["fp64"].values()) * value / 1e9,
-           "alg_bytes_per_tet_fp64": sum(ALG_BYTES["fp64"].values())}
-    if mixed:
-        hbm["effective_gbs_mixed"] = sum(ALG_BYTES["mixed"].values()) * mixed["tet_steps_per_s"] / 1e9
-    if cnt and cnt.get("workload") == args.workload and \
-            all(k in cnt.get("kernels", {}) for p_ in KERNEL_NAMES for k in KERNEL_NAMES[p_]):
-        counted, tb, tt = {}, 0.0, 0.0
-        for p_, names in KERNEL_NAMES.items():
-            b_ = sum(cnt["kernels"][k]["hbm_bytes_per_launch"] for k in names)
-            counted[p_] = {"bytes_per_launch": b_, "gbs": b_ / (per_launch[p_] * 1e-3) / 1e9}
-            tb += b_
-            tt += per_launch[p_] * 1e-3
-        hbm["counted"] = counted
-        hbm["counted_gbs_s_e_f"] = tb / tt / 1e9
-        hbm["counted_note"] = ("bytes from FETCH_SIZE and WRITE_SIZE (scaled by a plain copy) at "
-                               "the library's default launch shape; times from this run's events")
+    def roof(prec, r_):
+        p_ = r_["kernels_ms_per_step"]
+        ach = ALG_BYTES[prec][dom] * T / (p_[dom] * 1e-3) / 1e9
+        lay = (r_["autotune"] or {}).get("layout", "terms")
+        cnt_ = counters_for(kernel_source_hash(), args.workload, prec, lay)
+        tr = None
+        if cnt_ and all(k in cnt_["kernels"] for k in KERNEL_NAMES[dom]):
+            tr = sum(cnt_["kernels"][k]["hbm_bytes_per_launch"] for k in KERNEL_NAMES[dom])
+        return {"bound": "hbm", "kernel": "+".join(KERNEL_NAMES[dom]), "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": tr, "alg_bytes_per_tet": ALG_BYTES[prec][dom],
+                "avg_launch_ms": p_[dom], "precision": prec}, cnt_
 
-    # ---- 4. CPU oracle on a bounded sample
+    roofline, cnt = roof(head, hr)
+    hbm = {"spec_gbs": HBM_PEAK_GBS, "copy_peak_gbs": copy_peak_gbs()}
+    for prec, r_ in runs.items():
+        v_ = r_["modes"][r_["best"]]["tet_steps_per_s"]
+        hbm[f"effective_gbs_{prec}"] = sum(ALG_BYTES[prec].values()) * v_ / 1e9
+        hbm[f"alg_bytes_per_tet_{prec}"] = sum(ALG_BYTES[prec].values())
+        lay = (r_["autotune"] or {}).get("layout", "terms")
+        c_ = counters_for(kernel_source_hash(), args.workload, prec, lay)
+        if c_ and all(k in c_["kernels"] for p_ in KERNEL_NAMES for k in KERNEL_NAMES[p_]):
+            counted, tb, tt = {}, 0.0, 0.0
+            for p_, names in KERNEL_NAMES.items():
+                b_ = sum(c_["kernels"][k]["hbm_bytes_per_launch"] for k in names)
+                t_ = r_["kernels_ms_per_step"][p_] * 1e-3
+                counted[p_] = {"bytes_per_launch": b_, "gbs": b_ / t_ / 1e9}
+                tb += b_
+                tt += t_
+            hbm[f"counted_{prec}"] = counted
+            hbm[f"counted_gbs_s_e_f_{prec}"] = tb / tt / 1e9
+
+    # ---- CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu:
-        from oracle.oracle import Oracle
-        o = Oracle.from_mesh(mesh, mat, ramp_t0=ramp)
-        for g_ in groups:
-            o.add_velocity_bc(*g_)
-        o.set_dt(dt)
-        n_cpu = args.cpu_steps
-        if n_cpu <= 0:
-            t0 = time.perf_counter()
-            o.step(1)
-            one = time.perf_counter() - t0
-            n_cpu = max(1, min(200, int(20.0 / max(one, 1e-6))))
-            done = 1
-        else:
-            done = 0
-        log(f"oracle: {n_cpu} steps on the host")
-        t0 = time.perf_counter()
-        o.step(n_cpu - done)
-        el = time.perf_counter() - t0
-        n_timed = n_cpu - done
-        if n_timed == 0:
-            n_timed, el = 1, one
-        cpu = {"value": T * n_timed / el, "unit": "tet-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n_timed} steps of the same workload from t=0 (single-threaded FP64 "
-                         f"C++ oracle, {el:.1f} s)",
-               "host_cpus": os.cpu_count()}
+        cpu = cpu_baseline(args.workload, mesh, mat, ramp, groups)
 
+    best = hr["best"]
+    value, ms_step = hr["modes"][best]["tet_steps_per_s"], hr["modes"][best]["ms_per_step"]
+    mb = hr["modes"][best]
+    if mb["graph_launches"] > 0:
+        launch_desc = (f"{mb['graph_launches']} HIP graph launch(es) of {mb['graph_steps']} steps"
+                       + (f" + {mb['plain_steps']} plain steps" if mb["plain_steps"] else "")
+                       + ", no events")
+    else:
+        launch_desc = "plain launches, no events"
+    if len(hr["modes"]) > 1:
+        launch_desc += " (the faster of graphs and plain launches here; both under 'modes')"
+
+    def strip(r_):
+        return {k: v for k, v in r_.items() if k not in ("u_end", "energy")}
+
+    other = [p for p in runs if p != head]
     out = {
         "metric": METRIC, "value": value, "unit": "tet-steps/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": desc, "tets": T, "nodes": mesh.n_nodes,
-                   "dt_s": dt, "splits_after_run": int(e64["n_split"]),
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 force / f64 state" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": desc, "tets": T, "nodes": mesh.n_nodes, "dt_s": dt,
+                   "precision": head,
+                   "timed_window_steps": [step0 + 1, step0 + K],
+                   "steps_before_window": {"advance": adv, "warmup": W},
+                   "dynamic_splits_before_window": n_split0 - n_pre,
+                   "dynamic_splits_in_window": hr["splits_in_window"],
                    "launch": launch_desc},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels_ms_per_step": per_launch,
+        "kernels_ms_per_step": per,
         "hbm": hbm,
-        "autotune": tuned or None,
-        "per_pass_run": per_pass_run,
-        "modes": modes or None,
-        "mixed": mixed,
-        "host_handover": handover,
+        head: strip(hr),
+        "mixed_error": mixed_err,
+        "host_handover": host,
     }
-    if reaction:
-        out["reactions"] = reaction
+    for p_ in other:
+        out[p_] = strip(runs[p_])
+        out[p_]["tet_steps_per_s"] = runs[p_]["modes"][runs[p_]["best"]]["tet_steps_per_s"]
+        out[p_]["roofline"] = roof(p_, runs[p_])[0]
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(name, mesh, mat, ramp, groups):
+    """The oracle on the host at one thread and at every core of this process's
+    CPU share (threads give the same bits), each for about 12 s of stepping
+    from t = 0.  The 48M and 8M blocks are too large for the oracle in a
+    bench's time: their sample is a 100 x 50 x 25-cell block of the same
+    construction (750,000 tets: same cell size, material, load and notch
+    rule), whose per-tet cost is the block's."""
+    from oracle.oracle import Oracle
+    from paper_2508_04076_amd import meshgen as mg
+    if name in ("block", "block8m"):
+        sm = mg.block_notched(100, 50, 25)
+        sample = "100x50x25-cell notched block of the same construction (750,000 tets)"
+    else:
+        sm = mesh
+        sample = "the same mesh"
+    o = Oracle.from_mesh(sm, mat, ramp_t0=ramp)
+    for g_ in groups:
+        o.add_velocity_bc(*g_)
+    o.set_dt(0.5 * o.critical_dt())
+    o.step(1)  # initial acceleration and first step, untimed
+    ncpu = min(16, len(os.sched_getaffinity(0)))
+    res = {}
+    for nt in sorted({1, ncpu}):
+        o.set_threads(nt)
+        t0 = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t0
+        n = max(1, min(400, int(12.0 / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        o.step(n)
+        el = time.perf_counter() - t0
+        res[nt] = (sm.n_tets * n / el, n, el)
+        log(f"oracle, {nt} thread(s): {res[nt][0]:.4e} tet-steps/s ({n} steps, {el:.1f} s)")
+    v, n, el = res[ncpu]
+    v1, n1, el1 = res[1]
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    return {"value": v, "unit": "tet-steps/s", "cores": ncpu, "kind": "oracle",
+            "sample": f"{n} steps of the {sample}, from step 2 (FP64 C++ oracle, "
+                      f"{ncpu} threads, {el:.1f} s)",
+            "single_thread": {"value": v1, "steps": n1, "seconds": el1},
+            "host_cpu_model": model, "host_cpus_visible": os.cpu_count()}
 
 
 def bench_ensemble(args):
@@ -637,16 +671,19 @@ def window_cpu_baseline(mesh, mat, E, dt, gu, n_steps=8):
 
 # Algorithmic bytes per hex-step of the hexahedral passes (compulsory traffic,
 # FP64 / mixed), with E/H = 3 edges and N/H = 1 node per hex on a structured
-# grid: strain = ids 32 + G 192 + u gather 32 + write V eps 48; edge = CSR
-# 4 (E/H) + 48 + read V eps 48 + write sigma 48 (E/H) + einvV 8 (E/H);
-# force = ids 84 (12 edge ids 48, node lists 36) + G 192 + read sigma 48 (E/H)
-# + u, v read+write 96 + 1/m 8.  The per-hex stress sum handed from the element
-# pass to the node pass is an intermediate, not counted.
+# grid.  Each hex has one strain record per edge point (12 x 48 / 24 B) and
+# recomputes its gradients from the corner coordinates.  strain = hex nodes 32
+# + X gather 32 + u gather 32 + V 8 + write 12 records; edge = CSR offsets 12
+# + 12 entries 48 + read the 12 records + write sigma (E/H) + einvV (E/H);
+# force = hex nodes 32 + 12 edge ids 48 + 8 list positions 32 + X 32 + V 8 +
+# sigma (E/H) + node lists 32 + u, v read+write 96 + 1/m 8.  The nodal terms
+# handed from the element pass to the node pass are an intermediate, not
+# counted.
 HEX_BYTES = {
-    "fp64": {"strain": 32 + 192 + 32 + 48, "edge_stress": 12 + 48 + 48 + 144 + 24,
-             "node": 84 + 192 + 144 + 96 + 8},
-    "mixed": {"strain": 32 + 192 + 32 + 24, "edge_stress": 12 + 48 + 24 + 72 + 12,
-              "node": 84 + 192 + 72 + 96 + 8},
+    "fp64": {"strain": 32 + 32 + 32 + 8 + 12 * 48, "edge_stress": 12 + 48 + 12 * 48 + 144 + 24,
+             "node": 32 + 48 + 32 + 32 + 8 + 144 + 32 + 96 + 8},
+    "mixed": {"strain": 32 + 32 + 32 + 8 + 12 * 24, "edge_stress": 12 + 48 + 12 * 24 + 72 + 12,
+              "node": 32 + 48 + 32 + 32 + 8 + 72 + 32 + 96 + 8},
 }
 
 

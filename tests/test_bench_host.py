@@ -38,17 +38,19 @@ def test_source_hash_covers_every_hip_file(tmp_path, monkeypatch):
 def test_counters_of_other_sources_are_not_used(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "hbm_counters.json").write_text(json.dumps({"workload": "plate",
-                                                        "kernel_source_sha256": "0" * 64,
-                                                        "kernels": {}}))
-    (prof / "hbm_counters_block.json").write_text(json.dumps({"workload": "block",
-                                                              "kernel_source_sha256": "1" * 64,
-                                                              "kernels": {}}))
+    (prof / "hbm_counters_plate_fp64.json").write_text(json.dumps(
+        {"workload": "plate", "precision": "fp64", "layout": "stress_sums",
+         "kernel_source_sha256": "0" * 64, "kernels": {}}))
+    (prof / "hbm_counters_block_mixed.json").write_text(json.dumps(
+        {"workload": "block", "precision": "mixed", "layout": "terms",
+         "kernel_source_sha256": "1" * 64, "kernels": {}}))
     live = bench.kernel_source_hash()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.counters_for(live) is None
-    assert bench.counters_for("0" * 64)["workload"] == "plate"
-    # another workload's summary is found by name, and only for that workload
-    assert bench.counters_for("1" * 64, "block")["workload"] == "block"
-    assert bench.counters_for("0" * 64, "block") is None
-    assert bench.counters_for("1" * 64, "hex") is None
+    assert bench.counters_for(live, "plate", "fp64", "stress_sums") is None
+    assert bench.counters_for("0" * 64, "plate", "fp64", "stress_sums")["workload"] == "plate"
+    # another layout, precision or workload is not used
+    assert bench.counters_for("0" * 64, "plate", "fp64", "terms") is None
+    assert bench.counters_for("0" * 64, "plate", "mixed", "stress_sums") is None
+    assert bench.counters_for("1" * 64, "block", "mixed", "terms")["workload"] == "block"
+    assert bench.counters_for("1" * 64, "block", "fp64", "terms") is None
+    assert bench.counters_for("1" * 64, "hex", "mixed", "terms") is None
