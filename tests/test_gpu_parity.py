@@ -155,11 +155,13 @@ def test_front_G_readback():
     sim.close()
 
 
-def test_split_events_cube10_full_run():
+@pytest.mark.parametrize("mode", ["phantom", "erode"])
+def test_split_events_cube10_full_run(mode):
     # 10^3-cell cube, 6,000 tets, notch z = 0.5 over x < 0.3, 2,000 steps
-    _case("split events 10^3-cell cube, 2000 steps, graphs of 100 steps")
+    _case(f"split events 10^3-cell cube, 2000 steps, graphs of 100 steps, {mode}")
     mesh = mg.cube_notched(10)
-    sim, orc = _run_pair(mesh, 2000, chunks=4, sim_kw=dict(graph_steps=100))
+    sim, orc = _run_pair(mesh, 2000, chunks=4, sim_kw=dict(graph_steps=100, split_mode=mode),
+                         orc_kw=dict(split_mode=mode))
     ev = _events_equal(sim, orc)
     assert (ev[:, 3] > 0).sum() > 100
     ug, vg, _ = sim.get_state()

@@ -73,3 +73,38 @@ def test_topology_modes_agree_bitwise_and_with_the_oracle(precision):
         eo = orc.splits()[0]
         assert np.array_equal(e0[:, :3], eo[:, :3])
         assert _rel(u0, orc.get_state()[0]) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["single", "chip"])
+def test_split_batches_beyond_the_on_chip_sort(mode):
+    """Batches of 3,000 and 2,100 splits in one step (above the 2,048 the
+    one-workgroup rank sort holds on chip, so the topology pass sorts them in
+    global memory) against the oracle."""
+    _case(f"forced batches of 3000 and 2100 splits, topology mode {mode}")
+    from paper_2508_04076_amd.cem import Simulation
+    mesh = mg.cube_notched(12)
+    rng = np.random.default_rng(12)
+    free = np.setdiff1d(np.arange(mesh.n_tets), mesh.presplit_tets)
+    sizes = [3000, 2100]
+    tets = rng.choice(free, sum(sizes), replace=False)
+    masks = rng.choice([1, 2, 4, 8, 3, 5, 6, 9, 10, 12], sum(sizes))
+    sched = np.stack([np.repeat([2, 5], sizes), tets, masks], axis=1).astype(np.int32)
+    sim = Simulation.from_mesh(mesh, MAT, max_splits=mesh.n_tets)
+    sim.set_topology_mode(mode)
+    dt = 0.5 * sim.critical_dt()
+    sim.set_dt(dt)
+    sim.replay_splits(sched)
+    sim.step(8)
+    eg = sim.splits()[0]
+    per_step = np.unique(eg[eg[:, 0] > 0][:, 0], return_counts=True)[1]
+    assert per_step.tolist() == sizes
+    orc = Oracle.from_mesh(mesh, MAT)
+    orc.set_dt(dt)
+    orc.replay(sched)
+    orc.step(8)
+    eo = orc.splits()[0]
+    assert np.array_equal(eg[:, :3], eo[:, :3])
+    ug, vg, _ = sim.get_state()
+    uo, vo, _ = orc.get_state()
+    assert _rel(ug, uo) < 1e-10 and _rel(vg, vo) < 1e-10
+    sim.close()
