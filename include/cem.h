@@ -213,6 +213,18 @@ int cem_read_splits(cem_ctx* ctx, int32_t cap, cem_split_event* out, int32_t* n)
  * sorted by (tet, face); *n = total, at most cap written. */
 int cem_read_front_G(cem_ctx* ctx, int32_t cap, cem_front_g* out, int32_t* n);
 
+/* Allocation-free variant of cem_read_front_G for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): the same records in the same order, staged in one static
+ * device array per GPU (set up by the mesh upload) instead of buffers
+ * allocated per call.  The array holds 65,536 front slots, four per
+ * crack-front candidate tet: more than 16,384 candidates give CEM_ECAPACITY.
+ * cap = 0 only sets *n; otherwise cap must be at least *n (CEM_EINVAL,
+ * nothing written).  All contexts on one GPU share its array, which keeps the
+ * last call's contents: calls that overlap on one GPU (from several host
+ * threads) race. */
+int cem_read_front_G_static(cem_ctx* ctx, int32_t cap, cem_front_g* out, int32_t* n);
+
 /* Checkpoint of the whole simulation state into a host buffer (buf may be
  * NULL to query the size) and restore into a context created with the same
  * options and mesh. */

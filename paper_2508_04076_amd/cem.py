@@ -34,7 +34,7 @@ EXPORTS = [
     "cem_critical_dt_instances", "cem_read_energy_instances", "cem_set_launch", "cem_autotune",
     "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step",
     "cem_window_forward", "cem_window_backward", "cem_window_times", "cem_strain_energy_grad",
-    "cem_set_precision", "cem_set_graph_steps", "cem_last_run",
+    "cem_set_precision", "cem_set_graph_steps", "cem_last_run", "cem_read_front_G_static",
 ]
 
 
@@ -130,6 +130,7 @@ def load_library(path=LIB_PATH):
         "cem_set_precision": [p, i32],
         "cem_set_graph_steps": [p, i32],
         "cem_last_run": [p, p],
+        "cem_read_front_G_static": [p, i32, p, C.POINTER(C.c_int32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -316,6 +317,17 @@ class Simulation:
         self._chk(self.lib.cem_read_front_G(self.ctx, 0, None, C.byref(n)))
         arr = (cem_front_g * max(n.value, 1))()
         self._chk(self.lib.cem_read_front_G(self.ctx, n.value, C.cast(arr, C.c_void_p), C.byref(n)))
+        tfl = np.array([[a.tet, a.face, a.lone] for a in arr[: n.value]], dtype=np.int32).reshape(-1, 3)
+        g = np.array([[a.G_I, a.G_II] for a in arr[: n.value]], dtype=np.float64).reshape(-1, 2)
+        return tfl, g
+
+    def front_G_static(self):
+        """front_G through the allocation-free entry point (static staging)."""
+        n = C.c_int32()
+        self._chk(self.lib.cem_read_front_G_static(self.ctx, 0, None, C.byref(n)))
+        arr = (cem_front_g * max(n.value, 1))()
+        self._chk(self.lib.cem_read_front_G_static(self.ctx, n.value, C.cast(arr, C.c_void_p),
+                                                   C.byref(n)))
         tfl = np.array([[a.tet, a.face, a.lone] for a in arr[: n.value]], dtype=np.int32).reshape(-1, 3)
         g = np.array([[a.G_I, a.G_II] for a in arr[: n.value]], dtype=np.float64).reshape(-1, 2)
         return tfl, g

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <mutex>
 #include <vector>
 
 using namespace cem;
@@ -50,6 +51,7 @@ struct cem_ctx {
   int n_partial = 1024;
   bool bound = false;
   bool own_stream = false;
+  unsigned char* scratch = nullptr;  // this device's static staging (cem_read_front_G_static)
 
   // host mirrors (internal numbering)
   std::vector<double> X;       // 3 N0
@@ -893,6 +895,66 @@ int reverse_window(cem_ctx* c) {
   return reverse_step<R>(c, W.tape, 1, 0, lh, mh, nullptr);
 }
 
+// ---- allocation-free read of the crack-front release rates
+//
+// cem_read_front_G_static stages its device results in one file-scope device
+// array instead of buffers it allocates: room for kStaticFronts front slots
+// (four per crack-front candidate tet) as packed records, the raw
+// (tet, face, lone) and (G_I, G_II) arrays the front kernel writes, and the
+// record count.  Every GPU holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// that device (the array's name is a host-side stand-in).
+constexpr int kStaticFronts = 65536;
+constexpr size_t kStaticRecBytes = (size_t)kStaticFronts * sizeof(cem_front_g);
+constexpr size_t kStaticTflBytes = (size_t)kStaticFronts * 3 * sizeof(int);
+constexpr size_t kStaticGBytes = (size_t)kStaticFronts * 2 * sizeof(double);
+constexpr size_t kStaticBytes = kStaticRecBytes + kStaticTflBytes + kStaticGBytes + 256;
+static_assert(sizeof(cem_front_g) == 32, "front record layout");
+static_assert((kStaticRecBytes + kStaticTflBytes) % 8 == 0, "G array alignment");
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on the context's device, looked up once per
+// device with that device current.
+int static_scratch(cem_ctx* c, unsigned char** out) {
+  const int dev = c->opt.device;
+  if (dev >= kMaxDevices) return c->fail(CEM_EINVAL, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    HIPCHK(c, hipSetDevice(dev));
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return c->fail(CEM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return CEM_OK;
+}
+
+__global__ void k_zero_count(int* n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n = 0;
+}
+
+// (tet, face, lone) and (G_I, G_II) of front o -> one packed record.
+__global__ void k_pack_fronts(const int* __restrict__ tfl, const double* __restrict__ g,
+                              const int* __restrict__ n, cem_front_g* __restrict__ rec) {
+  int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= *n) return;
+  cem_front_g r;
+  r.tet = tfl[3 * o];
+  r.face = tfl[3 * o + 1];
+  r.lone = tfl[3 * o + 2];
+  r.pad = 0;
+  r.G_I = g[2 * o];
+  r.G_II = g[2 * o + 1];
+  rec[o] = r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -984,6 +1046,10 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
 
   // ---- device side
   HIPCHK(c, hipSetDevice(c->opt.device));
+  {
+    int rs = static_scratch(c, &c->scratch);  // set-up of the static staging, once per device
+    if (rs) return rs;
+  }
   if (!c->stream) {
     // graphs cannot capture the legacy null stream: use a stream of our own
     HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
@@ -1213,6 +1279,10 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   build_hex_topology(N, H, hx, h);
 
   HIPCHK(c, hipSetDevice(c->opt.device));
+  {
+    int rs = static_scratch(c, &c->scratch);  // set-up of the static staging, once per device
+    if (rs) return rs;
+  }
   if (!c->stream) {
     HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     c->own_stream = true;
@@ -1863,6 +1933,57 @@ int cem_read_splits(cem_ctx* c, int32_t cap, cem_split_event* out, int32_t* n) {
   HIPCHK(c, hipMemcpyAsync(G.data(), c->m.rec_G, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
   if ((r = sync(c))) return r;
   for (int i = 0; i < k; ++i) out[i] = cem_split_event{st[i], c->tet_old[tt[i]], mk[i], pt[i], G[i]};
+  return CEM_OK;
+}
+
+// ---- allocation-free read of the crack-front release rates (staging above)
+
+int cem_read_front_G_static(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !out)) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  if (c->m.etype == 8) {
+    *n = 0;
+    return CEM_OK;  // hexahedra have no crack fronts
+  }
+  if (!c->scratch) return c->fail(CEM_ESTATE, "static staging not set up");
+  if (c->need_init && c->dt_set && (r = initialize(c))) return r;
+  if ((r = read_counters(c))) return r;
+  const long long slots = 4LL * std::max(c->h_ctr->n_cand, 1);
+  if (slots > kStaticFronts)
+    return c->fail(CEM_ECAPACITY, "crack-front candidates need " + std::to_string(slots) +
+                                      " front slots; the static staging holds 65536");
+  unsigned char* base = c->scratch;
+  cem_front_g* d_rec = (cem_front_g*)base;
+  int* d_tfl = (int*)(base + kStaticRecBytes);
+  double* d_g = (double*)(base + kStaticRecBytes + kStaticTflBytes);
+  int* d_n = (int*)(base + kStaticRecBytes + kStaticTflBytes + kStaticGBytes);
+  if ((r = strain_stress(c, c->st.u))) return r;
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, c->stream, d_n);
+  HIPCHK(c, hipGetLastError());
+  hipError_t e = c->mixed ? Launch<float>::front_eval(c->m, c->st, c->w, c->d_ctr, d_tfl, d_g, d_n, c->stream)
+                          : Launch<double>::front_eval(c->m, c->st, c->w, c->d_ctr, d_tfl, d_g, d_n, c->stream);
+  HIPCHK(c, e);
+  hipLaunchKernelGGL(k_pack_fronts, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, c->stream,
+                     d_tfl, d_g, d_n, d_rec);
+  HIPCHK(c, hipGetLastError());
+  int nf = 0;
+  HIPCHK(c, hipMemcpyAsync(&nf, d_n, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  *n = nf;
+  if (cap == 0) return CEM_OK;
+  if (cap < nf)
+    return c->fail(CEM_EINVAL, "output holds " + std::to_string(cap) + " records for " +
+                                   std::to_string(nf) + " crack-front faces");
+  if (nf > 0) HIPCHK(c, hipMemcpyAsync(out, d_rec, sizeof(cem_front_g) * nf, hipMemcpyDeviceToHost, c->stream));
+  if ((r = sync(c))) return r;
+  for (int i = 0; i < nf; ++i) {
+    out[i].tet = c->tet_old[out[i].tet];
+    out[i].lone = c->node_old[out[i].lone];
+  }
+  std::sort(out, out + nf, [](const cem_front_g& x, const cem_front_g& y) {
+    return x.tet != y.tet ? x.tet < y.tet : x.face < y.face;
+  });
   return CEM_OK;
 }
 
