@@ -46,10 +46,17 @@ ALG_BYTES = {
     "fp64": {"strain": 149.0, "edge_stress": 146.0, "node": 200.0},
     "mixed": {"strain": 85.0, "edge_stress": 88.0, "node": 130.0},
 }
-# the node pass is two launches: per-element force terms (with the crack-front
-# workgroups riding along), then per-node sums
+# the force pass is two launches: per-element force terms (with the crack-front
+# workgroups riding along), then per-node sums; in the tiled layout, the
+# crack-front launch, the tiled force + node launch and the node pass of the
+# split copies' extra nodes
 KERNEL_NAMES = {"strain": ["k_strain"], "edge_stress": ["k_edge_stress"],
                 "node": ["k_elem_force_front", "k_node"]}
+KERNEL_NAMES_TILES = dict(KERNEL_NAMES, node=["k_front", "k_force_tile", "k_node"])
+
+
+def kernel_names(layout):
+    return KERNEL_NAMES_TILES if layout == "tiles" else KERNEL_NAMES
 # steps before the warm-up by default: past the onset of dynamic splitting
 DEFAULT_ADVANCE = {"block": 1000, "block8m": 600, "plate": 600, "dirichlet": 600, "cube": 200}
 
@@ -358,11 +365,12 @@ def main():
         p_ = r_["kernels_ms_per_step"]
         ach = ALG_BYTES[prec][dom] * T / (p_[dom] * 1e-3) / 1e9
         lay = (r_["autotune"] or {}).get("layout", "terms")
+        kn = kernel_names(lay)
         cnt_ = counters_for(kernel_source_hash(), args.workload, prec, lay)
         tr = None
-        if cnt_ and all(k in cnt_["kernels"] for k in KERNEL_NAMES[dom]):
-            tr = sum(cnt_["kernels"][k]["hbm_bytes_per_launch"] for k in KERNEL_NAMES[dom])
-        return {"bound": "hbm", "kernel": "+".join(KERNEL_NAMES[dom]), "achieved": ach,
+        if cnt_ and all(k in cnt_["kernels"] for k in kn[dom]):
+            tr = sum(cnt_["kernels"][k]["hbm_bytes_per_launch"] for k in kn[dom])
+        return {"bound": "hbm", "kernel": "+".join(kn[dom]), "achieved": ach, "layout": lay,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": tr, "alg_bytes_per_tet": ALG_BYTES[prec][dom],
                 "avg_launch_ms": p_[dom], "precision": prec}, cnt_
@@ -374,10 +382,11 @@ def main():
         hbm[f"effective_gbs_{prec}"] = sum(ALG_BYTES[prec].values()) * v_ / 1e9
         hbm[f"alg_bytes_per_tet_{prec}"] = sum(ALG_BYTES[prec].values())
         lay = (r_["autotune"] or {}).get("layout", "terms")
+        kn = kernel_names(lay)
         c_ = counters_for(kernel_source_hash(), args.workload, prec, lay)
-        if c_ and all(k in c_["kernels"] for p_ in KERNEL_NAMES for k in KERNEL_NAMES[p_]):
+        if c_ and all(k in c_["kernels"] for p_ in kn for k in kn[p_]):
             counted, tb, tt = {}, 0.0, 0.0
-            for p_, names in KERNEL_NAMES.items():
+            for p_, names in kn.items():
                 b_ = sum(c_["kernels"][k]["hbm_bytes_per_launch"] for k in names)
                 t_ = r_["kernels_ms_per_step"][p_] * 1e-3
                 counted[p_] = {"bytes_per_launch": b_, "gbs": b_ / t_ / 1e9}

@@ -56,7 +56,7 @@ enum { CEM_FP64 = 0, CEM_MIXED = 1 };          /* force arithmetic precision */
 enum { CEM_PHANTOM = 0, CEM_ERODE = 1 };       /* what a split does to the tet */
 enum { CEM_GSIG_PRINCIPAL = 0, CEM_GSIG_NORMAL = 1 };
 /* what the tet element force pass hands to the node pass (cem_set_launch) */
-enum { CEM_LAYOUT_TERMS = 0, CEM_LAYOUT_STRESS_SUMS = 1 };
+enum { CEM_LAYOUT_TERMS = 0, CEM_LAYOUT_STRESS_SUMS = 1, CEM_LAYOUT_TILES = 2 };
 
 typedef struct cem_ctx cem_ctx;
 
@@ -185,9 +185,21 @@ int cem_set_graph_steps(cem_ctx* ctx, int32_t graph_steps);
  * with fewer steps than a graph, a remainder, or profiling on). */
 int cem_last_run(cem_ctx* ctx, int64_t* out);
 
-/* Use caller device buffers (each at least capacity_nodes * 4 float64,
- * rows padded to 4) for u and v.  The current state is copied into them. */
+/* Use caller device buffers for u and v (e.g. torch tensors of shape
+ * [capacity_nodes][4], float64): each holds capacity_nodes rows of four
+ * float64 (x, y, z, unused), capacity_nodes >= n_nodes + 4 max_splits in
+ * CEM_PHANTOM mode, >= n_nodes otherwise (CEM_EINVAL below).  The current
+ * state is copied into them and the context works in them from then on; they
+ * are borrowed, must outlive the context and are never freed by it.  Rows are
+ * in the library's internal node order (a locality order of its own): row
+ * cem_node_rows gives for caller node i.  Work on them is enqueued on the
+ * context's stream; synchronize it before reading them elsewhere. */
 int cem_bind_state(cem_ctx* ctx, double* d_u, double* d_v, int64_t capacity_nodes);
+
+/* row[i] = the internal row of caller node i, for the first n nodes now
+ * (original nodes, then the extra nodes of the splits in split order, whose
+ * rows are their ids). */
+int cem_node_rows(cem_ctx* ctx, int32_t n, int32_t* row);
 
 /* Host state in and out, [n_nodes_now][3].  Either pointer may be NULL.  After
  * cem_set_state the next step first recomputes a = M^-1 (f_ext - f(u)). */
@@ -256,10 +268,15 @@ int cem_read_energy_instances(cem_ctx* ctx, int32_t n, cem_energy* out);
  * (f/36) G_l^T s of each tet (s = sum of its six edge stresses, G_l = 6 V grad
  * N_l, Eq. fint_discretization in its element form) at the node-list
  * positions; CEM_LAYOUT_STRESS_SUMS stores (f/36) s once per tet and the node
- * pass forms G_l^T from the corner coordinates.  The same forces either way,
- * up to rounding; which is faster depends on the mesh size and precision.
- * Hexahedra always use per-hex stress sums and ignore the layout.  Lanes and
- * layout set the order of the node sums, hence the rounding. */
+ * pass forms G_l^T from the corner coordinates; CEM_LAYOUT_TILES forms the
+ * terms and the node sums in one launch, a workgroup per tile of consecutive
+ * nodes, the terms kept on chip (the same bits as CEM_LAYOUT_TERMS at equal
+ * lanes; the crack-front pass then takes a launch of its own).  The same
+ * forces in every layout up to rounding; which is faster depends on the mesh
+ * size and precision.  Hexahedra always hand over nodal terms and ignore the
+ * layout.  Lanes and layout set the order of the node sums, hence the
+ * rounding.  CEM_LAYOUT_TILES on a mesh without tiles (a node with more than
+ * 3,072 list entries, or hexahedra) is CEM_EINVAL. */
 int cem_set_launch(cem_ctx* ctx, int32_t grid_cap, int32_t lanes, int32_t layout);
 /* Autotuner of the launch shape: times trial_steps steps of the live
  * simulation for each candidate (layout x grid 1024..8192 x lanes 4, 8, 16),

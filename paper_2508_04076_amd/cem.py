@@ -22,7 +22,7 @@ ERROR_NAMES = {-1: "CEM_EINVAL", -2: "CEM_ENOMEM", -3: "CEM_EHIP", -4: "CEM_EMES
 PRECISION = {"fp64": 0, "mixed": 1}
 SPLIT_MODE = {"phantom": 0, "erode": 1}
 GSIG = {"principal": 0, "normal": 1}
-LAYOUT = {"terms": 0, "stress_sums": 1}
+LAYOUT = {"terms": 0, "stress_sums": 1, "tiles": 2}
 
 EXPORTS = [
     "cem_create", "cem_destroy", "cem_last_error", "cem_upload_mesh", "cem_upload_hex_mesh",
@@ -35,6 +35,7 @@ EXPORTS = [
     "cem_add_velocity_bc", "cem_read_reactions", "cem_set_modulus", "cem_set_step",
     "cem_window_forward", "cem_window_backward", "cem_window_times", "cem_strain_energy_grad",
     "cem_set_precision", "cem_set_graph_steps", "cem_last_run", "cem_read_front_G_static",
+    "cem_node_rows",
 ]
 
 
@@ -131,6 +132,7 @@ def load_library(path=LIB_PATH):
         "cem_set_graph_steps": [p, i32],
         "cem_last_run": [p, p],
         "cem_read_front_G_static": [p, i32, p, C.POINTER(C.c_int32)],
+        "cem_node_rows": [p, i32, p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -266,6 +268,24 @@ class Simulation:
     @property
     def n_nodes(self):
         return self.counts()["nodes"]
+
+    def bind_state(self, u, v):
+        """Work in caller device tensors u, v of shape [capacity, 4] float64
+        (rows in the internal node order, see node_rows); they must outlive
+        the simulation."""
+        for x in (u, v):
+            if x.dtype.itemsize != 8 or x.dim() != 2 or x.shape[1] != 4 or not x.is_contiguous():
+                raise ValueError("bind_state needs contiguous [capacity, 4] float64 tensors")
+        self._chk(self.lib.cem_bind_state(self.ctx, C.c_void_p(u.data_ptr()),
+                                          C.c_void_p(v.data_ptr()), int(min(u.shape[0], v.shape[0]))))
+        self._bound = (u, v)
+
+    def node_rows(self, n=None):
+        """Internal row of each caller node (the first n nodes now)."""
+        n = self.n_nodes if n is None else n
+        out = np.zeros(n, dtype=np.int32)
+        self._chk(self.lib.cem_node_rows(self.ctx, int(n), _p(out)))
+        return out
 
     def set_state(self, u=None, v=None):
         n = self.n_nodes

@@ -15,6 +15,8 @@ constexpr int kTopoBlock = 1024;     // single-workgroup topology update
 constexpr int kTopoInline = CEM_TOPO_INLINE;  // larger batches sum masses and volumes in k_topo_sums
 constexpr int kDefaultLanes = 8;         // lanes per node in the node pass
 constexpr int kDefaultGridCap = 2048;    // workgroups of the persistent step launches
+constexpr int kTileBlock = 512;      // workgroup of the tiled force pass
+constexpr int kTileEntries = 3072;   // node-list entries of one tile (LDS: 3 values each)
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
@@ -66,6 +68,8 @@ struct Mesh {
   int ssum;                 // tets: what the force pass hands to the node pass: 0 = nodal
                             // terms at node-list positions, 1 = per-tet stress sums (the
                             // node pass forms G_l from the corner coordinates)
+  int tiled;                // tets: 1 = tiled force pass (terms in LDS per node tile)
+  int ntile;                // node tiles of the tiled force pass (0: none built)
   int n_inst;               // independent instances of a batch (0: one simulation)
   int etype;                // nodes per element: 4 (tetrahedra) or 8 (hexahedra)
 
@@ -105,6 +109,10 @@ struct Mesh {
   int* sched;               // forced schedule (step, tet, mask) triples
   double* rec_area;         // [S_cap] midpoint crack area of each split
   double* kap;              // [T_cap] modulus of each element slot over E (null: uniform E)
+  int* split_of;            // [T0] split index of a split tet (its copy B is slot T0 + index)
+  int* toff;                // [ntile + 1] first node of each tile
+  int* ttoff;               // [ntile + 1] offsets into ttet
+  int* ttet;                // tile element lists: parent tets with an entry in the tile, ascending
 
   // trilinear hexahedra (etype 8; no splitting, T_cap = T0)
   int4* hnodes;             // [2 T0] node ids 0-3, 4-7

@@ -224,24 +224,16 @@ __device__ __forceinline__ void bc_override(const Mesh& m, int b, double t, doub
 // entries g, g + G, ...; a fixed butterfly of shuffles combines the lanes, so
 // the sum is the same on every run), then the Newmark update.
 // KIND: 0 = contiguous terms (tets or hexes), 2 = tet stress sums
-template <class R, int MODE, int G, bool BC, int KIND>
-__global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st, const R* __restrict__ contrib,
-                                                 double4* __restrict__ fout,
-                                                 Counters* __restrict__ c) {
-  if (c->err || over_capacity(m, c)) return;
-  const int Nn = nodes_now(m, c);
-  Chunks it((long long)Nn * G);
-  const int g = (int)threadIdx.x % G;
-  for (int item; it.next(item);) {
-  const int i = item / G;
-  const bool active = i < Nn;
-  double fx, fy, fz;
-  if (KIND == 2) node_gather_tet<R, G>(m, contrib, i, active, g, fx, fy, fz);
-  else node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
-  if (!active || g != 0) continue;
+// Newmark update of node i from its internal force f (MODE NODE_STEP), the
+// initial acceleration (NODE_INIT) or f alone (NODE_FORCE); constrained
+// components follow their prescribed history (BC).
+template <int MODE, bool BC>
+__device__ __forceinline__ void node_update(const Mesh& m, const State& st, double4* __restrict__ fout,
+                                            Counters* __restrict__ c, int i, double fx, double fy,
+                                            double fz) {
   if (MODE == NODE_FORCE) {
     fout[i] = make_double4(fx, fy, fz, 0.0);
-    continue;
+    return;
   }
   const double dt = node_dt(m, i);
   const long long n = c->step;
@@ -266,7 +258,7 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st,
     }
     st.a[i] = make_double4(ax, ay, az, 0.0);
     st.uh[i] = uh;
-    continue;
+    return;
   }
   // NODE_STEP: f was evaluated at u_{n+1} = uh
   double r0 = ramp(m, (double)n * dt), r1 = ramp(m, (double)(n + 1) * dt);
@@ -301,6 +293,25 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st,
   bool bad = !(fabs(ax) <= DBL_MAX && fabs(ay) <= DBL_MAX && fabs(az) <= DBL_MAX) ||
              !(fabs(u1.x) <= m.umax && fabs(u1.y) <= m.umax && fabs(u1.z) <= m.umax);
   if (bad) atomicCAS(&c->err, 0, -6);
+}
+
+template <class R, int MODE, int G, bool BC, int KIND>
+__global__ __launch_bounds__(kBlock, CEM_WPE_NODE) void k_node(Mesh m, State st, const R* __restrict__ contrib,
+                                                 double4* __restrict__ fout,
+                                                 Counters* __restrict__ c, int first) {
+  if (c->err || over_capacity(m, c)) return;
+  const int Nn = nodes_now(m, c);
+  if (Nn <= first) return;
+  Chunks it((long long)(Nn - first) * G);
+  const int g = (int)threadIdx.x % G;
+  for (int item; it.next(item);) {
+    const int i = first + item / G;
+    const bool active = i < Nn;
+    double fx, fy, fz;
+    if (KIND == 2) node_gather_tet<R, G>(m, contrib, i, active, g, fx, fy, fz);
+    else node_gather<R, G>(m, contrib, i, active, g, fx, fy, fz);
+    if (!active || g != 0) continue;
+    node_update<MODE, BC>(m, st, fout, c, i, fx, fy, fz);
   }
 }
 
@@ -511,6 +522,109 @@ __device__ void front_block(const Mesh& m, const double4* __restrict__ u,
     __syncthreads();
   }
   if (threadIdx.x == 0 && red[0] != 0) atomicMax(&c->gmax_key, red[0]);
+}
+
+// Crack-front pass alone (the tiled force pass writes the state the front
+// pass reads, so it cannot ride along with it).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_front(Mesh m, const Six<R>* __restrict__ esig,
+                                                  const double4* __restrict__ uh,
+                                                  Counters* __restrict__ c, int flagging) {
+  if (c->err) return;
+  __shared__ unsigned long long red[kBlock];
+  front_block<R>(m, uh, esig, c, flagging, blockIdx.x, gridDim.x, red);
+}
+
+// Terms of element slot e into the tile's LDS when their node-list position
+// lies in the tile's range [P0, P1); entries of extra nodes (positions past
+// the original lists) go to the global term array, read by the node pass of
+// the extra nodes.
+template <class R>
+__device__ __forceinline__ void tile_elem(const Mesh& m, int e, const Six<R>* __restrict__ esig,
+                                          R* lds, int P0, int P1, R* __restrict__ contrib) {
+  const int4 nd = m.enodes[e];
+  const int code = (unsigned)nd.x >> kNodeBits;
+  R out[4][3];
+  if (code == FR_ZERO) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) out[l][0] = out[l][1] = out[l][2] = 0;
+  } else {
+    elem_terms(m, e, nd, code, esig, out);
+  }
+  const int4 pos = m.epos[e];
+  const int ps[4] = {pos.x, pos.y, pos.z, pos.w};
+  const int ext = 4 * m.T0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int q = ps[l];
+    if (q >= P0 && q < P1) {
+      R* o = lds + 3 * (q - P0);
+      o[0] = out[l][0];
+      o[1] = out[l][1];
+      o[2] = out[l][2];
+    } else if (q >= ext) {
+      put_term(contrib, q, out[l][0], out[l][1], out[l][2]);
+    }
+  }
+}
+
+// Tiled force pass (force and node update in one launch).  A workgroup owns a
+// tile: consecutive original nodes (a Hilbert-compact block) whose node-list
+// entries fit in kTileEntries.  Phase 1 forms the nodal terms of every element
+// slot with an entry in the tile (the tile's parent tets and the second copy
+// of each split one) into LDS at the entries' list positions; phase 2 sums
+// each node's entries from LDS in list order, G lanes per node with the
+// butterfly of node_gather, and updates the node.  The terms and their sums
+// are those of the term layout, so the results are the same bits; no term
+// makes a round trip through memory.  Tiles are dealt to the XCDs in eight
+// contiguous ranges.
+template <class R, int MODE, int G, bool BC>
+__global__ __launch_bounds__(kTileBlock) void k_force_tile(Mesh m, State st,
+                                                           const Six<R>* __restrict__ esig,
+                                                           R* __restrict__ contrib,
+                                                           double4* __restrict__ fout,
+                                                           Counters* __restrict__ c) {
+  if (c->err || over_capacity(m, c)) return;
+  __shared__ R lds[3 * kTileEntries];
+  const int x = (int)blockIdx.x % 8, j0 = (int)blockIdx.x / 8, stride = (int)gridDim.x / 8;
+  const int b_hi = (int)((long long)m.ntile * (x + 1) / 8);
+  const int g = (int)threadIdx.x % G;
+  const bool phantom = m.mode == MODE_PHANTOM;
+  for (int b = (int)((long long)m.ntile * x / 8) + j0; b < b_hi; b += stride) {
+    const int n0 = m.toff[b], n1 = m.toff[b + 1];
+    const int P0 = m.noff[n0], P1 = m.noff[n1];
+    for (int jj = m.ttoff[b] + (int)threadIdx.x; jj < m.ttoff[b + 1]; jj += kTileBlock) {
+      const int t = m.ttet[jj];
+      tile_elem<R>(m, t, esig, lds, P0, P1, contrib);
+      if (phantom) {
+        const int code = (unsigned)m.enodes[t].x >> kNodeBits;
+        if (code != FR_ONE) tile_elem<R>(m, m.T0 + m.split_of[t], esig, lds, P0, P1, contrib);
+      }
+    }
+    __syncthreads();
+    const int items = (n1 - n0) * G;
+    for (int base = 0; base < items; base += kTileBlock) {
+      const int item = base + (int)threadIdx.x;
+      const int i = n0 + item / G;
+      const bool active = item < items;
+      double fx = 0, fy = 0, fz = 0;
+      const int p0 = active ? m.noff[i] : 0, p1 = active ? m.noff[i + 1] : 0;
+      for (int q = p0 + g; q < p1; q += G) {
+        const R* o = lds + 3 * (q - P0);
+        fx += (double)o[0];
+        fy += (double)o[1];
+        fz += (double)o[2];
+      }
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off, G);
+        fy += __shfl_xor(fy, off, G);
+        fz += __shfl_xor(fz, off, G);
+      }
+      if (active && g == 0) node_update<MODE, BC>(m, st, fout, c, i, fx, fy, fz);
+    }
+    __syncthreads();  // the next tile overwrites the LDS
+  }
 }
 
 // The element force pass and the crack-front pass in one launch: the first fg
@@ -883,6 +997,7 @@ __device__ __forceinline__ void split_write(const Mesh& m, const State& st, R* _
     m.smask[t] = mask;
     m.rec_step[s] = dynamic ? (int)(c->step + 1) : (int)c->step;
     m.rec_tet[s] = t;
+    m.split_of[t] = s;
     m.rec_mask[s] = mask;
     m.rec_pat[s] = q.pat;
     m.rec_G[s] = q.G;
@@ -1521,34 +1636,77 @@ hipError_t Launch<R>::front_eval(const Mesh& m, const State& st, const Work& w, 
 
 template <class R, int G, int KIND>
 static void launch_node_kind(const Mesh& m, const State& st, const R* ct, Counters* c, int mode,
-                             double4* fout, hipStream_t s) {
-  dim3 g(persistent_grid(m, (long long)m.N_cap * G)), b(kBlock);
+                             double4* fout, hipStream_t s, int first = 0) {
+  dim3 g(persistent_grid(m, (long long)(m.N_cap - first) * G)), b(kBlock);
   // constrained nodes take their own kernel variant, so that a mesh without
   // prescribed velocities pays nothing for them
   if (mode == NODE_FORCE)
-    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_FORCE, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c, first);
   else if (mode == NODE_INIT && m.n_bc)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true, KIND>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, true, KIND>), g, b, 0, s, m, st, ct, fout, c, first);
   else if (mode == NODE_INIT)
-    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_INIT, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c, first);
   else if (m.n_bc)
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true, KIND>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, true, KIND>), g, b, 0, s, m, st, ct, fout, c, first);
   else
-    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c);
+    hipLaunchKernelGGL((k_node<R, NODE_STEP, G, false, KIND>), g, b, 0, s, m, st, ct, fout, c, first);
 }
 
 template <class R, int G>
 static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const Six<R>* sg,
-                              Counters* c, int mode, double4* fout, hipStream_t s) {
+                              Counters* c, int mode, double4* fout, hipStream_t s,
+                              int first = 0) {
   // hexes hand over their nodal terms at node-list positions, like the
   // tetrahedra's term layout
-  if (m.etype != 8 && m.ssum) launch_node_kind<R, G, 2>(m, st, ct, c, mode, fout, s);
-  else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s);
+  if (m.etype != 8 && m.ssum) launch_node_kind<R, G, 2>(m, st, ct, c, mode, fout, s, first);
+  else launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s, first);
+}
+
+template <class R, int G>
+static void launch_tile_lanes(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
+                              double4* fout, hipStream_t s) {
+  int grid = (m.ntile + 7) / 8 * 8;
+  if (grid > m.grid_cap) grid = m.grid_cap;
+  if (grid < 8) grid = 8;
+  dim3 g(grid), b(kTileBlock);
+  const Six<R>* sg = (const Six<R>*)w.esig;
+  R* ct = (R*)w.contrib;
+  if (mode == NODE_FORCE)
+    hipLaunchKernelGGL((k_force_tile<R, NODE_FORCE, G, false>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else if (mode == NODE_INIT && m.n_bc)
+    hipLaunchKernelGGL((k_force_tile<R, NODE_INIT, G, true>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else if (mode == NODE_INIT)
+    hipLaunchKernelGGL((k_force_tile<R, NODE_INIT, G, false>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else if (m.n_bc)
+    hipLaunchKernelGGL((k_force_tile<R, NODE_STEP, G, true>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else
+    hipLaunchKernelGGL((k_force_tile<R, NODE_STEP, G, false>), g, b, 0, s, m, st, sg, ct, fout, c);
+  // the extra nodes of split copies: their single terms were written to the
+  // global term array by the tiles
+  if (m.mode == MODE_PHANTOM) launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s, m.N0);
 }
 
 template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                            double4* fout, hipStream_t s, hipEvent_t mid, int front) {
+  if (m.etype != 8 && m.tiled) {
+    if (front >= 0) {
+      hipLaunchKernelGGL(k_front<R>, dim3((front_grid(m) + 7) / 8 * 8), dim3(kBlock), 0, s, m,
+                         (const Six<R>*)w.esig, (const double4*)st.uh, c, front);
+      if (front == 0) {  // forced schedule: select this step's entries
+        hipError_t e = launch_replay_select(m, c, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+    if (mid) {
+      hipError_t e = hipEventRecord(mid, s);
+      if (e != hipSuccess) return e;
+    }
+    if (m.lanes == 4) launch_tile_lanes<R, 4>(m, st, w, c, mode, fout, s);
+    else if (m.lanes == 16) launch_tile_lanes<R, 16>(m, st, w, c, mode, fout, s);
+    else launch_tile_lanes<R, 8>(m, st, w, c, mode, fout, s);
+    return hipGetLastError();
+  }
   if (m.etype == 8) {
     hipError_t e = launch_elem_force_hex<R>(m, w.esig, w.contrib, c, s);
     if (e != hipSuccess) return e;

@@ -315,6 +315,33 @@ void hilbert_order(int N, int T, int K, const std::vector<int>& elems, const dou
   for (int k = 0; k < N; ++k) new_of_old[val[k]] = k;
 }
 
+// Node tiles of the tiled force pass: runs of consecutive (Hilbert-ordered)
+// node ids whose node-list entries fit in kTileEntries, and per tile the
+// ascending tets that have an entry there.  Returns false (no tiles) if a
+// node alone has more entries than a tile holds.
+bool build_tiles(int N, const HostTopo& h, std::vector<int>& toff, std::vector<int>& ttoff,
+                 std::vector<int>& ttet) {
+  toff.assign(1, 0);
+  for (int i = 0; i < N; ++i) {
+    if (h.noff[i + 1] - h.noff[i] > kTileEntries) return false;
+    if (h.noff[i + 1] - h.noff[toff.back()] > kTileEntries) toff.push_back(i);
+  }
+  toff.push_back(N);
+  const int nt = (int)toff.size() - 1;
+  ttoff.assign(1, 0);
+  ttet.clear();
+  std::vector<int> tmp;
+  for (int b = 0; b < nt; ++b) {
+    tmp.clear();
+    for (int p = h.noff[toff[b]]; p < h.noff[toff[b + 1]]; ++p) tmp.push_back(h.nent[p] >> 2);
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    ttet.insert(ttet.end(), tmp.begin(), tmp.end());
+    ttoff.push_back((int)ttet.size());
+  }
+  return true;
+}
+
 int build_topology(cem_ctx* c, int N, int T, const std::vector<int>& tets, HostTopo& h) {
   // edges: sort (min, max) node-pair keys of every (tet, local edge)
   size_t M = (size_t)6 * T;
@@ -1077,6 +1104,8 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
   m.ssum = 0;
+  m.tiled = 0;
+  m.ntile = 0;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 4;
@@ -1136,6 +1165,19 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   ALLOC(m.rec_pat, std::max(S, 1), true);
   ALLOC(m.rec_G, std::max(S, 1), true);
   ALLOC(m.rec_area, std::max(S, 1), true);
+  ALLOC(m.split_of, T, true);
+  {
+    std::vector<int> toff, ttoff, ttet;
+    if (build_tiles(N, h, toff, ttoff, ttet)) {
+      m.ntile = (int)toff.size() - 1;
+      ALLOC(m.toff, toff.size(), false);
+      ALLOC(m.ttoff, ttoff.size(), false);
+      ALLOC(m.ttet, ttet.size(), false);
+      if ((r = upload(c, m.toff, toff.data(), toff.size()))) return r;
+      if ((r = upload(c, m.ttoff, ttoff.data(), ttoff.size()))) return r;
+      if ((r = upload(c, m.ttet, ttet.data(), ttet.size()))) return r;
+    }
+  }
   ALLOC(c->d_snodes, std::max(S, 1), false);
   ALLOC(c->d_sedges, (size_t)6 * std::max(S, 1), false);
   char* vb;
@@ -1303,6 +1345,9 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
   m.ssum = 0;
+  m.tiled = 0;
+  m.ntile = 0;
+  m.split_of = m.toff = m.ttoff = m.ttet = nullptr;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 8;
@@ -1593,6 +1638,16 @@ int cem_bind_state(cem_ctx* c, double* d_u, double* d_v, int64_t cap) {
   return CEM_OK;
 }
 
+int cem_node_rows(cem_ctx* c, int32_t n, int32_t* row) {
+  if (!c || (n > 0 && !row)) return CEM_EINVAL;
+  int r = ensure_ready(c, false);
+  if (r) return r;
+  const int now = nodes_now_host(c);
+  if (n < 0 || n > now) return c->fail(CEM_EINVAL, "more rows asked than nodes now");
+  for (int i = 0; i < n; ++i) row[i] = node_int(c, i);
+  return CEM_OK;
+}
+
 int cem_set_state(cem_ctx* c, const double* u, const double* v) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
@@ -1852,11 +1907,14 @@ int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes, int32_t layout) 
   c->gen++;
   if (grid_cap < 8 || grid_cap % 8 || (lanes != 4 && lanes != 8 && lanes != 16))
     return c->fail(CEM_EINVAL, "grid_cap must be a positive multiple of 8, lanes 4, 8 or 16");
-  if (layout != CEM_LAYOUT_TERMS && layout != CEM_LAYOUT_STRESS_SUMS)
-    return c->fail(CEM_EINVAL, "layout must be CEM_LAYOUT_TERMS or CEM_LAYOUT_STRESS_SUMS");
+  if (layout != CEM_LAYOUT_TERMS && layout != CEM_LAYOUT_STRESS_SUMS && layout != CEM_LAYOUT_TILES)
+    return c->fail(CEM_EINVAL, "layout must be CEM_LAYOUT_TERMS, CEM_LAYOUT_STRESS_SUMS or CEM_LAYOUT_TILES");
+  if (layout == CEM_LAYOUT_TILES && (c->m.etype == 8 || c->m.ntile == 0))
+    return c->fail(CEM_EINVAL, "no node tiles for this mesh");
   c->m.grid_cap = grid_cap;
   c->m.lanes = lanes;
-  c->m.ssum = c->m.etype == 8 ? 0 : layout;
+  c->m.ssum = c->m.etype == 8 ? 0 : layout == CEM_LAYOUT_STRESS_SUMS;
+  c->m.tiled = layout == CEM_LAYOUT_TILES;
   drop_graph(c);
   return CEM_OK;
 }
@@ -1877,8 +1935,10 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
   if ((r = cem_save_state(c, buf.data(), used, &used))) return r;
   const int grids[4] = {1024, 2048, 4096, 8192};
   const int lanes[3] = {4, 8, 16};
-  const int nlay = c->m.etype == 8 ? 1 : 2;  // hexes have one layout
-  int g0 = c->m.grid_cap, l0 = c->m.lanes, s0 = c->m.ssum;
+  // hexes have one layout; tets the term and stress-sum layouts, and the
+  // tiled pass when the mesh has tiles
+  const int nlay = c->m.etype == 8 ? 1 : (c->m.ntile > 0 ? 3 : 2);
+  int g0 = c->m.grid_cap, l0 = c->m.lanes, s0 = c->m.ssum + 2 * c->m.tiled;
   double best = 1e300;
   int bg = g0, bl = l0, bs = s0;
   int saved_prof = c->profiling;
@@ -1890,7 +1950,8 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
       for (int li = 0; li < 3 && r == CEM_OK; ++li) {
         c->m.grid_cap = grids[gi];
         c->m.lanes = lanes[li];
-        c->m.ssum = si;
+        c->m.ssum = si == 1;
+        c->m.tiled = si == 2;
         drop_graph(c);
         if ((r = cem_step(c, trial_steps))) break;
         double ms = c->times[0] / trial_steps;
@@ -1905,7 +1966,8 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
   c->profiling = saved_prof;
   c->m.grid_cap = r ? g0 : bg;
   c->m.lanes = r ? l0 : bl;
-  c->m.ssum = r ? s0 : bs;
+  c->m.ssum = (r ? s0 : bs) == 1;
+  c->m.tiled = (r ? s0 : bs) == 2;
   drop_graph(c);
   if (r) return r;
   if (best_grid) *best_grid = bg;

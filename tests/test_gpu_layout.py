@@ -1,6 +1,9 @@
 """The stress-sum force layout (the element pass hands (f/36) sum sigma per tet
-to the node pass, which forms G_l^T s itself from the corner coordinates)
-against the oracle and against the default term layout, through the C-ABI.
+to the node pass, which forms G_l^T s itself from the corner coordinates) and
+the tiled force pass (terms and node sums in one launch, a workgroup per
+tile of consecutive nodes, the terms kept in LDS) against the oracle and
+against the default term layout, through the C-ABI.  The tiled pass gives the
+term layout's bits at equal lanes.
 
 Tolerances as the other parity tests: FP64 forces 1e-12 normwise relative,
 FP64 trajectories 1e-9 relative L2 after splitting, identical split events;
@@ -34,7 +37,7 @@ def _sim(mesh, layout="stress_sums", lanes=8, **kw):
     return sim
 
 
-LAYOUTS = ["stress_sums"]
+LAYOUTS = ["stress_sums", "tiles"]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -97,6 +100,65 @@ def test_layouts_agree_on_the_plate():
     for layout in LAYOUTS:
         ub, eb = out[layout]
         assert np.array_equal(ea, eb) and _rel(ub, ua) < 1e-10, layout
+    assert np.array_equal(out["tiles"][0], ua)  # the term layout's bits
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["phantom", "erode"])
+def test_tiles_equal_terms_bitwise(precision, mode):
+    _case(f"tiles vs terms bitwise, cube 10, 400 steps through splitting, {precision} {mode}")
+    mesh = mg.cube_notched(10)
+    out = {}
+    for layout in ("terms", "tiles"):
+        for lanes in (4, 16):
+            sim = _sim(mesh, layout=layout, lanes=lanes, precision=precision, split_mode=mode,
+                       graph_steps=25)
+            sim.set_dt(6.797514528978e-06)
+            sim.step(400)
+            u, v, a = sim.get_state()
+            f = sim.internal_force(u)
+            out[(layout, lanes)] = (u, v, a, sim.splits()[0], f)
+            sim.close()
+    for lanes in (4, 16):
+        x, y = out[("terms", lanes)], out[("tiles", lanes)]
+        assert (x[3][:, 3] > 0).sum() > 100
+        for a_, b_ in zip(x, y):
+            assert np.array_equal(a_, b_), lanes
+
+
+def test_tiles_with_prescribed_velocities_and_a_batch():
+    _case("tiles vs terms bitwise: velocity-driven cube, and a batch of two meshes")
+    from paper_2508_04076_amd.cem import Simulation
+    mesh = mg.cube_notched(8)
+    mesh.load_tris, mesh.load_trac = None, None
+    top = np.nonzero(np.abs(mesh.X[:, 2] - 1.0) < 1e-12)[0]
+    bot = np.nonzero(np.abs(mesh.X[:, 2]) < 1e-12)[0]
+    vt = np.zeros((len(top), 3))
+    vt[:, 2] = 0.5
+    res = []
+    for layout in ("terms", "tiles"):
+        sim = _sim(mesh, layout=layout, lanes=8, max_splits=mesh.n_tets)
+        sim.add_velocity_bc(top, np.full(len(top), 4), vt, 1e-4)
+        sim.add_velocity_bc(bot, np.full(len(bot), 7), np.zeros((len(bot), 3)), 0.0)
+        sim.set_dt(0.5 * sim.critical_dt())
+        sim.step(300)
+        res.append((sim.get_state()[0], sim.splits()[0], sim.reactions(0)[0]))
+        sim.close()
+    for a_, b_ in zip(*res):
+        assert np.array_equal(a_, b_)
+    un, node_off, tet_off, _, _ = mg.ensemble(2, 3000, 6000, seed=4)
+    res = []
+    for layout in ("terms", "tiles"):
+        sim = Simulation(un.X, un.tets, MAT, max_splits=un.n_tets)
+        sim.set_instances(node_off, tet_off)
+        sim.set_traction(un.load_tris, un.load_trac, 1e-6)
+        sim.presplit(un.presplit_tets, un.presplit_masks)
+        sim.set_launch(1024, 8, layout)
+        sim.set_dt_instances(0.5 * sim.critical_dt_instances())
+        sim.step(200)
+        res.append((sim.get_state()[0], sim.splits()[0]))
+        sim.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
 
 
 def test_checkpoint_and_layout_switch():
