@@ -168,6 +168,8 @@ def main():
                     help="precision of `value` (default: mixed for the blocks, else fp64)")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="steps per HIP graph (capped at --steps)")
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the mixed-versus-FP64 runs from t = 0 (counter runs)")
     ap.add_argument("--error-steps", type=int, default=0,
                     help="length of the mixed-versus-FP64 error runs from t = 0 (default: to the "
                          "end of the timed window)")
@@ -237,7 +239,7 @@ def main():
     log(f"mesh upload {t_up:.1f} s")
     dt = 0.5 * sim.critical_dt()
     sim.set_dt(dt)
-    ck_init = sim.save_state() if not args.no_mixed else None
+    ck_init = sim.save_state() if not (args.no_mixed or args.no_error) else None
     # run up to the timed window (past the onset of dynamic splitting where the
     # load reaches the notch in time), then the warm-up steps
     done = 0
@@ -318,6 +320,7 @@ def main():
         runs["mixed"] = one_precision("mixed", ck0m)
         um = runs["mixed"]["u_end"]
         win_err = float(np.linalg.norm(um - u64_end) / np.linalg.norm(u64_end))
+    if not args.no_mixed and not args.no_error:
         # from t = 0 with the FP64 split schedule replayed, and free-running
         n_all = max(step0 + K, args.error_steps)
         sim.set_graph_steps(gs)

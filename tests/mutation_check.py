@@ -29,11 +29,10 @@ MUTANTS = [
  ("B row 4 index", "B[4][c + 1] = gz;", "B[4][c + 1] = gy;"),
  ("B row 5 operand", "B[5][c + 0] = gz;", "B[5][c + 0] = gx;"),
  ("inverse transposed", "for (int d = 0; d < 3; ++d) g[l][d] = inv[l - 1][d];", "for (int d = 0; d < 3; ++d) g[l][d] = inv[d][l - 1];"),
- ("smoothing weight V not Veff", "    for (int j : c->patch[k]) {\n      double w = c->el[j].Veff / S;\n      for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];",
-  "    for (int j : c->patch[k]) {\n      double w = c->el[j].V / S;\n      for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[j][r];"),
- ("smoothing overwrite", "eps[k][r] += w * eps_el[j][r];", "eps[k][r] = w * eps_el[j][r];"),
- ("V_k missing 1/D", "    if (S == 0.0) continue;\n    double Vk = S / c->D;\n    for (int j : c->patch[k]) {\n      double w = c->el[j].Veff / S;\n      double B[6][24];", "    if (S == 0.0) continue;\n    double Vk = S;\n    for (int j : c->patch[k]) {\n      double w = c->el[j].Veff / S;\n      double B[6][24];"),
- ("force sign", "f[c->el[j].n[q / 3]][q % 3] += Vk * w * s;", "f[c->el[j].n[q / 3]][q % 3] -= Vk * w * s;"),
+ ("smoothing weight V not Veff", "double w = c->el[j].Veff / S;\n        for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[per * j + q][r];", "double w = c->el[j].V / S;\n        for (int r = 0; r < 6; ++r) eps[k][r] += w * eps_el[per * j + q][r];"),
+ ("smoothing overwrite", "eps[k][r] += w * eps_el[per * j + q][r];", "eps[k][r] = w * eps_el[per * j + q][r];"),
+ ("V_k missing 1/D", "      double Vk = S / c->D;\n      for (size_t i = 0; i < c->patch[k].size(); ++i) {", "      double Vk = S;\n      for (size_t i = 0; i < c->patch[k].size(); ++i) {"),
+ ("force sign", "f[e.n[q / 3]][q % 3] += Vk * w * s;", "f[e.n[q / 3]][q % 3] -= Vk * w * s;"),
  ("force uses B^T eps", "for (int r = 0; r < 6; ++r) s += B[r][q] * sig[k][r];", "for (int r = 0; r < 6; ++r) s += B[r][q] * eps[k][r];"),
  ("mass from V", "c->m[e.n[l]] += c->rho * e.Veff / e.nn;", "c->m[e.n[l]] += c->rho * e.V / e.nn;"),
  ("mass split 1/3", "c->m[e.n[l]] += c->rho * e.Veff / e.nn;", "c->m[e.n[l]] += c->rho * e.Veff / 3.0;"),
@@ -99,7 +98,7 @@ MUTANTS = [
  ("Griffith test strict", "if (best >= c->Gc) out.push_back", "if (best > c->Gc) out.push_back"),
  ("tie gap too narrow", "double gap = 1e-6 * amax;", "double gap = 1e-10 * amax;"),
  ("tie gap too wide", "double gap = 1e-6 * amax;", "double gap = 1e-5 * amax;"),
- ("hex inverse Jacobian entry transposed", "  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "  inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
+ ("hex inverse Jacobian entry transposed", "double inv[3][3];  // J^{-1}\n  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;\n  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;", "double inv[3][3];  // J^{-1}\n  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;\n  inv[0][1] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;"),
  ("hex edge point at the element centre", "for (int d = 0; d < 3; ++d) xi[d] = 0.5 * (sg[p0][d] + sg[p1][d]);", "for (int d = 0; d < 3; ++d) xi[d] = 0.0 * (sg[p0][d] + sg[p1][d]);"),
  ("hex patch entries on the wrong edge point", "int q = per == 1 ? 0 : c->patch_q[k][i];", "int q = per == 1 ? 0 : (c->patch_q[k][i] + 1) % 12;"),
 ]

@@ -109,3 +109,38 @@ def test_autotune_keeps_state_and_picks_a_valid_shape():
     assert np.linalg.norm(ua - ur) <= 1e-9 * np.linalg.norm(ur)
     sim.close()
     ref.close()
+
+
+def test_full_ensemble_members_match_the_oracle():
+    """The 64-plate ensemble at full size (7.1M tets, seeded sizes 20k-200k and
+    tractions 0.5-2 MPa, 1 us ramp) under graphs: three members (the smallest,
+    a middle one and the largest) against the oracle run of that member alone,
+    over the first 30 steps (the pre-split notch included)."""
+    from paper_2508_04076_amd.cem import Simulation
+    print("\n[case] 64-plate ensemble, 30 graph steps, members against the oracle", flush=True)
+    un, node_off, tet_off, members, trac = mg.ensemble(64)
+    sim = Simulation(un.X, un.tets, MAT, precision="fp64", max_splits=un.n_tets // 4,
+                     graph_steps=10)
+    sim.set_instances(node_off, tet_off)
+    sim.set_traction(un.load_tris, un.load_trac, 1e-6)
+    sim.presplit(un.presplit_tets, un.presplit_masks)
+    dts = 0.5 * sim.critical_dt_instances()
+    sim.set_dt_instances(dts)
+    sim.step(30)
+    ub, vb, _ = sim.get_state()
+    sizes = np.array([m.n_tets for m in members])
+    pick = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
+    for i in pick:
+        o = Oracle.from_mesh(members[i], MAT, ramp_t0=1e-6)
+        o.set_threads(8)
+        o.set_dt(dts[i])
+        o.step(30)
+        n0 = members[i].n_nodes
+        uo, vo, _ = o.get_state()
+        uo, vo = uo[:n0], vo[:n0]  # the original nodes (extra nodes: the notch copies)
+        assert np.all(o.splits()[0][:, 3] == 0)  # no dynamic split in 30 steps
+        ui, vi = ub[node_off[i]:node_off[i + 1]], vb[node_off[i]:node_off[i + 1]]
+        err = np.linalg.norm(ui - uo) / np.linalg.norm(uo)
+        print(f"  member {i}: {members[i].n_tets} tets, rel L2 u {err:.2e}", flush=True)
+        assert err < 1e-10 and np.linalg.norm(vi - vo) < 1e-10 * np.linalg.norm(vo)
+    sim.close()
