@@ -137,9 +137,9 @@ def copy_peak_gbs(nbytes=1 << 30, reps=10):
 
 def counters_for(kernel_src_hash, workload, precision, layout):
     """HBM traffic per launch from the committed rocprofv3 counter summary
-    profiles/hbm_counters_<workload>_<precision>.json, if it was taken on the
-    current kernel source in the same force layout."""
-    p = os.path.join(ROOT, "profiles", f"hbm_counters_{workload}_{precision}.json")
+    profiles/hbm_counters_<workload>_<precision>_<layout>.json, if it was taken
+    on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"hbm_counters_{workload}_{precision}_{layout}.json")
     if not os.path.exists(p):
         return None
     try:

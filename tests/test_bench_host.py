@@ -38,10 +38,10 @@ def test_source_hash_covers_every_hip_file(tmp_path, monkeypatch):
 def test_counters_of_other_sources_are_not_used(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "hbm_counters_plate_fp64.json").write_text(json.dumps(
+    (prof / "hbm_counters_plate_fp64_stress_sums.json").write_text(json.dumps(
         {"workload": "plate", "precision": "fp64", "layout": "stress_sums",
          "kernel_source_sha256": "0" * 64, "kernels": {}}))
-    (prof / "hbm_counters_block_mixed.json").write_text(json.dumps(
+    (prof / "hbm_counters_block_mixed_terms.json").write_text(json.dumps(
         {"workload": "block", "precision": "mixed", "layout": "terms",
          "kernel_source_sha256": "1" * 64, "kernels": {}}))
     live = bench.kernel_source_hash()
