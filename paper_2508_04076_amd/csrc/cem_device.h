@@ -16,7 +16,9 @@ constexpr int kTopoInline = CEM_TOPO_INLINE;  // larger batches sum masses and v
 constexpr int kDefaultLanes = 8;         // lanes per node in the node pass
 constexpr int kDefaultGridCap = 2048;    // workgroups of the persistent step launches
 constexpr int kTileBlock = 512;      // workgroup of the tiled force pass
-constexpr int kTileEntries = 3072;   // node-list entries of one tile (LDS: 3 values each)
+// node-list entries of one tile (LDS: 3 values each, 72 KB in either precision)
+constexpr int kTileEntries64 = 3072;
+constexpr int kTileEntries32 = 6144;
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
@@ -69,7 +71,7 @@ struct Mesh {
                             // terms at node-list positions, 1 = per-tet stress sums (the
                             // node pass forms G_l from the corner coordinates)
   int tiled;                // tets: 1 = tiled force pass (terms in LDS per node tile)
-  int ntile;                // node tiles of the tiled force pass (0: none built)
+  int ntile[2];             // node tiles of the tiled force pass, float64 and float32 sets (0: none)
   int n_inst;               // independent instances of a batch (0: one simulation)
   int etype;                // nodes per element: 4 (tetrahedra) or 8 (hexahedra)
 
@@ -110,9 +112,11 @@ struct Mesh {
   double* rec_area;         // [S_cap] midpoint crack area of each split
   double* kap;              // [T_cap] modulus of each element slot over E (null: uniform E)
   int* split_of;            // [T0] split index of a split tet (its copy B is slot T0 + index)
-  int* toff;                // [ntile + 1] first node of each tile
-  int* ttoff;               // [ntile + 1] offsets into ttet
-  int* ttet;                // tile element lists: parent tets with an entry in the tile, ascending
+  // tiles of the tiled force pass, one set per precision ([0] float64, [1] float32: the
+  // float32 terms take half the LDS, so its tiles hold twice the entries)
+  int* toff[2];             // [ntile + 1] first node of each tile
+  int* ttoff[2];            // [ntile + 1] offsets into ttet
+  int* ttet[2];             // tile element lists: parent tets with an entry in the tile, ascending
 
   // trilinear hexahedra (etype 8; no splitting, T_cap = T0)
   int4* hnodes;             // [2 T0] node ids 0-3, 4-7

@@ -570,7 +570,7 @@ __device__ __forceinline__ void tile_elem(const Mesh& m, int e, const Six<R>* __
 
 // Tiled force pass (force and node update in one launch).  A workgroup owns a
 // tile: consecutive original nodes (a Hilbert-compact block) whose node-list
-// entries fit in kTileEntries.  Phase 1 forms the nodal terms of every element
+// entries fit in its LDS (3,072 float64 or 6,144 float32 terms).  Phase 1 forms the nodal terms of every element
 // slot with an entry in the tile (the tile's parent tets and the second copy
 // of each split one) into LDS at the entries' list positions; phase 2 sums
 // each node's entries from LDS in list order, G lanes per node with the
@@ -585,16 +585,21 @@ __global__ __launch_bounds__(kTileBlock) void k_force_tile(Mesh m, State st,
                                                            double4* __restrict__ fout,
                                                            Counters* __restrict__ c) {
   if (c->err || over_capacity(m, c)) return;
-  __shared__ R lds[3 * kTileEntries];
+  constexpr int P = sizeof(R) == 8 ? 0 : 1;
+  __shared__ R lds[3 * (P ? kTileEntries32 : kTileEntries64)];
+  const int* __restrict__ toff = m.toff[P];
+  const int* __restrict__ ttoff = m.ttoff[P];
+  const int* __restrict__ ttet = m.ttet[P];
+  const int ntile = m.ntile[P];
   const int x = (int)blockIdx.x % 8, j0 = (int)blockIdx.x / 8, stride = (int)gridDim.x / 8;
-  const int b_hi = (int)((long long)m.ntile * (x + 1) / 8);
+  const int b_hi = (int)((long long)ntile * (x + 1) / 8);
   const int g = (int)threadIdx.x % G;
   const bool phantom = m.mode == MODE_PHANTOM;
-  for (int b = (int)((long long)m.ntile * x / 8) + j0; b < b_hi; b += stride) {
-    const int n0 = m.toff[b], n1 = m.toff[b + 1];
+  for (int b = (int)((long long)ntile * x / 8) + j0; b < b_hi; b += stride) {
+    const int n0 = toff[b], n1 = toff[b + 1];
     const int P0 = m.noff[n0], P1 = m.noff[n1];
-    for (int jj = m.ttoff[b] + (int)threadIdx.x; jj < m.ttoff[b + 1]; jj += kTileBlock) {
-      const int t = m.ttet[jj];
+    for (int jj = ttoff[b] + (int)threadIdx.x; jj < ttoff[b + 1]; jj += kTileBlock) {
+      const int t = ttet[jj];
       tile_elem<R>(m, t, esig, lds, P0, P1, contrib);
       if (phantom) {
         const int code = (unsigned)m.enodes[t].x >> kNodeBits;
@@ -1665,7 +1670,7 @@ static void launch_node_lanes(const Mesh& m, const State& st, const R* ct, const
 template <class R, int G>
 static void launch_tile_lanes(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                               double4* fout, hipStream_t s) {
-  int grid = (m.ntile + 7) / 8 * 8;
+  int grid = (m.ntile[sizeof(R) == 8 ? 0 : 1] + 7) / 8 * 8;
   if (grid > m.grid_cap) grid = m.grid_cap;
   if (grid < 8) grid = 8;
   dim3 g(grid), b(kTileBlock);

@@ -316,15 +316,15 @@ void hilbert_order(int N, int T, int K, const std::vector<int>& elems, const dou
 }
 
 // Node tiles of the tiled force pass: runs of consecutive (Hilbert-ordered)
-// node ids whose node-list entries fit in kTileEntries, and per tile the
+// node ids whose node-list entries fit in cap, and per tile the
 // ascending tets that have an entry there.  Returns false (no tiles) if a
 // node alone has more entries than a tile holds.
-bool build_tiles(int N, const HostTopo& h, std::vector<int>& toff, std::vector<int>& ttoff,
+bool build_tiles(int N, const HostTopo& h, int cap, std::vector<int>& toff, std::vector<int>& ttoff,
                  std::vector<int>& ttet) {
   toff.assign(1, 0);
   for (int i = 0; i < N; ++i) {
-    if (h.noff[i + 1] - h.noff[i] > kTileEntries) return false;
-    if (h.noff[i + 1] - h.noff[toff.back()] > kTileEntries) toff.push_back(i);
+    if (h.noff[i + 1] - h.noff[i] > cap) return false;
+    if (h.noff[i + 1] - h.noff[toff.back()] > cap) toff.push_back(i);
   }
   toff.push_back(N);
   const int nt = (int)toff.size() - 1;
@@ -1105,7 +1105,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   m.lanes = kDefaultLanes;
   m.ssum = 0;
   m.tiled = 0;
-  m.ntile = 0;
+  m.ntile[0] = m.ntile[1] = 0;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 4;
@@ -1166,16 +1166,17 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   ALLOC(m.rec_G, std::max(S, 1), true);
   ALLOC(m.rec_area, std::max(S, 1), true);
   ALLOC(m.split_of, T, true);
-  {
+  for (int p = 0; p < 2; ++p) {
     std::vector<int> toff, ttoff, ttet;
-    if (build_tiles(N, h, toff, ttoff, ttet)) {
-      m.ntile = (int)toff.size() - 1;
-      ALLOC(m.toff, toff.size(), false);
-      ALLOC(m.ttoff, ttoff.size(), false);
-      ALLOC(m.ttet, ttet.size(), false);
-      if ((r = upload(c, m.toff, toff.data(), toff.size()))) return r;
-      if ((r = upload(c, m.ttoff, ttoff.data(), ttoff.size()))) return r;
-      if ((r = upload(c, m.ttet, ttet.data(), ttet.size()))) return r;
+    m.toff[p] = m.ttoff[p] = m.ttet[p] = nullptr;
+    if (build_tiles(N, h, p ? kTileEntries32 : kTileEntries64, toff, ttoff, ttet)) {
+      m.ntile[p] = (int)toff.size() - 1;
+      ALLOC(m.toff[p], toff.size(), false);
+      ALLOC(m.ttoff[p], ttoff.size(), false);
+      ALLOC(m.ttet[p], ttet.size(), false);
+      if ((r = upload(c, m.toff[p], toff.data(), toff.size()))) return r;
+      if ((r = upload(c, m.ttoff[p], ttoff.data(), ttoff.size()))) return r;
+      if ((r = upload(c, m.ttet[p], ttet.data(), ttet.size()))) return r;
     }
   }
   ALLOC(c->d_snodes, std::max(S, 1), false);
@@ -1346,8 +1347,9 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.lanes = kDefaultLanes;
   m.ssum = 0;
   m.tiled = 0;
-  m.ntile = 0;
-  m.split_of = m.toff = m.ttoff = m.ttet = nullptr;
+  m.ntile[0] = m.ntile[1] = 0;
+  m.split_of = nullptr;
+  for (int p = 0; p < 2; ++p) m.toff[p] = m.ttoff[p] = m.ttet[p] = nullptr;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 8;
@@ -1909,7 +1911,7 @@ int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes, int32_t layout) 
     return c->fail(CEM_EINVAL, "grid_cap must be a positive multiple of 8, lanes 4, 8 or 16");
   if (layout != CEM_LAYOUT_TERMS && layout != CEM_LAYOUT_STRESS_SUMS && layout != CEM_LAYOUT_TILES)
     return c->fail(CEM_EINVAL, "layout must be CEM_LAYOUT_TERMS, CEM_LAYOUT_STRESS_SUMS or CEM_LAYOUT_TILES");
-  if (layout == CEM_LAYOUT_TILES && (c->m.etype == 8 || c->m.ntile == 0))
+  if (layout == CEM_LAYOUT_TILES && (c->m.etype == 8 || c->m.ntile[0] == 0 || c->m.ntile[1] == 0))
     return c->fail(CEM_EINVAL, "no node tiles for this mesh");
   c->m.grid_cap = grid_cap;
   c->m.lanes = lanes;
@@ -1937,7 +1939,7 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
   const int lanes[3] = {4, 8, 16};
   // hexes have one layout; tets the term and stress-sum layouts, and the
   // tiled pass when the mesh has tiles
-  const int nlay = c->m.etype == 8 ? 1 : (c->m.ntile > 0 ? 3 : 2);
+  const int nlay = c->m.etype == 8 ? 1 : (c->m.ntile[0] > 0 && c->m.ntile[1] > 0 ? 3 : 2);
   int g0 = c->m.grid_cap, l0 = c->m.lanes, s0 = c->m.ssum + 2 * c->m.tiled;
   double best = 1e300;
   int bg = g0, bl = l0, bs = s0;
