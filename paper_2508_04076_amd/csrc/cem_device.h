@@ -15,10 +15,12 @@ constexpr int kTopoBlock = 1024;     // single-workgroup topology update
 constexpr int kTopoInline = CEM_TOPO_INLINE;  // larger batches sum masses and volumes in k_topo_sums
 constexpr int kDefaultLanes = 8;         // lanes per node in the node pass
 constexpr int kDefaultGridCap = 2048;    // workgroups of the persistent step launches
-constexpr int kTileBlock = 512;      // workgroup of the tiled force pass
-// node-list entries of one tile (LDS: 3 values each, 72 KB in either precision)
+// workgroup of the tiled force pass: float32 tiles fill a CU's LDS with one
+// 1,024-thread workgroup, float64 tiles take two of 512 threads
+template <class R> constexpr int tile_block() { return sizeof(R) == 8 ? 512 : 1024; }
+// node-list entries of one tile (LDS: 3 values each, 72 KB in float64, 144 KB in float32)
 constexpr int kTileEntries64 = 3072;
-constexpr int kTileEntries32 = 6144;
+constexpr int kTileEntries32 = 12288;
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 

@@ -579,7 +579,7 @@ __device__ __forceinline__ void tile_elem(const Mesh& m, int e, const Six<R>* __
 // makes a round trip through memory.  Tiles are dealt to the XCDs in eight
 // contiguous ranges.
 template <class R, int MODE, int G, bool BC>
-__global__ __launch_bounds__(kTileBlock) void k_force_tile(Mesh m, State st,
+__global__ __launch_bounds__(tile_block<R>()) void k_force_tile(Mesh m, State st,
                                                            const Six<R>* __restrict__ esig,
                                                            R* __restrict__ contrib,
                                                            double4* __restrict__ fout,
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(kTileBlock) void k_force_tile(Mesh m, State st,
   for (int b = (int)((long long)ntile * x / 8) + j0; b < b_hi; b += stride) {
     const int n0 = toff[b], n1 = toff[b + 1];
     const int P0 = m.noff[n0], P1 = m.noff[n1];
-    for (int jj = ttoff[b] + (int)threadIdx.x; jj < ttoff[b + 1]; jj += kTileBlock) {
+    for (int jj = ttoff[b] + (int)threadIdx.x; jj < ttoff[b + 1]; jj += tile_block<R>()) {
       const int t = ttet[jj];
       tile_elem<R>(m, t, esig, lds, P0, P1, contrib);
       if (phantom) {
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(kTileBlock) void k_force_tile(Mesh m, State st,
     }
     __syncthreads();
     const int items = (n1 - n0) * G;
-    for (int base = 0; base < items; base += kTileBlock) {
+    for (int base = 0; base < items; base += tile_block<R>()) {
       const int item = base + (int)threadIdx.x;
       const int i = n0 + item / G;
       const bool active = item < items;
@@ -1673,7 +1673,7 @@ static void launch_tile_lanes(const Mesh& m, const State& st, const Work& w, Cou
   int grid = (m.ntile[sizeof(R) == 8 ? 0 : 1] + 7) / 8 * 8;
   if (grid > m.grid_cap) grid = m.grid_cap;
   if (grid < 8) grid = 8;
-  dim3 g(grid), b(kTileBlock);
+  dim3 g(grid), b(tile_block<R>());
   const Six<R>* sg = (const Six<R>*)w.esig;
   R* ct = (R*)w.contrib;
   if (mode == NODE_FORCE)
@@ -1688,7 +1688,8 @@ static void launch_tile_lanes(const Mesh& m, const State& st, const Work& w, Cou
     hipLaunchKernelGGL((k_force_tile<R, NODE_STEP, G, false>), g, b, 0, s, m, st, sg, ct, fout, c);
   // the extra nodes of split copies: their single terms were written to the
   // global term array by the tiles
-  if (m.mode == MODE_PHANTOM) launch_node_kind<R, G, 0>(m, st, ct, c, mode, fout, s, m.N0);
+  // one lane per extra node: each has a single entry
+  if (m.mode == MODE_PHANTOM) launch_node_kind<R, 1, 0>(m, st, ct, c, mode, fout, s, m.N0);
 }
 
 template <class R>
