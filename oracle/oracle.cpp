@@ -47,7 +47,31 @@
 //     are the 12 hex edges, the smoothing domain of edge k has
 //     V_k = (1/12) sum of the volumes sharing it and the volume weights
 //     w_jk = V_j / sum V; the hex volume is exact with 2 x 2 x 2 Gauss points;
-//     the lumped mass is rho V / 8 per node; hexes do not split;
+//     the lumped mass is rho V / 8 per node;
+//   * hex crack patterns (Section 3, the parallelepiped patterns; the figure
+//     that draws them is missing from the text): cut planes are taken in the
+//     hex's natural coordinates xi through edge midpoints, c . xi = d with
+//     c in {-1, 0, 1}^3: the three mid-planes (d = 0), twelve wedge planes
+//     (two nonzero c, d = 1, cutting off the prism around one hex edge) and
+//     eight corner planes (three nonzero c, d = 2); a plane's cut edges are
+//     the edges whose midpoints lie on it.  A crack front is a face of an
+//     intact hex shared with a cracked hex whose plane cuts that face (at
+//     two of its edges, G1 on the lower local edge, G2 on the other).  Two
+//     opposite edges give III (the mid-plane through G1 G2, deactivating the
+//     hex) and IV (the two wedge planes through G1 G2 tilted toward either
+//     side), two neighbouring edges give V (the wedge plane through G1 G2
+//     along the face normal) and VI (the corner plane through G1 G2 and the
+//     midpoint G6 of the edge at their shared corner along the face normal).
+//     G_III, G_IV, G_V take Eq. G-I over the quad G1 G2 G4 G3, with G3 (G4)
+//     the fourth-edge point joined to G1 (G2), n the unit normal of the
+//     quad's diagonals, delta_1 and delta_2 the stretches of the G1 and G2
+//     edges; G_VI takes Eq. G-II over the triangle G1 G2 G6.  A III hex
+//     carries no volume after it cracks; after IV, V or VI the hex keeps its
+//     edge-point gradients and carries half its volume, the triangular prism
+//     (three tetrahedra of its own nodes) on the far side of the crack; its
+//     mass is kept; a hex cracks once; ties: larger G, then the lower local
+//     face, then III, IV toward -1, IV toward +1, V, VI; the crack area for
+//     U_d is that of the quad or the triangle;
 //   * hex critical step: the element bound takes the largest stiffness over
 //     the hex's edge points, (8 / rho) max_q lambda_max(B_q^T C B_q), which is
 //     at least lambda_max of its edge-averaged stiffness;
@@ -183,6 +207,7 @@ struct orc_ctx {
   std::vector<std::array<double, 288>> hexg;
   std::vector<std::array<int, 4>> orig;  // original (oriented) connectivity
   std::vector<std::array<int, 4>> nbr, nbr_face;
+  std::vector<std::array<int, 6>> hnbr, hnbr_face;  // hexes: neighbour across local face f
   std::vector<int> smask;  // per original tet: -1 intact, else side mask
   std::vector<double> m;
   std::vector<V3> F;
@@ -346,6 +371,9 @@ const int kEdgeLocal[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 // hex node order: bottom face 0-1-2-3 counter-clockwise, top face 4-7 above
 const int kHexEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
                              {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+// reference corner signs of the local nodes (Eq. hex_strain_discretization)
+const int kHexSign[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                            {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
 
 int elem_edges(const Elem& e, const int (**tab)[2]) {
   *tab = e.nn == 8 ? kHexEdge : kEdgeLocal;
@@ -563,11 +591,260 @@ void apply_split(orc_ctx* c, int t, int mask) {
   add_elem_to_edges(c, (int)c->el.size() - 1);
 }
 
+// ---- hexahedral crack patterns III-VI (Section 3, parallelepiped element)
+
+// Natural coordinate d of the midpoint of local hex edge q: -1, 0 or 1.
+int hex_mid(int q, int d) { return (kHexSign[kHexEdge[q][0]][d] + kHexSign[kHexEdge[q][1]][d]) / 2; }
+
+// The axis a hex edge runs along (the coordinate its midpoint has at 0).
+int hex_edge_axis(int q) {
+  for (int d = 0; d < 3; ++d)
+    if (hex_mid(q, d) == 0) return d;
+  return -1;
+}
+
+// The hex edge along `axis` whose midpoint has the two other coordinates
+// given (by axis: want[d] for d != axis).
+int hex_edge_at(int axis, const int want[3]) {
+  for (int q = 0; q < 12; ++q) {
+    if (hex_edge_axis(q) != axis) continue;
+    bool ok = true;
+    for (int d = 0; d < 3; ++d)
+      if (d != axis && hex_mid(q, d) != want[d]) ok = false;
+    if (ok) return q;
+  }
+  return -1;
+}
+
+// Crack plane c . xi = d of index p: 0-2 mid-planes (axis p), 3-14 wedge
+// planes (axis pair (0,1), (0,2), (1,2); signs of the two coefficients, the
+// first one slower), 15-22 corner planes (signs of c0, c1, c2, c0 slowest).
+void hex_plane(int p, int c[3], int* d) {
+  c[0] = c[1] = c[2] = 0;
+  if (p < 3) {
+    c[p] = 1;
+    *d = 0;
+  } else if (p < 15) {
+    const int pr[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    int k = (p - 3) / 4, r = (p - 3) % 4;
+    c[pr[k][0]] = (r & 2) ? 1 : -1;
+    c[pr[k][1]] = (r & 1) ? 1 : -1;
+    *d = 1;
+  } else {
+    int r = p - 15;
+    c[0] = (r & 4) ? 1 : -1;
+    c[1] = (r & 2) ? 1 : -1;
+    c[2] = (r & 1) ? 1 : -1;
+    *d = 2;
+  }
+}
+
+int hex_plane_index(const int c[3], int d) {
+  if (d == 0) return c[0] ? 0 : c[1] ? 1 : 2;
+  if (d == 1) {
+    int a = c[0] ? 0 : 1, b = c[2] ? 2 : 1;
+    int k = (a == 0 && b == 1) ? 0 : (a == 0 ? 1 : 2);
+    return 3 + 4 * k + 2 * (c[a] > 0) + (c[b] > 0);
+  }
+  return 15 + 4 * (c[0] > 0) + 2 * (c[1] > 0) + (c[2] > 0);
+}
+
+// Cut edges of plane p: bit q set when the midpoint of edge q lies on it.
+int hex_plane_mask(int p) {
+  int c[3], d, m = 0;
+  hex_plane(p, c, &d);
+  for (int q = 0; q < 12; ++q)
+    if (c[0] * hex_mid(q, 0) + c[1] * hex_mid(q, 1) + c[2] * hex_mid(q, 2) == d) m |= 1 << q;
+  return m;
+}
+
+// Volume fraction a hex keeps after cracking with plane p: none after III
+// (mid-plane), the triangular-prism half after IV, V and VI.
+double hex_plane_fraction(int p) { return p < 3 ? 0.0 : 0.5; }
+
+// Local face f = 2 axis + (side > 0): its four edges, as a bit mask.
+int hex_face_mask(int f) {
+  int axis = f / 2, side = (f & 1) ? 1 : -1, m = 0;
+  for (int q = 0; q < 12; ++q)
+    if (kHexSign[kHexEdge[q][0]][axis] == side && kHexSign[kHexEdge[q][1]][axis] == side) m |= 1 << q;
+  return m;
+}
+
+// One candidate of a hex front: its plane, pattern (3-6) and the local
+// edges of G1, G2 and G3, G4 (G-I quads) or G6 (G-II triangle, in G3).
+struct HexCand {
+  int plane, pattern, q1, q2, q3, q4;
+};
+
+// Candidates of the front on face f through the midpoints of local edges
+// qa < qb, in tie order: III, IV toward -1, IV toward +1 (opposite edges);
+// V, VI (neighbouring edges).
+std::vector<HexCand> hex_candidates(int f, int qa, int qb) {
+  std::vector<HexCand> out;
+  const int k = f / 2, s = (f & 1) ? 1 : -1;
+  const int i = hex_edge_axis(qa), j2 = hex_edge_axis(qb);
+  if (i == j2) {  // opposite edges, both along axis i
+    const int j = 3 - i - k;
+    int w3[3] = {0, 0, 0}, w4[3] = {0, 0, 0};
+    // III: the mid-plane xi_i = 0; G3, G4 on the i-edges of the opposite face
+    w3[j] = hex_mid(qa, j); w3[k] = -s;
+    w4[j] = hex_mid(qb, j); w4[k] = -s;
+    out.push_back({i, 3, qa, qb, hex_edge_at(i, w3), hex_edge_at(i, w4)});
+    // IV: sigma xi_i + s xi_k = 1; G3, G4 on the k-edges at xi_i = sigma
+    for (int sg = -1; sg <= 1; sg += 2) {
+      int c[3] = {0, 0, 0};
+      c[i] = sg;
+      c[k] = s;
+      w3[i] = sg; w3[j] = hex_mid(qa, j);
+      w4[i] = sg; w4[j] = hex_mid(qb, j);
+      out.push_back({hex_plane_index(c, 1), 4, qa, qb, hex_edge_at(k, w3), hex_edge_at(k, w4)});
+    }
+  } else {  // neighbouring edges: qa along i at xi_j = p, qb along j at xi_i = r
+    const int j = j2, p = hex_mid(qa, j), r = hex_mid(qb, i);
+    int c[3] = {0, 0, 0};
+    c[i] = r;
+    c[j] = p;
+    int w3[3] = {0, 0, 0}, w4[3] = {0, 0, 0};
+    w3[j] = p; w3[k] = -s;
+    w4[i] = r; w4[k] = -s;
+    out.push_back({hex_plane_index(c, 1), 5, qa, qb, hex_edge_at(i, w3), hex_edge_at(j, w4)});
+    c[k] = s;
+    int w6[3] = {0, 0, 0};
+    w6[i] = r; w6[j] = p;
+    out.push_back({hex_plane_index(c, 2), 6, qa, qb, hex_edge_at(k, w6), -1});
+  }
+  return out;
+}
+
+// Reference midpoint of local edge q of hex t.
+V3 hex_edge_point_x(const orc_ctx* c, int t, int q) {
+  const V3& a = c->X[c->el[t].n[kHexEdge[q][0]]];
+  const V3& b = c->X[c->el[t].n[kHexEdge[q][1]]];
+  return {0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]), 0.5 * (a[2] + b[2])};
+}
+
+int hex_global_edge(const orc_ctx* c, int t, int q) {
+  int a = c->el[t].n[kHexEdge[q][0]], b = c->el[t].n[kHexEdge[q][1]];
+  return c->edge_of.at(std::make_pair(std::min(a, b), std::max(a, b)));
+}
+
+// Eq. stretch-delta on local edge q of hex t: its end-to-end displacement
+// difference if the edge lengthens, else 0.
+V3 hex_stretch(const orc_ctx* c, const std::vector<V3>& u, int t, int q) {
+  int a = c->el[t].n[kHexEdge[q][0]], b = c->el[t].n[kHexEdge[q][1]];
+  V3 du = sub(u[b], u[a]);
+  V3 dX = sub(c->X[b], c->X[a]);
+  if (2.0 * dot(dX, du) + dot(du, du) > 0.0) return du;
+  return {0, 0, 0};
+}
+
+// Crack normal and surface area of candidate k of hex t: the quad G1 G2 G4 G3
+// (normal of its diagonals G1G4 and G2G3, area half their cross product) or
+// the triangle G1 G2 G6.
+void hex_cand_geometry(const orc_ctx* c, int t, const HexCand& k, V3* n, double* area) {
+  V3 P1 = hex_edge_point_x(c, t, k.q1), P2 = hex_edge_point_x(c, t, k.q2);
+  V3 P3 = hex_edge_point_x(c, t, k.q3);
+  V3 nn;
+  if (k.pattern == 6) {
+    nn = cross(sub(P2, P1), sub(P3, P1));
+  } else {
+    V3 P4 = hex_edge_point_x(c, t, k.q4);
+    nn = cross(sub(P4, P1), sub(P3, P2));
+  }
+  double l = norm(nn);
+  *area = 0.5 * l;
+  *n = {nn[0] / l, nn[1] / l, nn[2] / l};
+}
+
+// Release rate of candidate k of hex t (Eq. G-I for III, IV, V; Eq. G-II for VI).
+double hex_cand_G(const orc_ctx* c, const std::vector<V3>& u,
+                  const std::vector<std::array<double, 6>>& sig, int t, const HexCand& k) {
+  V3 n;
+  double area;
+  hex_cand_geometry(c, t, k, &n, &area);
+  V3 d1 = hex_stretch(c, u, t, k.q1), d2 = hex_stretch(c, u, t, k.q2);
+  double a1 = std::fabs(dot(d1, n)), a2 = std::fabs(dot(d2, n));
+  double s3 = stress_term(sig[hex_global_edge(c, t, k.q3)].data(), n, c->gsig);
+  if (k.pattern == 6) return 0.5 * s3 * (a1 + a2);
+  double s4 = stress_term(sig[hex_global_edge(c, t, k.q4)].data(), n, c->gsig);
+  return 0.5 * (s3 * a1 + s4 * a2);
+}
+
+// Fronts of a hex mesh: per face of a cracked hex cut at two edges, the intact
+// hex across it, its local face and its two local edges (qa * 16 + qb,
+// qa < qb, in `lone`).  Sorted by (hex, face).
+std::vector<FrontRec> hex_fronts(const orc_ctx* c) {
+  std::vector<FrontRec> fr;
+  for (int s = 0; s < c->T0; ++s) {
+    if (c->smask[s] < 0) continue;
+    const int cut = hex_plane_mask(c->smask[s]);
+    for (int f = 0; f < 6; ++f) {
+      int on = cut & hex_face_mask(f);
+      if (__builtin_popcount(on) != 2) continue;
+      int nb = c->hnbr[s][f];
+      if (nb < 0 || c->smask[nb] >= 0) continue;
+      int qs[2], k = 0;
+      for (int q = 0; q < 12; ++q)
+        if ((on >> q) & 1) qs[k++] = q;
+      int ql[2];
+      for (int r = 0; r < 2; ++r) {
+        int g = hex_global_edge(c, s, qs[r]);
+        ql[r] = -1;
+        for (int q = 0; q < 12; ++q)
+          if (hex_global_edge(c, nb, q) == g) ql[r] = q;
+      }
+      FrontRec r;
+      r.c = nb;
+      r.face = c->hnbr_face[s][f];
+      r.lone = std::min(ql[0], ql[1]) * 16 + std::max(ql[0], ql[1]);
+      r.GI = r.GII = 0;
+      fr.push_back(r);
+    }
+  }
+  std::sort(fr.begin(), fr.end(), [](const FrontRec& x, const FrontRec& y) {
+    return x.c != y.c ? x.c < y.c : x.face < y.face;
+  });
+  return fr;
+}
+
+// Area of the crack surface of plane p in hex t: the triangle of its three
+// cut-edge midpoints, or the quad of four, whose diagonals join the
+// midpoints farthest apart in natural coordinates.
+double hex_plane_area(const orc_ctx* c, int t, int p) {
+  int qs[4], n = 0;
+  const int cut = hex_plane_mask(p);
+  for (int q = 0; q < 12; ++q)
+    if ((cut >> q) & 1) qs[n++] = q;
+  V3 P[4];
+  for (int r = 0; r < n; ++r) P[r] = hex_edge_point_x(c, t, qs[r]);
+  if (n == 3) return 0.5 * norm(cross(sub(P[1], P[0]), sub(P[2], P[0])));
+  int far = 1, best = -1;
+  for (int r = 1; r < 4; ++r) {
+    int d2 = 0;
+    for (int d = 0; d < 3; ++d) {
+      int x = hex_mid(qs[r], d) - hex_mid(qs[0], d);
+      d2 += x * x;
+    }
+    if (d2 > best) { best = d2; far = r; }
+  }
+  int o[2], k = 0;
+  for (int r = 1; r < 4; ++r)
+    if (r != far) o[k++] = r;
+  return 0.5 * norm(cross(sub(P[far], P[0]), sub(P[o[1]], P[o[0]])));
+}
+
+// Crack hex t with plane p: it carries the volume fraction the plane leaves.
+void apply_hex_crack(orc_ctx* c, int t, int p) {
+  c->smask[t] = p;
+  c->el[t].Veff = hex_plane_fraction(p) * c->el[t].V;
+}
+
 // Crack front list (Section 3): faces of intact tets shared with a split tet
 // whose partition cuts that face.  Each record names the intact tet c, its
 // local face (opposite local node `face`) and the real node of the face that
 // lies alone on its side of the cut (N2).  Sorted by (c, face).
 std::vector<FrontRec> fronts(const orc_ctx* c) {
+  if (c->D == 12.0) return hex_fronts(c);
   std::vector<FrontRec> fr;
   for (int s = 0; s < c->T0; ++s) {
     int m = c->smask[s];
@@ -699,6 +976,13 @@ std::vector<Event> decide_splits(orc_ctx* c) {
     double best = -INFINITY;
     int bmask = 0, bpat = 0;
     for (; j < fr.size() && fr[j].c == fr[i].c; ++j) {
+      if (c->D == 12.0) {  // hex: candidates III-VI of this face, in tie order
+        for (const HexCand& k : hex_candidates(fr[j].face, fr[j].lone / 16, fr[j].lone % 16)) {
+          double G = hex_cand_G(c, c->u, sig, fr[j].c, k);
+          if (G > best) { best = G; bmask = k.plane; bpat = k.pattern; }
+        }
+        continue;
+      }
       double GI, GII;
       int mI, mII;
       front_G(c, c->u, sig, fr[j], &GI, &GII, &mI, &mII);
@@ -719,6 +1003,14 @@ std::vector<Event> decide_splits(orc_ctx* c) {
 void apply_events(orc_ctx* c, const std::vector<Event>& evs) {
   const auto& on = c->orig;
   for (const Event& e : evs) {
+    if (c->D == 12.0) {
+      c->Ud += c->Gc * hex_plane_area(c, e.tet, e.mask);
+      apply_hex_crack(c, e.tet, e.mask);
+      c->events.push_back(e);
+      c->events.back().step = (int)c->step;
+      c->nsplit++;
+      continue;
+    }
     V3 x[4];
     for (int l = 0; l < 4; ++l) x[l] = c->X[on[e.tet][l]];
     c->Ud += c->Gc * crack_area(x, e.mask);
@@ -727,7 +1019,7 @@ void apply_events(orc_ctx* c, const std::vector<Event>& evs) {
     c->events.back().step = (int)c->step;
     c->nsplit++;
   }
-  if (!evs.empty() && c->mode == 0) rebuild_masses(c);
+  if (!evs.empty() && c->mode == 0 && c->D == 6.0) rebuild_masses(c);
 }
 
 // One explicit Newmark step (beta = 0, gamma = 1/2), then the crack pass.
@@ -907,10 +1199,6 @@ int window_gradient(orc_ctx* c, int n, const double* gu, const double* gv, doubl
   return 0;
 }
 
-// Trilinear hexahedron (Eq. hex_strain_discretization), reference corner
-// signs of the local nodes: bottom face 0-1-2-3 counter-clockwise, top 4-7.
-const int kHexSign[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
-                            {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
 
 // grad N_i = J^{-T} grad_xi N_i of the eight shape functions at the natural
 // point xi (J[r][c] = dx_r / dxi_c); returns det J.
@@ -1072,11 +1360,13 @@ orc_ctx* orc_create(int n_nodes, const double* X, int n_tets, const int* tets, d
 // Trilinear hexahedral mesh (node order: bottom face 0-1-2-3 counter-clockwise
 // seen from above, top face 4-7 above them).  A hex with negative Jacobian
 // determinants throughout is mirrored (local nodes 1 <-> 3, 5 <-> 7); one
-// with mixed signs is rejected.  Hexes do not split (no crack pass).
+// with mixed signs is rejected.  Cracks start from precracked hexes
+// (orc_presplit with crack plane indices).
 orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex, double E, double nu,
-                        double rho) {
+                        double rho, double Gc, int gsig) {
   orc_ctx* c = new orc_ctx();
-  c->E = E; c->nu = nu; c->rho = rho; c->Gc = INFINITY;
+  c->E = E; c->nu = nu; c->rho = rho; c->Gc = Gc;
+  c->gsig = gsig;
   c->D = 12.0;
   lame(E, nu, &c->lam, &c->mu);
   c->N0 = n_nodes;
@@ -1121,6 +1411,33 @@ orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex,
   c->orig.assign(n_hex, {0, 0, 0, 0});
   c->nbr.assign(n_hex, {-1, -1, -1, -1});
   c->nbr_face.assign(n_hex, {-1, -1, -1, -1});
+  // face adjacency (local face f = 2 axis + (side > 0))
+  c->hnbr.assign(n_hex, {-1, -1, -1, -1, -1, -1});
+  c->hnbr_face.assign(n_hex, {-1, -1, -1, -1, -1, -1});
+  std::map<std::array<int, 4>, std::vector<std::pair<int, int>>> faces;
+  for (int t = 0; t < n_hex; ++t)
+    for (int f = 0; f < 6; ++f) {
+      std::array<int, 4> k;
+      int q = 0;
+      for (int l = 0; l < 8; ++l)
+        if (kHexSign[l][f / 2] == ((f & 1) ? 1 : -1)) k[q++] = c->el[t].n[l];
+      std::sort(k.begin(), k.end());
+      faces[k].push_back({t, f});
+    }
+  for (auto& kv : faces) {
+    if (kv.second.size() > 2) {
+      c->status = -5;
+      c->err = "face shared by more than two hexahedra";
+      return c;
+    }
+    if (kv.second.size() == 2) {
+      auto p = kv.second[0], q = kv.second[1];
+      c->hnbr[p.first][p.second] = q.first;
+      c->hnbr_face[p.first][p.second] = q.second;
+      c->hnbr[q.first][q.second] = p.first;
+      c->hnbr_face[q.first][q.second] = p.second;
+    }
+  }
   c->smask.assign(n_hex, -1);
   c->Et.assign(n_hex, E);
   c->u.assign(n_nodes, {0, 0, 0});
@@ -1155,7 +1472,23 @@ int orc_set_traction(orc_ctx* c, int n_faces, const int* tri, const double* t, d
 }
 
 int orc_presplit(orc_ctx* c, int n, const int* tet, const unsigned char* mask) {
-  if (c->D != 6.0) return c->fail(-7, "hexahedra do not split");
+  if (c->D == 12.0) {  // hexes: mask holds the crack plane index
+    std::vector<std::pair<int, int>> lst;
+    for (int i = 0; i < n; ++i) {
+      if (tet[i] < 0 || tet[i] >= c->T0) return c->fail(-1, "precrack hex out of range");
+      if (mask[i] >= 23) return c->fail(-1, "crack plane index out of range");
+      lst.push_back({tet[i], mask[i]});
+    }
+    std::sort(lst.begin(), lst.end());
+    for (auto& p : lst) {
+      if (c->smask[p.first] >= 0) continue;
+      apply_hex_crack(c, p.first, p.second);
+      c->events.push_back({(int)c->step, p.first, p.second, 0, 0.0});
+      c->nsplit++;
+    }
+    c->need_init = true;
+    return 0;
+  }
   std::vector<std::pair<int, int>> lst;
   for (int i = 0; i < n; ++i) {
     int nb = popcount4(mask[i] & 15);
@@ -1351,6 +1684,22 @@ int orc_front_G(orc_ctx* c, int cap, int* tfl3, double* g2, int* n_out) {
   std::vector<double> Vsum;
   edge_fields(c, c->u, eps, sig, Vsum);
   std::vector<FrontRec> fr = fronts(c);
+  if (c->D == 12.0) {  // one row per candidate: (hex, face, plane), (G, pattern)
+    int n = 0;
+    for (const FrontRec& r : fr)
+      for (const HexCand& k : hex_candidates(r.face, r.lone / 16, r.lone % 16)) {
+        if (n < cap) {
+          tfl3[3 * n] = r.c;
+          tfl3[3 * n + 1] = r.face;
+          tfl3[3 * n + 2] = k.plane;
+          g2[2 * n] = hex_cand_G(c, c->u, sig, r.c, k);
+          g2[2 * n + 1] = k.pattern;
+        }
+        n++;
+      }
+    *n_out = n;
+    return 0;
+  }
   *n_out = (int)fr.size();
   for (int i = 0; i < (int)fr.size() && i < cap; ++i) {
     double GI, GII;
@@ -1366,6 +1715,7 @@ int orc_front_G(orc_ctx* c, int cap, int* tfl3, double* g2, int* n_out) {
 }
 
 int orc_replay(orc_ctx* c, int n, const int* ev3) {
+  if (c->D == 12.0) return c->fail(-7, "a forced schedule is for tetrahedral meshes");
   c->schedule.clear();
   for (int i = 0; i < n; ++i) c->schedule.push_back({ev3[3 * i], ev3[3 * i + 1], ev3[3 * i + 2], 0, 0.0});
   std::stable_sort(c->schedule.begin(), c->schedule.end(), [](const Event& x, const Event& y) {
@@ -1373,6 +1723,11 @@ int orc_replay(orc_ctx* c, int n, const int* ev3) {
   });
   c->cursor = 0;
   c->replay = true;
+  return 0;
+}
+
+int orc_hex_plane_masks(int* out23) {
+  for (int p = 0; p < 23; ++p) out23[p] = hex_plane_mask(p);
   return 0;
 }
 

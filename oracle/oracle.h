@@ -31,9 +31,16 @@ orc_ctx* orc_create(int n_nodes, const double* X, int n_tets, const int* tets,
                     double E, double nu, double rho, double Gc,
                     int split_mode, int gsig);
 /* Trilinear hexahedra, 8 nodes each (bottom face 0-1-2-3 counter-clockwise
- * seen from above, top face 4-7 above them); no crack pass. */
+ * seen from above, top face 4-7 above them).  Crack patterns III-VI grow from
+ * hexes precracked by orc_presplit, whose mask argument then holds crack
+ * plane indices 0-22 (0-2 mid-planes, 3-14 wedge planes, 15-22 corner
+ * planes); split events report the plane in their mask column and the
+ * pattern (3-6; 0 for a precrack); orc_front_G gives one row per candidate:
+ * (hex, local face, plane) and (G, pattern). */
 orc_ctx* orc_create_hex(int n_nodes, const double* X, int n_hex, const int* hex,
-                        double E, double nu, double rho);
+                        double E, double nu, double rho, double Gc, int gsig);
+/* Cut-edge bit masks of the 23 hex crack planes. */
+int orc_hex_plane_masks(int* out23);
 int orc_create_status(const orc_ctx* c);
 const char* orc_error(const orc_ctx* c);
 void orc_destroy(orc_ctx* c);

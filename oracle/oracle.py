@@ -43,7 +43,7 @@ def lib():
         L.orc_create.restype = _p
         L.orc_create.argtypes = [_i, _p, _i, _p, _d, _d, _d, _d, _i, _i]
         L.orc_create_hex.restype = _p
-        L.orc_create_hex.argtypes = [_i, _p, _i, _p, _d, _d, _d]
+        L.orc_create_hex.argtypes = [_i, _p, _i, _p, _d, _d, _d, _d, _i]
         L.orc_error.restype = C.c_char_p
         L.orc_error.argtypes = [_p]
         L.orc_create_status.argtypes = [_p]
@@ -77,6 +77,7 @@ def lib():
             ("orc_add_velocity_bc", [_p, _i, _p, _p, _p, _d, _p]),
             ("orc_strain_energy_grad", [_p, _p, _p]),
             ("orc_reactions", [_p, _i, _i, _p, _p, _p]),
+            ("orc_hex_plane_masks", [_p]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -139,8 +140,9 @@ class Oracle:
         self._t = _i32(tets)
         L = lib()
         if hexes:
+            gs = {"principal": 0, "normal": 1}[gsig]
             self.c = L.orc_create_hex(len(self._X), _ptr(self._X), len(self._t), _ptr(self._t),
-                                      float(E), float(nu), float(rho))
+                                      float(E), float(nu), float(rho), float(Gc), gs)
         else:
             mode = {"phantom": 0, "erode": 1}[split_mode]
             gs = {"principal": 0, "normal": 1}[gsig]
@@ -176,12 +178,22 @@ class Oracle:
         return o
 
     @classmethod
-    def hex_mesh(cls, mesh, material, traction=True, ramp_t0=0.0):
-        """Oracle of a trilinear hexahedral mesh (no crack pass)."""
-        o = cls(mesh.X, mesh.hexes, material["E"], material["nu"], material["rho"], hexes=True)
+    def hex_mesh(cls, mesh, material, traction=True, ramp_t0=0.0, Gc=None, gsig="principal",
+                 presplit=True):
+        """Oracle of a trilinear hexahedral mesh; cracks grow from the
+        mesh's precracked hexes (crack plane indices)."""
+        o = cls(mesh.X, mesh.hexes, material["E"], material["nu"], material["rho"],
+                material["Gc"] if Gc is None else Gc, gsig=gsig, hexes=True)
         if traction and mesh.load_tris is not None:
             o.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
+        if presplit and getattr(mesh, "precrack_hexes", None) is not None:
+            o.presplit(mesh.precrack_hexes, mesh.precrack_planes)
         return o
+
+    def hex_plane_masks(self):
+        out = np.zeros(23, dtype=np.int32)
+        lib().orc_hex_plane_masks(_ptr(out))
+        return out
 
     def set_traction(self, tri, t, ramp_t0=0.0):
         tri, t = _i32(tri), _f64(t)

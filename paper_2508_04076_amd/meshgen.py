@@ -348,6 +348,8 @@ class HexMesh:
     h: tuple = None
     load_tris: np.ndarray = None
     load_trac: np.ndarray = None
+    precrack_hexes: np.ndarray = None   # [P] int32 hexes cracked before the run
+    precrack_planes: np.ndarray = None  # [P] uint8 their crack plane indices
 
     @property
     def n_nodes(self):
@@ -376,3 +378,23 @@ def hex_box(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0):
 def hex_bar(n=100, lx=1.0, w=0.01):
     """Slender hexahedral bar of n x 1 x 1 cells along x."""
     return hex_box(n, 1, 1, lx, w, w)
+
+
+def hex_notched(nx=12, ny=8, nz=2, lx=None, ly=None, lz=None, notch_cells=None, traction=1e6,
+                h=1e-3):
+    """Hex box of nx*ny*nz cells of size h, pulled by +-traction on its y
+    faces, with a notch: the hexes of cell row j = ny // 2 with i < notch_cells
+    (default nx // 3), through the thickness, precracked by their mid-plane
+    normal to y (crack plane index 1)."""
+    lx = nx * h if lx is None else lx
+    ly = ny * h if ly is None else ly
+    lz = nz * h if lz is None else lz
+    m = hex_box(nx, ny, nz, lx, ly, lz)
+    add_tension(m, 1, traction)
+    n = nx // 3 if notch_cells is None else notch_cells
+    i = np.arange(m.n_hex) % nx
+    j = (np.arange(m.n_hex) // nx) % ny
+    sel = np.nonzero((j == ny // 2) & (i < n))[0]
+    m.precrack_hexes = sel.astype(np.int32)
+    m.precrack_planes = np.full(len(sel), 1, dtype=np.uint8)
+    return m

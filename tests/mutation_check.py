@@ -58,13 +58,30 @@ MUTANTS = [
  ("reaction sign of load", "R[b][d] = c->m[i] * c->a[i][d] + f[i][d] - r * c->F[i][d];", "R[b][d] = c->m[i] * c->a[i][d] + f[i][d] + r * c->F[i][d];"),
  ("hex smoothing 1/12 -> 1/6", "  c->D = 12.0;", "  c->D = 6.0;"),
  ("hex dN factor", "dN[i][1] = f[0] * sg[i][1] * f[2] / 8.0;", "dN[i][1] = f[0] * sg[i][1] * f[2] / 4.0;"),
+ ("hex III G3 on the front face", "w3[j] = hex_mid(qa, j); w3[k] = -s;", "w3[j] = hex_mid(qa, j); w3[k] = s;"),
+ ("hex IV pairs G3 with G2", "w3[i] = sg; w3[j] = hex_mid(qa, j);", "w3[i] = sg; w3[j] = hex_mid(qb, j);"),
+ ("hex IV tilt toward the face", "      c[i] = sg;\n      c[k] = s;", "      c[i] = sg;\n      c[k] = -s;"),
+ ("hex V G4 on the front face", "w4[i] = r; w4[k] = -s;", "w4[i] = r; w4[k] = s;"),
+ ("hex VI corner on the far face", "    c[k] = s;\n    int w6[3]", "    c[k] = -s;\n    int w6[3]"),
+ ("hex quad normal from sides", "nn = cross(sub(P4, P1), sub(P3, P2));", "nn = cross(sub(P2, P1), sub(P3, P1));"),
+ ("hex G-II without 1/2", "if (k.pattern == 6) return 0.5 * s3 * (a1 + a2);", "if (k.pattern == 6) return s3 * (a1 + a2);"),
+ ("hex G-I both stresses at G3", "return 0.5 * (s3 * a1 + s4 * a2);", "return 0.5 * (s3 * a1 + s3 * a2);"),
+ ("hex stretch test off", "if (2.0 * dot(dX, du) + dot(du, du) > 0.0) return du;", "if (2.0 * dot(dX, du) + dot(du, du) > -1e300) return du;"),
+ ("hex III keeps half", "return p < 3 ? 0.0 : 0.5;", "return p < 3 ? 0.5 : 0.5;"),
+ ("hex prism keeps all", "return p < 3 ? 0.0 : 0.5;", "return p < 3 ? 0.0 : 1.0;"),
+ ("hex ties to the later candidate", "if (G > best) { best = G; bmask = k.plane; bpat = k.pattern; }", "if (G >= best) { best = G; bmask = k.plane; bpat = k.pattern; }"),
+ ("hex wedge index signs swapped", "return 3 + 4 * k + 2 * (c[a] > 0) + (c[b] > 0);", "return 3 + 4 * k + 2 * (c[b] > 0) + (c[a] > 0);"),
+ ("hex face side swapped", "int axis = f / 2, side = (f & 1) ? 1 : -1, m = 0;", "int axis = f / 2, side = (f & 1) ? -1 : 1, m = 0;"),
+ ("hex front into cracked hexes", "if (nb < 0 || c->smask[nb] >= 0) continue;\n      int qs[2]", "if (nb < 0) continue;\n      int qs[2]"),
+ ("hex crack area from a side", "return 0.5 * norm(cross(sub(P[far], P[0]), sub(P[o[1]], P[o[0]])));", "return 0.5 * norm(cross(sub(P[far], P[0]), sub(P[o[1]], P[0])));"),
+ ("hex crack area triangle factor", "if (n == 3) return 0.5 * norm(cross(sub(P[1], P[0]), sub(P[2], P[0])));", "if (n == 3) return norm(cross(sub(P[1], P[0]), sub(P[2], P[0])));"),
  ("uncut faces made fronts", "if (b0 == b1 && b1 == b2) continue;  // face not cut", "if (b0 == b1 && b1 == b2 && false) continue;"),
  ("front face index of the splitter", "r.face = c->nbr_face[s][f];", "r.face = f;"),
  ("erosion keeps half the volume", "par.Veff = 0.0;", "par.Veff = 0.5 * par.V;"),
  ("bc acceleration zero on the ramp", "? 1.0 / t0 : 0.0; }", "? 0.0 : 0.0; }"),
  ("critical step factor", "*dt_crit = 2.0 / std::sqrt(", "*dt_crit = 1.0 / std::sqrt("),
  ("replayed tet split twice", "      if (c->smask[e.tet] >= 0) continue;\n      e.pattern", "      e.pattern"),
- ("masses not rebuilt after splits", "  if (!evs.empty() && c->mode == 0) rebuild_masses(c);", "  (void)evs;"),
+ ("masses not rebuilt after splits", "  if (!evs.empty() && c->mode == 0 && c->D == 6.0) rebuild_masses(c);", "  (void)evs;"),
  ("adjoint: v sensitivity misses dt ub", "vb[i][d] = v1 + dt * u1;", "vb[i][d] = v1;"),
  ("adjoint: a sensitivity misses dt^2/2 ub", "ab[i][d] = 0.5 * dt * v1 + 0.5 * dt * dt * u1;", "ab[i][d] = 0.5 * dt * v1;"),
  ("adjoint: modulus term sign", "modulus_term(c, lam, us[s + 1], -1.0, Eb);", "modulus_term(c, lam, us[s + 1], 1.0, Eb);"),
@@ -94,7 +111,8 @@ MUTANTS = [
  ("stretch test without its quadratic term", "double d = 2.0 * dot(dX, du) + dot(du, du);", "double d = 2.0 * dot(dX, du);"),
  ("pattern II wins ties", "if (GII > best) { best = GII; bmask = mII; bpat = 2; }", "if (GII >= best) { best = GII; bmask = mII; bpat = 2; }"),
  ("later face wins ties", "if (GI > best) { best = GI; bmask = mI; bpat = 1; }", "if (GI >= best) { best = GI; bmask = mI; bpat = 1; }"),
- ("fronts visited in reverse face order", "return x.c != y.c ? x.c < y.c : x.face < y.face;", "return x.c != y.c ? x.c < y.c : x.face > y.face;"),
+ ("fronts visited in reverse face order", "return x.c != y.c ? x.c < y.c : x.face < y.face;\n  });\n  return fr;\n}\n\n// Release rates", "return x.c != y.c ? x.c < y.c : x.face > y.face;\n  });\n  return fr;\n}\n\n// Release rates"),
+ ("hex fronts in reverse face order", "return x.c != y.c ? x.c < y.c : x.face < y.face;\n  });\n  return fr;\n}\n\n// Area of the crack", "return x.c != y.c ? x.c < y.c : x.face > y.face;\n  });\n  return fr;\n}\n\n// Area of the crack"),
  ("Griffith test strict", "if (best >= c->Gc) out.push_back", "if (best > c->Gc) out.push_back"),
  ("tie gap too narrow", "double gap = 1e-6 * amax;", "double gap = 1e-10 * amax;"),
  ("tie gap too wide", "double gap = 1e-6 * amax;", "double gap = 1e-5 * amax;"),
