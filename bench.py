@@ -702,21 +702,23 @@ HEX_BYTES = {
 def bench_hex(args):
     """Trilinear hexahedra (ES-H-FEM, factor 1/12): the notched-plate geometry
     at 200 x 80 x 8 hex cells (128,000 hexes, 1 MPa ramped over 1 us), or a
-    400 x 200 x 100 block (8,000,000 hexes).  No splitting (hexahedra do not
-    split).  A step: strain, edge stress, element force + node update."""
+    400 x 200 x 100 block (8,000,000 hexes), each with a notch of precracked
+    hexes (mid-planes normal to y through the middle cell row, over the first
+    half of the plate or third of the block).  A step: strain, edge stress,
+    hex crack pass, element force + node update, crack topology."""
     import torch
     from paper_2508_04076_amd import meshgen as mg
     from paper_2508_04076_amd.cem import Simulation
 
     mat = dict(mg.BRANCHING_MATERIAL)
     if args.workload == "hex":
-        mesh = mg.add_tension(mg.hex_box(200, 80, 8, 0.1, 0.04, 0.004), 1, 1e6)
+        mesh = mg.hex_notched(200, 80, 8, 0.1, 0.04, 0.004, notch_cells=100, traction=1e6)
         desc = ("plate 100x40x4 mm as 200x80x8 trilinear hex cells (128,000 hexes), "
-                "1 MPa traction ramped over 1 us, no splitting")
+                "1 MPa traction ramped over 1 us, 800 precracked notch hexes")
     else:
-        mesh = mg.add_tension(mg.hex_box(400, 200, 100, 0.2, 0.1, 0.05), 1, 1e6)
+        mesh = mg.hex_notched(400, 200, 100, 0.2, 0.1, 0.05, notch_cells=133, traction=1e6)
         desc = ("block 200x100x50 mm as 400x200x100 trilinear hex cells (8,000,000 hexes), "
-                "1 MPa traction ramped over 1 us, no splitting")
+                "1 MPa traction ramped over 1 us, 13,300 precracked notch hexes")
     H = mesh.n_hex
     K, W = args.steps, args.warmup
     if not args.no_graph:
@@ -740,7 +742,8 @@ def bench_hex(args):
             sim.step(K)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
-            run = {"ms_per_step": wall * 1e3 / K, "hex_steps_per_s": H * K / wall, "dt_s": dt}
+            run = {"ms_per_step": wall * 1e3 / K, "hex_steps_per_s": H * K / wall, "dt_s": dt,
+                   "cracks": sim.counts()["splits"]}
             if not graph:
                 kt = sim.kernel_times()
                 run["kernels_ms_per_step"] = {k: kt[k] / K for k in
@@ -785,6 +788,7 @@ def bench_hex(args):
         "warmup": W, "ms_per_step": timed["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "hexes": H, "nodes": mesh.n_nodes, "dt_s": base["dt_s"],
+                   "cracked_hexes_after_run": timed["cracks"],
                    "launch": (f"HIP graphs of {args.graph_steps} steps, no events"
                               if timed is not base else "plain launches with per-pass HIP events")},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,

@@ -144,10 +144,28 @@ int cem_upload_mesh(cem_ctx* ctx, int32_t n_nodes, const double* X, int32_t n_te
  * 12 edges with its shape-function gradients at that edge's midpoint G_k
  * (Eq. strain_discretization evaluates dN/dx at G_k), the smoothing domains
  * have V_k = (1/12) sum of the patch volumes (volumes by 2 x 2 x 2 Gauss
- * points), and the lumped mass is rho V / 8 per node.  Hexes do not split:
- * the crack pass is off (Gc is ignored) and the splitting, batch, modulus and
- * gradient-window calls return CEM_ESTATE.  Tractions (triangles), prescribed
- * velocities, steps, energies and checkpoints work as for tetrahedra. */
+ * points), and the lumped mass is rho V / 8 per node.
+ * Cracks (Section 3, patterns III-VI of the parallelepiped element) grow from
+ * hexes cracked by cem_presplit, whose side_mask then holds a crack plane
+ * index: planes c . xi = d through edge midpoints in the hex's natural
+ * coordinates, 0-2 the mid-planes xi_a = 0, 3-14 the wedge planes
+ * +-xi_a +-xi_b = 1 (axis pairs (0,1), (0,2), (1,2); index 3 + 4 pair +
+ * 2 [c_a > 0] + [c_b > 0]), 15-22 the corner planes +-xi_0 +-xi_1 +-xi_2 = 2
+ * (index 15 + 4 [c0 > 0] + 2 [c1 > 0] + [c2 > 0]).  A face of an intact hex cut
+ * by a cracked neighbour's plane (at two of its edge midpoints G1, G2) is a
+ * crack front; opposite edges give III (the mid-plane, Eq. G-I; the hex is
+ * deactivated) and IV (the two wedge planes tilted toward either side, Eq.
+ * G-I), neighbouring edges V (the wedge plane along the face normal, Eq. G-I)
+ * and VI (the corner plane at their shared corner, Eq. G-II).  After IV-VI the
+ * hex keeps its gradients and half its volume (the triangular prism of its
+ * own nodes on the far side); masses stay; a hex cracks once; ties: larger
+ * G, lower local face (2 axis + (side > 0)), then III, IV toward -1, IV toward
+ * +1, V, VI.  Split events report the plane in side_mask and the pattern 3-6;
+ * cem_read_front_G gives one row per candidate: (hex, face, plane in `lone`),
+ * G in G_I and the pattern in G_II.  Forced schedules, batches, the
+ * per-element modulus, gradient windows and the static front readback return
+ * CEM_ESTATE for hexes.  Tractions (triangles), prescribed velocities, steps,
+ * energies and checkpoints work as for tetrahedra. */
 int cem_upload_hex_mesh(cem_ctx* ctx, int32_t n_nodes, const double* X, int32_t n_hex,
                         const int32_t* hexes, const cem_material* m);
 
@@ -160,7 +178,9 @@ int cem_set_traction(cem_ctx* ctx, int32_t n_faces, const int32_t* tri, const do
 
 /* Split tets from the host (e.g. a pre-notch): side_mask bit l puts local node
  * l (after orientation) on side B; it must be a 1|3 or 2|2 partition.  Already
- * split tets are ignored.  No dissipated energy is booked. */
+ * split tets are ignored.  No dissipated energy is booked.  On a hex mesh the
+ * elements are hexes and side_mask is a crack plane index 0-22
+ * (cem_upload_hex_mesh). */
 int cem_presplit(cem_ctx* ctx, int32_t n, const int32_t* tet, const uint8_t* side_mask);
 
 /* dt_crit = 2 / sqrt(max_e (4 / rho) lambda_max(B_e^T C B_e)): the element
@@ -234,7 +254,7 @@ int cem_read_front_G(cem_ctx* ctx, int32_t cap, cem_front_g* out, int32_t* n);
  * cap = 0 only sets *n; otherwise cap must be at least *n (CEM_EINVAL,
  * nothing written).  All contexts on one GPU share its array, which keeps the
  * last call's contents: calls that overlap on one GPU (from several host
- * threads) race. */
+ * threads) race.  Tetrahedral meshes only (CEM_ESTATE on a hex mesh). */
 int cem_read_front_G_static(cem_ctx* ctx, int32_t cap, cem_front_g* out, int32_t* n);
 
 /* Checkpoint of the whole simulation state into a host buffer (buf may be

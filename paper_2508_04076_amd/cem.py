@@ -163,8 +163,8 @@ class Simulation:
         self.ctx = None
         X = _f64(X, (-1, 3))
         tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 8 if hexes else 4)
-        if max_splits is None:
-            max_splits = 0 if hexes else max(len(tets) // 8, 64)
+        if max_splits is None:  # a hex cracks at most once
+            max_splits = len(tets) if hexes else max(len(tets) // 8, 64)
         self._torch_stream = None
         if stream is None:
             import torch
@@ -201,11 +201,18 @@ class Simulation:
         return sim
 
     @classmethod
-    def from_hex_mesh(cls, mesh, material, traction=True, ramp_t0=0.0, **kw):
-        """Simulation of a trilinear hexahedral mesh (meshgen.HexMesh)."""
-        sim = cls(mesh.X, mesh.hexes, material, hexes=True, **kw)
+    def from_hex_mesh(cls, mesh, material, traction=True, ramp_t0=0.0, Gc=None, presplit=True,
+                      **kw):
+        """Simulation of a trilinear hexahedral mesh (meshgen.HexMesh); cracks
+        grow from the mesh's precracked hexes (crack plane indices)."""
+        mat = dict(material)
+        if Gc is not None:
+            mat["Gc"] = Gc
+        sim = cls(mesh.X, mesh.hexes, mat, hexes=True, **kw)
         if traction and mesh.load_tris is not None:
             sim.set_traction(mesh.load_tris, mesh.load_trac, ramp_t0)
+        if presplit and getattr(mesh, "precrack_hexes", None) is not None:
+            sim.presplit(mesh.precrack_hexes, mesh.precrack_planes)
         return sim
 
     def close(self):

@@ -120,9 +120,13 @@ struct Mesh {
   int* ttoff[2];            // [ntile + 1] offsets into ttet
   int* ttet[2];             // tile element lists: parent tets with an entry in the tile, ascending
 
-  // trilinear hexahedra (etype 8; no splitting, T_cap = T0)
+  // trilinear hexahedra (etype 8; T_cap = T0).  A cracked hex keeps its slot
+  // and carries the volume fraction its crack plane leaves (vol scaled);
+  // smask holds its plane index, pmask the pending one.
   int4* hnodes;             // [2 T0] node ids 0-3, 4-7
   int2* he2e;               // [6 T0] twelve edge ids
+  int* hnbr;                // [6 T0] neighbour across local face f: 8 hex + its local face, -1 none
+  int* hfront;              // [6 T0] crack front on local face f: 16 qa + qb (its two cut local edges), -1 none
 
   // prescribed velocities in groups (all null, counts 0, when there are none)
   int n_bc, n_grp, hist_cap;

@@ -486,6 +486,40 @@ void build_hex_topology(int N, int H, const std::vector<int>& hx, HexTopo& h) {
     }
 }
 
+// Face neighbours of a hex mesh: out[6 t + f] = 8 u + g when local face f of
+// hex t (f = 2 axis + (side > 0); bottom face 0-1-2-3, top 4-7) is local face
+// g of hex u, else -1.  Faces are matched by their sorted node ids.
+bool hex_face_neighbours(int H, const std::vector<int>& hx, std::vector<int>& out) {
+  static const int kFace[6][4] = {{0, 3, 4, 7}, {1, 2, 5, 6}, {0, 1, 4, 5},
+                                  {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+  struct Rec {
+    unsigned long long k0, k1;
+    int id;
+  };
+  std::vector<Rec> rec((size_t)6 * H);
+  for (int t = 0; t < H; ++t)
+    for (int f = 0; f < 6; ++f) {
+      int a[4];
+      for (int j = 0; j < 4; ++j) a[j] = hx[8 * (size_t)t + kFace[f][j]];
+      std::sort(a, a + 4);
+      rec[6 * (size_t)t + f] = {((unsigned long long)a[0] << 32) | (unsigned)a[1],
+                                ((unsigned long long)a[2] << 32) | (unsigned)a[3], 8 * t + f};
+    }
+  std::sort(rec.begin(), rec.end(), [](const Rec& x, const Rec& y) {
+    return x.k0 != y.k0 ? x.k0 < y.k0 : x.k1 != y.k1 ? x.k1 < y.k1 : x.id < y.id;
+  });
+  out.assign((size_t)6 * H, -1);
+  for (size_t i = 0; i + 1 < rec.size(); ++i)
+    if (rec[i].k0 == rec[i + 1].k0 && rec[i].k1 == rec[i + 1].k1) {
+      if (i + 2 < rec.size() && rec[i + 2].k0 == rec[i].k0 && rec[i + 2].k1 == rec[i].k1) return false;
+      const int a = rec[i].id, b = rec[i + 1].id;
+      out[6 * (size_t)(a >> 3) + (a & 7)] = b;
+      out[6 * (size_t)(b >> 3) + (b & 7)] = a;
+      ++i;
+    }
+  return true;
+}
+
 // Jacobian determinants of a trilinear hex at its 2 x 2 x 2 Gauss points:
 // returns their minimum and maximum.
 void hex_det_range(const double* X, const int* nd, double* dmin, double* dmax) {
@@ -1273,7 +1307,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   if (!X || !hexes || !mat || N < 8 || H < 1) return c->fail(CEM_EINVAL, "empty mesh");
   if (N > kNodeMask / 2 || (long long)H * 12 > (1LL << 30))
     return c->fail(CEM_EINVAL, "mesh too large for 32-bit indexing");
-  if (!(mat->E > 0) || !(mat->rho > 0) || !(mat->nu > -1.0 && mat->nu < 0.5))
+  if (!(mat->E > 0) || !(mat->rho > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->Gc > 0))
     return c->fail(CEM_EINVAL, "invalid material");
   for (long long i = 0; i < (long long)H * 8; ++i)
     if (hexes[i] < 0 || hexes[i] >= N) return c->fail(CEM_EMESH, "node id out of range");
@@ -1331,18 +1365,19 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
     c->own_stream = true;
   }
   c->mat = *mat;
-  c->mat.Gc = INFINITY;  // hexahedra do not split
   Mesh& m = c->m;
+  // a hex cracks once, in its own slot: no copies, extra nodes or new edges
+  const int S = std::min(c->opt.max_splits, H);
   m.T0 = m.T_cap = H;
   m.N0 = m.N_cap = N;
   m.E0 = m.E_cap = h.E0;
-  m.S_cap = 0;
-  m.mode = CEM_PHANTOM;
-  m.gsig = 0;
+  m.S_cap = S;
+  m.mode = CEM_ERODE;
+  m.gsig = c->opt.gsig;
   m.lam = mat->E * mat->nu / ((1 + mat->nu) * (1 - 2 * mat->nu));
   m.mu = mat->E / (2 * (1 + mat->nu));
   m.rho = mat->rho;
-  m.Gc = INFINITY;
+  m.Gc = mat->Gc;
   m.grid_cap = kDefaultGridCap;
   m.lanes = kDefaultLanes;
   m.ssum = 0;
@@ -1380,7 +1415,26 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   ALLOC(m.invm, m.N_cap, true);
   ALLOC(m.lslot, m.N_cap, true);
   ALLOC(m.vol, m.T_cap, true);
-  ALLOC(m.splitlist, 1, false);
+  // crack state: plane per hex, pending crack, candidates, fronts, records
+  size_t nsplit_list = 1;  // a power of two >= S (room for the bitonic sort)
+  while (nsplit_list < (size_t)std::max(S, 1)) nsplit_list <<= 1;
+  ALLOC(m.tet_ext, H, false);
+  ALLOC(m.hnbr, (size_t)6 * H, false);
+  ALLOC(m.hfront, (size_t)6 * H, true);
+  ALLOC(m.smask, H, true);
+  ALLOC(m.pmask, H, true);
+  ALLOC(m.ppat, H, true);
+  ALLOC(m.pG, H, true);
+  ALLOC(m.cand, H, true);
+  ALLOC(m.candf, H, true);
+  ALLOC(m.splitlist, nsplit_list, false);
+  ALLOC(m.area, std::max(S, 1), false);
+  ALLOC(m.rec_step, std::max(S, 1), true);
+  ALLOC(m.rec_tet, std::max(S, 1), true);
+  ALLOC(m.rec_mask, std::max(S, 1), true);
+  ALLOC(m.rec_pat, std::max(S, 1), true);
+  ALLOC(m.rec_G, std::max(S, 1), true);
+  ALLOC(m.rec_area, std::max(S, 1), true);
   char* vb;
   ALLOC(vb, RS * 6 * 12 * (size_t)H, false);  // one V eps record per (hex, edge point)
   c->w.veps = vb;
@@ -1419,6 +1473,16 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   if ((r = upload(c, (int*)m.epos, h.nodepos.data(), h.nodepos.size()))) return r;
   std::vector<int> lsl(N, -1);
   if ((r = upload(c, m.lslot, lsl.data(), lsl.size()))) return r;
+  {
+    std::vector<int> ext_id(H), nbr6, minus((size_t)6 * H, -1), zero(H, 0);
+    for (int t = 0; t < H; ++t) ext_id[t] = c->tet_old[t];
+    if (!hex_face_neighbours(H, hx, nbr6)) return c->fail(CEM_EMESH, "face shared by more than two hexahedra");
+    if ((r = upload(c, m.tet_ext, ext_id.data(), ext_id.size()))) return r;
+    if ((r = upload(c, m.hnbr, nbr6.data(), nbr6.size()))) return r;
+    if ((r = upload(c, m.hfront, minus.data(), minus.size()))) return r;
+    if ((r = upload(c, m.smask, minus.data(), (size_t)H))) return r;
+    if ((r = upload(c, m.candf, zero.data(), zero.size()))) return r;
+  }
   HIPCHK(c, hipMemsetAsync(c->d_ctr, 0, sizeof(Counters), c->stream));
   for (double4* p : {c->st.u, c->st.v, c->st.a, c->st.uh})
     HIPCHK(c, hipMemsetAsync(p, 0, sizeof(double4) * N, c->stream));
@@ -1512,7 +1576,6 @@ int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
-  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "hexahedra do not split");
   c->gen++;
   if (c->step_host != 0) return c->fail(CEM_ESTATE, "pre-splits must precede the first step");
   if (n < 0 || (n > 0 && (!tet || !side_mask))) return c->fail(CEM_EINVAL, "bad presplit arguments");
@@ -1520,8 +1583,12 @@ int cem_presplit(cem_ctx* c, int32_t n, const int32_t* tet, const uint8_t* side_
   for (int i = 0; i < n; ++i) {
     int mk = side_mask[i];
     int nb = __builtin_popcount(mk & 15);
-    if (tet[i] < 0 || tet[i] >= c->m.T0) return c->fail(CEM_EINVAL, "presplit tet out of range");
-    if ((mk & ~15) || nb == 0 || nb == 4) return c->fail(CEM_EINVAL, "presplit mask is not a partition");
+    if (tet[i] < 0 || tet[i] >= c->m.T0) return c->fail(CEM_EINVAL, "presplit element out of range");
+    if (c->m.etype == 8) {  // hexes: a crack plane index
+      if (mk >= 23) return c->fail(CEM_EINVAL, "crack plane index out of range");
+    } else if ((mk & ~15) || nb == 0 || nb == 4) {
+      return c->fail(CEM_EINVAL, "presplit mask is not a partition");
+    }
     lst.push_back({tet[i], mk});
   }
   std::sort(lst.begin(), lst.end());
@@ -1721,7 +1788,7 @@ int cem_replay_splits(cem_ctx* c, int32_t n, const cem_split_event* ev) {
   if (!c) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
-  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "hexahedra do not split");
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "a forced schedule is for tetrahedral meshes");
   c->gen++;
   if (n < 0 || (n > 0 && !ev)) return c->fail(CEM_EINVAL, "bad schedule");
   std::vector<std::array<int, 3>> s;
@@ -2006,10 +2073,7 @@ int cem_read_front_G_static(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* 
   if (!c || !n || cap < 0 || (cap > 0 && !out)) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
-  if (c->m.etype == 8) {
-    *n = 0;
-    return CEM_OK;  // hexahedra have no crack fronts
-  }
+  if (c->m.etype == 8) return c->fail(CEM_ESTATE, "the static readback covers tetrahedral meshes");
   if (!c->scratch) return c->fail(CEM_ESTATE, "static staging not set up");
   if (c->need_init && c->dt_set && (r = initialize(c))) return r;
   if ((r = read_counters(c))) return r;
@@ -2055,14 +2119,11 @@ int cem_read_front_G(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* n) {
   if (!c || !n) return CEM_EINVAL;
   int r = ensure_ready(c, false);
   if (r) return r;
-  if (c->m.etype == 8) {
-    *n = 0;
-    return CEM_OK;  // hexahedra have no crack fronts
-  }
+  const bool hex = c->m.etype == 8;  // hexes: one row per candidate, up to 18 per hex
   if (c->need_init && c->dt_set && (r = initialize(c))) return r;
   if ((r = read_counters(c))) return r;
   int nc = c->h_ctr->n_cand;
-  size_t capf = (size_t)4 * std::max(nc, 1);
+  size_t capf = (size_t)(hex ? 18 : 4) * std::max(nc, 1);
   int* d_tfl = nullptr;
   double* d_g = nullptr;
   HIPCHK(c, hipMalloc(&d_tfl, sizeof(int) * 3 * capf));
@@ -2087,12 +2148,16 @@ int cem_read_front_G(cem_ctx* c, int32_t cap, cem_front_g* out, int32_t* n) {
   if (r) return r;
   for (int i = 0; i < nf; ++i) {
     tfl[3 * i] = c->tet_old[tfl[3 * i]];
-    tfl[3 * i + 2] = c->node_old[tfl[3 * i + 2]];
+    if (!hex) tfl[3 * i + 2] = c->node_old[tfl[3 * i + 2]];
   }
   std::vector<int> ord(nf);
   for (int i = 0; i < nf; ++i) ord[i] = i;
+  // (element, face) order; a hex face's candidates in plane order, which is
+  // their tie order (III, IV toward -1, IV toward +1; V, VI)
   std::sort(ord.begin(), ord.end(), [&](int x, int y) {
-    return tfl[3 * x] != tfl[3 * y] ? tfl[3 * x] < tfl[3 * y] : tfl[3 * x + 1] < tfl[3 * y + 1];
+    if (tfl[3 * x] != tfl[3 * y]) return tfl[3 * x] < tfl[3 * y];
+    if (tfl[3 * x + 1] != tfl[3 * y + 1]) return tfl[3 * x + 1] < tfl[3 * y + 1];
+    return tfl[3 * x + 2] < tfl[3 * y + 2];
   });
   *n = nf;
   for (int i = 0; i < nf && i < cap && out; ++i) {

@@ -97,24 +97,30 @@ def test_hex_bar_velocity_groups():
 def test_hex_refusals_numbering_and_checkpoint():
     _case("hex refusals, relabelled input, checkpoint")
     from paper_2508_04076_amd.cem import CemError, Simulation
-    mesh = mg.add_tension(mg.jitter(mg.hex_box(4, 3, 3), 0.2, seed=5), 1, 1e6)
-    sim = Simulation.from_hex_mesh(mesh, MAT)
+    mesh = mg.add_tension(mg.jitter(mg.hex_box(4, 3, 3), 0.2, seed=5), 1, 3e7)
+    mesh.precrack_hexes = np.array([5, 20], dtype=np.int32)
+    mesh.precrack_planes = np.array([1, 7], dtype=np.uint8)
+    sim = Simulation.from_hex_mesh(mesh, MAT, presplit=False)
     with pytest.raises(CemError):
-        sim.presplit([0], [1])
+        sim.presplit([0], [23])  # crack plane indices run 0-22
     with pytest.raises(CemError):
         sim.set_modulus(np.full(mesh.n_hex, MAT["E"]))
+    sim.presplit(mesh.precrack_hexes, mesh.precrack_planes)
     dt = 0.5 * sim.critical_dt()
     sim.set_dt(dt)
     with pytest.raises(CemError):
         sim.window_forward(2, 1)
-    assert len(sim.front_G()[0]) == 0
+    assert len(sim.front_G()[0]) > 0
     # relabelled nodes and hexes give the same answer in the caller's numbering
     rng = np.random.default_rng(3)
     pn, ph = rng.permutation(mesh.n_nodes), rng.permutation(mesh.n_hex)
     inv = np.empty_like(pn)
     inv[pn] = np.arange(len(pn))
+    hinv = np.argsort(ph)  # hex ph[i] of the mesh is hex i of the relabelled one
     m2 = mg.HexMesh(X=mesh.X[pn], hexes=inv[mesh.hexes[ph]].astype(np.int32),
-                    load_tris=inv[mesh.load_tris].astype(np.int32), load_trac=mesh.load_trac)
+                    load_tris=inv[mesh.load_tris].astype(np.int32), load_trac=mesh.load_trac,
+                    precrack_hexes=hinv[mesh.precrack_hexes].astype(np.int32),
+                    precrack_planes=mesh.precrack_planes)
     sim2 = Simulation.from_hex_mesh(m2, MAT)
     sim2.set_dt(dt)
     sim.step(40)
@@ -122,6 +128,12 @@ def test_hex_refusals_numbering_and_checkpoint():
     u1 = sim.get_state()[0]
     u2 = sim2.get_state()[0]
     assert _rel(u2, u1[pn]) < 1e-12
+    e1, e2 = sim.splits()[0], sim2.splits()[0]
+    assert len(e1) > 2 and len(e1) == len(e2)
+    back = e2.copy()
+    back[:, 1] = ph[e2[:, 1]]
+    key = lambda e: sorted(map(tuple, e.tolist()))
+    assert key(back) == key(e1)
     buf = sim.save_state()
     sim.step(10)
     ua = sim.get_state()[0]
