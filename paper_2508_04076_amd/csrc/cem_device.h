@@ -216,8 +216,8 @@ hipError_t launch_hex_geometry(const Mesh& m, hipStream_t s);
 template <class R>
 hipError_t launch_strain_hex(const Mesh& m, const double4* u, void* veps, Counters* c, hipStream_t s);
 template <class R>
-hipError_t launch_elem_force_hex(const Mesh& m, const void* esig, void* contrib, Counters* c,
-                                 hipStream_t s);
+hipError_t launch_elem_force_hex(const Mesh& m, const void* esig, void* contrib, const double4* uh,
+                                 Counters* c, int fg, int flagging, hipStream_t s);
 hipError_t launch_dtcrit_hex(const Mesh& m, Counters* c, hipStream_t s);
 
 // ---- reverse sweep of a fixed-topology window (adjoint.hip) ----

@@ -371,6 +371,75 @@ static inline int persistent_grid(const Mesh& m, long long items) {
   return (int)((g + 7) / 8 * 8);
 }
 
+// One Jacobi rotation in the (p, q) plane of the symmetric 3x3 tensor a, with
+// the tangent of the stable 2x2 symmetric Schur decomposition (Golub and Van
+// Loan, the classical Jacobi method): a_pq becomes 0, the diagonal moves by
+// t a_pq, the third row/column and the columns p, q of v rotate.
+template <int p, int q>
+__device__ __forceinline__ void jacobi_rot(double (&a)[3][3], double (&v)[3][3]) {
+  constexpr int r = 3 - p - q;
+  double apq = a[p][q];
+  if (apq == 0.0) return;
+  double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+  double t = fabs(th) > 1e150 ? 0.5 / th
+                               : (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+  double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+  a[p][p] -= t * apq;
+  a[q][q] += t * apq;
+  a[p][q] = a[q][p] = 0.0;
+  double arp = a[r][p], arq = a[r][q];
+  a[r][p] = a[p][r] = c * arp - s * arq;
+  a[r][q] = a[q][r] = s * arp + c * arq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double vp = v[k][p], vq = v[k][q];
+    v[k][p] = c * vp - s * vq;
+    v[k][q] = s * vp + c * vq;
+  }
+}
+
+// Stress term of Eqs. G-I / G-II for the smoothed edge stress s (Voigt) and the
+// unit crack normal n.  gsig 0: sigma_1 |P_1 n|, P_1 the projector on the
+// eigenspace of the largest eigenvalue; eigenvalues within 1e-6 max|lambda| of
+// it count as equal (two evaluations of one edge stress in different summation
+// orders differ by rounding, and the eigenvector of a closer pair moves by that
+// rounding over the gap).  The eigenpairs come from cyclic Jacobi sweeps,
+// accurate to rounding for the eigenvalues and to rounding over the gap for
+// the eigenvectors.  gsig 1: n . sigma . n.
+__device__ inline double stress_term(const double* s, double nx, double ny, double nz, int gsig) {
+  if (gsig == 1) {
+    return nx * (s[0] * nx + s[3] * ny + s[5] * nz) + ny * (s[3] * nx + s[1] * ny + s[4] * nz) +
+           nz * (s[5] * nx + s[4] * ny + s[2] * nz);
+  }
+  double a[3][3] = {{s[0], s[3], s[5]}, {s[3], s[1], s[4]}, {s[5], s[4], s[2]}};
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-36 * dia)) break;
+    jacobi_rot<0, 1>(a, v);
+    jacobi_rot<0, 2>(a, v);
+    jacobi_rot<1, 2>(a, v);
+  }
+  double w[3] = {a[0][0], a[1][1], a[2][2]};
+  double lmax = fmax(w[0], fmax(w[1], w[2]));
+  double amax = fmax(fabs(w[0]), fmax(fabs(w[1]), fabs(w[2])));
+  double gap = 1e-6 * amax;
+  double p2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double c = v[0][i] * nx + v[1][i] * ny + v[2][i] * nz;
+    if (w[i] >= lmax - gap) p2 += c * c;
+  }
+  return lmax * sqrt(p2);
+}
+
+template <class R> __device__ __forceinline__ void load_sig(const Six<R>* esig, int k, double* s) {
+  Six<R> v = load6(esig + k);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s[i] = (double)v.v[i];
+}
+
 }  // namespace cem
 
 #endif

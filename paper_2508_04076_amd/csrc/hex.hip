@@ -15,18 +15,18 @@
 //           (w_ek V_k = V_e / 12), written at the (hex, local) positions of the
 //           node lists, which the node pass sums per node in list order
 //           (shared with the tetrahedra's term layout).
-#include "device_util.h"
+#include "hex_crack.h"
 
 namespace cem {
 
 // hex node order: bottom face 0-1-2-3 counter-clockwise seen from above, top
 // face 4-7 above them; reference corner signs and the twelve edges
-__device__ __constant__ signed char kHexSign[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1},
-                                                       {-1, 1, -1},  {-1, -1, 1}, {1, -1, 1},
-                                                       {1, 1, 1},    {-1, 1, 1}};
-__device__ __constant__ signed char kHexEdgeL[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0},
-                                                        {4, 5}, {5, 6}, {6, 7}, {7, 4},
-                                                        {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+// (compile-time tables: with the edge-point loops unrolled, the shape-function
+// derivatives at each edge midpoint are constants, and their zeros fold away)
+constexpr signed char kHexSign[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                        {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+constexpr signed char kHexEdgeL[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
+                                          {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
 
 __device__ __forceinline__ void hex_nodes(const Mesh& m, int e, int* nd) {
   int4 a = m.hnodes[2 * e], b = m.hnodes[2 * e + 1];
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_strain_hex(Mesh m, const double4* __
       du[i][2] = (R)(ui.z - u0.z);
     }
     const double V = m.vol[e];
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < 12; ++q) {
       double xi[3], gd[8][3];
       hex_edge_point(q, xi);
@@ -156,13 +156,22 @@ __global__ __launch_bounds__(kBlock) void k_strain_hex(Mesh m, const double4* __
 }
 
 // The eight nodal terms of hex e, (V_e / 12) sum_q grad N_i(G_q)^T sigma_{k(q)},
-// written at the node-list positions of its (hex, local) entries.
+// written at the node-list positions of its (hex, local) entries.  The first
+// fg workgroups (dispatched first, so they run beside the element workgroups)
+// take the crack pass: both read the edge stresses and write disjoint data.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_elem_force_hex(Mesh m, const Six<R>* __restrict__ esig,
                                                            R* __restrict__ contrib,
-                                                           Counters* __restrict__ c) {
+                                                           const double4* __restrict__ uh,
+                                                           Counters* __restrict__ c, int fg,
+                                                           int flagging) {
   if (c->err) return;
-  Chunks it(m.T0);
+  if ((int)blockIdx.x < fg) {
+    __shared__ unsigned long long red[kBlock];
+    hex_front_block<R>(m, uh, esig, c, flagging, blockIdx.x, fg, red);
+    return;
+  }
+  Chunks it(m.T0, (int)gridDim.x - fg, fg);
   for (int e; it.next(e);) {
     if (e >= m.T0) continue;
     int nd[8];
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_elem_force_hex(Mesh m, const Six<R>*
     hex_coords(m, nd, x);
     const double w = m.vol[e] / 12.0;
     double f[8][3] = {};
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < 12; ++q) {
       const int2 k2 = m.he2e[6 * (size_t)e + (q >> 1)];
       const Six<R> sg = load6(esig + ((q & 1) ? k2.y : k2.x));
@@ -270,17 +279,19 @@ hipError_t launch_strain_hex(const Mesh& m, const double4* u, void* veps, Counte
 }
 
 template <class R>
-hipError_t launch_elem_force_hex(const Mesh& m, const void* esig, void* contrib, Counters* c,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_elem_force_hex<R>, dim3(persistent_grid(m, m.T0)), dim3(kBlock), 0, s, m,
-                     (const Six<R>*)esig, (R*)contrib, c);
+hipError_t launch_elem_force_hex(const Mesh& m, const void* esig, void* contrib, const double4* uh,
+                                 Counters* c, int fg, int flagging, hipStream_t s) {
+  hipLaunchKernelGGL(k_elem_force_hex<R>, dim3(fg + persistent_grid(m, m.T0)), dim3(kBlock), 0, s, m,
+                     (const Six<R>*)esig, (R*)contrib, uh, c, fg, flagging);
   return hipGetLastError();
 }
 
 template hipError_t launch_strain_hex<double>(const Mesh&, const double4*, void*, Counters*, hipStream_t);
 template hipError_t launch_strain_hex<float>(const Mesh&, const double4*, void*, Counters*, hipStream_t);
-template hipError_t launch_elem_force_hex<double>(const Mesh&, const void*, void*, Counters*, hipStream_t);
-template hipError_t launch_elem_force_hex<float>(const Mesh&, const void*, void*, Counters*, hipStream_t);
+template hipError_t launch_elem_force_hex<double>(const Mesh&, const void*, void*, const double4*,
+                                                  Counters*, int, int, hipStream_t);
+template hipError_t launch_elem_force_hex<float>(const Mesh&, const void*, void*, const double4*,
+                                                 Counters*, int, int, hipStream_t);
 
 hipError_t launch_dtcrit_hex(const Mesh& m, Counters* c, hipStream_t s) {
   hipLaunchKernelGGL(k_dtcrit_hex, dim3(grid_for(m.T0)), dim3(kBlock), 0, s, m, c);
