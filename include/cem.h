@@ -106,19 +106,22 @@ typedef struct {
 
 typedef struct {
   int32_t step;       /* step at whose end the split was applied (0: before stepping) */
-  int32_t tet;        /* original tet id */
-  int32_t side_mask;  /* bit l set: local node l on side B (the lone node's side) */
-  int32_t pattern;    /* 1 = pattern I (quadrilateral), 2 = pattern II (triangle), 0 = host pre-split */
+  int32_t tet;        /* original tet id (hex meshes: hex id) */
+  int32_t side_mask;  /* bit l set: local node l on side B (the lone node's side); hexes: crack plane 0-22 */
+  int32_t pattern;    /* 1 = pattern I (quadrilateral), 2 = pattern II (triangle), hexes 3-6 = III-VI,
+                         0 = host pre-split */
   double G;           /* release rate that triggered the split (0 for pre-splits) */
 } cem_split_event;
 
 typedef struct {
-  int32_t tet;   /* intact candidate tet */
-  int32_t face;  /* its local face on the crack front (face opposite local node `face`) */
-  int32_t lone;  /* node of that face alone on its side of the neighbour's cut (N2) */
+  int32_t tet;   /* intact candidate tet (hex meshes: hex) */
+  int32_t face;  /* its local face on the crack front (face opposite local node `face`; hexes:
+                    2 axis + (side > 0)) */
+  int32_t lone;  /* node of that face alone on its side of the neighbour's cut (N2); hexes: the
+                    candidate's crack plane */
   int32_t pad;
-  double G_I;    /* Eq. G-I */
-  double G_II;   /* Eq. G-II */
+  double G_I;    /* Eq. G-I (hexes: the candidate's G, Eq. G-I or G-II) */
+  double G_II;   /* Eq. G-II (hexes: the candidate's pattern, 3-6) */
 } cem_front_g;
 
 /* Create a context.  Validates the options only (no device call). */
