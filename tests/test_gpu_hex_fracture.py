@@ -10,6 +10,8 @@ through the C-ABI.
   within 1e-9, u, v within 1e-9 (relative L2), U_d and Gmax within 1e-9.  Mixed
   precision: the same events over the first 200 steps, u within 1e-5.
 - A checkpoint taken between cracks restores the same continuation bitwise.
+- A jittered notched plate pulled apart by prescribed velocities: identical
+  crack events, u within 1e-9, reactions and their work within 1e-9.
 - Refusals: a plane index past 22, a forced schedule, the static readback.
 """
 import numpy as np
@@ -152,4 +154,35 @@ def test_refusals():
     ev, G = sim.splits()
     o = Oracle.hex_mesh(m, MAT)
     assert np.array_equal(ev, o.splits()[0])
+    sim.close()
+
+
+def test_fracture_under_prescribed_velocities():
+    _case("hex notched plate pulled apart by prescribed velocities, 300 steps FP64")
+    m = mg.hex_notched(16, 10, 2)
+    m.X = mg.jitter(m, 0.1, seed=11).X
+    m.load_tris, m.load_trac = None, None
+    top = np.nonzero(np.abs(m.X[:, 1] - m.X[:, 1].max()) < 1e-12)[0]
+    bot = np.nonzero(np.abs(m.X[:, 1]) < 1e-12)[0]
+    vt = np.zeros((len(top), 3))
+    vt[:, 1] = 2.0
+    o = Oracle.hex_mesh(m, MAT)
+    sim = _sim(m)
+    dt = 0.5 * o.critical_dt()
+    o.set_dt(dt)
+    sim.set_dt(dt)
+    for x in (o, sim):
+        x.add_velocity_bc(top, np.full(len(top), 2), vt, 50 * dt)
+        x.add_velocity_bc(bot, np.full(len(bot), 2), np.zeros((len(bot), 3)), 0.0)
+    o.step(300)
+    sim.step(300)
+    eo, Go = o.splits()
+    eg, Gg = sim.splits()
+    assert (eo[:, 3] > 0).sum() > 10 and np.array_equal(eg, eo)
+    assert np.allclose(Gg, Go, rtol=1e-9, atol=0)
+    assert _rel(sim.get_state()[0], o.get_state()[0]) < 1e-9
+    for g in (0, 1):
+        ro, wo = o.reactions(g)
+        rg, wg = sim.reactions(g)
+        assert _rel(rg[:, 2:5], ro[:, 2:5]) < 1e-9 and wg == pytest.approx(wo, rel=1e-9)
     sim.close()
