@@ -53,10 +53,11 @@ ALG_BYTES = {
 KERNEL_NAMES = {"strain": ["k_strain"], "edge_stress": ["k_edge_stress"],
                 "node": ["k_elem_force_front", "k_node"]}
 KERNEL_NAMES_TILES = dict(KERNEL_NAMES, node=["k_front", "k_force_tile", "k_node"])
+KERNEL_NAMES_TILES_FX = dict(KERNEL_NAMES, node=["k_front", "k_force_fx", "k_node"])
 
 
 def kernel_names(layout):
-    return KERNEL_NAMES_TILES if layout == "tiles" else KERNEL_NAMES
+    return {"tiles": KERNEL_NAMES_TILES, "tiles_fx": KERNEL_NAMES_TILES_FX}.get(layout, KERNEL_NAMES)
 # steps before the warm-up by default: past the onset of dynamic splitting
 DEFAULT_ADVANCE = {"block": 1000, "block8m": 600, "plate": 600, "dirichlet": 600, "cube": 200}
 

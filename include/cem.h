@@ -56,7 +56,7 @@ enum { CEM_FP64 = 0, CEM_MIXED = 1 };          /* force arithmetic precision */
 enum { CEM_PHANTOM = 0, CEM_ERODE = 1 };       /* what a split does to the tet */
 enum { CEM_GSIG_PRINCIPAL = 0, CEM_GSIG_NORMAL = 1 };
 /* what the tet element force pass hands to the node pass (cem_set_launch) */
-enum { CEM_LAYOUT_TERMS = 0, CEM_LAYOUT_STRESS_SUMS = 1, CEM_LAYOUT_TILES = 2 };
+enum { CEM_LAYOUT_TERMS = 0, CEM_LAYOUT_STRESS_SUMS = 1, CEM_LAYOUT_TILES = 2, CEM_LAYOUT_TILES_FX = 3 };
 
 typedef struct cem_ctx cem_ctx;
 
@@ -294,15 +294,21 @@ int cem_read_energy_instances(cem_ctx* ctx, int32_t n, cem_energy* out);
  * pass forms G_l^T from the corner coordinates; CEM_LAYOUT_TILES forms the
  * terms and the node sums in one launch, a workgroup per tile of consecutive
  * nodes, the terms kept on chip (the same bits as CEM_LAYOUT_TERMS at equal
- * lanes; the crack-front pass then takes a launch of its own).  The same
- * forces in every layout up to rounding; which is faster depends on the mesh
- * size and precision.  Hexahedra always hand over nodal terms and ignore the
- * layout.  Lanes and layout set the order of the node sums, hence the
- * rounding.  CEM_LAYOUT_TILES on a mesh without tiles (a node with more than
- * 3,072 list entries, or hexahedra) is CEM_EINVAL. */
+ * lanes; the crack-front pass then takes a launch of its own);
+ * CEM_LAYOUT_TILES_FX does the same with tiles of up to 6,144 nodes whose
+ * sums are 64-bit fixed point in LDS (each term rounded to a multiple of
+ * 2^-k, k from the step's largest edge stress so that no node sum can reach
+ * 2^61; integer additions make the sums independent of their order; lanes are
+ * ignored).  The same forces in every layout up to rounding; which is faster
+ * depends on the mesh size and precision.  Hexahedra always hand over nodal
+ * terms and ignore the layout.  Lanes and layout set the order of the node
+ * sums, hence the rounding.  A tiled layout on a mesh without tiles (a node
+ * with more than 3,072 list entries for CEM_LAYOUT_TILES, or hexahedra) is
+ * CEM_EINVAL. */
 int cem_set_launch(cem_ctx* ctx, int32_t grid_cap, int32_t lanes, int32_t layout);
 /* Autotuner of the launch shape: times trial_steps steps of the live
- * simulation for each candidate (layout x grid 1024..8192 x lanes 4, 8, 16),
+ * simulation for each candidate (layout x grid 1024..8192 x lanes 4, 8, 16;
+ * one lane count for CEM_LAYOUT_TILES_FX),
  * restores the state after every trial and keeps the fastest (any output may
  * be NULL). */
 int cem_autotune(cem_ctx* ctx, int32_t trial_steps, int32_t* best_grid, int32_t* best_lanes,

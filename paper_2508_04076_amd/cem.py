@@ -22,7 +22,7 @@ ERROR_NAMES = {-1: "CEM_EINVAL", -2: "CEM_ENOMEM", -3: "CEM_EHIP", -4: "CEM_EMES
 PRECISION = {"fp64": 0, "mixed": 1}
 SPLIT_MODE = {"phantom": 0, "erode": 1}
 GSIG = {"principal": 0, "normal": 1}
-LAYOUT = {"terms": 0, "stress_sums": 1, "tiles": 2}
+LAYOUT = {"terms": 0, "stress_sums": 1, "tiles": 2, "tiles_fx": 3}
 
 EXPORTS = [
     "cem_create", "cem_destroy", "cem_last_error", "cem_upload_mesh", "cem_upload_hex_mesh",

@@ -21,6 +21,10 @@ template <class R> constexpr int tile_block() { return sizeof(R) == 8 ? 512 : 10
 // node-list entries of one tile (LDS: 3 values each, 72 KB in float64, 144 KB in float32)
 constexpr int kTileEntries64 = 3072;
 constexpr int kTileEntries32 = 12288;
+// nodes per tile of the fixed-point tiled force pass: three 64-bit sums per
+// node in LDS (144 KB), one 1,024-thread workgroup per CU
+constexpr int kFxNodes = 6144;
+constexpr int kFxBlock = 1024;
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
@@ -50,6 +54,7 @@ struct Counters {
   int batch_n;                    // volumes are left to k_topo_sums (0: none)
   int batch_apply_n;              // splits left to k_topo_apply / k_topo_finish (0: none)
   int dead_pending;               // candidates among them (dead list entries)
+  unsigned long long sig_key;     // ordered key of max |sigma| over the edges (fixed-point tiles)
 };
 
 // Six float values of a symmetric tensor in Voigt order
@@ -72,7 +77,8 @@ struct Mesh {
   int ssum;                 // tets: what the force pass hands to the node pass: 0 = nodal
                             // terms at node-list positions, 1 = per-tet stress sums (the
                             // node pass forms G_l from the corner coordinates)
-  int tiled;                // tets: 1 = tiled force pass (terms in LDS per node tile)
+  int tiled;                // tets: 1 = tiled force pass (terms in LDS per node tile),
+                            // 2 = fixed-point tiled pass (64-bit node sums in LDS)
   int ntile[2];             // node tiles of the tiled force pass, float64 and float32 sets (0: none)
   int n_inst;               // independent instances of a batch (0: one simulation)
   int etype;                // nodes per element: 4 (tetrahedra) or 8 (hexahedra)
@@ -119,6 +125,13 @@ struct Mesh {
   int* toff[2];             // [ntile + 1] first node of each tile
   int* ttoff[2];            // [ntile + 1] offsets into ttet
   int* ttet[2];             // tile element lists: parent tets with an entry in the tile, ascending
+  // tiles of the fixed-point tiled pass (up to kFxNodes consecutive nodes each)
+  int ntile_fx;
+  int* toff_fx;
+  int* ttoff_fx;
+  int* ttet_fx;
+  double fx_g1;             // max over tets and local nodes of |G_l|_1 (G_l = 6 V grad N_l)
+  int fx_deg;               // longest node list of an original node
 
   // trilinear hexahedra (etype 8; T_cap = T0).  A cracked hex keeps its slot
   // and carries the volume fraction its crack plane leaves (vol scaled);

@@ -61,8 +61,10 @@ __device__ __forceinline__ double elem_volume(const Mesh& m, int4 nd) {
 template <class R>
 __global__ __launch_bounds__(kBlock, CEM_WPE_STRAIN) void k_strain(Mesh m, const double4* __restrict__ u,
                                                    Six<R>* __restrict__ veps,
-                                                   const Counters* __restrict__ c) {
+                                                   Counters* __restrict__ c) {
   if (c->err) return;
+  // the edge pass that follows takes max |sigma| afresh (fixed-point tiles)
+  if (m.tiled == 2 && blockIdx.x == 0 && threadIdx.x == 0) c->sig_key = 0;
   const int Tn = elems_now(m, c);
   Chunks it(Tn);
   for (int e; it.next(e);) {
@@ -87,9 +89,10 @@ template <class R>
 __global__ __launch_bounds__(kBlock, CEM_WPE_EDGE) void k_edge_stress(Mesh m, const Six<R>* __restrict__ veps,
                                                         const R* __restrict__ einvV,
                                                         Six<R>* __restrict__ esig,
-                                                        const Counters* __restrict__ c) {
+                                                        Counters* __restrict__ c) {
   if (c->err) return;
   const int En = edges_now(m, c);
+  double smax = 0.0;  // max |sigma| component (scale of the fixed-point tiles)
   Chunks it(En);
   for (int k; it.next(k);) {
     if (k >= En) continue;
@@ -100,6 +103,14 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_EDGE) void k_edge_stress(Mesh m, co
     for (int i = 0; i < 6; ++i) eps[i] = acc[i] * iv;
     hooke((R)m.lam, (R)m.mu, eps, sig);
     store6(esig + k, sig);
+    if (m.tiled == 2)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) smax = fmax(smax, fabs((double)sig[i]));
+  }
+  if (m.tiled == 2) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
+    if ((threadIdx.x & 63) == 0 && smax > 0.0) atomicMax(&c->sig_key, dkey(smax));
   }
 }
 
@@ -561,6 +572,84 @@ __global__ __launch_bounds__(tile_block<R>()) void k_force_tile(Mesh m, State st
       if (active && g == 0) node_update<MODE, BC>(m, st, fout, c, i, fx, fy, fz);
     }
     __syncthreads();  // the next tile overwrites the LDS
+  }
+}
+
+// Terms of element slot e into the 64-bit node sums of the fixed-point tile
+// (nodes [n0, n1)): each term rounded to a multiple of 1 / S and added as an
+// integer, so the sums do not depend on the order of the additions; terms
+// of extra nodes go to the global term array.
+template <class R>
+__device__ __forceinline__ void fx_elem(const Mesh& m, int e, const Six<R>* __restrict__ esig,
+                                        unsigned long long* acc, int n0, int n1, double S,
+                                        R* __restrict__ contrib) {
+  const int4 nd = m.enodes[e];
+  const int code = (unsigned)nd.x >> kNodeBits;
+  if (code == FR_ZERO) return;
+  R out[4][3];
+  elem_terms(m, e, nd, code, esig, out);
+  const int ns[4] = {nd.x & kNodeMask, nd.y, nd.z, nd.w};
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int i = ns[l];
+    if (i >= n0 && i < n1) {
+      unsigned long long* a = acc + 3 * (i - n0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) atomicAdd(a + d, (unsigned long long)__double2ll_rn((double)out[l][d] * S));
+    } else if (i >= m.N0) {  // an extra node of a split copy: its single entry
+      const int4 pos = m.epos[e];
+      put_term(contrib, l == 0 ? pos.x : l == 1 ? pos.y : l == 2 ? pos.z : pos.w, out[l][0], out[l][1],
+               out[l][2]);
+    }
+  }
+}
+
+// Fixed-point tiled force pass: a workgroup owns a tile of up to kFxNodes
+// consecutive original nodes and keeps one 64-bit sum per node and component
+// in LDS.  Phase 1 adds the terms of every element slot with a node in the
+// tile (integer additions: the result does not depend on their order, so
+// any assignment of elements to threads gives the same bits); phase 2
+// converts each node's sums and updates the node.  The scale S = 2^k is the
+// largest power of two with (longest node list) * |term bound| * S < 2^61,
+// the bound |G_l|_1 max |sigma| / 6 from the edge pass's max |sigma|: each
+// term is kept to 2^-k, far below its own rounding at the bound's scale.
+// Twelve-times larger tiles than the term-slot tiles, so fewer tets are formed
+// twice on tile borders.
+template <class R, int MODE, bool BC>
+__global__ __launch_bounds__(kFxBlock) void k_force_fx(Mesh m, State st,
+                                                       const Six<R>* __restrict__ esig,
+                                                       R* __restrict__ contrib,
+                                                       double4* __restrict__ fout,
+                                                       Counters* __restrict__ c) {
+  if (c->err || over_capacity(m, c)) return;
+  __shared__ unsigned long long acc[3 * kFxNodes];
+  const unsigned long long key = c->sig_key;
+  const double bound = key ? m.fx_g1 * key_to_double(key) / 6.0 * (double)m.fx_deg : 0.0;
+  int ex = 0;
+  if (bound > 0.0) (void)frexp(bound, &ex);  // bound < 2^ex
+  const double S = ldexp(1.0, 61 - ex), iS = ldexp(1.0, ex - 61);
+  const int x = (int)blockIdx.x % 8, j0 = (int)blockIdx.x / 8, stride = (int)gridDim.x / 8;
+  const int b_hi = (int)((long long)m.ntile_fx * (x + 1) / 8);
+  const bool phantom = m.mode == MODE_PHANTOM;
+  for (int b = (int)((long long)m.ntile_fx * x / 8) + j0; b < b_hi; b += stride) {
+    const int n0 = m.toff_fx[b], n1 = m.toff_fx[b + 1];
+    for (int q = (int)threadIdx.x; q < 3 * (n1 - n0); q += kFxBlock) acc[q] = 0ull;
+    __syncthreads();
+    for (int jj = m.ttoff_fx[b] + (int)threadIdx.x; jj < m.ttoff_fx[b + 1]; jj += kFxBlock) {
+      const int t = m.ttet_fx[jj];
+      fx_elem<R>(m, t, esig, acc, n0, n1, S, contrib);
+      if (phantom) {
+        const int code = (unsigned)m.enodes[t].x >> kNodeBits;
+        if (code != FR_ONE) fx_elem<R>(m, m.T0 + m.split_of[t], esig, acc, n0, n1, S, contrib);
+      }
+    }
+    __syncthreads();
+    for (int i = n0 + (int)threadIdx.x; i < n1; i += kFxBlock) {
+      const unsigned long long* a = acc + 3 * (i - n0);
+      node_update<MODE, BC>(m, st, fout, c, i, (double)(long long)a[0] * iS,
+                            (double)(long long)a[1] * iS, (double)(long long)a[2] * iS);
+    }
+    __syncthreads();  // the next tile clears the sums
   }
 }
 
@@ -1744,6 +1833,29 @@ static void launch_tile_lanes(const Mesh& m, const State& st, const Work& w, Cou
 }
 
 template <class R>
+static void launch_fx(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
+                      double4* fout, hipStream_t s) {
+  int grid = (m.ntile_fx + 7) / 8 * 8;
+  if (grid > m.grid_cap) grid = m.grid_cap;
+  if (grid < 8) grid = 8;
+  dim3 g(grid), b(kFxBlock);
+  const Six<R>* sg = (const Six<R>*)w.esig;
+  R* ct = (R*)w.contrib;
+  if (mode == NODE_FORCE)
+    hipLaunchKernelGGL((k_force_fx<R, NODE_FORCE, false>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else if (mode == NODE_INIT && m.n_bc)
+    hipLaunchKernelGGL((k_force_fx<R, NODE_INIT, true>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else if (mode == NODE_INIT)
+    hipLaunchKernelGGL((k_force_fx<R, NODE_INIT, false>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else if (m.n_bc)
+    hipLaunchKernelGGL((k_force_fx<R, NODE_STEP, true>), g, b, 0, s, m, st, sg, ct, fout, c);
+  else
+    hipLaunchKernelGGL((k_force_fx<R, NODE_STEP, false>), g, b, 0, s, m, st, sg, ct, fout, c);
+  // the extra nodes of split copies: one lane each (a single entry)
+  if (m.mode == MODE_PHANTOM) launch_node_kind<R, 1, 0>(m, st, ct, c, mode, fout, s, m.N0);
+}
+
+template <class R>
 hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counters* c, int mode,
                            double4* fout, hipStream_t s, hipEvent_t mid, int front) {
   if (m.etype != 8 && m.tiled) {
@@ -1759,7 +1871,8 @@ hipError_t Launch<R>::node(const Mesh& m, const State& st, const Work& w, Counte
       hipError_t e = hipEventRecord(mid, s);
       if (e != hipSuccess) return e;
     }
-    if (m.lanes == 4) launch_tile_lanes<R, 4>(m, st, w, c, mode, fout, s);
+    if (m.tiled == 2) launch_fx<R>(m, st, w, c, mode, fout, s);
+    else if (m.lanes == 4) launch_tile_lanes<R, 4>(m, st, w, c, mode, fout, s);
     else if (m.lanes == 16) launch_tile_lanes<R, 16>(m, st, w, c, mode, fout, s);
     else launch_tile_lanes<R, 8>(m, st, w, c, mode, fout, s);
     return hipGetLastError();

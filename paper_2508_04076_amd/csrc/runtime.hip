@@ -342,6 +342,51 @@ bool build_tiles(int N, const HostTopo& h, int cap, std::vector<int>& toff, std:
   return true;
 }
 
+// Tiles of the fixed-point tiled pass: runs of up to kFxNodes consecutive
+// nodes, each with the parent tets that have an entry in it (ascending).
+void build_tiles_fx(int N, const HostTopo& h, std::vector<int>& toff, std::vector<int>& ttoff,
+                    std::vector<int>& ttet) {
+  toff.clear();
+  for (int i = 0; i < N; i += kFxNodes) toff.push_back(i);
+  toff.push_back(N);
+  const int nt = (int)toff.size() - 1;
+  ttoff.assign(1, 0);
+  ttet.clear();
+  std::vector<int> tmp;
+  for (int b = 0; b < nt; ++b) {
+    tmp.clear();
+    for (int p = h.noff[toff[b]]; p < h.noff[toff[b + 1]]; ++p) tmp.push_back(h.nent[p] >> 2);
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    ttet.insert(ttet.end(), tmp.begin(), tmp.end());
+    ttoff.push_back((int)ttet.size());
+  }
+}
+
+// Largest |G_l|_1 over the tets and their local nodes (G_l = 6 V grad N_l:
+// G_1 = c2 x c3, G_2 = c3 x c1, G_3 = c1 x c2, G_0 = -(G_1 + G_2 + G_3)).
+double max_face_normal_l1(int T, const std::vector<int>& tets, const double* X) {
+  double g1 = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const double* x0 = X + 3 * (size_t)tets[4 * t];
+    double cc[3][3];
+    for (int l = 0; l < 3; ++l)
+      for (int d = 0; d < 3; ++d) cc[l][d] = X[3 * (size_t)tets[4 * t + 1 + l] + d] - x0[d];
+    double G[4][3];
+    for (int l = 0; l < 3; ++l) {
+      const double* a = cc[(l + 1) % 3];
+      const double* b = cc[(l + 2) % 3];
+      G[l + 1][0] = a[1] * b[2] - a[2] * b[1];
+      G[l + 1][1] = a[2] * b[0] - a[0] * b[2];
+      G[l + 1][2] = a[0] * b[1] - a[1] * b[0];
+    }
+    for (int d = 0; d < 3; ++d) G[0][d] = -(G[1][d] + G[2][d] + G[3][d]);
+    for (int l = 0; l < 4; ++l)
+      g1 = std::max(g1, std::fabs(G[l][0]) + std::fabs(G[l][1]) + std::fabs(G[l][2]));
+  }
+  return g1;
+}
+
 int build_topology(cem_ctx* c, int N, int T, const std::vector<int>& tets, HostTopo& h) {
   // edges: sort (min, max) node-pair keys of every (tet, local edge)
   size_t M = (size_t)6 * T;
@@ -1213,6 +1258,20 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
       if ((r = upload(c, m.ttet[p], ttet.data(), ttet.size()))) return r;
     }
   }
+  {
+    std::vector<int> toff, ttoff, ttet;
+    build_tiles_fx(N, h, toff, ttoff, ttet);
+    m.ntile_fx = (int)toff.size() - 1;
+    ALLOC(m.toff_fx, toff.size(), false);
+    ALLOC(m.ttoff_fx, ttoff.size(), false);
+    ALLOC(m.ttet_fx, std::max<size_t>(ttet.size(), 1), false);
+    if ((r = upload(c, m.toff_fx, toff.data(), toff.size()))) return r;
+    if ((r = upload(c, m.ttoff_fx, ttoff.data(), ttoff.size()))) return r;
+    if (!ttet.empty() && (r = upload(c, m.ttet_fx, ttet.data(), ttet.size()))) return r;
+    m.fx_g1 = max_face_normal_l1(T, c->tets, c->X.data());
+    m.fx_deg = 0;
+    for (int i = 0; i < N; ++i) m.fx_deg = std::max(m.fx_deg, h.noff[i + 1] - h.noff[i]);
+  }
   ALLOC(c->d_snodes, std::max(S, 1), false);
   ALLOC(c->d_sedges, (size_t)6 * std::max(S, 1), false);
   char* vb;
@@ -1385,6 +1444,10 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.ntile[0] = m.ntile[1] = 0;
   m.split_of = nullptr;
   for (int p = 0; p < 2; ++p) m.toff[p] = m.ttoff[p] = m.ttet[p] = nullptr;
+  m.ntile_fx = 0;
+  m.toff_fx = m.ttoff_fx = m.ttet_fx = nullptr;
+  m.fx_g1 = 0.0;
+  m.fx_deg = 0;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 8;
@@ -1976,14 +2039,17 @@ int cem_set_launch(cem_ctx* c, int32_t grid_cap, int32_t lanes, int32_t layout) 
   c->gen++;
   if (grid_cap < 8 || grid_cap % 8 || (lanes != 4 && lanes != 8 && lanes != 16))
     return c->fail(CEM_EINVAL, "grid_cap must be a positive multiple of 8, lanes 4, 8 or 16");
-  if (layout != CEM_LAYOUT_TERMS && layout != CEM_LAYOUT_STRESS_SUMS && layout != CEM_LAYOUT_TILES)
-    return c->fail(CEM_EINVAL, "layout must be CEM_LAYOUT_TERMS, CEM_LAYOUT_STRESS_SUMS or CEM_LAYOUT_TILES");
+  if (layout < CEM_LAYOUT_TERMS || layout > CEM_LAYOUT_TILES_FX)
+    return c->fail(CEM_EINVAL, "layout must be CEM_LAYOUT_TERMS, CEM_LAYOUT_STRESS_SUMS, "
+                               "CEM_LAYOUT_TILES or CEM_LAYOUT_TILES_FX");
   if (layout == CEM_LAYOUT_TILES && (c->m.etype == 8 || c->m.ntile[0] == 0 || c->m.ntile[1] == 0))
+    return c->fail(CEM_EINVAL, "no node tiles for this mesh");
+  if (layout == CEM_LAYOUT_TILES_FX && (c->m.etype == 8 || c->m.ntile_fx == 0))
     return c->fail(CEM_EINVAL, "no node tiles for this mesh");
   c->m.grid_cap = grid_cap;
   c->m.lanes = lanes;
   c->m.ssum = c->m.etype == 8 ? 0 : layout == CEM_LAYOUT_STRESS_SUMS;
-  c->m.tiled = layout == CEM_LAYOUT_TILES;
+  c->m.tiled = layout == CEM_LAYOUT_TILES ? 1 : layout == CEM_LAYOUT_TILES_FX ? 2 : 0;
   drop_graph(c);
   return CEM_OK;
 }
@@ -2004,23 +2070,35 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
   if ((r = cem_save_state(c, buf.data(), used, &used))) return r;
   const int grids[4] = {1024, 2048, 4096, 8192};
   const int lanes[3] = {4, 8, 16};
-  // hexes have one layout; tets the term and stress-sum layouts, and the
-  // tiled pass when the mesh has tiles
-  const int nlay = c->m.etype == 8 ? 1 : (c->m.ntile[0] > 0 && c->m.ntile[1] > 0 ? 3 : 2);
-  int g0 = c->m.grid_cap, l0 = c->m.lanes, s0 = c->m.ssum + 2 * c->m.tiled;
+  // hexes have one layout; tets the term and stress-sum layouts, the tiled
+  // pass when the mesh has tiles and the fixed-point tiled pass
+  const bool have_tiles = c->m.ntile[0] > 0 && c->m.ntile[1] > 0;
+  int lays[4], nlay = 0;
+  lays[nlay++] = CEM_LAYOUT_TERMS;
+  if (c->m.etype != 8) {
+    lays[nlay++] = CEM_LAYOUT_STRESS_SUMS;
+    if (have_tiles) lays[nlay++] = CEM_LAYOUT_TILES;
+    if (c->m.ntile_fx > 0) lays[nlay++] = CEM_LAYOUT_TILES_FX;
+  }
+  int g0 = c->m.grid_cap, l0 = c->m.lanes;
+  int s0 = c->m.ssum ? CEM_LAYOUT_STRESS_SUMS
+                     : c->m.tiled == 1 ? CEM_LAYOUT_TILES : c->m.tiled == 2 ? CEM_LAYOUT_TILES_FX : CEM_LAYOUT_TERMS;
   double best = 1e300;
   int bg = g0, bl = l0, bs = s0;
   int saved_prof = c->profiling;
   c->profiling = 0;
   // one warm-up trial, then every candidate
   if ((r = cem_step(c, trial_steps)) == CEM_OK) r = cem_load_state(c, buf.data(), used);
-  for (int si = 0; si < nlay && r == CEM_OK; ++si)
+  for (int k = 0; k < nlay && r == CEM_OK; ++k)
     for (int gi = 0; gi < 4 && r == CEM_OK; ++gi)
       for (int li = 0; li < 3 && r == CEM_OK; ++li) {
+        const int si = lays[k];
+        // the fixed-point tiles have one lane per node: a single lane count
+        if (si == CEM_LAYOUT_TILES_FX && li > 0) continue;
         c->m.grid_cap = grids[gi];
         c->m.lanes = lanes[li];
-        c->m.ssum = si == 1;
-        c->m.tiled = si == 2;
+        c->m.ssum = si == CEM_LAYOUT_STRESS_SUMS;
+        c->m.tiled = si == CEM_LAYOUT_TILES ? 1 : si == CEM_LAYOUT_TILES_FX ? 2 : 0;
         drop_graph(c);
         if ((r = cem_step(c, trial_steps))) break;
         double ms = c->times[0] / trial_steps;
@@ -2033,10 +2111,11 @@ int cem_autotune(cem_ctx* c, int32_t trial_steps, int32_t* best_grid, int32_t* b
         r = cem_load_state(c, buf.data(), used);
       }
   c->profiling = saved_prof;
+  const int sf = r ? s0 : bs;
   c->m.grid_cap = r ? g0 : bg;
   c->m.lanes = r ? l0 : bl;
-  c->m.ssum = (r ? s0 : bs) == 1;
-  c->m.tiled = (r ? s0 : bs) == 2;
+  c->m.ssum = sf == CEM_LAYOUT_STRESS_SUMS;
+  c->m.tiled = sf == CEM_LAYOUT_TILES ? 1 : sf == CEM_LAYOUT_TILES_FX ? 2 : 0;
   drop_graph(c);
   if (r) return r;
   if (best_grid) *best_grid = bg;

@@ -3,7 +3,8 @@ to the node pass, which forms G_l^T s itself from the corner coordinates) and
 the tiled force pass (terms and node sums in one launch, a workgroup per
 tile of consecutive nodes, the terms kept in LDS) against the oracle and
 against the default term layout, through the C-ABI.  The tiled pass gives the
-term layout's bits at equal lanes.
+term layout's bits at equal lanes.  The fixed-point tiled pass (64-bit node
+sums in LDS) gives bits that depend on no launch shape.
 
 Tolerances as the other parity tests: FP64 forces 1e-12 normwise relative,
 FP64 trajectories 1e-9 relative L2 after splitting, identical split events;
@@ -37,7 +38,7 @@ def _sim(mesh, layout="stress_sums", lanes=8, **kw):
     return sim
 
 
-LAYOUTS = ["stress_sums", "tiles"]
+LAYOUTS = ["stress_sums", "tiles", "tiles_fx"]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -148,7 +149,7 @@ def test_tiles_with_prescribed_velocities_and_a_batch():
         assert np.array_equal(a_, b_)
     un, node_off, tet_off, _, _ = mg.ensemble(2, 3000, 6000, seed=4)
     res = []
-    for layout in ("terms", "tiles"):
+    for layout in ("terms", "tiles", "tiles_fx"):
         sim = Simulation(un.X, un.tets, MAT, max_splits=un.n_tets)
         sim.set_instances(node_off, tet_off)
         sim.set_traction(un.load_tris, un.load_trac, 1e-6)
@@ -159,6 +160,7 @@ def test_tiles_with_prescribed_velocities_and_a_batch():
         res.append((sim.get_state()[0], sim.splits()[0]))
         sim.close()
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][1], res[2][1]) and _rel(res[2][0], res[0][0]) < 1e-10
 
 
 def test_checkpoint_and_layout_switch():
@@ -205,3 +207,23 @@ def test_hexes_ignore_the_layout():
         us.append(sim.get_state()[0])
         sim.close()
     assert np.array_equal(us[0], us[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fixed_point_tiles_do_not_depend_on_the_launch(precision):
+    _case(f"tiles_fx: grid 8 / 64 / 1024, 300 steps through splitting, {precision}; vs terms")
+    mesh = mg.cube_notched(10)
+    out = []
+    for layout, grid in (("tiles_fx", 8), ("tiles_fx", 64), ("tiles_fx", 1024), ("terms", 1024)):
+        sim = _sim(mesh, layout=layout, precision=precision, graph_steps=25)
+        sim.set_launch(grid, 4, layout)
+        sim.set_dt(6.797514528978e-06)
+        sim.step(300)
+        out.append((sim.get_state()[0], sim.splits()[0]))
+        sim.close()
+    assert (out[0][1][:, 3] > 0).sum() > 50
+    for u, e in out[1:3]:
+        assert np.array_equal(u, out[0][0]) and np.array_equal(e, out[0][1])
+    assert np.array_equal(out[3][1], out[0][1])
+    assert _rel(out[0][0], out[3][0]) < (1e-10 if precision == "fp64" else 1e-6)
+
