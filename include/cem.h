@@ -295,7 +295,7 @@ int cem_read_energy_instances(cem_ctx* ctx, int32_t n, cem_energy* out);
  * terms and the node sums in one launch, a workgroup per tile of consecutive
  * nodes, the terms kept on chip (the same bits as CEM_LAYOUT_TERMS at equal
  * lanes; the crack-front pass then takes a launch of its own);
- * CEM_LAYOUT_TILES_FX does the same with tiles of up to 6,144 nodes whose
+ * CEM_LAYOUT_TILES_FX does the same with tiles of up to 1,536 nodes whose
  * sums are 64-bit fixed point in LDS (each term rounded to a multiple of
  * 2^-k, k from the step's largest edge stress so that no node sum can reach
  * 2^61; integer additions make the sums independent of their order; lanes are

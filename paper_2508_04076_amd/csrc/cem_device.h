@@ -22,9 +22,9 @@ template <class R> constexpr int tile_block() { return sizeof(R) == 8 ? 512 : 10
 constexpr int kTileEntries64 = 3072;
 constexpr int kTileEntries32 = 12288;
 // nodes per tile of the fixed-point tiled force pass: three 64-bit sums per
-// node in LDS (144 KB), one 1,024-thread workgroup per CU
-constexpr int kFxNodes = 6144;
-constexpr int kFxBlock = 1024;
+// node in LDS (36 KB), four 512-thread workgroups per CU
+constexpr int kFxNodes = 1536;
+constexpr int kFxBlock = 512;
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
