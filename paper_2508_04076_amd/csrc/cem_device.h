@@ -22,9 +22,15 @@ template <class R> constexpr int tile_block() { return sizeof(R) == 8 ? 512 : 10
 constexpr int kTileEntries64 = 3072;
 constexpr int kTileEntries32 = 12288;
 // nodes per tile of the fixed-point tiled force pass: three 64-bit sums per
-// node in LDS (36 KB), four 512-thread workgroups per CU
+// node in LDS (36 KB), four 512-thread workgroups per CU.  Meshes with fewer
+// than kFxTargetTiles full tiles take smaller tiles (down to kFxMinNodes, in
+// steps of 64) so that the launch still spreads over every CU.
 constexpr int kFxNodes = 1536;
 constexpr int kFxBlock = 512;
+constexpr int kFxMinNodes = 128;
+constexpr int kFxTargetTiles = 2048;
+constexpr int kSigSlots = 64;        // one wave reads them all
+constexpr int kSigStride = 32;       // 256 bytes apart
 constexpr int kNodeBits = 28;        // node id bits in the packed node word
 constexpr int kNodeMask = (1 << kNodeBits) - 1;
 
@@ -54,7 +60,6 @@ struct Counters {
   int batch_n;                    // volumes are left to k_topo_sums (0: none)
   int batch_apply_n;              // splits left to k_topo_apply / k_topo_finish (0: none)
   int dead_pending;               // candidates among them (dead list entries)
-  unsigned long long sig_key;     // ordered key of max |sigma| over the edges (fixed-point tiles)
 };
 
 // Six float values of a symmetric tensor in Voigt order
@@ -132,6 +137,11 @@ struct Mesh {
   int* ttet_fx;
   double fx_g1;             // max over tets and local nodes of |G_l|_1 (G_l = 6 V grad N_l)
   int fx_deg;               // longest node list of an original node
+  // [kSigSlots slots, kSigStride apart] ordered keys of max |sigma| over the
+  // edges of this step, each slot taken by every kSigSlots-th workgroup of
+  // the edge pass (spread over memory so that the atomics do not queue on
+  // one address); the force pass takes the largest
+  unsigned long long* sig_slot;
 
   // trilinear hexahedra (etype 8; T_cap = T0).  A cracked hex keeps its slot
   // and carries the volume fraction its crack plane leaves (vol scaled);

@@ -61,10 +61,10 @@ __device__ __forceinline__ double elem_volume(const Mesh& m, int4 nd) {
 template <class R>
 __global__ __launch_bounds__(kBlock, CEM_WPE_STRAIN) void k_strain(Mesh m, const double4* __restrict__ u,
                                                    Six<R>* __restrict__ veps,
-                                                   Counters* __restrict__ c) {
+                                                   const Counters* __restrict__ c) {
   if (c->err) return;
   // the edge pass that follows takes max |sigma| afresh (fixed-point tiles)
-  if (m.tiled == 2 && blockIdx.x == 0 && threadIdx.x == 0) c->sig_key = 0;
+  if (m.tiled == 2 && blockIdx.x == 0 && threadIdx.x < kSigSlots) m.sig_slot[threadIdx.x * kSigStride] = 0;
   const int Tn = elems_now(m, c);
   Chunks it(Tn);
   for (int e; it.next(e);) {
@@ -89,7 +89,7 @@ template <class R>
 __global__ __launch_bounds__(kBlock, CEM_WPE_EDGE) void k_edge_stress(Mesh m, const Six<R>* __restrict__ veps,
                                                         const R* __restrict__ einvV,
                                                         Six<R>* __restrict__ esig,
-                                                        Counters* __restrict__ c) {
+                                                        const Counters* __restrict__ c) {
   if (c->err) return;
   const int En = edges_now(m, c);
   double smax = 0.0;  // max |sigma| component (scale of the fixed-point tiles)
@@ -108,9 +108,20 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_EDGE) void k_edge_stress(Mesh m, co
       for (int i = 0; i < 6; ++i) smax = fmax(smax, fabs((double)sig[i]));
   }
   if (m.tiled == 2) {
+    // one atomic per workgroup, on the slot of its residue: on a small mesh
+    // every workgroup ends at once, and thousands of atomics on one address
+    // would outlast the pass itself
+    __shared__ double wmax[kBlock / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
-    if ((threadIdx.x & 63) == 0 && smax > 0.0) atomicMax(&c->sig_key, dkey(smax));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = smax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = wmax[0];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) b = fmax(b, wmax[w]);
+      if (b > 0.0) atomicMax(m.sig_slot + (blockIdx.x % kSigSlots) * kSigStride, dkey(b));
+    }
   }
 }
 
@@ -624,7 +635,13 @@ __global__ __launch_bounds__(kFxBlock) void k_force_fx(Mesh m, State st,
                                                        Counters* __restrict__ c) {
   if (c->err || over_capacity(m, c)) return;
   __shared__ unsigned long long acc[3 * kFxNodes];
-  const unsigned long long key = c->sig_key;
+  static_assert(kSigSlots == 64, "one wave reduces the slots");
+  unsigned long long key = m.sig_slot[(threadIdx.x & 63) * kSigStride];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(key, off);
+    key = o > key ? o : key;
+  }
   const double bound = key ? m.fx_g1 * key_to_double(key) / 6.0 * (double)m.fx_deg : 0.0;
   int ex = 0;
   if (bound > 0.0) (void)frexp(bound, &ex);  // bound < 2^ex

@@ -342,12 +342,21 @@ bool build_tiles(int N, const HostTopo& h, int cap, std::vector<int>& toff, std:
   return true;
 }
 
-// Tiles of the fixed-point tiled pass: runs of up to kFxNodes consecutive
+// Nodes per tile of the fixed-point tiled pass: kFxNodes, or fewer (a multiple
+// of 64, at least kFxMinNodes) when that gives at least kFxTargetTiles tiles.
+static int fx_tile_nodes(int N) {
+  int t = (int)(((long long)N + kFxTargetTiles - 1) / kFxTargetTiles);
+  t = (t + 63) / 64 * 64;
+  return std::min(kFxNodes, std::max(kFxMinNodes, t));
+}
+
+// Tiles of the fixed-point tiled pass: runs of fx_tile_nodes(N) consecutive
 // nodes, each with the parent tets that have an entry in it (ascending).
 void build_tiles_fx(int N, const HostTopo& h, std::vector<int>& toff, std::vector<int>& ttoff,
                     std::vector<int>& ttet) {
+  const int tn = fx_tile_nodes(N);
   toff.clear();
-  for (int i = 0; i < N; i += kFxNodes) toff.push_back(i);
+  for (int i = 0; i < N; i += tn) toff.push_back(i);
   toff.push_back(N);
   const int nt = (int)toff.size() - 1;
   ttoff.assign(1, 0);
@@ -1268,6 +1277,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
     if ((r = upload(c, m.toff_fx, toff.data(), toff.size()))) return r;
     if ((r = upload(c, m.ttoff_fx, ttoff.data(), ttoff.size()))) return r;
     if (!ttet.empty() && (r = upload(c, m.ttet_fx, ttet.data(), ttet.size()))) return r;
+    ALLOC(m.sig_slot, (size_t)kSigSlots * kSigStride, false);
     m.fx_g1 = max_face_normal_l1(T, c->tets, c->X.data());
     m.fx_deg = 0;
     for (int i = 0; i < N; ++i) m.fx_deg = std::max(m.fx_deg, h.noff[i + 1] - h.noff[i]);
@@ -1448,6 +1458,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.toff_fx = m.ttoff_fx = m.ttet_fx = nullptr;
   m.fx_g1 = 0.0;
   m.fx_deg = 0;
+  m.sig_slot = nullptr;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 8;
