@@ -545,10 +545,11 @@ def bench_ensemble(args):
         "config": {"workload": "batch of 64 notched plates, 20k-200k tets each (seed 2), "
                                "tractions 0.5-2 MPa, one launch per pass",
                    "tets": T, "instances": 64, "dt_range_s": [float(dts.min()), float(dts.max())],
-                   "launch": f"HIP graphs of {gs} steps; autotuned grid {tuned['grid_cap']}, "
-                             f"{tuned['lanes']} lanes per node",
+                   "launch": f"HIP graphs of {gs} steps; autotuned {tuned['layout']} layout, "
+                             f"grid {tuned['grid_cap']}, {tuned['lanes']} lanes per node",
                    "splits_after_run": int(sum(x["n_split"] for x in e))},
-        "roofline": {"bound": "hbm", "kernel": "k_elem_force+k_node", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "+".join(kernel_names(tuned["layout"])["node"]),
+                     "layout": tuned["layout"], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "alg_bytes_per_tet": ALG_BYTES[prec]["node"],
                      "avg_launch_ms": per["node"]},
