@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void k_strain2(Mesh m, const double4* __res
     R ol[6] = {0, 0, 0, 0, 0, 0}, ou[6] = {0, 0, 0, 0, 0, 0};
     if (code != FR_ZERO) {
       R g[3][3], d[3][3];
-      face_normals(m.X[n0], m.X[nd.y], m.X[nd.z], m.X[nd.w], g);
+      slot_normals<R>(m, e, nd, g);
       R f = (R)(frac_of(code) / 6.0);
       node_diffs(lam[n0], lam[nd.y], lam[nd.z], lam[nd.w], d);
       sym_grad(g, d, f, ol);

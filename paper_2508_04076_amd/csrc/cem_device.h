@@ -91,6 +91,12 @@ struct Mesh {
   int4* enodes;             // [T_cap] node ids; .x also holds the fraction code
   int2* et2e;               // [T_cap * 3] six edge ids (local edge order 01 02 03 12 13 23)
   double4* X;               // [N_cap] coordinates (extra nodes copy their twin)
+  // [T_cap][9] g_1, g_2, g_3 (g_l = 6 V grad N_l, the corner face normals of
+  // face_normals) of each element slot in float32, streamed by the
+  // mixed-precision strain passes instead of four coordinate gathers (the
+  // force passes, whose coordinate gathers hide behind their stress gathers,
+  // keep forming them); a split copy takes its parent's row (the same corners)
+  float* gtab;
   int* poff;                // [E_cap + 1] edge patch offsets
   int* pent;                // [6 T0 + 10 S_cap] element ids, -1 = removed
   int* noff;                // [N_cap + 1] node -> (element, local) offsets
@@ -215,6 +221,7 @@ hipError_t launch_topology_t(const Mesh& m, const State& st, const Work& w, Coun
                              int dynamic, int advance, int4* snodes, int* sedges, hipStream_t s);
 hipError_t launch_replay_select(const Mesh& m, Counters* c, hipStream_t s);
 hipError_t launch_masses(const Mesh& m, hipStream_t s);
+hipError_t launch_normals(const Mesh& m, const Counters* c, hipStream_t s);
 hipError_t launch_loads(const Mesh& m, const int4* ftri, const double4* ftrac, const int* lfoff,
                         const int* lfent, hipStream_t s);
 hipError_t launch_dtcrit(const Mesh& m, Counters* c, hipStream_t s);

@@ -112,6 +112,27 @@ __device__ __forceinline__ void face_normals(double4 x0, double4 x1, double4 x2,
   g[2][0] = c1y * c2z - c1z * c2y; g[2][1] = c1z * c2x - c1x * c2z; g[2][2] = c1x * c2y - c1y * c2x;
 }
 
+// The float32 corner normals of element slot e from the table (the values
+// face_normals<float> gives for its corners).
+__device__ __forceinline__ void table_normals(const Mesh& m, int e, float g[3][3]) {
+  const float* p = m.gtab + 9 * (size_t)e;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[l][d] = p[3 * l + d];
+}
+
+// g_1..g_3 of element slot e with corners nd: from the table in float32,
+// from the coordinates in float64.
+template <class R>
+__device__ __forceinline__ void slot_normals(const Mesh& m, int e, int4 nd, R g[3][3]) {
+  if constexpr (sizeof(R) == 4) {
+    table_normals(m, e, g);
+  } else {
+    face_normals(m.X[nd.x & kNodeMask], m.X[nd.y], m.X[nd.z], m.X[nd.w], g);
+  }
+}
+
 // d_l = u_l - u_0 (l = 1..3), taken in float64 before any conversion to R.
 template <class R>
 __device__ __forceinline__ void node_diffs(double4 u0, double4 u1, double4 u2, double4 u3,

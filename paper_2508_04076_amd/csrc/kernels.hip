@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock, CEM_WPE_STRAIN) void k_strain(Mesh m, const
   R out[6] = {0, 0, 0, 0, 0, 0};
   if (code != FR_ZERO) {
     R g[3][3], d[3][3];
-    face_normals(m.X[n0], m.X[nd.y], m.X[nd.z], m.X[nd.w], g);
+    slot_normals<R>(m, e, nd, g);
     node_diffs(u[n0], u[nd.y], u[nd.z], u[nd.w], d);
     sym_grad(g, d, (R)(frac_of(code) / 6.0), out);
   }
@@ -1136,6 +1136,9 @@ __device__ __forceinline__ void split_write(const Mesh& m, const State& st, R* _
     m.et2e[3 * tb] = make_int2(eB[0], eB[1]);
     m.et2e[3 * tb + 1] = make_int2(eB[2], eB[3]);
     m.et2e[3 * tb + 2] = make_int2(eB[4], eB[5]);
+    // the copy's corners sit where the parent's do (extra nodes copy their twins)
+#pragma unroll
+    for (int r = 0; r < 9; ++r) m.gtab[9 * (size_t)tb + r] = m.gtab[9 * (size_t)t + r];
   }
 }
 
@@ -1516,6 +1519,20 @@ __global__ __launch_bounds__(kBlock) void k_volumes(Mesh m) {
   int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= m.T0) return;
   m.vol[e] = elem_volume(m, m.enodes[e]);
+}
+
+// Corner-normal table rows of every element slot in use, from the coordinates.
+__global__ __launch_bounds__(kBlock) void k_normals(Mesh m, const Counters* __restrict__ c) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= elems_now(m, c)) return;
+  const int4 nd = m.enodes[e];
+  float g[3][3];
+  face_normals(m.X[nd.x & kNodeMask], m.X[nd.y], m.X[nd.z], m.X[nd.w], g);
+  float* p = m.gtab + 9 * (size_t)e;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[3 * l + d] = g[l][d];
 }
 
 // Lumped mass m_i = sum rho V_eff / 4 over the elements holding node i.
@@ -2005,6 +2022,12 @@ hipError_t launch_set_presplit(const Mesh& m, Counters* c, const int* tets, cons
   if (g < 1) g = 1;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_set_presplit, dim3(g), dim3(kBlock), 0, s, m, c, tets, masks, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(const Mesh& m, const Counters* c, hipStream_t s) {
+  if (m.etype == 8 || !m.gtab || m.T_cap == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normals, dim3(grid_for(m.T_cap)), dim3(kBlock), 0, s, m, c);
   return hipGetLastError();
 }
 

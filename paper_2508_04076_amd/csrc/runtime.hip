@@ -1278,6 +1278,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
     if ((r = upload(c, m.ttoff_fx, ttoff.data(), ttoff.size()))) return r;
     if (!ttet.empty() && (r = upload(c, m.ttet_fx, ttet.data(), ttet.size()))) return r;
     ALLOC(m.sig_slot, (size_t)kSigSlots * kSigStride, false);
+    ALLOC(m.gtab, (size_t)9 * m.T_cap, false);
     m.fx_g1 = max_face_normal_l1(T, c->tets, c->X.data());
     m.fx_deg = 0;
     for (int i = 0; i < N; ++i) m.fx_deg = std::max(m.fx_deg, h.noff[i + 1] - h.noff[i]);
@@ -1361,6 +1362,7 @@ int cem_upload_mesh(cem_ctx* c, int32_t N, const double* X, int32_t T, const int
   HIPCHK(c, hipMemsetAsync(m.vol, 0, sizeof(double) * m.T_cap, c->stream));
   HIPCHK(c, hipMemsetAsync(m.invm, 0, sizeof(double) * m.N_cap, c->stream));
   HIPCHK(c, launch_masses(m, c->stream));
+  HIPCHK(c, launch_normals(m, c->d_ctr, c->stream));
   if (c->mixed) HIPCHK(c, Launch<float>::edge_volumes(m, c->w, -1, c->stream));
   else HIPCHK(c, Launch<double>::edge_volumes(m, c->w, -1, c->stream));
   if ((r = sync(c))) return r;
@@ -1459,6 +1461,7 @@ int cem_upload_hex_mesh(cem_ctx* c, int32_t N, const double* X, int32_t H, const
   m.fx_g1 = 0.0;
   m.fx_deg = 0;
   m.sig_slot = nullptr;
+  m.gtab = nullptr;
   m.topo_multi = 0;
   m.n_inst = 0;
   m.etype = 8;
@@ -2316,6 +2319,8 @@ int cem_load_state(cem_ctx* c, const void* buf, int64_t size) {
     HIPCHK(c, hipMemcpyAsync(g.ptr, p, g.bytes, hipMemcpyHostToDevice, c->stream));
     p += g.bytes;
   }
+  // the corner-normal rows of the restored split copies
+  HIPCHK(c, launch_normals(c->m, c->d_ctr, c->stream));
   if ((r = sync(c))) return r;
   std::memcpy(c->split_host.data(), p, c->m.T0);
   c->need_init = h[8] != 0;
