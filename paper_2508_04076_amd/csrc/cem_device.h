@@ -22,7 +22,8 @@ template <class R> constexpr int tile_block() { return sizeof(R) == 8 ? 512 : 10
 constexpr int kTileEntries64 = 3072;
 constexpr int kTileEntries32 = 12288;
 // nodes per tile of the fixed-point tiled force pass: three 64-bit sums per
-// node in LDS (36 KB), four 512-thread workgroups per CU.  Meshes with fewer
+// node in LDS (36 KB; the registers leave room for two 512-thread workgroups
+// per CU in float32, one in float64).  Meshes with fewer
 // than kFxTargetTiles full tiles take smaller tiles (down to kFxMinNodes, in
 // steps of 64) so that the launch still spreads over every CU.
 constexpr int kFxNodes = 1536;

@@ -626,7 +626,7 @@ __device__ __forceinline__ void fx_elem(const Mesh& m, int e, const Six<R>* __re
 // term is kept to 2^-k, far below its own rounding at the bound's scale.
 // With no per-entry slots a tile holds more nodes than the term-slot tiles
 // (1,536 against 128 or 512), so fewer tets are formed twice on tile borders,
-// and four workgroups still share a CU's LDS.
+// and its LDS is small enough for several workgroups per CU.
 template <class R, int MODE, bool BC>
 __global__ __launch_bounds__(kFxBlock) void k_force_fx(Mesh m, State st,
                                                        const Six<R>* __restrict__ esig,
