@@ -202,18 +202,24 @@ def test_deterministic_and_graph_equals_plain():
             assert np.array_equal(x, y)
 
 
-def test_checkpoint_resume_bitwise():
-    _case("checkpoint cube 8")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_checkpoint_resume_bitwise(precision):
+    # the checkpoint holds split copies made by dynamic splits of the first
+    # context only: the second must take their geometry (in mixed precision
+    # the corner-normal rows of the copies) from the restored topology
+    _case(f"checkpoint cube 8 {precision}")
     mesh = mg.cube_notched(8)
-    a = _sim(mesh)
+    a = _sim(mesh, precision=precision)
     dt = 0.5 * a.critical_dt()
     a.set_dt(dt)
     a.step(80)
+    ev0, _ = a.splits()
+    assert (ev0[:, 0] > 0).sum() > 0
     buf = a.save_state()
     a.step(80)
     ua, va, _ = a.get_state()
     eva, _ = a.splits()
-    b = _sim(mesh)
+    b = _sim(mesh, precision=precision)
     b.set_dt(dt)
     b.load_state(buf)
     b.step(80)
