@@ -4,8 +4,9 @@ The oracle cannot build meshes of this size in a test's time, so these are
 properties that hold at any size: symmetry of the smoothed stiffness
 (<K u, v> = <u, K v>), zero force under rigid-body motion, the linear patch
 test (constant strain reproduced, no force away from boundaries and crack
-faces), and mixed precision against FP64 within the 1e-5 relative L2 bound
-on u with the FP64 split schedule replayed.
+faces), the fixed-point tiled force pass at its full tile size against the
+term layout (1e-12 normwise), and mixed precision against FP64 within the
+1e-5 relative L2 bound on u with the FP64 split schedule replayed.
 """
 import numpy as np
 import pytest
@@ -92,7 +93,8 @@ def test_block8m_mixed_against_fp64(block8m):
 
 def test_block48m_symmetry_and_mixed():
     # the 400 x 200 x 100-cell block (48,000,000 tets, 960,000 pre-split)
-    _case("block 48,000,000 tets: symmetry; mixed vs FP64, 100 steps, schedule replayed")
+    _case("block 48,000,000 tets: symmetry; fixed-point tiles vs terms; mixed with fixed-point "
+          "tiles vs FP64, 100 steps, schedule replayed")
     mesh = mg.block_notched()
     s64 = _sim(mesh, graph_steps=50)
     n = s64.n_nodes
@@ -101,6 +103,12 @@ def test_block48m_symmetry_and_mixed():
     v = rng.standard_normal((n, 3)) * 1e-7
     Ku, Kv = s64.internal_force(u), s64.internal_force(v)
     assert abs((Ku * v).sum() - (u * Kv).sum()) <= 1e-12 * np.sqrt((Ku * Ku).sum() * (v * v).sum())
+    # the fixed-point tiles at their full size (8.1M nodes: 1,536-node tiles),
+    # the bench's force pass, against the term layout
+    s64.set_launch(8192, 4, "tiles_fx")
+    Ku_fx = s64.internal_force(u)
+    assert np.linalg.norm(Ku_fx - Ku) <= 1e-12 * np.linalg.norm(Ku)
+    s64.set_launch(2048, 8, "terms")
     dt = 0.5 * s64.critical_dt()
     s64.set_dt(dt)
     s64.step(100)
@@ -108,6 +116,7 @@ def test_block48m_symmetry_and_mixed():
     ev = s64.splits()[0]
     s64.close()
     mx = _sim(mesh, graph_steps=50, precision="mixed")
+    mx.set_launch(8192, 4, "tiles_fx")
     mx.set_dt(dt)
     dyn = ev[ev[:, 3] > 0][:, :3]
     if len(dyn):
